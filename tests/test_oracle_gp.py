@@ -1,0 +1,159 @@
+"""Pins of the oracle's Gauss-point update (CPU only).
+
+* an elastic step reproduces the linear DMN: sigma = C_lin E, C_algo = C_lin
+  (C_lin from Milton's formula, an independent route);
+* at convergence the leaf strains average to E and the Hill-Mandel identity
+  E . sigma = sum_j w~_j eps_j . sigma_j holds;
+* the algorithmic tangent equals central finite differences of sigma(E);
+* depth 1 agrees with a general-purpose root finder on the interface
+  condition written out by hand;
+* equal normals collapse a nonlinear depth-4 DMN to a single laminate;
+* identical elastic phases leave the jumps at zero;
+* the status codes of the failure modes.
+"""
+import numpy as np
+import pytest
+import scipy.optimize as so
+
+import synthetic as S
+from oracle import gp as G
+from oracle.j2 import J2Material, j2_update
+from oracle.linear import dmn_linear
+from oracle.mandel import N_matrix, iso_from_E_nu
+
+
+def model_for(net, fiber=S.FIBER, matrix=S.MATRIX):
+    return G.DmnModel(net.depth, net.w, net.normals, fiber, matrix)
+
+
+def test_elastic_step_equals_linear_dmn():
+    rng = np.random.default_rng(30)
+    net = S.random_dmn(rng, 3, 0.25)
+    m = model_for(net)
+    E = 1e-4 * S.unit_directions(rng, 1)[0]
+    out = G.gp_update(m, E, np.zeros((4, 7)), np.zeros(21))
+    assert out["status"] == 0 and out["iters"] == 1
+    Cf = iso_from_E_nu(S.FIBER["E"], S.FIBER["nu"])
+    Cm = iso_from_E_nu(S.MATRIX["E"], S.MATRIX["nu"])
+    Clin = dmn_linear(3, net.w, net.normals, Cf, Cm)
+    assert np.abs(out["C"] - Clin).max() <= 1e-11 * np.abs(Clin).max()
+    assert np.abs(out["sigma"] - Clin @ E).max() <= 1e-11 * np.abs(out["sigma"]).max()
+    assert np.all(out["z"] == 0.0)
+
+
+def plastic_state(K, seed, steps=6, mag=0.02):
+    rng = np.random.default_rng(seed)
+    net = S.random_dmn(rng, K, 0.25)
+    m = model_for(net)
+    d = S.unit_directions(rng, 1)[0]
+    path = [(n / steps) * mag * d for n in range(1, steps + 1)]
+    outs = G.run_path(m, path)
+    assert all(o["status"] == 0 for o in outs)
+    return m, path, outs
+
+
+def test_equilibrium_strain_average_and_hill_mandel():
+    m, path, outs = plastic_state(4, 31)
+    last = outs[-1]
+    assert np.any(last["z"][:, 6] > 0)
+    eps, sig = last["eps"], last["sig_leaf"]
+    wt = m.w / m.w.sum()
+    assert np.allclose(wt @ eps, path[-1], atol=1e-15)
+    lhs = path[-1] @ last["sigma"]
+    rhs = np.sum(wt * np.einsum("ja,ja->j", eps, sig))
+    assert abs(lhs - rhs) <= 1e-8 * abs(lhs)
+
+
+def test_algorithmic_tangent_matches_finite_differences():
+    m, path, outs = plastic_state(3, 32)
+    z_n, a_n = outs[-2]["z"], outs[-2]["a"]
+    E = path[-1]
+    tight = G.NewtonOptions(tol=1e-14, max_iter=50)
+    C = G.gp_update(m, E, z_n, a_n, tight)["C"]
+    h = 1e-7
+    fd = np.zeros((6, 6))
+    for c in range(6):
+        d = np.zeros(6)
+        d[c] = h
+        fd[:, c] = (G.gp_update(m, E + d, z_n, a_n, tight)["sigma"]
+                    - G.gp_update(m, E - d, z_n, a_n, tight)["sigma"]) / (2 * h)
+    assert np.abs(fd - C).max() <= 1e-5 * np.abs(C).max()
+    assert np.abs(C - C.T).max() <= 1e-10 * np.abs(C).max()
+
+
+def test_depth1_matches_generic_root_finder():
+    rng = np.random.default_rng(33)
+    net = S.random_dmn(rng, 1, 0.3)
+    m = model_for(net)
+    mat = J2Material(**S.MATRIX)
+    Cf = iso_from_E_nu(S.FIBER["E"], S.FIBER["nu"])
+    c1 = net.w[0] / net.w.sum()
+    c2 = 1 - c1
+    N = N_matrix(net.normals[0])
+    d = S.unit_directions(rng, 1)[0]
+    z, a = np.zeros((1, 7)), np.zeros(3)
+    for n in range(1, 6):
+        E = n * 0.005 * d
+        out = G.gp_update(m, E, z, a, G.NewtonOptions(tol=1e-14, max_iter=50))
+
+        def interface(x):
+            sf = Cf @ (E - c2 * N @ x)
+            sm = j2_update(mat, E + c1 * N @ x, z[0, :6], z[0, 6])["sigma"]
+            return N.T @ (sm - sf)
+
+        sol = so.root(interface, a, method="hybr", options=dict(xtol=1e-14))
+        x = sol.x
+        sf = Cf @ (E - c2 * N @ x)
+        mo = j2_update(mat, E + c1 * N @ x, z[0, :6], z[0, 6])
+        sbar = c1 * sf + c2 * mo["sigma"]
+        assert np.abs(out["sigma"] - sbar).max() <= 1e-9 * np.abs(sbar).max()
+        z, a = out["z"], out["a"]
+
+
+def test_equal_normals_collapse_nonlinear():
+    rng = np.random.default_rng(34)
+    net = S.random_dmn(rng, 4, 0.25)
+    n = net.normals[0]
+    deep = G.DmnModel(4, net.w, np.tile(n, (15, 1)), S.FIBER, S.MATRIX)
+    f = net.w[0::2].sum()
+    one = G.DmnModel(1, np.array([f, 1 - f]), n[None, :], S.FIBER, S.MATRIX)
+    d = S.unit_directions(rng, 1)[0]
+    path = [k * 0.004 * d for k in range(1, 7)]
+    tight = G.NewtonOptions(tol=1e-14, max_iter=50)
+    a_deep = G.run_path(deep, path, tight)
+    a_one = G.run_path(one, path, tight)
+    for x, y in zip(a_deep, a_one):
+        assert np.abs(x["sigma"] - y["sigma"]).max() <= 1e-9 * np.abs(y["sigma"]).max()
+        assert np.abs(x["C"] - y["C"]).max() <= 1e-8 * np.abs(y["C"]).max()
+
+
+def test_identical_elastic_phases_keep_zero_jumps():
+    rng = np.random.default_rng(35)
+    net = S.random_dmn(rng, 3, 0.25)
+    soft = dict(S.MATRIX)
+    m = G.DmnModel(3, net.w, net.normals, dict(E=soft["E"], nu=soft["nu"]), soft)
+    E = 1e-4 * S.unit_directions(rng, 1)[0]
+    out = G.gp_update(m, E, np.zeros((4, 7)), np.zeros(21))
+    assert out["status"] == 0
+    assert np.abs(out["a"]).max() <= 1e-15
+    C = iso_from_E_nu(soft["E"], soft["nu"])
+    assert np.allclose(out["sigma"], C @ E, rtol=1e-13)
+
+
+def test_status_codes():
+    rng = np.random.default_rng(36)
+    net = S.random_dmn(rng, 2, 0.25)
+    z, a = np.zeros((2, 7)), np.zeros(9)
+    E = 0.02 * S.unit_directions(rng, 1)[0]
+    bad = G.DmnModel(2, np.array([0.5, -0.1, 0.3, 0.3]), net.normals, S.FIBER, S.MATRIX)
+    assert G.gp_update(bad, E, z, a)["status"] == G.BADPARAM
+    zero_pair = G.DmnModel(2, np.array([0.0, 0.0, 0.5, 0.5]), net.normals, S.FIBER, S.MATRIX)
+    assert G.gp_update(zero_pair, E, z, a)["status"] == G.BADPARAM
+    m = model_for(net)
+    out = G.gp_update(m, E * np.nan, z, a)
+    assert out["status"] == G.NONFINITE and np.all(out["z"] == z)
+    out = G.gp_update(m, E, z, a, G.NewtonOptions(max_iter=0))
+    assert out["status"] == G.MAXITER and out["iters"] == 0
+    # zero strain from the virgin state: zero residual, converged without a step
+    out = G.gp_update(m, np.zeros(6), z, a)
+    assert out["status"] == 0 and out["iters"] == 0
