@@ -1,0 +1,189 @@
+/*
+ * libdmn — batched online evaluation and training kernels of direct deep
+ * material networks (DMNs) on AMD Instinct MI355X (gfx950).
+ *
+ * A direct DMN of depth K is a perfect binary tree of 2^K - 1 rank-one
+ * laminates over 2^K leaves (FE-DMN paper, Sec. 2.1).  Leaves alternate
+ * between phase 1 (the linear elastic fibre; even 0-based leaf index) and
+ * phase 2 (the J2 elasto-plastic matrix; odd index).  Laminate volume
+ * fractions follow from the leaf weights by weight propagation
+ * (c1 = W_left / (W_left + W_right), Sec. 2.1); every laminate has a
+ * lamination normal.
+ *
+ * Conventions shared by all calls
+ *   - Mandel notation: symmetric tensors are 6-vectors
+ *     [11, 22, 33, sqrt2*23, sqrt2*13, sqrt2*12]; stiffnesses and tangents are
+ *     6x6 Mandel matrices stored row-major as 36 numbers.  Mandel l2 norms are
+ *     Frobenius norms.
+ *   - Paper order of laminates (Sec. 3.1/3.2): deepest level K first, then
+ *     K-1, ..., root last; laminate (k, i) (level k, 1-based index i) sits at
+ *     position 2^K - 2^k + i - 1.  Normals and jump vectors use this order.
+ *   - Per-point arrays are point-major: the record of point p is contiguous
+ *     (an FE code's per-integration-point state vector).
+ *   - Every pointer argument of type void* / int32_t* inside the structs and
+ *     the data arguments is a DEVICE pointer owned by the caller; the structs
+ *     themselves are host memory read during the call only.  Device buffers
+ *     must stay alive until the stream reaches the enqueued work.
+ *   - Calls enqueue kernels on `stream` and return at once.  They allocate
+ *     nothing, never synchronise and never read device data on the host, so
+ *     they can be captured into a HIP graph.  The return code reflects only
+ *     host-side argument validation and launch errors; per-point device
+ *     outcomes are written to the status arrays.
+ *   - Workspace: each call needs a device workspace of at least the size its
+ *     *_workspace_size() query returns (256-byte aligned base).
+ *   - No C++ exception crosses this interface.  Calls on different streams
+ *     may run concurrently as long as they use different workspaces.
+ */
+#ifndef DMN_H
+#define DMN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes (host-side) */
+#define DMN_OK 0
+#define DMN_EINVAL (-1)       /* null pointer, depth outside [1,10], bad sizes or options */
+#define DMN_EWORKSPACE (-2)   /* workspace missing or smaller than the size query */
+#define DMN_EHIP (-3)         /* a HIP launch failed */
+#define DMN_EUNSUPPORTED (-4) /* precision / option combination not implemented */
+
+/* precision of storage and arithmetic */
+#define DMN_F64 0       /* FP64 storage, FP64 arithmetic */
+#define DMN_F32 1       /* FP32 storage, FP32 arithmetic (linear map only) */
+#define DMN_F32_STATE 2 /* FP32 storage of per-point arrays, FP64 arithmetic (reserved) */
+
+/* per-point status written by dmn_update_gauss_points */
+#define DMN_STATUS_OK 0        /* converged */
+#define DMN_STATUS_MAXITER 1   /* Newton iteration limit reached */
+#define DMN_STATUS_NONFINITE 2 /* non-finite input or residual */
+#define DMN_STATUS_NOTSPD 3    /* a laminate pivot of the Hessian is not positive definite */
+#define DMN_STATUS_LOCAL 4     /* J2 return mapping did not converge */
+#define DMN_STATUS_BADPARAM 5  /* negative leaf weight or a laminate with zero child weight */
+
+#define DMN_MAX_DEPTH 10
+
+/* A direct DMN: depth K, leaf weights w[2^K] (non-negative, need not sum to
+ * one: fractions are weight ratios and averages use w / sum(w)), normals
+ * n[2^K - 1][3] in paper order (unit length expected; used as passed).
+ * Both arrays are device memory in the precision of the call. */
+typedef struct dmn_net {
+  int32_t depth;
+  const void* w;
+  const void* n;
+} dmn_net;
+
+/* Isotropic linear elastic phase 1 (the fibre): Young's modulus, Poisson ratio. */
+typedef struct dmn_elastic {
+  double E, nu;
+} dmn_elastic;
+
+/* J2 phase 2 (the matrix), Sec. 4.1: von Mises yield with
+ * sigma_Y(p) = sigma0 + k_inf p + dsigma (1 - exp(-b p)), p the accumulated
+ * equivalent plastic strain. */
+typedef struct dmn_j2 {
+  double E, nu, sigma0, k_inf, dsigma, b;
+} dmn_j2;
+
+/* Newton options (Sec. 3.2, Sec. 4.6): stop when
+ * |A^T W sigma| <= tol (2^K - 1) |sigma_bar| (Frobenius norms); at most
+ * max_iter Newton steps; backtracking halves the step while the trial residual
+ * is non-finite or |r(a + s da)| > (1 - armijo s) |r(a)|, at most
+ * max_backtrack times (the last trial is then taken as it is). */
+typedef struct dmn_newton_opts {
+  double tol;
+  int32_t max_iter;
+  int32_t max_backtrack;
+  double armijo;
+} dmn_newton_opts;
+
+/* One batch of Gauss points that share a DMN.  With M = 2^(K-1) matrix
+ * leaves and L = 2^K - 1 laminates (all arrays FP64, point-major):
+ *   E       [P][6]     macro strain of the new step
+ *   z_in    [P][M][7]  internal variables of the last converged step, per
+ *                      matrix leaf: plastic strain (Mandel 6) then p
+ *   z_out   [P][M][7]  updated internal variables
+ *   a_in    [P][L][3]  jumps of the last converged step (initial guess)
+ *   a_out   [P][L][3]  converged jumps
+ *   sigma   [P][6]     effective stress sum_j w~_j sigma_j
+ *   tangent [P][36]    algorithmic tangent d sigma / d E
+ *   iters   [P]        Newton steps taken
+ *   status  [P]        DMN_STATUS_*
+ * The update is functional: z_in and a_in are never written, and must not
+ * alias z_out / a_out.  On a non-zero status z_out = z_in and a_out = a_in so
+ * the caller can retry with a smaller increment; sigma then holds the last
+ * iterate and tangent is NaN. */
+typedef struct dmn_point_group {
+  dmn_net net;
+  int64_t P;
+  const void* E;
+  const void* z_in;
+  void* z_out;
+  const void* a_in;
+  void* a_out;
+  void* sigma;
+  void* tangent;
+  int32_t* iters;
+  int32_t* status;
+} dmn_point_group;
+
+/* Version string of the library. */
+const char* dmn_version(void);
+
+/* Workspace bytes for dmn_homogenize_linear. */
+size_t dmn_homogenize_linear_workspace_size(int32_t depth, int64_t B, int prec);
+
+/* Linear DMN homogenisation DMN^L (Sec. 3.1, stiffness propagation):
+ * for each of B samples, phase stiffnesses C1[b], C2[b] (6x6 Mandel,
+ * row-major, [B][36]; read as their symmetric part) are homogenised bottom-up
+ * through the laminate tree of `net`; the result goes to Cbar[b] ([B][36],
+ * symmetric).  prec: DMN_F64 or DMN_F32 (all arrays, including w and n, in
+ * that precision).  An invalid DMN (negative weight, zero child weight) or a
+ * non-SPD laminate pivot sets the device error word at the start of the
+ * workspace (int32, 0 = fine; read it after the stream has finished) and
+ * leaves NaN in the affected outputs. */
+int dmn_homogenize_linear(const dmn_net* net, int64_t B, int prec, const void* C1,
+                          const void* C2, void* Cbar, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Workspace bytes for dmn_homogenize_backward. */
+size_t dmn_homogenize_backward_workspace_size(int32_t depth, int64_t B, int prec);
+
+/* Vector-Jacobian product of dmn_homogenize_linear: given the cotangent
+ * gCbar[B][36] of Cbar, writes (overwrites)
+ *   gw [2^K]     sum over samples of d<gCbar, Cbar>/d w
+ *   gn [L][3]    sum over samples of d<gCbar, Cbar>/d n (n as passed; the
+ *                map is invariant to the length of n, so gn is tangential)
+ *   gC1, gC2 [B][36]  per-sample d<gCbar, Cbar>/d C1, C2 (symmetric), or NULL
+ * The batch sums use a fixed reduction order (bit-reproducible run to run).
+ * The forward is recomputed inside the call.  Same error word as the forward. */
+int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void* C1,
+                            const void* C2, const void* gCbar, void* gw, void* gn, void* gC1,
+                            void* gC2, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes for dmn_update_gauss_points. */
+size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int32_t n_groups,
+                                              int prec);
+
+/* Online evaluation of DMNs at Gauss points (Sec. 3.2, Sec. 4.6): for every
+ * point of every group, solve the DMN's Euler-Lagrange equation
+ * A^T W sigma(E + A a, z_in) = 0 for the jumps a by Newton's method from
+ * a_in, with the J2 return mapping at matrix leaves and linear elasticity at
+ * fibre leaves; return the effective stress, the algorithmic tangent, the
+ * updated internal variables and the converged jumps.  Groups may have
+ * different depths.  prec: DMN_F64.  At most 64 groups per call. */
+int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
+                            const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
+                            const dmn_newton_opts* opts, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMN_H */

@@ -20,10 +20,12 @@ from .tree import fractions, gradient_operator, lam_pos, n_laminates
 def milton_alpha(CL, CR):
     """Reading: alpha = half the smallest eigenvalue of both children (the paper only
     asks for alpha 'sufficiently large or suitably small'); the laminate result does
-    not depend on the admissible alpha chosen."""
-    lo = min(np.linalg.eigvalsh(np.real(0.5 * (CL + CL.T))).min(),
-             np.linalg.eigvalsh(np.real(0.5 * (CR + CR.T))).min())
-    return 0.5 * lo
+    not depend on the admissible alpha chosen.  Works on stacks [..., 6, 6] and
+    returns [..., 1, 1]."""
+    sym = lambda C: np.real(0.5 * (C + np.swapaxes(C, -1, -2)))
+    lo = np.minimum(np.linalg.eigvalsh(sym(CL)).min(axis=-1),
+                    np.linalg.eigvalsh(sym(CR)).min(axis=-1))
+    return (0.5 * lo)[..., None, None]
 
 
 def laminate_milton(CL, CR, c1, c2, n, alpha=None):
@@ -31,7 +33,8 @@ def laminate_milton(CL, CR, c1, c2, n, alpha=None):
 
     (P + alpha [C - alpha I]^-1)^-1 = c1 (P + alpha [CL - alpha I]^-1)^-1
                                     + c2 (P + alpha [CR - alpha I]^-1)^-1,
-    solved for C.  Complex-safe for complex-step differentiation.
+    solved for C.  CL, CR may be stacks [..., 6, 6] sharing the laminate.
+    Complex-safe for complex-step differentiation.
     """
     P = projector_P(n)
     I = np.eye(6)

@@ -1,0 +1,11 @@
+"""MI355X-native engine for the hot path of the FE-DMN method.
+
+Batched online evaluation of direct deep material networks at Gauss points
+(J2 leaves, Newton on the laminate jumps with a tree block-Cholesky), the
+linear DMN homogenisation used in offline training and its hand-written
+backward.  All computation runs in the HIP kernels of libdmn.so; this package
+only marshals arguments.
+"""
+from .api import (PointGroup, dmn_homogenize_backward, dmn_homogenize_linear,  # noqa: F401
+                  dmn_update_gauss_points, error_word, workspace)
+from ._lib import DmnError, STATUS  # noqa: F401

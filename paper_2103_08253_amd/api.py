@@ -1,0 +1,188 @@
+"""Python binding of libdmn with the C ABI's names (argument marshalling only).
+
+Every function takes torch tensors that already live on the GPU, checks
+their dtypes, shapes and contiguity, and enqueues the library call on the
+current HIP stream.  No computation happens here.
+"""
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional
+
+import torch
+
+from . import _lib as L
+
+_PREC = {torch.float64: L.DMN_F64, torch.float32: L.DMN_F32}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str, dtype, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _net(w: torch.Tensor, n: torch.Tensor, dtype):
+    K = int(round(torch.log2(torch.tensor(float(w.numel()))).item()))
+    if 2 ** K != w.numel() or not 1 <= K <= 10:
+        raise ValueError("w must hold 2^K leaf weights with 1 <= K <= 10")
+    _need(w, "w", dtype, (2 ** K,))
+    _need(n, "n", dtype, (2 ** K - 1, 3))
+    return L.DmnNet(K, w.data_ptr(), n.data_ptr()), K
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """Device workspace (torch's allocator returns 512-byte aligned blocks)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def error_word(ws: torch.Tensor) -> int:
+    """Device error word of a linear / backward call (synchronises on read)."""
+    return int(ws[:4].view(torch.int32).item())
+
+
+def dmn_homogenize_linear(w, n, C1, C2, Cbar=None, ws=None):
+    """Cbar[b] = DMN^L(C1[b], C2[b]) for a batch [B, 6, 6] (or [B, 36])."""
+    dtype = C1.dtype
+    if dtype not in _PREC:
+        raise TypeError("float64 or float32 expected")
+    net, K = _net(w, n, dtype)
+    B = C1.shape[0]
+    _need(C1, "C1", dtype)
+    _need(C2, "C2", dtype)
+    if C1.numel() != 36 * B or C2.numel() != 36 * B:
+        raise ValueError("C1, C2 must be [B, 6, 6]")
+    if Cbar is None:
+        Cbar = torch.empty((B, 6, 6), dtype=dtype, device=C1.device)
+    _need(Cbar, "Cbar", dtype)
+    prec = _PREC[dtype]
+    lib = L.lib()
+    nbytes = lib.dmn_homogenize_linear_workspace_size(K, B, prec)
+    if ws is None or ws.numel() < nbytes:
+        ws = workspace(nbytes, C1.device)
+    rc = lib.dmn_homogenize_linear(ctypes.byref(net), B, prec, _ptr(C1), _ptr(C2), _ptr(Cbar),
+                                   _ptr(ws), ws.numel(), _stream())
+    L.check(rc, "dmn_homogenize_linear")
+    return Cbar, ws
+
+
+def dmn_homogenize_backward(w, n, C1, C2, gCbar, want_input_grads=False, ws=None):
+    """(gw, gn, gC1, gC2) of sum_b <gCbar[b], Cbar[b]>; gC1/gC2 None unless requested."""
+    dtype = C1.dtype
+    net, K = _net(w, n, dtype)
+    B = C1.shape[0]
+    for t, nm in ((C1, "C1"), (C2, "C2"), (gCbar, "gCbar")):
+        _need(t, nm, dtype)
+        if t.numel() != 36 * B:
+            raise ValueError(f"{nm} must be [B, 6, 6]")
+    gw = torch.empty(2 ** K, dtype=dtype, device=C1.device)
+    gn = torch.empty((2 ** K - 1, 3), dtype=dtype, device=C1.device)
+    gC1 = gC2 = None
+    if want_input_grads:
+        gC1 = torch.empty((B, 6, 6), dtype=dtype, device=C1.device)
+        gC2 = torch.empty((B, 6, 6), dtype=dtype, device=C1.device)
+    prec = _PREC[dtype]
+    lib = L.lib()
+    nbytes = lib.dmn_homogenize_backward_workspace_size(K, B, prec)
+    if ws is None or ws.numel() < nbytes:
+        ws = workspace(nbytes, C1.device)
+    rc = lib.dmn_homogenize_backward(ctypes.byref(net), B, prec, _ptr(C1), _ptr(C2), _ptr(gCbar),
+                                     _ptr(gw), _ptr(gn), _ptr(gC1), _ptr(gC2), _ptr(ws),
+                                     ws.numel(), _stream())
+    L.check(rc, "dmn_homogenize_backward")
+    return gw, gn, gC1, gC2, ws
+
+
+@dataclass
+class PointGroup:
+    """Device arrays of one batch of Gauss points sharing a DMN (see include/dmn.h)."""
+    w: torch.Tensor
+    n: torch.Tensor
+    E: torch.Tensor
+    z_in: torch.Tensor
+    z_out: torch.Tensor
+    a_in: torch.Tensor
+    a_out: torch.Tensor
+    sigma: torch.Tensor
+    tangent: torch.Tensor
+    iters: torch.Tensor
+    status: torch.Tensor
+
+    @staticmethod
+    def allocate(w, n, E, z_in=None, a_in=None):
+        """Outputs (and zero initial state if not given) for the points of E [P, 6]."""
+        K = int(round(torch.log2(torch.tensor(float(w.numel()))).item()))
+        P = E.shape[0]
+        dev, dt = E.device, torch.float64
+        M, Lm = 2 ** (K - 1), 2 ** K - 1
+        if z_in is None:
+            z_in = torch.zeros((P, M, 7), dtype=dt, device=dev)
+        if a_in is None:
+            a_in = torch.zeros((P, Lm, 3), dtype=dt, device=dev)
+        return PointGroup(w, n, E, z_in, torch.empty_like(z_in), a_in, torch.empty_like(a_in),
+                          torch.empty((P, 6), dtype=dt, device=dev),
+                          torch.empty((P, 6, 6), dtype=dt, device=dev),
+                          torch.empty(P, dtype=torch.int32, device=dev),
+                          torch.empty(P, dtype=torch.int32, device=dev))
+
+    def advance(self):
+        """Make the outputs the next step's inputs (swap the state buffers)."""
+        self.z_in, self.z_out = self.z_out, self.z_in
+        self.a_in, self.a_out = self.a_out, self.a_in
+
+    def to_c(self):
+        net, K = _net(self.w, self.n, torch.float64)
+        P = self.E.shape[0]
+        M, Lm = 2 ** (K - 1), 2 ** K - 1
+        _need(self.E, "E", torch.float64, (P, 6))
+        for t, nm in ((self.z_in, "z_in"), (self.z_out, "z_out")):
+            _need(t, nm, torch.float64, (P, M, 7))
+        for t, nm in ((self.a_in, "a_in"), (self.a_out, "a_out")):
+            _need(t, nm, torch.float64, (P, Lm, 3))
+        _need(self.sigma, "sigma", torch.float64, (P, 6))
+        _need(self.tangent, "tangent", torch.float64)
+        if self.tangent.numel() != 36 * P:
+            raise ValueError("tangent must be [P, 6, 6]")
+        _need(self.iters, "iters", torch.int32, (P,))
+        _need(self.status, "status", torch.int32, (P,))
+        return L.DmnPointGroup(net, P, self.E.data_ptr(), self.z_in.data_ptr(),
+                               self.z_out.data_ptr(), self.a_in.data_ptr(), self.a_out.data_ptr(),
+                               self.sigma.data_ptr(), self.tangent.data_ptr(),
+                               self.iters.data_ptr(), self.status.data_ptr())
+
+
+def _materials(fiber: dict, matrix: dict):
+    return (L.DmnElastic(fiber["E"], fiber["nu"]),
+            L.DmnJ2(matrix["E"], matrix["nu"], matrix["sigma0"], matrix["k_inf"],
+                    matrix["dsigma"], matrix["b"]))
+
+
+def dmn_update_gauss_points(groups: List[PointGroup], fiber: dict, matrix: dict, tol=1e-10,
+                            max_iter=25, max_backtrack=10, armijo=1e-4, ws=None):
+    """One load step at every point of every group (outputs written in place)."""
+    arr = (L.DmnPointGroup * len(groups))(*[g.to_c() for g in groups])
+    fib, mat = _materials(fiber, matrix)
+    opts = L.DmnNewtonOpts(tol, max_iter, max_backtrack, armijo)
+    lib = L.lib()
+    nbytes = lib.dmn_update_gauss_points_workspace_size(arr, len(groups), L.DMN_F64)
+    if nbytes == 0:
+        raise L.DmnError("dmn_update_gauss_points_workspace_size rejected the groups")
+    if ws is None or ws.numel() < nbytes:
+        ws = workspace(nbytes, groups[0].E.device)
+    rc = lib.dmn_update_gauss_points(arr, len(groups), ctypes.byref(fib), ctypes.byref(mat),
+                                     L.DMN_F64, ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                     _stream())
+    L.check(rc, "dmn_update_gauss_points")
+    return ws

@@ -1,0 +1,210 @@
+// C ABI of libdmn: argument validation, workspace layout and launch
+// sequencing.  No allocation, no synchronisation, no device reads on the host.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "dmn_internal.hpp"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+inline size_t elt_size(int prec) { return prec == DMN_F32 ? sizeof(float) : sizeof(double); }
+
+// Workspace layout: [header 256 B: int32 error word at 0]
+//                   then per table: [flag 256 B][rows L x 8 elements, aligned]
+inline size_t table_bytes(int depth, int prec) {
+  const size_t L = ((size_t)1 << depth) - 1;
+  return kAlign + align_up(L * dmn::kTabStride * elt_size(prec));
+}
+
+inline bool depth_ok(int32_t d) { return d >= 1 && d <= DMN_MAX_DEPTH; }
+
+struct Table {
+  int32_t* flag;
+  void* rows;
+};
+
+inline Table table_at(void* ws, size_t offset) {
+  char* p = (char*)ws + offset;
+  return Table{(int32_t*)p, (void*)(p + kAlign)};
+}
+
+inline bool phase_ok(const dmn_elastic* f) {
+  return f && f->E > 0.0 && f->nu > -1.0 && f->nu < 0.5;
+}
+inline bool j2_ok(const dmn_j2* m) {
+  return m && m->E > 0.0 && m->nu > -1.0 && m->nu < 0.5 && m->sigma0 > 0.0 && m->k_inf >= 0.0 &&
+         m->dsigma >= 0.0 && m->b >= 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dmn_version(void) { return "libdmn 0.1 gfx950"; }
+
+size_t dmn_homogenize_linear_workspace_size(int32_t depth, int64_t B, int prec) {
+  if (!depth_ok(depth) || B < 0 || (prec != DMN_F64 && prec != DMN_F32)) return 0;
+  return kAlign + table_bytes(depth, prec);
+}
+
+int dmn_homogenize_linear(const dmn_net* net, int64_t B, int prec, const void* C1,
+                          const void* C2, void* Cbar, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  if (!net || !depth_ok(net->depth) || B < 0) return DMN_EINVAL;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!net->w || !net->n) return DMN_EINVAL;
+  if (B > 0 && (!C1 || !C2 || !Cbar)) return DMN_EINVAL;
+  const size_t need = dmn_homogenize_linear_workspace_size(net->depth, B, prec);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
+  int32_t* err = (int32_t*)ws;
+  Table tb = table_at(ws, kAlign);
+  if (dmn::launch_prep_tables(net->w, net->n, net->depth, prec, tb.rows, tb.flag, err, stream))
+    return DMN_EHIP;
+  if (B == 0) return DMN_OK;
+  if (dmn::launch_linear_forward(net->depth, prec, tb.rows, tb.flag, B, C1, C2, Cbar, err,
+                                 stream))
+    return DMN_EHIP;
+  return DMN_OK;
+}
+
+size_t dmn_homogenize_backward_workspace_size(int32_t depth, int64_t B, int prec) {
+  if (!depth_ok(depth) || B < 0 || (prec != DMN_F64 && prec != DMN_F32)) return 0;
+  const size_t L = ((size_t)1 << depth) - 1;
+  const size_t slots = (size_t)dmn::linear_backward_partials(depth, B);
+  return kAlign + table_bytes(depth, prec) + align_up(L * 4 * sizeof(double)) +
+         align_up(slots * L * 4 * sizeof(double));
+}
+
+int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void* C1,
+                            const void* C2, const void* gCbar, void* gw, void* gn, void* gC1,
+                            void* gC2, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!net || !depth_ok(net->depth) || B < 0) return DMN_EINVAL;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!net->w || !net->n || !gw || !gn) return DMN_EINVAL;
+  if (B > 0 && (!C1 || !C2 || !gCbar)) return DMN_EINVAL;
+  if ((gC1 == nullptr) != (gC2 == nullptr)) return DMN_EINVAL;
+  const size_t need = dmn_homogenize_backward_workspace_size(net->depth, B, prec);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
+  const int K = net->depth;
+  const size_t L = ((size_t)1 << K) - 1;
+  int32_t* err = (int32_t*)ws;
+  Table tb = table_at(ws, kAlign);
+  double* gsum = (double*)((char*)ws + kAlign + table_bytes(K, prec));
+  double* partials = (double*)((char*)gsum + align_up(L * 4 * sizeof(double)));
+  if (dmn::launch_prep_tables(net->w, net->n, K, prec, tb.rows, tb.flag, err, stream))
+    return DMN_EHIP;
+  // B == 0 still runs the (empty) reduction so gw, gn are overwritten with zeros
+  if (dmn::launch_linear_backward(K, prec, tb.rows, tb.flag, B, C1, C2, gCbar, gw, gn, gC1, gC2,
+                                  partials, gsum, err, stream))
+    return DMN_EHIP;
+  return DMN_OK;
+}
+
+size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int32_t n_groups,
+                                              int prec) {
+  if (!groups || n_groups < 1 || n_groups > 64 || prec != DMN_F64) return 0;
+  size_t total = kAlign;
+  for (int i = 0; i < n_groups; ++i) {
+    if (!depth_ok(groups[i].net.depth)) return 0;
+    total += table_bytes(groups[i].net.depth, prec);
+  }
+  return total;
+}
+
+int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
+                            const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
+                            const dmn_newton_opts* opts, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  if (!groups || n_groups < 1 || n_groups > 64) return DMN_EINVAL;
+  if (prec != DMN_F64) return DMN_EUNSUPPORTED;
+  if (!phase_ok(fiber) || !j2_ok(matrix) || !opts) return DMN_EINVAL;
+  if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->max_backtrack < 0 ||
+      !(opts->armijo >= 0.0 && opts->armijo < 1.0))
+    return DMN_EINVAL;
+  for (int i = 0; i < n_groups; ++i) {
+    const dmn_point_group& g = groups[i];
+    if (!depth_ok(g.net.depth) || g.P < 0 || !g.net.w || !g.net.n) return DMN_EINVAL;
+    if (g.P > 0 && (!g.E || !g.z_in || !g.z_out || !g.a_in || !g.a_out || !g.sigma ||
+                    !g.tangent || !g.iters || !g.status))
+      return DMN_EINVAL;
+    if (g.P > 0 && (g.z_in == g.z_out || g.a_in == g.a_out)) return DMN_EINVAL;
+    const int lp = dmn::gp_default_lanes_per_point(g.net.depth);
+    if ((g.P + 63) / 64 * lp > (int64_t)0x7fffffff) return DMN_EINVAL;
+  }
+  const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
+
+  // tables, one per group
+  std::vector<Table> tabs(n_groups);
+  size_t off = kAlign;
+  for (int i = 0; i < n_groups; ++i) {
+    tabs[i] = table_at(ws, off);
+    off += table_bytes(groups[i].net.depth, prec);
+    if (dmn::launch_prep_tables(groups[i].net.w, groups[i].net.n, groups[i].net.depth, prec,
+                                tabs[i].rows, tabs[i].flag, nullptr, stream))
+      return DMN_EHIP;
+  }
+
+  dmn::GpLaunch base;
+  memset(&base, 0, sizeof(base));
+  base.max_iter = opts->max_iter;
+  base.max_bt = opts->max_backtrack;
+  base.tol = opts->tol;
+  base.armijo = opts->armijo;
+  base.fib.K = fiber->E / (3.0 * (1.0 - 2.0 * fiber->nu));
+  base.fib.G = fiber->E / (2.0 * (1.0 + fiber->nu));
+  base.mat.K = matrix->E / (3.0 * (1.0 - 2.0 * matrix->nu));
+  base.mat.G = matrix->E / (2.0 * (1.0 + matrix->nu));
+  base.mat.sigma0 = matrix->sigma0;
+  base.mat.k_inf = matrix->k_inf;
+  base.mat.dsigma = matrix->dsigma;
+  base.mat.b = matrix->b;
+
+  // one launch per depth (deepest first), up to kMaxGroupsPerLaunch groups each
+  std::vector<int> order;
+  for (int i = 0; i < n_groups; ++i)
+    if (groups[i].P > 0) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return groups[a].net.depth > groups[b].net.depth;
+  });
+  size_t pos = 0;
+  while (pos < order.size()) {
+    const int K = groups[order[pos]].net.depth;
+    const int lp = dmn::gp_default_lanes_per_point(K);
+    const int ppb = dmn::gp_points_per_block(K, lp);
+    dmn::GpLaunch args = base;
+    args.ng = 0;
+    long long blocks = 0;
+    while (pos < order.size() && groups[order[pos]].net.depth == K &&
+           args.ng < dmn::kMaxGroupsPerLaunch) {
+      const int i = order[pos];
+      const dmn_point_group& g = groups[i];
+      dmn::GroupArgs& a = args.g[args.ng++];
+      a.E = (const double*)g.E;
+      a.z_in = (const double*)g.z_in;
+      a.z_out = (double*)g.z_out;
+      a.a_in = (const double*)g.a_in;
+      a.a_out = (double*)g.a_out;
+      a.sigma = (double*)g.sigma;
+      a.tangent = (double*)g.tangent;
+      a.iters = g.iters;
+      a.status = g.status;
+      a.tab = (const double*)tabs[i].rows;
+      a.flag = tabs[i].flag;
+      a.P = g.P;
+      a.block0 = (int)blocks;
+      blocks += (g.P + ppb - 1) / ppb;
+      ++pos;
+    }
+    if (blocks > 0x7fffffff) return DMN_EINVAL;
+    if (dmn::launch_gp_update(K, lp, args, (int)blocks, stream)) return DMN_EHIP;
+  }
+  return DMN_OK;
+}
+
+}  // extern "C"

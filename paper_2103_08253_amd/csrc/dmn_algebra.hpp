@@ -1,0 +1,501 @@
+// Device algebra of the DMN laminate tree on gfx950.
+//
+// Conventions
+//   * Mandel 6-vectors [11, 22, 33, sqrt2*23, sqrt2*13, sqrt2*12]; the Mandel
+//     dot product is the Frobenius product, so all norms are Frobenius norms.
+//   * Symmetric 6x6 matrices are packed as their 21 upper-triangle entries,
+//     row by row (index given by sidx).
+//   * N(n) is the symmetrisation operator a -> sym(a (x) n) of the laminate
+//     normal n (Sec. 3.2), a 6x3 matrix with nine non-zeros; it is never
+//     stored, every product with it is written out.
+//
+// The laminate step below is the block-Cholesky elimination of the Newton
+// Hessian A^T W D A (Sec. 3.2, Newton system) restricted to one laminate:
+// given the affine responses  sigma_X(e) = tau_X + C_X e  of the two child
+// subtrees (X = L, R), the interface condition of the laminate
+//   N^T (sigma_R(e + c1 N da) - sigma_L(e - c2 N da)) = 0
+// is solved for the jump increment da, giving the laminate's own affine
+// response.  With S = c2 C_L + c1 C_R, K = N^T S N, U = (C_R - C_L) N:
+//   C   = c1 C_L + c2 C_R - c1 c2 U K^-1 U^T        (condensed tangent)
+//   tau = c1 tau_L + c2 tau_R - c1 c2 U K^-1 N^T (tau_R - tau_L)
+//   da  = -(g + G e),  g = K^-1 N^T (tau_R - tau_L),  G = K^-1 U^T
+// Applied to stiffnesses alone (no tau) this is the linear laminate of
+// Sec. 3.1 in Schur-complement form; it equals Milton's projector formula.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dmn {
+
+constexpr double kRsqrt2 = 0.70710678118654752440;
+
+// packed index of (i, j) in a symmetric 6x6 matrix
+__host__ __device__ constexpr int sidx(int i, int j) {
+  return i <= j ? i * 6 - (i * (i - 1)) / 2 + (j - i) : j * 6 - (j * (j - 1)) / 2 + (i - j);
+}
+
+template <typename T>
+struct Normal {
+  T n0, n1, n2;
+  // N x for x in R^3
+  __device__ __forceinline__ void apply(const T x[3], T y[6]) const {
+    const T r = T(kRsqrt2);
+    y[0] = n0 * x[0];
+    y[1] = n1 * x[1];
+    y[2] = n2 * x[2];
+    y[3] = r * (n2 * x[1] + n1 * x[2]);
+    y[4] = r * (n2 * x[0] + n0 * x[2]);
+    y[5] = r * (n1 * x[0] + n0 * x[1]);
+  }
+  // N^T v for v in R^6
+  __device__ __forceinline__ void applyT(const T v[6], T y[3]) const {
+    const T r = T(kRsqrt2);
+    y[0] = n0 * v[0] + r * (n2 * v[4] + n1 * v[5]);
+    y[1] = n1 * v[1] + r * (n2 * v[3] + n0 * v[5]);
+    y[2] = n2 * v[2] + r * (n1 * v[3] + n0 * v[4]);
+  }
+};
+
+// 3x3 SPD inverse by Cholesky. Returns false if a pivot is not positive
+// (or not finite); M is then left unspecified.
+template <typename T>
+__device__ __forceinline__ bool spd3_inverse(T k00, T k01, T k02, T k11, T k12, T k22,
+                                             T& m00, T& m01, T& m02, T& m11, T& m12,
+                                             T& m22) {
+  bool ok = k00 > T(0);
+  T l00 = sqrt(ok ? k00 : T(1));
+  T i00 = T(1) / l00;
+  T l10 = k01 * i00, l20 = k02 * i00;
+  T d1 = k11 - l10 * l10;
+  ok = ok && d1 > T(0);
+  T l11 = sqrt(d1 > T(0) ? d1 : T(1));
+  T i11 = T(1) / l11;
+  T l21 = (k12 - l20 * l10) * i11;
+  T d2 = k22 - l20 * l20 - l21 * l21;
+  ok = ok && d2 > T(0);
+  T l22 = sqrt(d2 > T(0) ? d2 : T(1));
+  T i22 = T(1) / l22;
+  // L^-1 (lower triangular)
+  T j10 = -l10 * i00 * i11;
+  T j21 = -l21 * i11 * i22;
+  T j20 = -(l20 * i00 + l21 * j10) * i22;
+  // M = L^-T L^-1
+  m00 = i00 * i00 + j10 * j10 + j20 * j20;
+  m01 = j10 * i11 + j20 * j21;
+  m02 = j20 * i22;
+  m11 = i11 * i11 + j21 * j21;
+  m12 = j21 * i22;
+  m22 = i22 * i22;
+  return ok;
+}
+
+// Rows of S N for symmetric packed S: (S N)[r][:] = N^T S[r][:]
+template <typename T>
+__device__ __forceinline__ void sym_times_N(const T S[21], const Normal<T>& nv, T SN[6][3]) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    T row[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) row[c] = S[sidx(r, c)];
+    nv.applyT(row, SN[r]);
+  }
+}
+
+// Linear laminate (Sec. 3.1) in Schur form: C = c1 CL + c2 CR - c1 c2 U K^-1 U^T.
+// Optionally returns the intermediates the backward pass needs.
+template <typename T>
+__device__ __forceinline__ bool laminate_linear(const T CL[21], const T CR[21], const Normal<T>& nv,
+                                                T c1, T c2, T C[21]) {
+  T S[21], dC[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) {
+    S[k] = c2 * CL[k] + c1 * CR[k];
+    dC[k] = CR[k] - CL[k];
+  }
+  T SN[6][3], U[6][3];
+  sym_times_N(S, nv, SN);
+  sym_times_N(dC, nv, U);
+  T col[6], kc[3];
+  T Km[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) col[r] = SN[r][c];
+    nv.applyT(col, kc);
+    Km[0][c] = kc[0];
+    Km[1][c] = kc[1];
+    Km[2][c] = kc[2];
+  }
+  T m00, m01, m02, m11, m12, m22;
+  bool ok = spd3_inverse(Km[0][0], Km[0][1], Km[0][2], Km[1][1], Km[1][2], Km[2][2], m00, m01,
+                         m02, m11, m12, m22);
+  T V[6][3];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    V[r][0] = U[r][0] * m00 + U[r][1] * m01 + U[r][2] * m02;
+    V[r][1] = U[r][0] * m01 + U[r][1] * m11 + U[r][2] * m12;
+    V[r][2] = U[r][0] * m02 + U[r][1] * m12 + U[r][2] * m22;
+  }
+  const T cc = c1 * c2;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      T vu = V[i][0] * U[j][0] + V[i][1] * U[j][1] + V[i][2] * U[j][2];
+      C[sidx(i, j)] = c1 * CL[sidx(i, j)] + c2 * CR[sidx(i, j)] - cc * vu;
+    }
+  return ok;
+}
+
+// Vector-Jacobian product of laminate_linear.  Gm is the cotangent of the
+// output C as a full symmetric matrix stored packed (so <Gm, dC> sums all 36
+// entries).  Returns the cotangents of CL and CR (same convention), of c1
+// (with c2 = 1 - c1), and of the normal components.
+//   T = U K^-1 U^T,  Gt = -c1 c2 Gm,  V = U K^-1
+//   G_U = 2 Gt V,  G_K = -V^T Gt V,  G_S = N G_K N^T,  G_dC = sym(G_U N^T)
+//   G_CL = c1 Gm + c2 G_S - G_dC,  G_CR = c2 Gm + c1 G_S + G_dC
+//   G_c1 = <Gm, CL - CR> - (1 - 2 c1) <Gm, T> + <G_S, CR - CL>
+//   G_N  = 2 S N G_K + dC G_U,  G_n_d = <G_N, dN/dn_d>
+template <typename T>
+__device__ __forceinline__ void laminate_linear_vjp(const T CL[21], const T CR[21],
+                                                    const Normal<T>& nv, T c1, T c2,
+                                                    const T Gm[21], T GL[21], T GR[21], T& gc1,
+                                                    T gn[3]) {
+  T S[21], dC[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) {
+    S[k] = c2 * CL[k] + c1 * CR[k];
+    dC[k] = CR[k] - CL[k];
+  }
+  T SN[6][3], U[6][3];
+  sym_times_N(S, nv, SN);
+  sym_times_N(dC, nv, U);
+  T col[6], kc[3];
+  T Km[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) col[r] = SN[r][c];
+    nv.applyT(col, kc);
+    Km[0][c] = kc[0];
+    Km[1][c] = kc[1];
+    Km[2][c] = kc[2];
+  }
+  T m00, m01, m02, m11, m12, m22;
+  spd3_inverse(Km[0][0], Km[0][1], Km[0][2], Km[1][1], Km[1][2], Km[2][2], m00, m01, m02, m11,
+               m12, m22);
+  T V[6][3];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    V[r][0] = U[r][0] * m00 + U[r][1] * m01 + U[r][2] * m02;
+    V[r][1] = U[r][0] * m01 + U[r][1] * m11 + U[r][2] * m12;
+    V[r][2] = U[r][0] * m02 + U[r][1] * m12 + U[r][2] * m22;
+  }
+  const T cc = c1 * c2;
+  // X = Gt V = -cc Gm V ; G_U = 2 X
+  T X[6][3];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) acc += Gm[sidx(i, j)] * V[j][a];
+      X[i][a] = -cc * acc;
+    }
+  // G_K = -V^T X (symmetric 3x3)
+  T GK[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      T acc = T(0);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) acc += V[i][a] * X[i][b];
+      GK[a][b] = -acc;
+      GK[b][a] = -acc;
+    }
+  // N G_K (6x3), then G_S = (N G_K) N^T, row i = N (N G_K)[i][:]
+  T NGK[6][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T x[3] = {GK[0][c], GK[1][c], GK[2][c]}, y[6];
+    nv.apply(x, y);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) NGK[r][c] = y[r];
+  }
+  T GS[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T y[6];
+    nv.apply(NGK[i], y);
+#pragma unroll
+    for (int j = i; j < 6; ++j) GS[sidx(i, j)] = y[j];
+  }
+  // Y = G_U N^T, row i = N G_U[i][:] ; G_dC = sym(Y)
+  T Y[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T gu[3] = {T(2) * X[i][0], T(2) * X[i][1], T(2) * X[i][2]};
+    nv.apply(gu, Y[i]);
+  }
+  T Tm[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j)
+      Tm[sidx(i, j)] = V[i][0] * U[j][0] + V[i][1] * U[j][1] + V[i][2] * U[j][2];
+  T a1 = T(0), a2 = T(0);
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      const int k = sidx(i, j);
+      const T wgt = i == j ? T(1) : T(2);
+      const T gdc = T(0.5) * (Y[i][j] + Y[j][i]);
+      GL[k] = c1 * Gm[k] + c2 * GS[k] - gdc;
+      GR[k] = c2 * Gm[k] + c1 * GS[k] + gdc;
+      a1 += wgt * (Gm[k] - GS[k]) * dC[k];
+      a2 += wgt * Gm[k] * Tm[k];
+    }
+  gc1 = -a1 - (T(1) - T(2) * c1) * a2;
+  // G_N = 2 SN G_K + dC G_U
+  T GN[6][3];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T acc = T(0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc += T(2) * SN[i][b] * GK[b][a];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) acc += dC[sidx(i, j)] * T(2) * X[j][a];
+      GN[i][a] = acc;
+    }
+  const T r = T(kRsqrt2);
+  gn[0] = GN[0][0] + r * (GN[4][2] + GN[5][1]);
+  gn[1] = GN[1][1] + r * (GN[3][2] + GN[5][0]);
+  gn[2] = GN[2][2] + r * (GN[3][1] + GN[4][0]);
+}
+
+// Newton laminate step: condensed tangent C, affine offset tau, plain stress
+// average sb, top-down factors G (3x6, row-major) and g (3), and the squared
+// norm of the laminate's residual  rfac N^T (sb_R - sb_L), where
+// rfac = W_L W_R / (W sum(w)) makes it the laminate's block of A^T W sigma.
+template <typename T>
+__device__ __forceinline__ bool laminate_newton(const T CL[21], const T tL[6], const T sL[6],
+                                                const T CR[21], const T tR[6], const T sR[6],
+                                                const Normal<T>& nv, T c1, T c2, T rfac,
+                                                T C[21], T tau[6], T sb[6], T G[18], T g[3],
+                                                T& rr) {
+  T S[21], dC[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) {
+    S[k] = c2 * CL[k] + c1 * CR[k];
+    dC[k] = CR[k] - CL[k];
+  }
+  T SN[6][3], U[6][3];
+  sym_times_N(S, nv, SN);
+  sym_times_N(dC, nv, U);
+  T col[6], kc[3];
+  T Km[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) col[r] = SN[r][c];
+    nv.applyT(col, kc);
+    Km[0][c] = kc[0];
+    Km[1][c] = kc[1];
+    Km[2][c] = kc[2];
+  }
+  T m00, m01, m02, m11, m12, m22;
+  bool ok = spd3_inverse(Km[0][0], Km[0][1], Km[0][2], Km[1][1], Km[1][2], Km[2][2], m00, m01,
+                         m02, m11, m12, m22);
+  T V[6][3];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    V[r][0] = U[r][0] * m00 + U[r][1] * m01 + U[r][2] * m02;
+    V[r][1] = U[r][0] * m01 + U[r][1] * m11 + U[r][2] * m12;
+    V[r][2] = U[r][0] * m02 + U[r][1] * m12 + U[r][2] * m22;
+  }
+  const T cc = c1 * c2;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      T vu = V[i][0] * U[j][0] + V[i][1] * U[j][1] + V[i][2] * U[j][2];
+      C[sidx(i, j)] = c1 * CL[sidx(i, j)] + c2 * CR[sidx(i, j)] - cc * vu;
+    }
+  // G = K^-1 U^T = V^T
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int s = 0; s < 6; ++s) G[a * 6 + s] = V[s][a];
+  // g = K^-1 N^T (tau_R - tau_L);  tau = c1 tau_L + c2 tau_R - c1 c2 U g
+  T dt[6], q[3];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) dt[s] = tR[s] - tL[s];
+  nv.applyT(dt, q);
+  g[0] = m00 * q[0] + m01 * q[1] + m02 * q[2];
+  g[1] = m01 * q[0] + m11 * q[1] + m12 * q[2];
+  g[2] = m02 * q[0] + m12 * q[1] + m22 * q[2];
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+    tau[s] = c1 * tL[s] + c2 * tR[s] - cc * (U[s][0] * g[0] + U[s][1] * g[1] + U[s][2] * g[2]);
+  // plain average and residual block
+  T ds[6], r[3];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    sb[s] = c1 * sL[s] + c2 * sR[s];
+    ds[s] = sR[s] - sL[s];
+  }
+  nv.applyT(ds, r);
+  rr += rfac * rfac * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  return ok;
+}
+
+// Top-down step: da = -(g + G e); children receive e -/+ c N da.
+template <typename T>
+__device__ __forceinline__ void laminate_descend(const T G[18], const T g[3], const T e[6],
+                                                 const Normal<T>& nv, T c1, T c2, T da[3],
+                                                 T eL[6], T eR[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T acc = g[a];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) acc += G[a * 6 + s] * e[s];
+    da[a] = -acc;
+  }
+  T Nd[6];
+  nv.apply(da, Nd);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    eL[s] = e[s] - c2 * Nd[s];
+    eR[s] = e[s] + c1 * Nd[s];
+  }
+}
+
+// Strain localisation through one laminate with jump a: children strains e -/+ c N a.
+template <typename T>
+__device__ __forceinline__ void laminate_localize(const T a[3], const T e[6], const Normal<T>& nv,
+                                                  T c1, T c2, T eL[6], T eR[6]) {
+  T Na[6];
+  nv.apply(a, Na);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    eL[s] = e[s] - c2 * Na[s];
+    eR[s] = e[s] + c1 * Na[s];
+  }
+}
+
+// ---------------------------------------------------------------- leaf laws
+
+struct IsoElastic {
+  double K, G;  // compression and shear modulus
+};
+
+// isotropic elastic leaf: sigma = K tr(e) I + 2G dev(e)
+__device__ __forceinline__ void iso_stress(const IsoElastic& m, const double e[6], double s[6]) {
+  const double tr = e[0] + e[1] + e[2];
+  const double lam = m.K - 2.0 * m.G / 3.0;
+  s[0] = lam * tr + 2.0 * m.G * e[0];
+  s[1] = lam * tr + 2.0 * m.G * e[1];
+  s[2] = lam * tr + 2.0 * m.G * e[2];
+  s[3] = 2.0 * m.G * e[3];
+  s[4] = 2.0 * m.G * e[4];
+  s[5] = 2.0 * m.G * e[5];
+}
+
+__device__ __forceinline__ void iso_packed(const IsoElastic& m, double C[21]) {
+  const double lam = m.K - 2.0 * m.G / 3.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      double v = (i < 3 && j < 3) ? lam : 0.0;
+      if (i == j) v += 2.0 * m.G;
+      C[sidx(i, j)] = v;
+    }
+}
+
+struct J2Law {
+  double K, G, sigma0, k_inf, dsigma, b;
+};
+
+constexpr double kSqrt23 = 0.81649658092772603273;  // sqrt(2/3)
+constexpr double kLocalTol = 1e-14;
+constexpr int kLocalMaxIt = 50;
+
+// J2 radial return (implicit Euler) with sigma_Y(p) = s0 + k p + ds (1 - exp(-b p)).
+// Outputs stress, packed consistent tangent and the new internal variables.
+// Returns false when the scalar Newton iteration does not converge.
+__device__ __forceinline__ bool j2_return(const J2Law& m, const double eps[6], const double epn[6],
+                                          double pn, double sig[6], double Dp[21], double ep[6],
+                                          double& p) {
+  double e[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) e[s] = eps[s] - epn[s];
+  const double tr = e[0] + e[1] + e[2];
+  const double tr3 = tr * (1.0 / 3.0);
+  double str[6];
+  str[0] = 2.0 * m.G * (e[0] - tr3);
+  str[1] = 2.0 * m.G * (e[1] - tr3);
+  str[2] = 2.0 * m.G * (e[2] - tr3);
+  str[3] = 2.0 * m.G * e[3];
+  str[4] = 2.0 * m.G * e[4];
+  str[5] = 2.0 * m.G * e[5];
+  double q2 = 0.0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) q2 += str[s] * str[s];
+  const double q = sqrt(q2);
+  const double syn = m.sigma0 + m.k_inf * pn + m.dsigma * (1.0 - exp(-m.b * pn));
+  const double f = q - kSqrt23 * syn;
+  double x = 0.0, theta = 1.0, theta_bar = 0.0;
+  bool ok = true;
+  if (f > 0.0) {
+    const double xtol = kLocalTol * q / (2.0 * m.G);
+    ok = false;
+    for (int it = 0; it < kLocalMaxIt; ++it) {
+      const double pp = pn + kSqrt23 * x;
+      const double ex = exp(-m.b * pp);
+      const double sy = m.sigma0 + m.k_inf * pp + m.dsigma * (1.0 - ex);
+      const double dsy = m.k_inf + m.dsigma * m.b * ex;
+      const double gv = q - 2.0 * m.G * x - kSqrt23 * sy;
+      const double dg = -2.0 * m.G - (2.0 / 3.0) * dsy;
+      const double dx = -gv / dg;
+      x += dx;
+      if (fabs(dx) <= xtol) {
+        ok = true;
+        break;
+      }
+    }
+    const double pp = pn + kSqrt23 * x;
+    const double dsy = m.k_inf + m.dsigma * m.b * exp(-m.b * pp);
+    theta = 1.0 - 2.0 * m.G * x / q;
+    theta_bar = 1.0 / (1.0 + dsy / (3.0 * m.G)) - (1.0 - theta);
+  }
+  const double iq = f > 0.0 ? 1.0 / q : 0.0;
+  double nh[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) nh[s] = str[s] * iq;
+  const double Ktr = m.K * tr;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) sig[s] = (s < 3 ? Ktr : 0.0) + theta * str[s];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) ep[s] = epn[s] + x * nh[s];
+  p = pn + kSqrt23 * x;
+  // D = 3K P1 + 2G theta P2 - 2G theta_bar nh (x) nh
+  const double g2 = 2.0 * m.G * theta;
+  const double lam = m.K - g2 / 3.0;
+  const double gb = 2.0 * m.G * theta_bar;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      double v = (i < 3 && j < 3) ? lam : 0.0;
+      if (i == j) v += g2;
+      Dp[sidx(i, j)] = v - gb * nh[i] * nh[j];
+    }
+  return ok;
+}
+
+}  // namespace dmn

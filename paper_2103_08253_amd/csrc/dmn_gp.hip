@@ -1,0 +1,598 @@
+// Batched online evaluation of direct DMNs at Gauss points (FE-DMN paper,
+// Sec. 3.2 online evaluation, Sec. 4.6 convergence test) on gfx950.
+//
+// Work mapping.  One 64-lane wavefront owns 64 / LP Gauss points; the LP
+// lanes of a point split its laminate tree: lane t owns the depth-D subtree
+// whose root is laminate (K-D+1, t+1) together with its 2^D leaves, and keeps
+// that subtree's leaf strains, jumps and top-down factors in registers.  The
+// K-D levels above the lane subtrees are combined with wavefront shuffles
+// (lane t receives its right sibling's condensed response from lane
+// t + 2^(m-1)); their top-down factors and jumps live in LDS, written and read
+// only by the lane that computes the laminate.
+//
+// One Newton iteration (Sec. 3.2, Newton system) is
+//   leaves:     fibre sigma = C_f eps; matrix J2 radial return -> sigma, D;
+//   bottom-up:  block-Cholesky condensation of A^T W D A in postorder
+//               (no fill-in): condensed C, tau, plain average, residual;
+//   root:       C is the algorithmic tangent, the plain average the
+//               effective stress, the summed squared blocks |A^T W sigma|^2;
+//   top-down:   jump increments da and leaf strain increments A da;
+// with backtracking on the residual norm.  The per-point control (stop test,
+// iteration cap, backtracking, status codes) is uniform across the lanes of
+// a point.
+#include "dmn_internal.hpp"
+
+namespace dmn {
+namespace {
+
+template <int K, int D>
+struct Cfg {
+  static_assert(D >= 1 && D <= K, "subtree depth");
+  static constexpr int LP = 1 << (K - D);  // lanes per point
+  static_assert(LP <= 64, "at most one point per wave is split over lanes");
+  static constexpr int PPW = 64 / LP;      // points per wave
+  static constexpr int NLEAF = 1 << D;     // leaves per lane
+  static constexpr int NLAM = NLEAF - 1;   // laminates per lane
+  static constexpr int NUP = LP - 1;       // laminates above the lane subtrees
+  static constexpr int NUPS = NUP > 0 ? NUP : 1;
+  static constexpr int L = (1 << K) - 1;
+  static constexpr int M = 1 << (K - 1);   // matrix leaves per point
+  static constexpr int UP0 = (1 << K) - LP;  // paper position of the first upper laminate
+  static constexpr int UPLEV = K - D;
+  static constexpr int SLOTS = PPW * NUPS;
+};
+
+__host__ __device__ constexpr int ilog2(int h) { return h <= 1 ? 0 : 1 + ilog2(h / 2); }
+
+// paper position of the lane subtree's heap node H (1-based heap) of lane t
+template <int K, int D, int H>
+__device__ __forceinline__ int lane_pos(int t) {
+  constexpr int m = ilog2(H);
+  constexpr int k = K - D + 1 + m;
+  return (1 << K) - (1 << k) + t * (1 << m) + (H - (1 << m));
+}
+
+// paper position of the upper laminate computed by lane t at upper step m
+template <int K, int D>
+__device__ __forceinline__ int upper_pos(int m, int t) {
+  const int k = K - D + 1 - m;
+  return (1 << K) - (1 << k) + (t >> m);
+}
+
+struct LamRow {
+  Normal<double> nv;
+  double c1, c2, rf;
+};
+
+__device__ __forceinline__ LamRow load_row(const double* __restrict__ tab, int pos) {
+  const double* r = tab + (size_t)pos * kTabStride;
+  LamRow o;
+  o.c1 = r[0];
+  o.c2 = r[1];
+  o.nv.n0 = r[2];
+  o.nv.n1 = r[3];
+  o.nv.n2 = r[4];
+  o.rf = r[5];
+  return o;
+}
+
+// LDS storage of the upper laminates of all points of a wave (SoA by field).
+template <int K, int D>
+struct UpperLds {
+  double G[18][Cfg<K, D>::SLOTS];
+  double g[3][Cfg<K, D>::SLOTS];
+  double a[3][Cfg<K, D>::SLOTS];
+  double da[3][Cfg<K, D>::SLOTS];
+};
+
+// Lane-resident state of one point's lane subtree.
+template <int K, int D>
+struct LaneState {
+  using C = Cfg<K, D>;
+  double eps[C::NLEAF][6];   // leaf strains at the accepted iterate
+  double deps[C::NLEAF][6];  // leaf strain increments A da of the Newton step
+  double a[C::NLAM][3];      // jumps
+  double da[C::NLAM][3];     // Newton jump increments
+  double G[C::NLAM][18];     // top-down factors of the last evaluation
+  double g[C::NLAM][3];
+};
+
+struct EvalOut {
+  double C[21];   // condensed tangent (meaningful on the point's lane 0)
+  double sb[6];   // plain stress average (lane 0)
+  double rr;      // squared residual norm (reduced over the point's lanes)
+  int lfail;      // J2 return failed somewhere in the point
+  int spdfail;    // a laminate pivot was not positive
+};
+
+template <int K, int D>
+struct Ctx {
+  using C = Cfg<K, D>;
+  const double* __restrict__ tab;
+  const double* __restrict__ zin;  // this point's z_in
+  IsoElastic fib;
+  J2Law mat;
+  int t;
+  int slot;
+};
+
+// ---------------------------------------------------------------- bottom-up
+
+template <int K, int D, int H>
+__device__ __forceinline__ void up_node(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                        const double (&ev)[Cfg<K, D>::NLEAF][6], double (&Cn)[21],
+                                        double (&tn)[6], double (&sn)[6], double& rr, int& lfail,
+                                        int& spdfail) {
+  using C = Cfg<K, D>;
+  if constexpr (H >= C::NLEAF) {
+    constexpr int q = H - C::NLEAF;
+    if constexpr (q % 2 == 0) {  // fibre leaf
+      iso_stress(cx.fib, ev[q], sn);
+      iso_packed(cx.fib, Cn);
+    } else {                     // matrix leaf
+      const int mloc = cx.t * (C::NLEAF / 2) + q / 2;
+      const double* z = cx.zin + (size_t)mloc * 7;
+      double epn[6], ep[6], p;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) epn[s] = z[s];
+      bool ok = j2_return(cx.mat, ev[q], epn, z[6], sn, Cn, ep, p);
+      lfail |= ok ? 0 : 1;
+    }
+#pragma unroll
+    for (int s = 0; s < 6; ++s) tn[s] = sn[s];
+  } else {
+    double CL[21], tL[6], sL[6], CR[21], tR[6], sR[6];
+    up_node<K, D, 2 * H>(cx, st, ev, CL, tL, sL, rr, lfail, spdfail);
+    up_node<K, D, 2 * H + 1>(cx, st, ev, CR, tR, sR, rr, lfail, spdfail);
+    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
+    bool ok = laminate_newton(CL, tL, sL, CR, tR, sR, row.nv, row.c1, row.c2, row.rf, Cn, tn, sn,
+                              st.G[H - 1], st.g[H - 1], rr);
+    spdfail |= ok ? 0 : 1;
+  }
+}
+
+__device__ __forceinline__ double shfl_down_d(double v, int o, int width) {
+  return __shfl_down(v, (unsigned)o, width);
+}
+__device__ __forceinline__ double shfl_up_d(double v, int o, int width) {
+  return __shfl_up(v, (unsigned)o, width);
+}
+
+// Full evaluation at leaf strains ev: leaf laws + bottom-up condensation.
+template <int K, int D>
+__device__ __forceinline__ void evaluate(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                         UpperLds<K, D>& up, const double (&ev)[Cfg<K, D>::NLEAF][6],
+                                         EvalOut& out) {
+  using C = Cfg<K, D>;
+  double rr = 0.0;
+  int lfail = 0, spdfail = 0;
+  double cC[21], cT[6], cS[6];
+  up_node<K, D, 1>(cx, st, ev, cC, cT, cS, rr, lfail, spdfail);
+#pragma unroll
+  for (int m = 1; m <= C::UPLEV; ++m) {
+    const int o = 1 << (m - 1);
+    double rC[21], rT[6], rS[6];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) rC[k] = shfl_down_d(cC[k], o, C::LP);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      rT[k] = shfl_down_d(cT[k], o, C::LP);
+      rS[k] = shfl_down_d(cS[k], o, C::LP);
+    }
+    if ((cx.t & (2 * o - 1)) == 0) {
+      const int pos = upper_pos<K, D>(m, cx.t);
+      const int u = cx.slot * C::NUPS + (pos - C::UP0);
+      const LamRow row = load_row(cx.tab, pos);
+      double nC[21], nT[6], nS[6], Gu[18], gu[3];
+      bool ok = laminate_newton(cC, cT, cS, rC, rT, rS, row.nv, row.c1, row.c2, row.rf, nC, nT,
+                                nS, Gu, gu, rr);
+      spdfail |= ok ? 0 : 1;
+#pragma unroll
+      for (int k = 0; k < 18; ++k) up.G[k][u] = Gu[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) up.g[k][u] = gu[k];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) cC[k] = nC[k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        cT[k] = nT[k];
+        cS[k] = nS[k];
+      }
+    }
+  }
+  // reductions over the LP lanes of each point
+#pragma unroll
+  for (int o = 1; o < C::LP; o <<= 1) {
+    rr += __shfl_xor(rr, o, C::LP);
+    lfail |= __shfl_xor(lfail, o, C::LP);
+    spdfail |= __shfl_xor(spdfail, o, C::LP);
+  }
+#pragma unroll
+  for (int k = 0; k < 21; ++k) out.C[k] = cC[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out.sb[k] = cS[k];
+  out.rr = rr;
+  out.lfail = lfail;
+  out.spdfail = spdfail;
+}
+
+// ---------------------------------------------------------------- top-down
+
+template <int K, int D, int H>
+__device__ __forceinline__ void down_node(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                          const double (&e)[6]) {
+  using C = Cfg<K, D>;
+  if constexpr (H >= C::NLEAF) {
+#pragma unroll
+    for (int s = 0; s < 6; ++s) st.deps[H - C::NLEAF][s] = e[s];
+  } else {
+    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
+    double eL[6], eR[6];
+    laminate_descend(st.G[H - 1], st.g[H - 1], e, row.nv, row.c1, row.c2, st.da[H - 1], eL, eR);
+    down_node<K, D, 2 * H>(cx, st, eL);
+    down_node<K, D, 2 * H + 1>(cx, st, eR);
+  }
+}
+
+// Newton direction: da for all laminates, leaf strain increments A da.
+template <int K, int D>
+__device__ __forceinline__ void direction(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                          UpperLds<K, D>& up) {
+  using C = Cfg<K, D>;
+  double e[6] = {0, 0, 0, 0, 0, 0};  // the macro strain is fixed during Newton
+#pragma unroll
+  for (int m = C::UPLEV; m >= 1; --m) {
+    const int o = 1 << (m - 1);
+    double eR[6] = {0, 0, 0, 0, 0, 0};
+    if ((cx.t & (2 * o - 1)) == 0) {
+      const int pos = upper_pos<K, D>(m, cx.t);
+      const int u = cx.slot * C::NUPS + (pos - C::UP0);
+      const LamRow row = load_row(cx.tab, pos);
+      double Gu[18], gu[3], dau[3], eL[6];
+#pragma unroll
+      for (int k = 0; k < 18; ++k) Gu[k] = up.G[k][u];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gu[k] = up.g[k][u];
+      laminate_descend(Gu, gu, e, row.nv, row.c1, row.c2, dau, eL, eR);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) up.da[k][u] = dau[k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] = eL[k];
+    }
+    double rcv[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
+    if ((cx.t & (2 * o - 1)) == o) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] = rcv[k];
+    }
+  }
+  down_node<K, D, 1>(cx, st, e);
+}
+
+// ------------------------------------------------------- strain localisation
+
+template <int K, int D, int H>
+__device__ __forceinline__ void loc_node(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                         const double* __restrict__ ain, const double (&e)[6]) {
+  using C = Cfg<K, D>;
+  if constexpr (H >= C::NLEAF) {
+#pragma unroll
+    for (int s = 0; s < 6; ++s) st.eps[H - C::NLEAF][s] = e[s];
+  } else {
+    const int pos = lane_pos<K, D, H>(cx.t);
+    const LamRow row = load_row(cx.tab, pos);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) st.a[H - 1][k] = ain[(size_t)pos * 3 + k];
+    double eL[6], eR[6];
+    laminate_localize(st.a[H - 1], e, row.nv, row.c1, row.c2, eL, eR);
+    loc_node<K, D, 2 * H>(cx, st, ain, eL);
+    loc_node<K, D, 2 * H + 1>(cx, st, ain, eR);
+  }
+}
+
+// Leaf strains eps = E + A a from the stored jumps; loads the jumps.
+template <int K, int D>
+__device__ __forceinline__ void localize(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                         UpperLds<K, D>& up, const double* __restrict__ ain,
+                                         const double (&E)[6]) {
+  using C = Cfg<K, D>;
+  double e[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) e[k] = E[k];
+#pragma unroll
+  for (int m = C::UPLEV; m >= 1; --m) {
+    const int o = 1 << (m - 1);
+    double eR[6] = {0, 0, 0, 0, 0, 0};
+    if ((cx.t & (2 * o - 1)) == 0) {
+      const int pos = upper_pos<K, D>(m, cx.t);
+      const int u = cx.slot * C::NUPS + (pos - C::UP0);
+      const LamRow row = load_row(cx.tab, pos);
+      double au[3], eL[6];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        au[k] = ain[(size_t)pos * 3 + k];
+        up.a[k][u] = au[k];
+      }
+      laminate_localize(au, e, row.nv, row.c1, row.c2, eL, eR);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] = eL[k];
+    }
+    double rcv[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
+    if ((cx.t & (2 * o - 1)) == o) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] = rcv[k];
+    }
+  }
+  loc_node<K, D, 1>(cx, st, ain, e);
+}
+
+// ---------------------------------------------------------------- outputs
+
+template <int K, int D, int H>
+__device__ __forceinline__ void write_lane_a(const LaneState<K, D>& st, int t, bool ok,
+                                             const double* __restrict__ ain,
+                                             double* __restrict__ aout) {
+  if constexpr (H <= Cfg<K, D>::NLAM) {
+    const int pos = lane_pos<K, D, H>(t);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      aout[(size_t)pos * 3 + k] = ok ? st.a[H - 1][k] : ain[(size_t)pos * 3 + k];
+    write_lane_a<K, D, H + 1>(st, t, ok, ain, aout);
+  }
+}
+
+// Write the point's outputs.  ok: converged (z recomputed at the accepted
+// strains); otherwise the input state is copied through and the tangent is NaN.
+template <int K, int D>
+__device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K, D>& st,
+                                         const UpperLds<K, D>& up, const GroupArgs& G,
+                                         long long pt, const EvalOut& ev, int status, int iters) {
+  using C = Cfg<K, D>;
+  const bool ok = status == 0;
+  const int t = cx.t;
+  // internal variables of this lane's matrix leaves
+  double* zout = G.z_out + (size_t)pt * C::M * 7;
+#pragma unroll
+  for (int q = 1; q < C::NLEAF; q += 2) {
+    const int mloc = t * (C::NLEAF / 2) + q / 2;
+    const double* z = cx.zin + (size_t)mloc * 7;
+    double* zo = zout + (size_t)mloc * 7;
+    if (ok) {
+      double epn[6], ep[6], p, sg[6], Dp[21];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) epn[s] = z[s];
+      j2_return(cx.mat, st.eps[q], epn, z[6], sg, Dp, ep, p);
+#pragma unroll
+      for (int s = 0; s < 6; ++s) zo[s] = ep[s];
+      zo[6] = p;
+    } else {
+#pragma unroll
+      for (int s = 0; s < 7; ++s) zo[s] = z[s];
+    }
+  }
+  // jumps of the lane subtree
+  const double* ain = G.a_in + (size_t)pt * C::L * 3;
+  double* aout = G.a_out + (size_t)pt * C::L * 3;
+  write_lane_a<K, D, 1>(st, t, ok, ain, aout);
+  // jumps of the upper laminates computed by this lane
+#pragma unroll
+  for (int m = 1; m <= C::UPLEV; ++m) {
+    const int o = 1 << (m - 1);
+    if ((t & (2 * o - 1)) == 0) {
+      const int pos = upper_pos<K, D>(m, t);
+      const int u = cx.slot * C::NUPS + (pos - C::UP0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) aout[(size_t)pos * 3 + k] = ok ? up.a[k][u] : ain[(size_t)pos * 3 + k];
+    }
+  }
+  if (t == 0) {
+    double* sg = G.sigma + (size_t)pt * 6;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) sg[s] = ev.sb[s];
+    double* tg = G.tangent + (size_t)pt * 36;
+    const double nan = __builtin_nan("");
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) tg[i * 6 + j] = ok ? ev.C[sidx(i, j)] : nan;
+    G.iters[pt] = iters;
+    G.status[pt] = status;
+  }
+}
+
+// ---------------------------------------------------------------- kernel
+
+template <int K, int D>
+__global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
+  using C = Cfg<K, D>;
+  __shared__ UpperLds<K, D> up;
+  const int blk = blockIdx.x;
+  int gi = 0;
+#pragma unroll 1
+  for (int q = 1; q < args.ng; ++q)
+    if (blk >= args.g[q].block0) gi = q;
+  const GroupArgs& G = args.g[gi];
+  const int lane = threadIdx.x;
+  Ctx<K, D> cx;
+  cx.slot = lane / C::LP;
+  cx.t = lane % C::LP;
+  cx.tab = G.tab;
+  cx.fib = args.fib;
+  cx.mat = args.mat;
+  const long long pt_raw = (long long)(blk - G.block0) * C::PPW + cx.slot;
+  const bool in_range = pt_raw < G.P;
+  const long long pt = in_range ? pt_raw : G.P - 1;  // tail lanes shadow the last point
+  cx.zin = G.z_in + (size_t)pt * C::M * 7;
+  const double* ain = G.a_in + (size_t)pt * C::L * 3;
+
+  LaneState<K, D> st;
+  EvalOut ev;
+  double E[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) E[s] = G.E[(size_t)pt * 6 + s];
+
+  int status = 0, iters = 0;
+  bool done = !in_range;
+  if (*G.flag != 0) {  // invalid DMN parameters: every point of the group fails
+#pragma unroll
+    for (int k = 0; k < 21; ++k) ev.C[k] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) ev.sb[s] = __builtin_nan("");
+    if (in_range) finalize(cx, st, up, G, pt, ev, DMN_STATUS_BADPARAM, 0);
+    return;
+  }
+
+  // non-finite inputs of the point
+  int bad = 0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) bad |= isfinite(E[s]) ? 0 : 1;
+  for (int q = 0; q < C::NLEAF / 2 * 7; ++q) bad |= isfinite(cx.zin[(size_t)cx.t * (C::NLEAF / 2) * 7 + q]) ? 0 : 1;
+  localize(cx, st, up, ain, E);
+#pragma unroll
+  for (int h = 0; h < C::NLAM; ++h)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) bad |= isfinite(st.a[h][k]) ? 0 : 1;
+#pragma unroll
+  for (int m = 1; m <= C::UPLEV; ++m) {
+    const int o = 1 << (m - 1);
+    if ((cx.t & (2 * o - 1)) == 0) {
+      const int u = cx.slot * C::NUPS + (upper_pos<K, D>(m, cx.t) - C::UP0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) bad |= isfinite(up.a[k][u]) ? 0 : 1;
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < C::LP; o <<= 1) bad |= __shfl_xor(bad, o, C::LP);
+
+  evaluate(cx, st, up, st.eps, ev);
+  if (bad && !done) {
+    finalize(cx, st, up, G, pt, ev, DMN_STATUS_NONFINITE, 0);
+    done = true;
+  }
+
+  const double scale = args.tol * (double)C::L;
+  const int base = cx.slot * C::LP;
+  double rn = 0.0;
+  while (true) {
+    if (!done) {
+      double sb0 = 0.0;
+      double sn2 = 0.0;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        sb0 = __shfl(ev.sb[s], base, 64);
+        sn2 += sb0 * sb0;
+      }
+      const double sn = sqrt(sn2);
+      rn = sqrt(ev.rr);
+      int fin = -1;
+      if (ev.lfail) fin = DMN_STATUS_LOCAL;
+      else if (!isfinite(rn) || !isfinite(sn)) fin = DMN_STATUS_NONFINITE;
+      else if (rn == 0.0 || rn <= scale * sn) fin = ev.spdfail ? DMN_STATUS_NOTSPD : 0;
+      else if (iters >= args.max_iter) fin = DMN_STATUS_MAXITER;
+      else if (ev.spdfail) fin = DMN_STATUS_NOTSPD;
+      if (fin >= 0) {
+        status = fin;
+        done = true;
+        finalize(cx, st, up, G, pt, ev, status, iters);
+      }
+    }
+    if (!__any(!done)) break;
+    direction(cx, st, up);
+    double s = 1.0;
+    bool pending = !done;
+    for (int bt = 0; bt <= args.max_bt; ++bt) {
+      const double sp = pending ? s : 0.0;
+      double et[C::NLEAF][6];
+#pragma unroll
+      for (int q = 0; q < C::NLEAF; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) et[q][k] = st.eps[q][k] + sp * st.deps[q][k];
+      evaluate(cx, st, up, et, ev);
+      if (pending) {
+        double sn2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const double v = __shfl(ev.sb[k], base, 64);
+          sn2 += v * v;
+        }
+        const double rt = sqrt(ev.rr);
+        const bool good = isfinite(rt) && isfinite(sn2) && !ev.lfail;
+        if ((good && rt <= (1.0 - args.armijo * s) * rn) || bt == args.max_bt) {
+#pragma unroll
+          for (int q = 0; q < C::NLEAF; ++q)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) st.eps[q][k] = et[q][k];
+#pragma unroll
+          for (int h = 0; h < C::NLAM; ++h)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) st.a[h][k] += s * st.da[h][k];
+#pragma unroll
+          for (int m = 1; m <= C::UPLEV; ++m) {
+            const int o = 1 << (m - 1);
+            if ((cx.t & (2 * o - 1)) == 0) {
+              const int u = cx.slot * C::NUPS + (upper_pos<K, D>(m, cx.t) - C::UP0);
+#pragma unroll
+              for (int k = 0; k < 3; ++k) up.a[k][u] += s * up.da[k][u];
+            }
+          }
+          ++iters;
+          pending = false;
+        } else {
+          s *= 0.5;
+        }
+      }
+      if (!__any(pending)) break;
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- dispatch
+
+int gp_default_lanes_per_point(int depth) {
+  int d = depth - 6;
+  if (d < 1) d = 1;
+  return 1 << (depth - d);
+}
+
+int gp_points_per_block(int depth, int lanes_per_point) {
+  (void)depth;
+  return 64 / lanes_per_point;
+}
+
+template <int K, int D>
+static int launch_kd(const GpLaunch& args, int n_blocks, hipStream_t stream) {
+  hipLaunchKernelGGL((gp_update_kernel<K, D>), dim3(n_blocks), dim3(64), 0, stream, args);
+  return (int)hipGetLastError();
+}
+
+int launch_gp_update(int depth, int lanes_per_point, const GpLaunch& args, int n_blocks,
+                     hipStream_t stream) {
+  const int D = depth - ilog2(lanes_per_point);
+  switch (depth * 16 + D) {
+#define DMN_GP_CASE(KK, DD) \
+  case KK * 16 + DD:        \
+    return launch_kd<KK, DD>(args, n_blocks, stream);
+    DMN_GP_CASE(1, 1)
+    DMN_GP_CASE(2, 1)
+    DMN_GP_CASE(3, 1)
+    DMN_GP_CASE(4, 1)
+    DMN_GP_CASE(5, 1)
+    DMN_GP_CASE(6, 1)
+    DMN_GP_CASE(7, 1)
+    DMN_GP_CASE(7, 2)
+    DMN_GP_CASE(8, 2)
+    DMN_GP_CASE(8, 3)
+    DMN_GP_CASE(9, 3)
+    DMN_GP_CASE(10, 4)
+#undef DMN_GP_CASE
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dmn

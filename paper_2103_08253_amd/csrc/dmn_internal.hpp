@@ -1,0 +1,67 @@
+// Internal declarations shared by the libdmn translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dmn.h"
+#include "dmn_algebra.hpp"
+
+namespace dmn {
+
+// Per-laminate table row, in paper order, built on the device from (w, n):
+//   c1, c2, n0, n1, n2, rfac, dc1/dW_L, dc1/dW_R
+// rfac = W_L W_R / (W sum(w)) scales the laminate's residual block; the last
+// two entries are the derivatives of c1 = W_L / (W_L + W_R).
+constexpr int kTabStride = 8;
+
+// Point-group description passed by value to the Gauss-point kernel.
+struct GroupArgs {
+  const double* E;
+  const double* z_in;
+  double* z_out;
+  const double* a_in;
+  double* a_out;
+  double* sigma;
+  double* tangent;
+  int32_t* iters;
+  int32_t* status;
+  const double* tab;   // [L][kTabStride]
+  const int32_t* flag; // nonzero: invalid DMN parameters
+  long long P;
+  int block0;          // first workgroup index of this group in the launch
+  int pad;
+};
+
+constexpr int kMaxGroupsPerLaunch = 12;
+
+struct GpLaunch {
+  GroupArgs g[kMaxGroupsPerLaunch];
+  int ng;
+  int max_iter;
+  int max_bt;
+  int pad;
+  double tol;
+  double armijo;
+  IsoElastic fib;
+  J2Law mat;
+};
+
+// Host launchers (return hipError_t as int).
+int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
+                       int32_t* err, hipStream_t stream);
+int launch_gp_update(int depth, int lanes_per_point, const GpLaunch& args, int n_blocks,
+                     hipStream_t stream);
+int gp_points_per_block(int depth, int lanes_per_point);
+int gp_default_lanes_per_point(int depth);
+
+int launch_linear_forward(int depth, int prec, const void* tab, const int32_t* flag, long long B,
+                          const void* C1, const void* C2, void* Cbar, int32_t* err,
+                          hipStream_t stream);
+int launch_linear_backward(int depth, int prec, const void* tab, const int32_t* flag,
+                           long long B, const void* C1, const void* C2, const void* gCbar,
+                           void* gw, void* gn, void* gC1, void* gC2, double* partials,
+                           double* gsum, int32_t* err, hipStream_t stream);
+// number of partial-sum slots (waves x samples per wave) the backward uses
+long long linear_backward_partials(int depth, long long B);
+
+}  // namespace dmn

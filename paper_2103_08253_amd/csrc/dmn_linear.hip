@@ -1,0 +1,500 @@
+// Linear DMN homogenisation DMN^L (FE-DMN paper, Sec. 3.1: stiffness
+// propagation from level K to the root, one rank-one laminate per node) and
+// its vector-Jacobian product with respect to the leaf weights and the
+// lamination normals (the gradients offline training needs).
+//
+// Work mapping as in the Gauss-point kernel: LP lanes per sample, lane t owns
+// the depth-D subtree rooted at laminate (K-D+1, t+1); the K-D upper levels
+// are combined with shuffles.  Leaves alternate between C1 (even) and C2
+// (odd).  The backward pass recomputes the forward, keeping the lane
+// subtree's node stiffnesses in registers and the lane roots and upper nodes
+// in LDS, then runs the laminate VJPs from the root down.  Parameter
+// cotangents are accumulated per lane over the samples a wave processes and
+// reduced over waves in a fixed order (bit-reproducible).
+#include "dmn_internal.hpp"
+
+namespace dmn {
+namespace {
+
+template <int K, int D>
+struct LCfg {
+  static constexpr int LP = 1 << (K - D);
+  static constexpr int PPW = 64 / LP;
+  static constexpr int NLEAF = 1 << D;
+  static constexpr int NLAM = NLEAF - 1;
+  static constexpr int NUP = LP - 1;
+  static constexpr int L = (1 << K) - 1;
+  static constexpr int UP0 = (1 << K) - LP;
+  static constexpr int UPLEV = K - D;
+  static constexpr int NODES = 2 * LP - 1;  // lane roots + upper laminates per sample
+};
+
+__host__ __device__ constexpr int ilog2l(int h) { return h <= 1 ? 0 : 1 + ilog2l(h / 2); }
+
+template <int K, int D, int H>
+__device__ __forceinline__ int lpos(int t) {
+  constexpr int m = ilog2l(H);
+  constexpr int k = K - D + 1 + m;
+  return (1 << K) - (1 << k) + t * (1 << m) + (H - (1 << m));
+}
+
+template <int K, int D>
+__device__ __forceinline__ int upos(int m, int t) {
+  const int k = K - D + 1 - m;
+  return (1 << K) - (1 << k) + (t >> m);
+}
+
+template <typename T>
+struct LRow {
+  Normal<T> nv;
+  T c1, c2;
+};
+
+template <typename T>
+__device__ __forceinline__ LRow<T> lrow(const T* __restrict__ tab, int pos) {
+  const T* r = tab + (size_t)pos * kTabStride;
+  LRow<T> o;
+  o.c1 = r[0];
+  o.c2 = r[1];
+  o.nv.n0 = r[2];
+  o.nv.n1 = r[3];
+  o.nv.n2 = r[4];
+  return o;
+}
+
+// symmetric part of a row-major 6x6, packed
+template <typename T>
+__device__ __forceinline__ void load_sym(const T* __restrict__ A, T P[21]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j)
+      P[sidx(i, j)] = i == j ? A[i * 6 + i] : T(0.5) * (A[i * 6 + j] + A[j * 6 + i]);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_full(T* __restrict__ A, const T P[21]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) A[i * 6 + j] = P[sidx(i, j)];
+}
+
+// bottom-up over the lane subtree; stores the laminate outputs when Store
+template <typename T, int K, int D, int H, bool Store>
+__device__ __forceinline__ void lin_up(const T* __restrict__ tab, int t, const T (&C1)[21],
+                                       const T (&C2)[21], T (&Cn)[21], int& fail,
+                                       T (&nodes)[LCfg<K, D>::NLAM][21]) {
+  using C = LCfg<K, D>;
+  if constexpr (H >= C::NLEAF) {
+    constexpr int q = H - C::NLEAF;
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Cn[k] = (q % 2 == 0) ? C1[k] : C2[k];
+  } else {
+    T CL[21], CR[21];
+    lin_up<T, K, D, 2 * H, Store>(tab, t, C1, C2, CL, fail, nodes);
+    lin_up<T, K, D, 2 * H + 1, Store>(tab, t, C1, C2, CR, fail, nodes);
+    const LRow<T> row = lrow(tab, lpos<K, D, H>(t));
+    fail |= laminate_linear(CL, CR, row.nv, row.c1, row.c2, Cn) ? 0 : 1;
+    if constexpr (Store) {
+#pragma unroll
+      for (int k = 0; k < 21; ++k) nodes[H - 1][k] = Cn[k];
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_dn(T v, int o, int w) {
+  return __shfl_down(v, (unsigned)o, w);
+}
+template <typename T>
+__device__ __forceinline__ T shfl_upv(T v, int o, int w) {
+  return __shfl_up(v, (unsigned)o, w);
+}
+
+template <typename T, int K, int D>
+__global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ tab,
+                                                        const int32_t* __restrict__ flag,
+                                                        long long B, const T* __restrict__ C1,
+                                                        const T* __restrict__ C2,
+                                                        T* __restrict__ Cbar,
+                                                        int32_t* __restrict__ err) {
+  using C = LCfg<K, D>;
+  const int lane = threadIdx.x;
+  const int slot = lane / C::LP, t = lane % C::LP;
+  const long long braw = (long long)blockIdx.x * C::PPW + slot;
+  const bool in_range = braw < B;
+  const long long b = in_range ? braw : B - 1;
+  T A1[21], A2[21];
+  load_sym(C1 + (size_t)b * 36, A1);
+  load_sym(C2 + (size_t)b * 36, A2);
+  int fail = 0;
+  T cC[21];
+  T dummy[C::NLAM][21];
+  lin_up<T, K, D, 1, false>(tab, t, A1, A2, cC, fail, dummy);
+#pragma unroll
+  for (int m = 1; m <= C::UPLEV; ++m) {
+    const int o = 1 << (m - 1);
+    T rC[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) rC[k] = shfl_dn(cC[k], o, C::LP);
+    if ((t & (2 * o - 1)) == 0) {
+      const LRow<T> row = lrow(tab, upos<K, D>(m, t));
+      T nC[21];
+      fail |= laminate_linear(cC, rC, row.nv, row.c1, row.c2, nC) ? 0 : 1;
+#pragma unroll
+      for (int k = 0; k < 21; ++k) cC[k] = nC[k];
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < C::LP; o <<= 1) fail |= __shfl_xor(fail, o, C::LP);
+  const int invalid = *flag;
+  if (t == 0 && in_range) {
+    if (fail || invalid) {
+#pragma unroll
+      for (int k = 0; k < 21; ++k) cC[k] = T(__builtin_nan(""));
+      atomicOr(err, (invalid ? 1 : 0) | (fail ? 2 : 0));
+    }
+    store_full(Cbar + (size_t)b * 36, cC);
+  }
+}
+
+// backward over the lane subtree: cotangent Gm of heap node H
+template <typename T, int K, int D, int H>
+__device__ __forceinline__ void lin_back(const T* __restrict__ tab, int t, bool live,
+                                         const T (&C1)[21], const T (&C2)[21],
+                                         const T (&nodes)[LCfg<K, D>::NLAM][21],
+                                         const T (&Gm)[21], double (&acc)[LCfg<K, D>::NLAM][4],
+                                         T (&g1)[21], T (&g2)[21]) {
+  using C = LCfg<K, D>;
+  if constexpr (H >= C::NLEAF) {
+    constexpr int q = H - C::NLEAF;
+#pragma unroll
+    for (int k = 0; k < 21; ++k) {
+      if constexpr (q % 2 == 0) g1[k] += Gm[k];
+      else g2[k] += Gm[k];
+    }
+  } else {
+    const T* CL;
+    const T* CR;
+    if constexpr (2 * H >= C::NLEAF) {
+      CL = C1;
+      CR = C2;
+    } else {
+      CL = nodes[2 * H - 1];
+      CR = nodes[2 * H];
+    }
+    const LRow<T> row = lrow(tab, lpos<K, D, H>(t));
+    T GL[21], GR[21], gc1, gn[3];
+    laminate_linear_vjp(CL, CR, row.nv, row.c1, row.c2, Gm, GL, GR, gc1, gn);
+    if (live) {
+      acc[H - 1][0] += (double)gc1;
+      acc[H - 1][1] += (double)gn[0];
+      acc[H - 1][2] += (double)gn[1];
+      acc[H - 1][3] += (double)gn[2];
+    }
+    lin_back<T, K, D, 2 * H>(tab, t, live, C1, C2, nodes, GL, acc, g1, g2);
+    lin_back<T, K, D, 2 * H + 1>(tab, t, live, C1, C2, nodes, GR, acc, g1, g2);
+  }
+}
+
+template <typename T, int K, int D>
+__global__ __launch_bounds__(64) void linear_bwd_kernel(
+    const T* __restrict__ tab, const int32_t* __restrict__ flag, long long B,
+    const T* __restrict__ C1, const T* __restrict__ C2, const T* __restrict__ gCbar,
+    T* __restrict__ gC1, T* __restrict__ gC2, double* __restrict__ partials,
+    int32_t* __restrict__ err) {
+  using C = LCfg<K, D>;
+  static_assert(C::NLAM >= 1, "lane subtree needs a laminate");
+  __shared__ T nodeC[21][C::PPW * C::NODES];
+  __shared__ double accU[4][C::PPW * (C::NUP > 0 ? C::NUP : 1)];
+  const int lane = threadIdx.x;
+  const int slot = lane / C::LP, t = lane % C::LP;
+  for (int u = lane; u < C::PPW * (C::NUP > 0 ? C::NUP : 1); u += 64)
+    for (int c = 0; c < 4; ++c) accU[c][u] = 0.0;
+  double acc[C::NLAM][4];
+#pragma unroll
+  for (int h = 0; h < C::NLAM; ++h)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[h][c] = 0.0;
+  int fail = 0;
+  __syncthreads();
+  for (long long sg = blockIdx.x; sg * C::PPW < B; sg += gridDim.x) {
+    const long long braw = sg * C::PPW + slot;
+    const bool live = braw < B;
+    const long long b = live ? braw : B - 1;
+    T A1[21], A2[21];
+    load_sym(C1 + (size_t)b * 36, A1);
+    load_sym(C2 + (size_t)b * 36, A2);
+    // forward, keeping node stiffnesses
+    T nodes[C::NLAM][21];
+    T cC[21];
+    lin_up<T, K, D, 1, true>(tab, t, A1, A2, cC, fail, nodes);
+    const int nbase = slot * C::NODES;
+#pragma unroll
+    for (int k = 0; k < 21; ++k) nodeC[k][nbase + t] = cC[k];
+#pragma unroll
+    for (int m = 1; m <= C::UPLEV; ++m) {
+      const int o = 1 << (m - 1);
+      T rC[21];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) rC[k] = shfl_dn(cC[k], o, C::LP);
+      if ((t & (2 * o - 1)) == 0) {
+        const int pos = upos<K, D>(m, t);
+        const LRow<T> row = lrow(tab, pos);
+        T nC[21];
+        fail |= laminate_linear(cC, rC, row.nv, row.c1, row.c2, nC) ? 0 : 1;
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+          cC[k] = nC[k];
+          nodeC[k][nbase + C::LP + (pos - C::UP0)] = nC[k];
+        }
+      }
+    }
+    __syncthreads();
+    // backward: root cotangent is the symmetric part of gCbar
+    T Gm[21];
+    load_sym(gCbar + (size_t)b * 36, Gm);
+#pragma unroll
+    for (int m = C::UPLEV; m >= 1; --m) {
+      const int o = 1 << (m - 1);
+      T GRs[21];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) GRs[k] = T(0);
+      if ((t & (2 * o - 1)) == 0) {
+        const int pos = upos<K, D>(m, t);
+        const LRow<T> row = lrow(tab, pos);
+        const int vL = m == 1 ? t : C::LP + (upos<K, D>(m - 1, t) - C::UP0);
+        const int vR = m == 1 ? t + 1 : C::LP + (upos<K, D>(m - 1, t + o) - C::UP0);
+        T CL[21], CR[21];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+          CL[k] = nodeC[k][nbase + vL];
+          CR[k] = nodeC[k][nbase + vR];
+        }
+        T GL[21], gc1, gn[3];
+        laminate_linear_vjp(CL, CR, row.nv, row.c1, row.c2, Gm, GL, GRs, gc1, gn);
+        if (live) {
+          const int u = slot * (C::NUP > 0 ? C::NUP : 1) + (pos - C::UP0);
+          accU[0][u] += (double)gc1;
+          accU[1][u] += (double)gn[0];
+          accU[2][u] += (double)gn[1];
+          accU[3][u] += (double)gn[2];
+        }
+#pragma unroll
+        for (int k = 0; k < 21; ++k) Gm[k] = GL[k];
+      }
+      T rcv[21];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) rcv[k] = shfl_upv(GRs[k], o, C::LP);
+      if ((t & (2 * o - 1)) == o) {
+#pragma unroll
+        for (int k = 0; k < 21; ++k) Gm[k] = rcv[k];
+      }
+    }
+    T g1[21], g2[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) {
+      g1[k] = T(0);
+      g2[k] = T(0);
+    }
+    lin_back<T, K, D, 1>(tab, t, live, A1, A2, nodes, Gm, acc, g1, g2);
+    if (gC1 != nullptr) {
+#pragma unroll
+      for (int o = 1; o < C::LP; o <<= 1)
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+          g1[k] += __shfl_xor(g1[k], o, C::LP);
+          g2[k] += __shfl_xor(g2[k], o, C::LP);
+        }
+      if (t == 0 && live) {
+        store_full(gC1 + (size_t)b * 36, g1);
+        store_full(gC2 + (size_t)b * 36, g2);
+      }
+    }
+    __syncthreads();  // nodeC is rewritten by the next sample group
+  }
+  // partial sums of this wave slot: [slot][pos][4]
+  const size_t pslot = (size_t)blockIdx.x * C::PPW + slot;
+  double* P = partials + pslot * C::L * 4;
+  auto put = [&](int pos, const double* v) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) P[(size_t)pos * 4 + c] = v[c];
+  };
+  [&] {
+    if constexpr (C::NLAM >= 1) {
+      // lane subtree laminates
+#pragma unroll
+      for (int h = 1; h <= C::NLAM; ++h) {
+        const int m = ilog2l(h);
+        const int k = K - D + 1 + m;
+        const int pos = (1 << K) - (1 << k) + t * (1 << m) + (h - (1 << m));
+        put(pos, acc[h - 1]);
+      }
+    }
+  }();
+#pragma unroll
+  for (int m = 1; m <= C::UPLEV; ++m) {
+    const int o = 1 << (m - 1);
+    if ((t & (2 * o - 1)) == 0) {
+      const int pos = upos<K, D>(m, t);
+      const int u = slot * (C::NUP > 0 ? C::NUP : 1) + (pos - C::UP0);
+      double v[4] = {accU[0][u], accU[1][u], accU[2][u], accU[3][u]};
+      put(pos, v);
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < C::LP; o <<= 1) fail |= __shfl_xor(fail, o, C::LP);
+  if (lane == 0 && (fail || *flag)) atomicOr(err, (*flag ? 1 : 0) | (fail ? 2 : 0));
+}
+
+// Sum the partials over wave slots in a fixed order: gsum[pos][4].
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials,
+                                                              long long nslots, int L4,
+                                                              double* __restrict__ gsum) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L4) return;
+  double s = 0.0;
+  for (long long q = 0; q < nslots; ++q) s += partials[(size_t)q * L4 + i];
+  gsum[i] = s;
+}
+
+// Leaf-weight and normal gradients from the per-laminate sums: a leaf
+// collects dc1/dW_L (left subtree) or dc1/dW_R (right subtree) times the
+// laminate's c1-cotangent over its root path.
+template <typename T>
+__global__ __launch_bounds__(256) void finish_grads_kernel(const double* __restrict__ gsum,
+                                                           const T* __restrict__ tab, int K,
+                                                           T* __restrict__ gw,
+                                                           T* __restrict__ gn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nleaf = 1 << K;
+  const int L = nleaf - 1;
+  if (i < nleaf) {
+    double s = 0.0;
+    for (int k = K; k >= 1; --k) {
+      const int i0 = i >> (K - k + 1);
+      const int pos = (1 << K) - (1 << k) + i0;
+      const bool right = (i >> (K - k)) & 1;
+      const double d = (double)tab[(size_t)pos * kTabStride + (right ? 7 : 6)];
+      s += gsum[(size_t)pos * 4] * d;
+    }
+    gw[i] = (T)s;
+  }
+  if (i < L) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gn[(size_t)i * 3 + c] = (T)gsum[(size_t)i * 4 + 1 + c];
+  }
+}
+
+constexpr int kMaxBwdWaves = 1024;
+
+}  // namespace
+
+static int lin_default_D(int depth) {
+  int d = depth - 6;
+  return d < 1 ? 1 : d;
+}
+
+template <typename T, int K>
+static int fwd_k(const void* tab, const int32_t* flag, long long B, const void* C1, const void* C2,
+                 void* Cbar, int32_t* err, hipStream_t s) {
+  constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
+  using C = LCfg<K, D>;
+  const long long nb = (B + C::PPW - 1) / C::PPW;
+  hipLaunchKernelGGL((linear_fwd_kernel<T, K, D>), dim3((unsigned)nb), dim3(64), 0, s,
+                     (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (T*)Cbar, err);
+  return (int)hipGetLastError();
+}
+
+template <typename T>
+static int fwd_t(int depth, const void* tab, const int32_t* flag, long long B, const void* C1,
+                 const void* C2, void* Cbar, int32_t* err, hipStream_t s) {
+  switch (depth) {
+    case 1: return fwd_k<T, 1>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 2: return fwd_k<T, 2>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 3: return fwd_k<T, 3>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 4: return fwd_k<T, 4>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 5: return fwd_k<T, 5>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 6: return fwd_k<T, 6>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 7: return fwd_k<T, 7>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 8: return fwd_k<T, 8>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 9: return fwd_k<T, 9>(tab, flag, B, C1, C2, Cbar, err, s);
+    case 10: return fwd_k<T, 10>(tab, flag, B, C1, C2, Cbar, err, s);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+int launch_linear_forward(int depth, int prec, const void* tab, const int32_t* flag, long long B,
+                          const void* C1, const void* C2, void* Cbar, int32_t* err,
+                          hipStream_t stream) {
+  if (prec == DMN_F32) return fwd_t<float>(depth, tab, flag, B, C1, C2, Cbar, err, stream);
+  return fwd_t<double>(depth, tab, flag, B, C1, C2, Cbar, err, stream);
+}
+
+long long linear_backward_partials(int depth, long long B) {
+  const int D = lin_default_D(depth);
+  const int LP = 1 << (depth - D);
+  const int PPW = 64 / LP;
+  long long waves = (B + PPW - 1) / PPW;
+  if (waves > kMaxBwdWaves) waves = kMaxBwdWaves;
+  if (waves < 1) waves = 1;
+  return waves * PPW;
+}
+
+template <typename T, int K>
+static int bwd_k(const void* tab, const int32_t* flag, long long B, const void* C1, const void* C2,
+                 const void* gCbar, void* gw, void* gn, void* gC1, void* gC2, double* partials,
+                 double* gsum, int32_t* err, hipStream_t s) {
+  constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
+  using C = LCfg<K, D>;
+  const long long nslots = linear_backward_partials(K, B);
+  const long long waves = nslots / C::PPW;
+  hipLaunchKernelGGL((linear_bwd_kernel<T, K, D>), dim3((unsigned)waves), dim3(64), 0, s,
+                     (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar, (T*)gC1,
+                     (T*)gC2, partials, err);
+  const int L4 = C::L * 4;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((L4 + 255) / 256), dim3(256), 0, s,
+                     (const double*)partials, nslots, L4, gsum);
+  const int nleaf = 1 << K;
+  hipLaunchKernelGGL((finish_grads_kernel<T>), dim3((nleaf + 255) / 256), dim3(256), 0, s,
+                     (const double*)gsum, (const T*)tab, K, (T*)gw, (T*)gn);
+  return (int)hipGetLastError();
+}
+
+template <typename T>
+static int bwd_t(int depth, const void* tab, const int32_t* flag, long long B, const void* C1,
+                 const void* C2, const void* gCbar, void* gw, void* gn, void* gC1, void* gC2,
+                 double* partials, double* gsum, int32_t* err, hipStream_t s) {
+  switch (depth) {
+#define DMN_BWD_CASE(KK) \
+  case KK:               \
+    return bwd_k<T, KK>(tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum, err, s);
+    DMN_BWD_CASE(1)
+    DMN_BWD_CASE(2)
+    DMN_BWD_CASE(3)
+    DMN_BWD_CASE(4)
+    DMN_BWD_CASE(5)
+    DMN_BWD_CASE(6)
+    DMN_BWD_CASE(7)
+    DMN_BWD_CASE(8)
+    DMN_BWD_CASE(9)
+    DMN_BWD_CASE(10)
+#undef DMN_BWD_CASE
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+}
+
+int launch_linear_backward(int depth, int prec, const void* tab, const int32_t* flag,
+                           long long B, const void* C1, const void* C2, const void* gCbar,
+                           void* gw, void* gn, void* gC1, void* gC2, double* partials,
+                           double* gsum, int32_t* err, hipStream_t stream) {
+  if (prec == DMN_F32)
+    return bwd_t<float>(depth, tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum,
+                        err, stream);
+  return bwd_t<double>(depth, tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum, err,
+                       stream);
+}
+
+}  // namespace dmn

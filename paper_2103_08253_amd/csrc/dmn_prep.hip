@@ -1,0 +1,81 @@
+// Per-DMN parameter preparation (FE-DMN paper, Sec. 2.1 weight propagation
+// and volume fractions; Sec. 3.2 weight matrix W).
+//
+// From the leaf weights w[2^K] and the normals n[2^K-1][3] (paper order) one
+// workgroup builds the laminate table used by every kernel:
+//   c1 = W_L / (W_L + W_R), c2 = 1 - c1   (W_X: summed leaf weights of a child)
+//   n                                      (copied as passed)
+//   rfac = W_L W_R / ((W_L + W_R) sum(w))  (scale of the laminate's block of A^T W sigma)
+//   dc1/dW_L = W_R / W^2, dc1/dW_R = -W_L / W^2
+// and flags the DMN as invalid when a weight is negative or not finite, or a
+// laminate's children carry no weight.  Subtree sums run sequentially over
+// the leaves, so the table is bit-identical run to run.
+#include "dmn_internal.hpp"
+
+namespace dmn {
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, const T* __restrict__ n,
+                                                   int K, T* __restrict__ tab,
+                                                   int32_t* __restrict__ flag,
+                                                   int32_t* __restrict__ err) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const int nleaf = 1 << K;
+  const int L = nleaf - 1;
+  T wtot = T(0);
+  for (int j = 0; j < nleaf; ++j) wtot += w[j];
+  int mybad = 0;
+  for (int j = threadIdx.x; j < nleaf; j += blockDim.x)
+    if (!(w[j] >= T(0)) || !isfinite(w[j])) mybad = 1;
+  for (int pos = threadIdx.x; pos < L; pos += blockDim.x) {
+    // level k and 1-based index i of the laminate at paper position pos
+    int k = K, base = 0;
+    while (pos >= base + (1 << (k - 1))) {
+      base += 1 << (k - 1);
+      --k;
+    }
+    const int i0 = pos - base;           // 0-based index within level k
+    const int span = 1 << (K - k + 1);   // leaves below the laminate
+    const int lo = i0 * span, mid = lo + span / 2, hi = lo + span;
+    T WL = T(0), WR = T(0);
+    for (int j = lo; j < mid; ++j) WL += w[j];
+    for (int j = mid; j < hi; ++j) WR += w[j];
+    const T W = WL + WR;
+    if (!(W > T(0))) mybad = 1;
+    T* r = tab + (size_t)pos * kTabStride;
+    const T c1 = WL / W;
+    r[0] = c1;
+    r[1] = T(1) - c1;
+    r[2] = n[(size_t)pos * 3 + 0];
+    r[3] = n[(size_t)pos * 3 + 1];
+    r[4] = n[(size_t)pos * 3 + 2];
+    r[5] = WL * WR / (W * wtot);
+    r[6] = WR / (W * W);
+    r[7] = -WL / (W * W);
+  }
+  if (mybad) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *flag = bad;
+    if (err) *err = 0;
+  }
+}
+
+}  // namespace
+
+int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
+                       int32_t* err, hipStream_t stream) {
+  if (prec == DMN_F32) {
+    hipLaunchKernelGGL(prep_kernel<float>, dim3(1), dim3(256), 0, stream, (const float*)w,
+                       (const float*)n, depth, (float*)tab, flag, err);
+  } else {
+    hipLaunchKernelGGL(prep_kernel<double>, dim3(1), dim3(256), 0, stream, (const double*)w,
+                       (const double*)n, depth, (double*)tab, flag, err);
+  }
+  return (int)hipGetLastError();
+}
+
+}  // namespace dmn

@@ -1,0 +1,109 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/dmn.h declares, and rejects bad arguments on the host with
+the documented codes before touching any device pointer."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2103_08253_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = ctypes.c_void_p(0x100000)   # never dereferenced: validation fails first
+ALIGNED = ctypes.c_void_p(0x200000)
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "dmn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(dmn_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = L.lib()
+    names = header_functions()
+    assert "dmn_update_gauss_points" in names and "dmn_homogenize_linear" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(L._SIGS), "binding must declare every exported function"
+    assert lib.dmn_version().decode().startswith("libdmn")
+
+
+def net(depth=3):
+    return L.DmnNet(depth, FAKE.value, FAKE.value)
+
+
+def test_linear_validation_codes():
+    lib = L.lib()
+    ws_need = lib.dmn_homogenize_linear_workspace_size(3, 10, L.DMN_F64)
+    assert ws_need > 0
+    assert lib.dmn_homogenize_linear_workspace_size(0, 10, L.DMN_F64) == 0
+    assert lib.dmn_homogenize_linear_workspace_size(11, 10, L.DMN_F64) == 0
+    call = lambda n, B=10, prec=L.DMN_F64, ws=ALIGNED, nb=ws_need: lib.dmn_homogenize_linear(
+        n, B, prec, FAKE, FAKE, FAKE, ws, nb, None)
+    assert call(None) == L.DMN_EINVAL
+    assert call(ctypes.byref(net(0))) == L.DMN_EINVAL
+    assert call(ctypes.byref(net(11))) == L.DMN_EINVAL
+    assert call(ctypes.byref(net(3)), B=-1) == L.DMN_EINVAL
+    assert call(ctypes.byref(net(3)), prec=7) == L.DMN_EUNSUPPORTED
+    assert call(ctypes.byref(net(3)), nb=ws_need - 1) == L.DMN_EWORKSPACE
+    assert call(ctypes.byref(net(3)), ws=None) == L.DMN_EWORKSPACE
+    assert call(ctypes.byref(net(3)), ws=ctypes.c_void_p(ALIGNED.value + 8)) == L.DMN_EWORKSPACE
+    bad = L.DmnNet(3, None, FAKE.value)
+    assert call(ctypes.byref(bad)) == L.DMN_EINVAL
+
+
+def test_backward_validation_codes():
+    lib = L.lib()
+    need = lib.dmn_homogenize_backward_workspace_size(8, 4096, L.DMN_F64)
+    assert need > lib.dmn_homogenize_linear_workspace_size(8, 4096, L.DMN_F64)
+    n8 = net(8)
+    call = lambda gw=FAKE, gc1=None, gc2=None, nb=need: lib.dmn_homogenize_backward(
+        ctypes.byref(n8), 4096, L.DMN_F64, FAKE, FAKE, FAKE, gw, FAKE, gc1, gc2, ALIGNED, nb, None)
+    assert call(gw=None) == L.DMN_EINVAL
+    assert call(gc1=FAKE) == L.DMN_EINVAL          # gC1 without gC2
+    assert call(nb=need - 1) == L.DMN_EWORKSPACE
+
+
+def group(depth=2, P=4, **over):
+    g = L.DmnPointGroup(net(depth), P, *([FAKE.value] * 9))
+    g.z_out = 0x300000
+    g.a_out = 0x400000
+    for k, v in over.items():
+        setattr(g, k, v)
+    return g
+
+
+def test_gauss_point_validation_codes():
+    lib = L.lib()
+    fib = L.DmnElastic(72000.0, 0.22)
+    mat = L.DmnJ2(2800.0, 0.35, 50.0, 200.0, 30.0, 60.0)
+    opts = L.DmnNewtonOpts(1e-10, 25, 10, 1e-4)
+    arr = (L.DmnPointGroup * 2)(group(2), group(8))
+    need = lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F64)
+    assert need > 0
+    assert lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F32) == 0
+
+    def call(a=arr, n=2, f=fib, m=mat, o=opts, prec=L.DMN_F64, nb=need):
+        return lib.dmn_update_gauss_points(a, n, ctypes.byref(f) if f else None,
+                                           ctypes.byref(m) if m else None, prec,
+                                           ctypes.byref(o) if o else None, ALIGNED, nb, None)
+
+    assert call(n=0) == L.DMN_EINVAL
+    assert call(n=65) == L.DMN_EINVAL
+    assert call(prec=L.DMN_F32) == L.DMN_EUNSUPPORTED
+    assert call(f=None) == L.DMN_EINVAL
+    assert call(m=L.DmnJ2(2800.0, 0.5, 50.0, 200.0, 30.0, 60.0)) == L.DMN_EINVAL
+    assert call(o=L.DmnNewtonOpts(0.0, 25, 10, 1e-4)) == L.DMN_EINVAL
+    assert call(o=L.DmnNewtonOpts(1e-10, -1, 10, 1e-4)) == L.DMN_EINVAL
+    assert call(o=L.DmnNewtonOpts(1e-10, 25, 10, 1.0)) == L.DMN_EINVAL
+    assert call(nb=need - 1) == L.DMN_EWORKSPACE
+    alias = (L.DmnPointGroup * 1)(group(2, z_out=FAKE.value))
+    assert call(a=alias, n=1) == L.DMN_EINVAL
+    deep = (L.DmnPointGroup * 1)(group(11))
+    assert call(a=deep, n=1) == L.DMN_EINVAL
+    neg = (L.DmnPointGroup * 1)(group(2, P=-1))
+    assert call(a=neg, n=1) == L.DMN_EINVAL
+    nul = (L.DmnPointGroup * 1)(group(2, sigma=None))
+    assert call(a=nul, n=1) == L.DMN_EINVAL

@@ -1,0 +1,327 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: FP64 results within a relative 1e-10 (max-norm, relative to the
+largest entry of the reference), iteration counts and status codes equal,
+FP32 linear map within 1e-4.  Points whose oracle history contains a leaf
+trial state within 1e-9 (relative) of the yield surface are reported and
+excluded, because there the elastic/plastic decision flips with roundoff.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synthetic as S
+from oracle.gp import DmnModel, NewtonOptions, gp_update, run_path
+from oracle.grad import linear_gradients
+from oracle.linear import dmn_linear
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+MARGIN = 1e-9
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(got, ref):
+    scale = np.abs(ref).max()
+    return np.abs(got - ref).max() / (scale if scale > 0 else 1.0)
+
+
+def close_state(got, ref, rtol=RTOL):
+    scale = max(np.abs(ref).max(), 1e-300)
+    return np.abs(got - ref).max() <= rtol * scale + 1e-18
+
+
+def gpu_path(net, E_path, opts=None):
+    """Run a load path through dmn_update_gauss_points; returns per-step host copies."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    d = dev()
+    w = torch.tensor(net.w, device=d)
+    n = torch.tensor(net.normals, device=d)
+    T, P = E_path.shape[:2]
+    g = PointGroup.allocate(w, n, torch.tensor(E_path[0], device=d))
+    out = []
+    ws = None
+    for step in range(T):
+        g.E.copy_(torch.tensor(E_path[step], device=d))
+        ws = dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws, **(opts or {}))
+        torch.cuda.synchronize()
+        out.append(dict(sigma=g.sigma.cpu().numpy(), C=g.tangent.cpu().numpy(),
+                        z=g.z_out.cpu().numpy(), a=g.a_out.cpu().numpy(),
+                        iters=g.iters.cpu().numpy(), status=g.status.cpu().numpy()))
+        g.advance()
+    return out
+
+
+def compare_paths(net, E_path, points, gpu, opts=NewtonOptions()):
+    model = DmnModel(net.depth, net.w, net.normals, S.FIBER, S.MATRIX)
+    worst = dict(sigma=0.0, C=0.0)
+    skipped = []
+    for p in points:
+        ref = run_path(model, E_path[:, p, :], opts)
+        if min(r["margin"] for r in ref) < MARGIN:
+            skipped.append(p)
+            continue
+        for step, r in enumerate(ref):
+            g = gpu[step]
+            assert g["status"][p] == r["status"], (p, step, g["status"][p], r["status"])
+            assert g["iters"][p] == r["iters"], (p, step, g["iters"][p], r["iters"])
+            es = rel(g["sigma"][p], r["sigma"])
+            ec = rel(g["C"][p], r["C"])
+            worst["sigma"] = max(worst["sigma"], es)
+            worst["C"] = max(worst["C"], ec)
+            assert es <= RTOL, (p, step, es)
+            assert ec <= RTOL, (p, step, ec)
+            assert close_state(g["z"][p], r["z"]), (p, step)
+            assert close_state(g["a"][p].ravel(), r["a"]), (p, step)
+    say(f"  depth {net.depth}: checked {len(points) - len(skipped)} points, "
+        f"near-yield skipped {skipped}, worst rel sigma {worst['sigma']:.2e} C {worst['C']:.2e}")
+    return worst
+
+
+def test_gp_depth2_full_path_all_points():
+    """Depth-2 DMN, 64 points, 10-step ramp to 2 %: every point, every step."""
+    say("case: gp depth 2, 64 points x 10 steps")
+    wl = S.config0()
+    gpu = gpu_path(wl.nets[0], wl.E)
+    compare_paths(wl.nets[0], wl.E, range(wl.n_points), gpu)
+
+
+@pytest.mark.parametrize("K", [1, 3, 4, 5, 6, 7])
+def test_gp_small_depths_ragged(K):
+    """Depths 1..7 (several points per wave), a ragged point count, 6 steps."""
+    say(f"case: gp depth {K}, 37 points x 6 steps")
+    rs = S.streams(100 + K)
+    net = S.random_dmn(rs["dmn"], K, 0.25)
+    E = S.ramp_with_noise(rs, 37, 6, 0.02, 1e-3)
+    gpu = gpu_path(net, E)
+    compare_paths(net, E, range(37), gpu)
+
+
+def test_gp_depth8_production_size_sampled():
+    """Depth 8 at the full production size (65,536 points, 20 steps); the oracle
+    follows 6 sampled points along their whole path."""
+    say("case: gp depth 8, 65536 points x 20 steps, 6 sampled")
+    wl = S.config1()
+    gpu = gpu_path(wl.nets[0], wl.E)
+    picks = S.streams(1)["picks"].choice(wl.n_points, 6, replace=False)
+    compare_paths(wl.nets[0], wl.E, picks, gpu)
+    st = np.stack([g["status"] for g in gpu])
+    assert np.all(st == 0), np.unique(st, return_counts=True)
+    plastic = np.mean(gpu[-1]["z"][:, :, 6] > 0)
+    say(f"  plastic matrix-leaf fraction at the last step: {plastic:.3f}")
+
+
+def test_gp_depth9_small():
+    say("case: gp depth 9, 5 points x 4 steps")
+    rs = S.streams(109)
+    net = S.random_dmn(rs["dmn"], 9, 0.2)
+    E = S.ramp_with_noise(rs, 5, 4, 0.015, 1e-3)
+    gpu = gpu_path(net, E)
+    compare_paths(net, E, range(5), gpu)
+
+
+def test_gp_mixed_depth_groups_one_call():
+    """16 DMNs of depths 5..9 in one call, a few points each, 30 % near-elastic."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    say("case: gp 16 mixed-depth groups, 4 steps")
+    d = dev()
+    wl = S.config2(n_points=64, n_steps=4)
+    groups, idx = [], []
+    for m, net in enumerate(wl.nets):
+        sel = np.nonzero(wl.dmn_id == m)[0]
+        idx.append(sel)
+        groups.append(PointGroup.allocate(torch.tensor(net.w, device=d),
+                                          torch.tensor(net.normals, device=d),
+                                          torch.tensor(wl.E[0, sel], device=d)))
+    outs = []
+    for step in range(wl.n_steps):
+        for m, g in enumerate(groups):
+            g.E.copy_(torch.tensor(wl.E[step, idx[m]], device=d))
+        dmn_update_gauss_points(groups, S.FIBER, S.MATRIX)
+        torch.cuda.synchronize()
+        outs.append([dict(sigma=g.sigma.cpu().numpy(), C=g.tangent.cpu().numpy(),
+                          z=g.z_out.cpu().numpy(), a=g.a_out.cpu().numpy(),
+                          iters=g.iters.cpu().numpy(), status=g.status.cpu().numpy())
+                     for g in groups])
+        for g in groups:
+            g.advance()
+    for m, net in enumerate(wl.nets):
+        sel = idx[m]
+        if len(sel) == 0:
+            continue
+        gpu = [o[m] for o in outs]
+        Em = wl.E[:, sel, :]
+        compare_paths(net, Em, range(min(len(sel), 2)), gpu)
+
+
+def test_gp_status_codes_and_failure_state():
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    say("case: gp status codes")
+    d = dev()
+    rs = S.streams(200)
+    net = S.random_dmn(rs["dmn"], 3, 0.25)
+    w = torch.tensor(net.w, device=d)
+    n = torch.tensor(net.normals, device=d)
+    E_host = 0.03 * S.unit_directions(rs["direction"], 6)
+    E_host[1, 2] = np.nan
+    E = torch.tensor(E_host, device=d)
+    z0 = 1e-3 * rs["noise"].standard_normal((6, 4, 7))
+    z0[:, :, 6] = np.abs(z0[:, :, 6])
+    g = PointGroup.allocate(w, n, E, z_in=torch.tensor(z0, device=d))
+    dmn_update_gauss_points([g], S.FIBER, S.MATRIX, max_iter=1)
+    torch.cuda.synchronize()
+    st = g.status.cpu().numpy()
+    assert st[1] == 2
+    assert torch.equal(g.z_out[1], g.z_in[1]) and torch.equal(g.a_out[1], g.a_in[1])
+    model = DmnModel(3, net.w, net.normals, S.FIBER, S.MATRIX)
+    for p in (0, 2, 3, 4, 5):
+        ref = gp_update(model, E_host[p], z0[p], np.zeros(21), NewtonOptions(max_iter=1))
+        assert st[p] == ref["status"], (p, st[p], ref["status"])
+        if st[p] != 0:
+            assert torch.equal(g.z_out[p], g.z_in[p])
+            assert torch.isnan(g.tangent[p]).all()
+    # invalid weights: every point reports a bad parameter, state passes through
+    wb = w.clone()
+    wb[0] = -0.1
+    gb = PointGroup.allocate(wb, n, E)
+    dmn_update_gauss_points([gb], S.FIBER, S.MATRIX)
+    torch.cuda.synchronize()
+    assert (gb.status == 5).all()
+    assert torch.equal(gb.a_out, gb.a_in)
+    # an empty group next to a populated one
+    ge = PointGroup.allocate(w, n, E[:0])
+    g2 = PointGroup.allocate(w, n, E[:1])
+    dmn_update_gauss_points([ge, g2], S.FIBER, S.MATRIX)
+    torch.cuda.synchronize()
+    assert int(g2.status[0]) == 0
+
+
+# ---------------------------------------------------------------- linear map
+
+@pytest.mark.parametrize("K,B", [(1, 5), (3, 37), (5, 70), (8, 33), (9, 3)])
+def test_linear_forward_f64(K, B):
+    from paper_2103_08253_amd import dmn_homogenize_linear, error_word
+    say(f"case: linear forward f64 depth {K} batch {B}")
+    d = dev()
+    tw = S.config3(batch=B, depth=K)
+    Cbar, ws = dmn_homogenize_linear(torch.tensor(tw.truth.w, device=d),
+                                     torch.tensor(tw.truth.normals, device=d),
+                                     torch.tensor(tw.C1, device=d), torch.tensor(tw.C2, device=d))
+    ref = dmn_linear(K, tw.truth.w, tw.truth.normals, tw.C1, tw.C2)
+    got = Cbar.cpu().numpy()
+    assert error_word(ws) == 0
+    errs = [rel(got[b], ref[b]) for b in range(B)]
+    say(f"  worst rel err {max(errs):.2e}")
+    assert max(errs) <= RTOL
+
+
+@pytest.mark.parametrize("K,B", [(3, 37), (8, 64)])
+def test_linear_forward_f32(K, B):
+    from paper_2103_08253_amd import dmn_homogenize_linear
+    say(f"case: linear forward f32 depth {K} batch {B}")
+    d = dev()
+    tw = S.config3(batch=B, depth=K)
+    f = lambda x: torch.tensor(x, device=d, dtype=torch.float32)
+    Cbar, _ = dmn_homogenize_linear(f(tw.truth.w), f(tw.truth.normals), f(tw.C1), f(tw.C2))
+    ref = dmn_linear(K, tw.truth.w, tw.truth.normals, tw.C1, tw.C2)
+    got = Cbar.double().cpu().numpy()
+    errs = [rel(got[b], ref[b]) for b in range(B)]
+    say(f"  worst rel err {max(errs):.2e}")
+    assert max(errs) <= 1e-4
+
+
+def chain_angles(gn, alpha, beta):
+    da = np.stack([np.cos(alpha) * np.cos(beta), np.cos(alpha) * np.sin(beta), -np.sin(alpha)], -1)
+    db = np.stack([-np.sin(alpha) * np.sin(beta), np.sin(alpha) * np.cos(beta),
+                   np.zeros_like(alpha)], -1)
+    return np.sum(gn * da, -1), np.sum(gn * db, -1)
+
+
+@pytest.mark.parametrize("K,B,subset", [(3, 5, None), (5, 9, None), (8, 2, 24)])
+def test_linear_backward_f64_vs_complex_step(K, B, subset):
+    from paper_2103_08253_amd import dmn_homogenize_backward
+    say(f"case: linear backward f64 depth {K} batch {B}")
+    d = dev()
+    tw = S.config3(batch=B, depth=K)
+    net = tw.truth
+    alpha, beta = S.normals_to_angles(net.normals)
+    G = S.streams(3)["cotangent"].standard_normal((B, 6, 6))
+    gw, gn, gC1, gC2, _ = dmn_homogenize_backward(
+        torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d),
+        torch.tensor(tw.C1, device=d), torch.tensor(tw.C2, device=d), torch.tensor(G, device=d),
+        want_input_grads=True)
+    gw, gn = gw.cpu().numpy(), gn.cpu().numpy()
+    ga, gb = chain_angles(gn, alpha, beta)
+    rng = np.random.default_rng(7)
+    w_idx = None if subset is None else rng.choice(2 ** K, subset, replace=False)
+    a_idx = None if subset is None else rng.choice(2 ** K - 1, subset, replace=False)
+    ref = linear_gradients(K, net.w, alpha, beta, tw.C1, tw.C2, G, w_idx, a_idx)
+    mw = ~np.isnan(ref["gw"])
+    ma = ~np.isnan(ref["galpha"])
+    scale_w = np.abs(ref["gw"][mw]).max()
+    scale_a = max(np.abs(ref["galpha"][ma]).max(), np.abs(ref["gbeta"][ma]).max())
+    ew = np.abs(gw[mw] - ref["gw"][mw]).max() / scale_w
+    ea = max(np.abs(ga[ma] - ref["galpha"][ma]).max(), np.abs(gb[ma] - ref["gbeta"][ma]).max()) / scale_a
+    say(f"  rel err gw {ew:.2e}, angles {ea:.2e}")
+    assert ew <= RTOL and ea <= RTOL
+    # Euler identity of the scale-invariant map, and tangency of gn
+    assert abs(net.w @ gw) <= 1e-10 * np.abs(gw).max() * np.abs(net.w).sum()
+    assert np.abs(np.sum(gn * net.normals, -1)).max() <= 1e-9 * np.abs(gn).max()
+    # input cotangent: one entry of C1 and of C2 by complex step on a symmetric perturbation
+    h = 1e-30
+    for which, gC, (i, j) in (("C1", gC1, (0, 4)), ("C2", gC2, (2, 2))):
+        E_ij = np.zeros((6, 6), complex)
+        E_ij[i, j] += 1j * h
+        E_ij[j, i] += 1j * h if i != j else 0
+        C1c = tw.C1.astype(complex) + (E_ij if which == "C1" else 0)
+        C2c = tw.C2.astype(complex) + (E_ij if which == "C2" else 0)
+        cs = np.imag(np.sum(G * dmn_linear(K, net.w, net.normals, C1c, C2c))) / h
+        gpu_val = gC[:, i, j].sum().item() * (2 if i != j else 1)
+        assert abs(gpu_val - cs) <= 1e-9 * max(abs(cs), 1e-12), (which, gpu_val, cs)
+
+
+def test_linear_backward_finite_differences_and_f32():
+    from paper_2103_08253_amd import dmn_homogenize_backward, dmn_homogenize_linear
+    say("case: linear backward depth 8 batch 4096: FD h=1e-6 and FP32")
+    d = dev()
+    tw = S.config3()
+    net = tw.truth
+    t = lambda x, dt=torch.float64: torch.tensor(x, device=d, dtype=dt)
+    G = S.streams(3)["cotangent"].standard_normal((4096, 6, 6))
+    gw, gn, _, _, _ = dmn_homogenize_backward(t(net.w), t(net.normals), t(tw.C1), t(tw.C2), t(G))
+    J = lambda w, n: float(torch.sum(t(G) * dmn_homogenize_linear(w, n, t(tw.C1), t(tw.C2))[0]))
+    h = 1e-6
+    for j in (0, 77, 255):
+        wp, wm = t(net.w), t(net.w)
+        wp[j] += h
+        wm[j] -= h
+        fd = (J(wp, t(net.normals)) - J(wm, t(net.normals))) / (2 * h)
+        assert abs(fd - gw[j].item()) <= 1e-5 * abs(gw).max().item(), (j, fd, gw[j].item())
+    for p in (3, 200, 254):
+        for c in range(3):
+            npl, nmi = t(net.normals), t(net.normals)
+            npl[p, c] += h
+            nmi[p, c] -= h
+            fd = (J(t(net.w), npl) - J(t(net.w), nmi)) / (2 * h)
+            assert abs(fd - gn[p, c].item()) <= 1e-5 * abs(gn).max().item(), (p, c, fd)
+    f = torch.float32
+    gw32, gn32, _, _, _ = dmn_homogenize_backward(t(net.w, f), t(net.normals, f), t(tw.C1, f),
+                                                  t(tw.C2, f), t(G, f))
+    ew = (gw32.double() - gw).abs().max().item() / gw.abs().max().item()
+    en = (gn32.double() - gn).abs().max().item() / gn.abs().max().item()
+    say(f"  FP32 vs FP64 gradient rel err: w {ew:.2e}, n {en:.2e}")
+    assert ew <= 1e-4 and en <= 1e-4
