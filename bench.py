@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the DMN hot path on one MI355X.
+
+One bench step is one pass of the whole hot path over one batch:
+  * one load step of the depth-8 production workload: 65,536 Gauss points,
+    FP64 (parameter prep, localisation, J2 leaves, tree Newton with
+    backtracking, stress + tangent + state), taken in order along the seeded
+    20-step strain path; and
+  * one training forward + backward of the depth-8 linear DMN map on a batch
+    of 4,096 phase-stiffness pairs (FP64) with a seeded cotangent.
+
+Inputs are synthetic (see synthetic/), resident on the GPU before timing.
+Prints one JSON line.  `value` is Gauss-point updates per second of whole
+step time; the training rate and per-component times are reported beside it,
+together with the roofline of the dominant kernel and the FP64 CPU oracle
+timed on a bounded sample on the host cores.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 2] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DMN Gauss-point updates/s (stress+tangent, depth 8, FP64) + train fwd+bwd samples/s"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gp_update_depth8_traffic.json")
+GP_SOURCES = ["paper_2103_08253_amd/csrc/dmn_gp.hip", "paper_2103_08253_amd/csrc/dmn_algebra.hpp",
+              "paper_2103_08253_amd/csrc/dmn_internal.hpp"]
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed rocprofv3 counters, if they were taken
+    on the current kernel source; None otherwise."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest(GP_SOURCES):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------- CPU baseline
+
+def _oracle_worker(args):
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+    import synthetic as S
+    from oracle.gp import DmnModel, NewtonOptions, run_path
+    points, n_steps = args
+    wl = S.config1()
+    net = wl.nets[0]
+    model = DmnModel(net.depth, net.w, net.normals, S.FIBER, S.MATRIX)
+    n = 0
+    for p in points:
+        outs = run_path(model, wl.E[:n_steps, p, :], NewtonOptions())
+        n += len(outs)
+    return n
+
+
+def cpu_baseline(n_points=24, n_steps=20, workers=None):
+    """The FP64 oracle (dense Newton, LAPACK Cholesky) on a sample of the same
+    workload: n_points seeded points along their full 20-step path, one process
+    per core with single-threaded BLAS."""
+    import multiprocessing as mp
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    workers = workers or min(16, os.cpu_count() or 1, n_points)
+    chunks = [list(range(i, n_points, workers)) for i in range(workers)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_worker, [([0], 1)] * workers)  # import + workload setup
+        t0 = time.perf_counter()
+        done = sum(pool.map(_oracle_worker, [(c, n_steps) for c in chunks]))
+        dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="GP updates/s", cores=workers, kind="oracle",
+                sample=f"{n_points} points x {n_steps} load steps of the depth-8 production "
+                       f"workload ({done} updates, {dt:.1f} s wall on {workers} processes)")
+
+
+# ---------------------------------------------------------------- GPU bench
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-points", type=int, default=24)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single "
+              "MI355X (points are independent; see the sharding notes of the design).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    from paper_2103_08253_amd import (PointGroup, dmn_homogenize_backward,
+                                      dmn_homogenize_linear, dmn_update_gauss_points)
+    from paper_2103_08253_amd import roofline as R
+    from paper_2103_08253_amd import _lib
+
+    _lib.lib()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    wl = S.config1()
+    net = wl.nets[0]
+    T, P = wl.n_steps, wl.n_points
+    E_path = torch.tensor(wl.E, device=dev)           # [20, P, 6]
+    w = torch.tensor(net.w, device=dev)
+    n = torch.tensor(net.normals, device=dev)
+    g = PointGroup.allocate(w, n, E_path[0])
+
+    tw = S.config3()
+    B = tw.C1.shape[0]
+    C1 = torch.tensor(tw.C1, device=dev)
+    C2 = torch.tensor(tw.C2, device=dev)
+    Gc = torch.tensor(S.streams(3)["cotangent"].standard_normal((B, 6, 6)), device=dev)
+    wt = torch.tensor(tw.v0, device=dev)
+    nt = torch.tensor(S.angles_to_normals(tw.alpha0, tw.beta0), device=dev)
+
+    ws_gp = None
+    ws_lin = ws_bwd = None
+
+    def reset_state():
+        g.z_in.zero_()
+        g.a_in.zero_()
+
+    def gp_step(k):
+        nonlocal ws_gp
+        g.E = E_path[k % T]
+        if k % T == 0 and k > 0:
+            reset_state()
+        ws_gp = dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws_gp)
+        g.advance()
+
+    def train_step():
+        nonlocal ws_lin, ws_bwd
+        _, ws_lin = dmn_homogenize_linear(wt, nt, C1, C2, ws=ws_lin)
+        out = dmn_homogenize_backward(wt, nt, C1, C2, Gc, ws=ws_bwd)
+        ws_bwd = out[-1]
+
+    for k in range(args.warmup):
+        gp_step(k)
+        train_step()
+    torch.cuda.synchronize()
+    reset_state()
+
+    K = args.steps
+    iters_log = torch.empty((K, P), dtype=torch.int32, device=dev)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record()
+        gp_step(k)
+        ev[k][1].record()
+        iters_log[k].copy_(g.iters)
+        ev[k][2].record()
+        train_step()
+        ev[k][3].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    gp_ms = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)])
+    tr_ms = np.array([ev[k][2].elapsed_time(ev[k][3]) for k in range(K)])
+    status_ok = bool((g.status == 0).all().item())
+    it = iters_log.cpu().numpy()
+    flops = np.array([sum(int(c) * R.gp_update_flops(8, int(v))
+                          for v, c in zip(*np.unique(it[k], return_counts=True)))
+                      for k in range(K)], dtype=np.float64)
+    achieved_tf = flops.sum() / (gp_ms.sum() * 1e-3) / 1e12
+    bytes_launch = P * R.gp_update_bytes(8)
+    traffic = measured_traffic()
+    train_flops = B * (R.linear_forward_flops(8) + R.linear_backward_flops(8))
+
+    ms_per_step = wall * 1e3 / K
+    rec = dict(
+        metric=METRIC,
+        value=P * K / wall,
+        unit="GP updates/s",
+        n_gpus=1, steps=K, warmup=args.warmup,
+        ms_per_step=ms_per_step,
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload="depth8_production: 65536 Gauss points, 20-step strain path "
+                             "(ramp to 1.5 % + N(0,1e-3) walk), J2 matrix + elastic fibre; "
+                             "plus depth-8 linear fwd+bwd on 4096 SPD phase pairs",
+                    depth=8, gauss_points=P, load_steps_in_path=T, train_batch=B,
+                    newton_tol=1e-10),
+        train_samples_per_s=B * K / (tr_ms.sum() * 1e-3),
+        components=dict(
+            gp_update=dict(ms_mean=float(gp_ms.mean()), ms_min=float(gp_ms.min()),
+                           ms_max=float(gp_ms.max()),
+                           updates_per_s=float(P / (gp_ms.mean() * 1e-3)),
+                           mean_newton_iters=float(it.mean()), all_converged=status_ok,
+                           algorithmic_gflop_per_launch=float(flops.mean() / 1e9),
+                           algorithmic_bytes_per_launch=bytes_launch),
+            train_fwd_bwd=dict(ms_mean=float(tr_ms.mean()),
+                               samples_per_s=float(B / (tr_ms.mean() * 1e-3)),
+                               tflops=float(train_flops / (tr_ms.mean() * 1e-3) / 1e12))),
+        roofline=dict(bound="alu", achieved=float(achieved_tf), peak=R.FP64_PEAK_TFLOPS,
+                      unit="TFLOP/s", frac=float(achieved_tf / R.FP64_PEAK_TFLOPS),
+                      traffic=traffic, kernel="gp_update_kernel<8,2> (FP64 VALU)"),
+    )
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(args.cpu_points)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -277,79 +277,84 @@ __device__ __forceinline__ void laminate_linear_vjp(const T CL[21], const T CR[2
   gn[2] = GN[2][2] + r * (GN[3][1] + GN[4][0]);
 }
 
-// Newton laminate step: condensed tangent C, affine offset tau, plain stress
-// average sb, top-down factors G (3x6, row-major) and g (3), and the squared
-// norm of the laminate's residual  rfac N^T (sb_R - sb_L), where
-// rfac = W_L W_R / (W sum(w)) makes it the laminate's block of A^T W sigma.
+// Newton laminate step, in place: on entry (C, tau, sb) hold the left
+// child's condensed tangent, affine offset and plain stress average; on exit
+// they hold the laminate's.  Also returns the top-down factors G (3x6,
+// row-major) and g (3), accumulates the squared norm of the laminate's
+// residual block rfac N^T (sb_R - sb_L) into rr (rfac = W_L W_R / (W sum(w))
+// makes it the laminate's block of A^T W sigma), and returns false when the
+// 3x3 pivot N^T S N is not positive definite.  Written to keep few values live:
+// S and C_R - C_L are formed one row at a time.
 template <typename T>
-__device__ __forceinline__ bool laminate_newton(const T CL[21], const T tL[6], const T sL[6],
-                                                const T CR[21], const T tR[6], const T sR[6],
+__device__ __forceinline__ bool laminate_newton(T C[21], T tau[6], T sb[6], const T CR[21],
+                                                const T tR[6], const T sR[6],
                                                 const Normal<T>& nv, T c1, T c2, T rfac,
-                                                T C[21], T tau[6], T sb[6], T G[18], T g[3],
-                                                T& rr) {
-  T S[21], dC[21];
+                                                T G[18], T g[3], T& rr) {
+  const T r = T(kRsqrt2);
+  const T n0 = nv.n0, n1 = nv.n1, n2 = nv.n2;
+  const T n0r = n0 * r, n1r = n1 * r, n2r = n2 * r;
+  T k00 = 0, k01 = 0, k02 = 0, k11 = 0, k12 = 0, k22 = 0;
+  T U[6][3];
 #pragma unroll
-  for (int k = 0; k < 21; ++k) {
-    S[k] = c2 * CL[k] + c1 * CR[k];
-    dC[k] = CR[k] - CL[k];
-  }
-  T SN[6][3], U[6][3];
-  sym_times_N(S, nv, SN);
-  sym_times_N(dC, nv, U);
-  T col[6], kc[3];
-  T Km[3][3];
+  for (int i = 0; i < 6; ++i) {
+    T srow[6], drow[6], sn[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int r = 0; r < 6; ++r) col[r] = SN[r][c];
-    nv.applyT(col, kc);
-    Km[0][c] = kc[0];
-    Km[1][c] = kc[1];
-    Km[2][c] = kc[2];
+    for (int j = 0; j < 6; ++j) {
+      srow[j] = c2 * C[sidx(i, j)] + c1 * CR[sidx(i, j)];
+      drow[j] = CR[sidx(i, j)] - C[sidx(i, j)];
+    }
+    nv.applyT(srow, sn);  // row i of S N
+    nv.applyT(drow, U[i]);
+    // K[a][b] += N[i][a] (S N)[i][b], N's nine non-zeros written out
+    if (i == 0) { k00 += n0 * sn[0]; k01 += n0 * sn[1]; k02 += n0 * sn[2]; }
+    if (i == 1) { k11 += n1 * sn[1]; k12 += n1 * sn[2]; }
+    if (i == 2) { k22 += n2 * sn[2]; }
+    if (i == 3) { k11 += n2r * sn[1]; k12 += n2r * sn[2]; k22 += n1r * sn[2]; }
+    if (i == 4) { k00 += n2r * sn[0]; k01 += n2r * sn[1]; k02 += n2r * sn[2]; k22 += n0r * sn[2]; }
+    if (i == 5) { k00 += n1r * sn[0]; k01 += n1r * sn[1]; k02 += n1r * sn[2];
+                  k11 += n0r * sn[1]; k12 += n0r * sn[2]; }
   }
   T m00, m01, m02, m11, m12, m22;
-  bool ok = spd3_inverse(Km[0][0], Km[0][1], Km[0][2], Km[1][1], Km[1][2], Km[2][2], m00, m01,
-                         m02, m11, m12, m22);
-  T V[6][3];
-#pragma unroll
-  for (int r = 0; r < 6; ++r) {
-    V[r][0] = U[r][0] * m00 + U[r][1] * m01 + U[r][2] * m02;
-    V[r][1] = U[r][0] * m01 + U[r][1] * m11 + U[r][2] * m12;
-    V[r][2] = U[r][0] * m02 + U[r][1] * m12 + U[r][2] * m22;
-  }
+  const bool ok = spd3_inverse(k00, k01, k02, k11, k12, k22, m00, m01, m02, m11, m12, m22);
   const T cc = c1 * c2;
+  // g = K^-1 N^T (tau_R - tau_L); tau = c1 tau_L + c2 tau_R - c1 c2 U g
+  {
+    T dt[6], q[3];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) dt[s] = tR[s] - tau[s];
+    nv.applyT(dt, q);
+    g[0] = m00 * q[0] + m01 * q[1] + m02 * q[2];
+    g[1] = m01 * q[0] + m11 * q[1] + m12 * q[2];
+    g[2] = m02 * q[0] + m12 * q[1] + m22 * q[2];
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+      tau[s] = c1 * tau[s] + c2 * tR[s] - cc * (U[s][0] * g[0] + U[s][1] * g[1] + U[s][2] * g[2]);
+  }
+  // residual block and plain average
+  {
+    T ds[6], rv[3];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) ds[s] = sR[s] - sb[s];
+    nv.applyT(ds, rv);
+    rr += rfac * rfac * (rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) sb[s] = c1 * sb[s] + c2 * sR[s];
+  }
+  // G = K^-1 U^T (= (U K^-1)^T)
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    G[0 * 6 + s] = U[s][0] * m00 + U[s][1] * m01 + U[s][2] * m02;
+    G[1 * 6 + s] = U[s][0] * m01 + U[s][1] * m11 + U[s][2] * m12;
+    G[2 * 6 + s] = U[s][0] * m02 + U[s][1] * m12 + U[s][2] * m22;
+  }
+  // condensed tangent, in place: C = c1 C_L + c2 C_R - c1 c2 (U K^-1) U^T
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
     for (int j = i; j < 6; ++j) {
-      T vu = V[i][0] * U[j][0] + V[i][1] * U[j][1] + V[i][2] * U[j][2];
-      C[sidx(i, j)] = c1 * CL[sidx(i, j)] + c2 * CR[sidx(i, j)] - cc * vu;
+      const T vu = G[i] * U[j][0] + G[6 + i] * U[j][1] + G[12 + i] * U[j][2];
+      C[sidx(i, j)] = c1 * C[sidx(i, j)] + c2 * CR[sidx(i, j)] - cc * vu;
     }
-  // G = K^-1 U^T = V^T
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int s = 0; s < 6; ++s) G[a * 6 + s] = V[s][a];
-  // g = K^-1 N^T (tau_R - tau_L);  tau = c1 tau_L + c2 tau_R - c1 c2 U g
-  T dt[6], q[3];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) dt[s] = tR[s] - tL[s];
-  nv.applyT(dt, q);
-  g[0] = m00 * q[0] + m01 * q[1] + m02 * q[2];
-  g[1] = m01 * q[0] + m11 * q[1] + m12 * q[2];
-  g[2] = m02 * q[0] + m12 * q[1] + m22 * q[2];
-#pragma unroll
-  for (int s = 0; s < 6; ++s)
-    tau[s] = c1 * tL[s] + c2 * tR[s] - cc * (U[s][0] * g[0] + U[s][1] * g[1] + U[s][2] * g[2]);
-  // plain average and residual block
-  T ds[6], r[3];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    sb[s] = c1 * sL[s] + c2 * sR[s];
-    ds[s] = sR[s] - sL[s];
-  }
-  nv.applyT(ds, r);
-  rr += rfac * rfac * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   return ok;
 }
 

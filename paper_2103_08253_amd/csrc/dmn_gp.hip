@@ -4,22 +4,23 @@
 // Work mapping.  One 64-lane wavefront owns 64 / LP Gauss points; the LP
 // lanes of a point split its laminate tree: lane t owns the depth-D subtree
 // whose root is laminate (K-D+1, t+1) together with its 2^D leaves, and keeps
-// that subtree's leaf strains, jumps and top-down factors in registers.  The
-// K-D levels above the lane subtrees are combined with wavefront shuffles
+// that subtree's jumps, Newton increments and top-down factors in registers.
+// The K-D levels above the lane subtrees are combined with wavefront shuffles
 // (lane t receives its right sibling's condensed response from lane
-// t + 2^(m-1)); their top-down factors and jumps live in LDS, written and read
-// only by the lane that computes the laminate.
+// t + 2^(m-1)); their factors and jumps live in LDS, written and read only by
+// the lane that computes the laminate.
 //
-// One Newton iteration (Sec. 3.2, Newton system) is
-//   leaves:     fibre sigma = C_f eps; matrix J2 radial return -> sigma, D;
-//   bottom-up:  block-Cholesky condensation of A^T W D A in postorder
-//               (no fill-in): condensed C, tau, plain average, residual;
-//   root:       C is the algorithmic tangent, the plain average the
-//               effective stress, the summed squared blocks |A^T W sigma|^2;
-//   top-down:   jump increments da and leaf strain increments A da;
-// with backtracking on the residual norm.  The per-point control (stop test,
-// iteration cap, backtracking, status codes) is uniform across the lanes of
-// a point.
+// One evaluation at jumps a:
+//   localisation: leaf strains eps = E + A a, top-down through the tree;
+//   leaves:       fibre sigma = C_f eps; matrix J2 radial return -> sigma, D;
+//   bottom-up:    block-Cholesky condensation of A^T W D A in postorder (no
+//                 fill-in): condensed C, tau, plain average, residual blocks;
+//   root:         C is the algorithmic tangent, the plain average the effective
+//                 stress, the summed squared blocks |A^T W sigma|^2.
+// A Newton step adds the top-down pass for the increments da.  Each loop trip
+// of the kernel performs exactly one evaluation, at a + s da (s = 0 for the
+// initial state, s = 1, 1/2, ... for backtracking trials), followed by the
+// per-point decision; all shuffles run in wave-uniform code.
 #include "dmn_internal.hpp"
 
 namespace dmn {
@@ -89,67 +90,31 @@ struct UpperLds {
 template <int K, int D>
 struct LaneState {
   using C = Cfg<K, D>;
-  double eps[C::NLEAF][6];   // leaf strains at the accepted iterate
-  double deps[C::NLEAF][6];  // leaf strain increments A da of the Newton step
-  double a[C::NLAM][3];      // jumps
-  double da[C::NLAM][3];     // Newton jump increments
-  double G[C::NLAM][18];     // top-down factors of the last evaluation
+  double a[C::NLAM][3];   // accepted jumps
+  double da[C::NLAM][3];  // Newton increments
+  double G[C::NLAM][18];  // top-down factors of the last evaluation
   double g[C::NLAM][3];
 };
 
 struct EvalOut {
-  double C[21];   // condensed tangent (meaningful on the point's lane 0)
-  double sb[6];   // plain stress average (lane 0)
-  double rr;      // squared residual norm (reduced over the point's lanes)
-  int lfail;      // J2 return failed somewhere in the point
-  int spdfail;    // a laminate pivot was not positive
+  double C[21];  // condensed tangent (meaningful on the point's lane 0)
+  double sb[6];  // plain stress average (lane 0)
+  double rr;     // squared residual norm (reduced over the point's lanes)
+  double sn2;    // squared norm of the effective stress (broadcast)
+  int lfail;     // J2 return failed somewhere in the point
+  int spdfail;   // a laminate pivot was not positive
 };
 
 template <int K, int D>
 struct Ctx {
-  using C = Cfg<K, D>;
   const double* __restrict__ tab;
   const double* __restrict__ zin;  // this point's z_in
   IsoElastic fib;
   J2Law mat;
   int t;
   int slot;
+  int base;  // first lane of this point in the wave
 };
-
-// ---------------------------------------------------------------- bottom-up
-
-template <int K, int D, int H>
-__device__ __forceinline__ void up_node(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                        const double (&ev)[Cfg<K, D>::NLEAF][6], double (&Cn)[21],
-                                        double (&tn)[6], double (&sn)[6], double& rr, int& lfail,
-                                        int& spdfail) {
-  using C = Cfg<K, D>;
-  if constexpr (H >= C::NLEAF) {
-    constexpr int q = H - C::NLEAF;
-    if constexpr (q % 2 == 0) {  // fibre leaf
-      iso_stress(cx.fib, ev[q], sn);
-      iso_packed(cx.fib, Cn);
-    } else {                     // matrix leaf
-      const int mloc = cx.t * (C::NLEAF / 2) + q / 2;
-      const double* z = cx.zin + (size_t)mloc * 7;
-      double epn[6], ep[6], p;
-#pragma unroll
-      for (int s = 0; s < 6; ++s) epn[s] = z[s];
-      bool ok = j2_return(cx.mat, ev[q], epn, z[6], sn, Cn, ep, p);
-      lfail |= ok ? 0 : 1;
-    }
-#pragma unroll
-    for (int s = 0; s < 6; ++s) tn[s] = sn[s];
-  } else {
-    double CL[21], tL[6], sL[6], CR[21], tR[6], sR[6];
-    up_node<K, D, 2 * H>(cx, st, ev, CL, tL, sL, rr, lfail, spdfail);
-    up_node<K, D, 2 * H + 1>(cx, st, ev, CR, tR, sR, rr, lfail, spdfail);
-    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
-    bool ok = laminate_newton(CL, tL, sL, CR, tR, sR, row.nv, row.c1, row.c2, row.rf, Cn, tn, sn,
-                              st.G[H - 1], st.g[H - 1], rr);
-    spdfail |= ok ? 0 : 1;
-  }
-}
 
 __device__ __forceinline__ double shfl_down_d(double v, int o, int width) {
   return __shfl_down(v, (unsigned)o, width);
@@ -158,60 +123,154 @@ __device__ __forceinline__ double shfl_up_d(double v, int o, int width) {
   return __shfl_up(v, (unsigned)o, width);
 }
 
-// Full evaluation at leaf strains ev: leaf laws + bottom-up condensation.
+__device__ __forceinline__ bool upper_active(int t, int m) { return (t & ((1 << m) - 1)) == 0; }
+__device__ __forceinline__ bool upper_right(int t, int m) {
+  return (t & ((1 << m) - 1)) == (1 << (m - 1));
+}
+
+// ------------------------------------------------------- strain localisation
+
+template <int K, int D, int H>
+__device__ __forceinline__ void loc_node(const Ctx<K, D>& cx, const LaneState<K, D>& st, double s,
+                                         const double (&e)[6],
+                                         double (&eps)[Cfg<K, D>::NLEAF][6]) {
+  using C = Cfg<K, D>;
+  if constexpr (H >= C::NLEAF) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) eps[H - C::NLEAF][k] = e[k];
+  } else {
+    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
+    double aj[3], eL[6], eR[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) aj[k] = st.a[H - 1][k] + s * st.da[H - 1][k];
+    laminate_localize(aj, e, row.nv, row.c1, row.c2, eL, eR);
+    loc_node<K, D, 2 * H>(cx, st, s, eL, eps);
+    loc_node<K, D, 2 * H + 1>(cx, st, s, eR, eps);
+  }
+}
+
+// Leaf strains at jumps a + s da (wave-uniform: contains shuffles).
 template <int K, int D>
-__device__ __forceinline__ void evaluate(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                         UpperLds<K, D>& up, const double (&ev)[Cfg<K, D>::NLEAF][6],
-                                         EvalOut& out) {
+__device__ __forceinline__ void localize(const Ctx<K, D>& cx, const LaneState<K, D>& st,
+                                         const UpperLds<K, D>& up, const double (&E)[6], double s,
+                                         double (&eps)[Cfg<K, D>::NLEAF][6]) {
+  using C = Cfg<K, D>;
+  double e[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) e[k] = E[k];
+#pragma unroll 1
+  for (int m = C::UPLEV; m >= 1; --m) {
+    const int o = 1 << (m - 1);
+    double eR[6] = {0, 0, 0, 0, 0, 0};
+    if (upper_active(cx.t, m)) {
+      const int pos = upper_pos<K, D>(m, cx.t);
+      const int u = cx.slot * C::NUPS + (pos - C::UP0);
+      const LamRow row = load_row(cx.tab, pos);
+      double aj[3], eL[6];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) aj[k] = up.a[k][u] + s * up.da[k][u];
+      laminate_localize(aj, e, row.nv, row.c1, row.c2, eL, eR);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] = eL[k];
+    }
+    double rcv[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
+    if (upper_right(cx.t, m)) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] = rcv[k];
+    }
+  }
+  loc_node<K, D, 1>(cx, st, s, e, eps);
+}
+
+// ---------------------------------------------------------------- bottom-up
+
+template <int K, int D, int H>
+__device__ __forceinline__ void up_node(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                        const double (&eps)[Cfg<K, D>::NLEAF][6],
+                                        double (&Cn)[21], double (&tn)[6], double (&sn)[6],
+                                        double& rr, int& lfail, int& spdfail) {
+  using C = Cfg<K, D>;
+  if constexpr (H >= C::NLEAF) {
+    constexpr int q = H - C::NLEAF;
+    if constexpr (q % 2 == 0) {  // fibre leaf
+      iso_stress(cx.fib, eps[q], sn);
+      iso_packed(cx.fib, Cn);
+    } else {                     // matrix leaf
+      const int mloc = cx.t * (C::NLEAF / 2) + q / 2;
+      const double* z = cx.zin + (size_t)mloc * 7;
+      double epn[6], ep[6], p;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) epn[k] = z[k];
+      const bool ok = j2_return(cx.mat, eps[q], epn, z[6], sn, Cn, ep, p);
+      lfail |= ok ? 0 : 1;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tn[k] = sn[k];
+  } else {
+    up_node<K, D, 2 * H>(cx, st, eps, Cn, tn, sn, rr, lfail, spdfail);
+    double CR[21], tR[6], sR[6];
+    up_node<K, D, 2 * H + 1>(cx, st, eps, CR, tR, sR, rr, lfail, spdfail);
+    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
+    const bool ok = laminate_newton(Cn, tn, sn, CR, tR, sR, row.nv, row.c1, row.c2, row.rf,
+                                    st.G[H - 1], st.g[H - 1], rr);
+    spdfail |= ok ? 0 : 1;
+  }
+}
+
+// Leaf laws, bottom-up condensation and per-point reductions at leaf strains
+// eps (wave-uniform: contains shuffles).
+template <int K, int D>
+__device__ __forceinline__ void evaluate_full(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                              UpperLds<K, D>& up,
+                                              const double (&eps)[Cfg<K, D>::NLEAF][6],
+                                              EvalOut& out) {
   using C = Cfg<K, D>;
   double rr = 0.0;
   int lfail = 0, spdfail = 0;
-  double cC[21], cT[6], cS[6];
-  up_node<K, D, 1>(cx, st, ev, cC, cT, cS, rr, lfail, spdfail);
-#pragma unroll
+  double cT[6];
+  up_node<K, D, 1>(cx, st, eps, out.C, cT, out.sb, rr, lfail, spdfail);
+#pragma unroll 1
   for (int m = 1; m <= C::UPLEV; ++m) {
     const int o = 1 << (m - 1);
     double rC[21], rT[6], rS[6];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) rC[k] = shfl_down_d(cC[k], o, C::LP);
+    for (int k = 0; k < 21; ++k) rC[k] = shfl_down_d(out.C[k], o, C::LP);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       rT[k] = shfl_down_d(cT[k], o, C::LP);
-      rS[k] = shfl_down_d(cS[k], o, C::LP);
+      rS[k] = shfl_down_d(out.sb[k], o, C::LP);
     }
-    if ((cx.t & (2 * o - 1)) == 0) {
+    if (upper_active(cx.t, m)) {
       const int pos = upper_pos<K, D>(m, cx.t);
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
       const LamRow row = load_row(cx.tab, pos);
-      double nC[21], nT[6], nS[6], Gu[18], gu[3];
-      bool ok = laminate_newton(cC, cT, cS, rC, rT, rS, row.nv, row.c1, row.c2, row.rf, nC, nT,
-                                nS, Gu, gu, rr);
+      double Gu[18], gu[3];
+      const bool ok = laminate_newton(out.C, cT, out.sb, rC, rT, rS, row.nv, row.c1, row.c2,
+                                      row.rf, Gu, gu, rr);
       spdfail |= ok ? 0 : 1;
 #pragma unroll
       for (int k = 0; k < 18; ++k) up.G[k][u] = Gu[k];
 #pragma unroll
       for (int k = 0; k < 3; ++k) up.g[k][u] = gu[k];
-#pragma unroll
-      for (int k = 0; k < 21; ++k) cC[k] = nC[k];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        cT[k] = nT[k];
-        cS[k] = nS[k];
-      }
     }
   }
-  // reductions over the LP lanes of each point
+  // reductions over the LP lanes of each point; broadcast of the root average
 #pragma unroll
   for (int o = 1; o < C::LP; o <<= 1) {
     rr += __shfl_xor(rr, o, C::LP);
     lfail |= __shfl_xor(lfail, o, C::LP);
     spdfail |= __shfl_xor(spdfail, o, C::LP);
   }
+  double sn2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < 21; ++k) out.C[k] = cC[k];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) out.sb[k] = cS[k];
+  for (int k = 0; k < 6; ++k) {
+    const double v = __shfl(out.sb[k], cx.base, 64);
+    sn2 += v * v;
+  }
   out.rr = rr;
+  out.sn2 = sn2;
   out.lfail = lfail;
   out.spdfail = spdfail;
 }
@@ -219,32 +278,34 @@ __device__ __forceinline__ void evaluate(const Ctx<K, D>& cx, LaneState<K, D>& s
 // ---------------------------------------------------------------- top-down
 
 template <int K, int D, int H>
-__device__ __forceinline__ void down_node(const Ctx<K, D>& cx, LaneState<K, D>& st,
+__device__ __forceinline__ void down_node(const Ctx<K, D>& cx, LaneState<K, D>& st, bool commit,
                                           const double (&e)[6]) {
   using C = Cfg<K, D>;
-  if constexpr (H >= C::NLEAF) {
-#pragma unroll
-    for (int s = 0; s < 6; ++s) st.deps[H - C::NLEAF][s] = e[s];
-  } else {
+  if constexpr (H < C::NLEAF) {
     const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
-    double eL[6], eR[6];
-    laminate_descend(st.G[H - 1], st.g[H - 1], e, row.nv, row.c1, row.c2, st.da[H - 1], eL, eR);
-    down_node<K, D, 2 * H>(cx, st, eL);
-    down_node<K, D, 2 * H + 1>(cx, st, eR);
+    double eL[6], eR[6], dah[3];
+    laminate_descend(st.G[H - 1], st.g[H - 1], e, row.nv, row.c1, row.c2, dah, eL, eR);
+    if (commit) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) st.da[H - 1][k] = dah[k];
+    }
+    down_node<K, D, 2 * H>(cx, st, commit, eL);
+    down_node<K, D, 2 * H + 1>(cx, st, commit, eR);
   }
 }
 
-// Newton direction: da for all laminates, leaf strain increments A da.
+// Newton increments da for all laminates of the points with commit set
+// (wave-uniform: contains shuffles).
 template <int K, int D>
 __device__ __forceinline__ void direction(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                          UpperLds<K, D>& up) {
+                                          UpperLds<K, D>& up, bool commit) {
   using C = Cfg<K, D>;
   double e[6] = {0, 0, 0, 0, 0, 0};  // the macro strain is fixed during Newton
-#pragma unroll
+#pragma unroll 1
   for (int m = C::UPLEV; m >= 1; --m) {
     const int o = 1 << (m - 1);
     double eR[6] = {0, 0, 0, 0, 0, 0};
-    if ((cx.t & (2 * o - 1)) == 0) {
+    if (upper_active(cx.t, m)) {
       const int pos = upper_pos<K, D>(m, cx.t);
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
       const LamRow row = load_row(cx.tab, pos);
@@ -254,79 +315,22 @@ __device__ __forceinline__ void direction(const Ctx<K, D>& cx, LaneState<K, D>& 
 #pragma unroll
       for (int k = 0; k < 3; ++k) gu[k] = up.g[k][u];
       laminate_descend(Gu, gu, e, row.nv, row.c1, row.c2, dau, eL, eR);
+      if (commit) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) up.da[k][u] = dau[k];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = eL[k];
-    }
-    double rcv[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
-    if ((cx.t & (2 * o - 1)) == o) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = rcv[k];
-    }
-  }
-  down_node<K, D, 1>(cx, st, e);
-}
-
-// ------------------------------------------------------- strain localisation
-
-template <int K, int D, int H>
-__device__ __forceinline__ void loc_node(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                         const double* __restrict__ ain, const double (&e)[6]) {
-  using C = Cfg<K, D>;
-  if constexpr (H >= C::NLEAF) {
-#pragma unroll
-    for (int s = 0; s < 6; ++s) st.eps[H - C::NLEAF][s] = e[s];
-  } else {
-    const int pos = lane_pos<K, D, H>(cx.t);
-    const LamRow row = load_row(cx.tab, pos);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) st.a[H - 1][k] = ain[(size_t)pos * 3 + k];
-    double eL[6], eR[6];
-    laminate_localize(st.a[H - 1], e, row.nv, row.c1, row.c2, eL, eR);
-    loc_node<K, D, 2 * H>(cx, st, ain, eL);
-    loc_node<K, D, 2 * H + 1>(cx, st, ain, eR);
-  }
-}
-
-// Leaf strains eps = E + A a from the stored jumps; loads the jumps.
-template <int K, int D>
-__device__ __forceinline__ void localize(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                         UpperLds<K, D>& up, const double* __restrict__ ain,
-                                         const double (&E)[6]) {
-  using C = Cfg<K, D>;
-  double e[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) e[k] = E[k];
-#pragma unroll
-  for (int m = C::UPLEV; m >= 1; --m) {
-    const int o = 1 << (m - 1);
-    double eR[6] = {0, 0, 0, 0, 0, 0};
-    if ((cx.t & (2 * o - 1)) == 0) {
-      const int pos = upper_pos<K, D>(m, cx.t);
-      const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row(cx.tab, pos);
-      double au[3], eL[6];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        au[k] = ain[(size_t)pos * 3 + k];
-        up.a[k][u] = au[k];
+        for (int k = 0; k < 3; ++k) up.da[k][u] = dau[k];
       }
-      laminate_localize(au, e, row.nv, row.c1, row.c2, eL, eR);
 #pragma unroll
       for (int k = 0; k < 6; ++k) e[k] = eL[k];
     }
     double rcv[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
-    if ((cx.t & (2 * o - 1)) == o) {
+    if (upper_right(cx.t, m)) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) e[k] = rcv[k];
     }
   }
-  loc_node<K, D, 1>(cx, st, ain, e);
+  down_node<K, D, 1>(cx, st, commit, e);
 }
 
 // ---------------------------------------------------------------- outputs
@@ -344,16 +348,17 @@ __device__ __forceinline__ void write_lane_a(const LaneState<K, D>& st, int t, b
   }
 }
 
-// Write the point's outputs.  ok: converged (z recomputed at the accepted
-// strains); otherwise the input state is copied through and the tangent is NaN.
+// Write the point's outputs.  ok: converged (z from the J2 return at the
+// accepted strains eps); otherwise the input state is copied through and the
+// tangent is NaN.  No shuffles: runs under per-point control flow.
 template <int K, int D>
 __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K, D>& st,
                                          const UpperLds<K, D>& up, const GroupArgs& G,
-                                         long long pt, const EvalOut& ev, int status, int iters) {
+                                         long long pt, const double (&eps)[Cfg<K, D>::NLEAF][6],
+                                         const EvalOut& ev, int status, int iters) {
   using C = Cfg<K, D>;
   const bool ok = status == 0;
   const int t = cx.t;
-  // internal variables of this lane's matrix leaves
   double* zout = G.z_out + (size_t)pt * C::M * 7;
 #pragma unroll
   for (int q = 1; q < C::NLEAF; q += 2) {
@@ -363,35 +368,33 @@ __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K,
     if (ok) {
       double epn[6], ep[6], p, sg[6], Dp[21];
 #pragma unroll
-      for (int s = 0; s < 6; ++s) epn[s] = z[s];
-      j2_return(cx.mat, st.eps[q], epn, z[6], sg, Dp, ep, p);
+      for (int k = 0; k < 6; ++k) epn[k] = z[k];
+      j2_return(cx.mat, eps[q], epn, z[6], sg, Dp, ep, p);
 #pragma unroll
-      for (int s = 0; s < 6; ++s) zo[s] = ep[s];
+      for (int k = 0; k < 6; ++k) zo[k] = ep[k];
       zo[6] = p;
     } else {
 #pragma unroll
-      for (int s = 0; s < 7; ++s) zo[s] = z[s];
+      for (int k = 0; k < 7; ++k) zo[k] = z[k];
     }
   }
-  // jumps of the lane subtree
   const double* ain = G.a_in + (size_t)pt * C::L * 3;
   double* aout = G.a_out + (size_t)pt * C::L * 3;
   write_lane_a<K, D, 1>(st, t, ok, ain, aout);
-  // jumps of the upper laminates computed by this lane
-#pragma unroll
+#pragma unroll 1
   for (int m = 1; m <= C::UPLEV; ++m) {
-    const int o = 1 << (m - 1);
-    if ((t & (2 * o - 1)) == 0) {
+    if (upper_active(t, m)) {
       const int pos = upper_pos<K, D>(m, t);
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) aout[(size_t)pos * 3 + k] = ok ? up.a[k][u] : ain[(size_t)pos * 3 + k];
+      for (int k = 0; k < 3; ++k)
+        aout[(size_t)pos * 3 + k] = ok ? up.a[k][u] : ain[(size_t)pos * 3 + k];
     }
   }
   if (t == 0) {
     double* sg = G.sigma + (size_t)pt * 6;
 #pragma unroll
-    for (int s = 0; s < 6; ++s) sg[s] = ev.sb[s];
+    for (int k = 0; k < 6; ++k) sg[k] = ev.sb[k];
     double* tg = G.tangent + (size_t)pt * 36;
     const double nan = __builtin_nan("");
 #pragma unroll
@@ -419,6 +422,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   Ctx<K, D> cx;
   cx.slot = lane / C::LP;
   cx.t = lane % C::LP;
+  cx.base = cx.slot * C::LP;
   cx.tab = G.tab;
   cx.fib = args.fib;
   cx.mat = args.mat;
@@ -430,121 +434,128 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
 
   LaneState<K, D> st;
   EvalOut ev;
+  double eps[C::NLEAF][6];
   double E[6];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) E[s] = G.E[(size_t)pt * 6 + s];
+  for (int k = 0; k < 6; ++k) E[k] = G.E[(size_t)pt * 6 + k];
 
-  int status = 0, iters = 0;
-  bool done = !in_range;
-  if (*G.flag != 0) {  // invalid DMN parameters: every point of the group fails
-#pragma unroll
-    for (int k = 0; k < 21; ++k) ev.C[k] = 0.0;
-#pragma unroll
-    for (int s = 0; s < 6; ++s) ev.sb[s] = __builtin_nan("");
-    if (in_range) finalize(cx, st, up, G, pt, ev, DMN_STATUS_BADPARAM, 0);
-    return;
-  }
-
-  // non-finite inputs of the point
+  // load the jumps and check the inputs of the point for non-finite values
   int bad = 0;
 #pragma unroll
-  for (int s = 0; s < 6; ++s) bad |= isfinite(E[s]) ? 0 : 1;
-  for (int q = 0; q < C::NLEAF / 2 * 7; ++q) bad |= isfinite(cx.zin[(size_t)cx.t * (C::NLEAF / 2) * 7 + q]) ? 0 : 1;
-  localize(cx, st, up, ain, E);
+  for (int k = 0; k < 6; ++k) bad |= isfinite(E[k]) ? 0 : 1;
 #pragma unroll
-  for (int h = 0; h < C::NLAM; ++h)
+  for (int q = 0; q < C::NLEAF / 2 * 7; ++q)
+    bad |= isfinite(cx.zin[(size_t)cx.t * (C::NLEAF / 2) * 7 + q]) ? 0 : 1;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) bad |= isfinite(st.a[h][k]) ? 0 : 1;
+  for (int h = 1; h <= C::NLAM; ++h) {
+    const int m = ilog2(h);
+    const int k = K - D + 1 + m;
+    const int pos = (1 << K) - (1 << k) + cx.t * (1 << m) + (h - (1 << m));
 #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      st.a[h - 1][c] = ain[(size_t)pos * 3 + c];
+      st.da[h - 1][c] = 0.0;
+      bad |= isfinite(st.a[h - 1][c]) ? 0 : 1;
+    }
+  }
+#pragma unroll 1
   for (int m = 1; m <= C::UPLEV; ++m) {
-    const int o = 1 << (m - 1);
-    if ((cx.t & (2 * o - 1)) == 0) {
-      const int u = cx.slot * C::NUPS + (upper_pos<K, D>(m, cx.t) - C::UP0);
+    if (upper_active(cx.t, m)) {
+      const int pos = upper_pos<K, D>(m, cx.t);
+      const int u = cx.slot * C::NUPS + (pos - C::UP0);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) bad |= isfinite(up.a[k][u]) ? 0 : 1;
+      for (int c = 0; c < 3; ++c) {
+        const double v = ain[(size_t)pos * 3 + c];
+        up.a[c][u] = v;
+        up.da[c][u] = 0.0;
+        bad |= isfinite(v) ? 0 : 1;
+      }
     }
   }
 #pragma unroll
   for (int o = 1; o < C::LP; o <<= 1) bad |= __shfl_xor(bad, o, C::LP);
 
-  evaluate(cx, st, up, st.eps, ev);
-  if (bad && !done) {
-    finalize(cx, st, up, G, pt, ev, DMN_STATUS_NONFINITE, 0);
-    done = true;
+  if (*G.flag != 0) {  // invalid DMN parameters: every point of the group fails
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ev.sb[k] = __builtin_nan("");
+    if (in_range) finalize(cx, st, up, G, pt, eps, ev, DMN_STATUS_BADPARAM, 0);
+    return;
   }
 
   const double scale = args.tol * (double)C::L;
-  const int base = cx.slot * C::LP;
-  double rn = 0.0;
+  int status = 0, iters = 0, bt = 0;
+  bool done = !in_range;
+  bool first = true;
+  double s = 0.0, rn = 0.0;
+#pragma unroll 1
   while (true) {
+    localize(cx, st, up, E, done ? 0.0 : s, eps);
+    evaluate_full(cx, st, up, eps, ev);
+    bool just_done = false, need_dir = false;
     if (!done) {
-      double sb0 = 0.0;
-      double sn2 = 0.0;
-#pragma unroll
-      for (int s = 0; s < 6; ++s) {
-        sb0 = __shfl(ev.sb[s], base, 64);
-        sn2 += sb0 * sb0;
-      }
-      const double sn = sqrt(sn2);
-      rn = sqrt(ev.rr);
-      int fin = -1;
-      if (ev.lfail) fin = DMN_STATUS_LOCAL;
-      else if (!isfinite(rn) || !isfinite(sn)) fin = DMN_STATUS_NONFINITE;
-      else if (rn == 0.0 || rn <= scale * sn) fin = ev.spdfail ? DMN_STATUS_NOTSPD : 0;
-      else if (iters >= args.max_iter) fin = DMN_STATUS_MAXITER;
-      else if (ev.spdfail) fin = DMN_STATUS_NOTSPD;
-      if (fin >= 0) {
-        status = fin;
-        done = true;
-        finalize(cx, st, up, G, pt, ev, status, iters);
-      }
-    }
-    if (!__any(!done)) break;
-    direction(cx, st, up);
-    double s = 1.0;
-    bool pending = !done;
-    for (int bt = 0; bt <= args.max_bt; ++bt) {
-      const double sp = pending ? s : 0.0;
-      double et[C::NLEAF][6];
-#pragma unroll
-      for (int q = 0; q < C::NLEAF; ++q)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) et[q][k] = st.eps[q][k] + sp * st.deps[q][k];
-      evaluate(cx, st, up, et, ev);
-      if (pending) {
-        double sn2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const double v = __shfl(ev.sb[k], base, 64);
-          sn2 += v * v;
+      bool accepted = false;
+      if (first) {
+        first = false;
+        accepted = true;
+        if (bad) {
+          status = DMN_STATUS_NONFINITE;
+          just_done = true;
         }
+      } else {
         const double rt = sqrt(ev.rr);
-        const bool good = isfinite(rt) && isfinite(sn2) && !ev.lfail;
-        if ((good && rt <= (1.0 - args.armijo * s) * rn) || bt == args.max_bt) {
-#pragma unroll
-          for (int q = 0; q < C::NLEAF; ++q)
-#pragma unroll
-            for (int k = 0; k < 6; ++k) st.eps[q][k] = et[q][k];
+        const bool good = isfinite(rt) && isfinite(ev.sn2) && !ev.lfail;
+        if ((good && rt <= (1.0 - args.armijo * s) * rn) || bt >= args.max_bt) {
 #pragma unroll
           for (int h = 0; h < C::NLAM; ++h)
 #pragma unroll
             for (int k = 0; k < 3; ++k) st.a[h][k] += s * st.da[h][k];
-#pragma unroll
+#pragma unroll 1
           for (int m = 1; m <= C::UPLEV; ++m) {
-            const int o = 1 << (m - 1);
-            if ((cx.t & (2 * o - 1)) == 0) {
+            if (upper_active(cx.t, m)) {
               const int u = cx.slot * C::NUPS + (upper_pos<K, D>(m, cx.t) - C::UP0);
 #pragma unroll
               for (int k = 0; k < 3; ++k) up.a[k][u] += s * up.da[k][u];
             }
           }
           ++iters;
-          pending = false;
+          accepted = true;
         } else {
           s *= 0.5;
+          ++bt;
         }
       }
-      if (!__any(pending)) break;
+      if (accepted && !just_done) {
+        rn = sqrt(ev.rr);
+        const double sn = sqrt(ev.sn2);
+        int fin = -1;
+        if (ev.lfail) fin = DMN_STATUS_LOCAL;
+        else if (!isfinite(rn) || !isfinite(sn)) fin = DMN_STATUS_NONFINITE;
+        else if (rn == 0.0 || rn <= scale * sn) fin = ev.spdfail ? DMN_STATUS_NOTSPD : 0;
+        else if (iters >= args.max_iter) fin = DMN_STATUS_MAXITER;
+        else if (ev.spdfail) fin = DMN_STATUS_NOTSPD;
+        if (fin >= 0) {
+          status = fin;
+          just_done = true;
+        } else {
+          need_dir = true;
+        }
+      }
+    }
+    if (__any(just_done)) {
+      // strains at the accepted jumps, for the internal variables of finished points
+      localize(cx, st, up, E, 0.0, eps);
+      if (just_done) {
+        finalize(cx, st, up, G, pt, eps, ev, status, iters);
+        done = true;
+      }
+    }
+    if (!__any(!done)) break;
+    if (__any(need_dir)) {
+      direction(cx, st, up, need_dir);
+      if (need_dir) {
+        s = 1.0;
+        bt = 0;
+      }
     }
   }
 }
