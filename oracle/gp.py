@@ -45,21 +45,30 @@ class NewtonOptions:
     max_iter: int = 25
     max_backtrack: int = 10
     armijo: float = 1e-4
+    # extra full Newton steps after the stop test is met (complex-step runs: the
+    # imaginary part of an iterate is the derivative at the previous iterate, so
+    # one more step makes it the derivative at the converged jumps)
+    polish: int = 0
 
 
 class DmnModel:
-    """A depth-K DMN with its phase laws, holding the explicit gradient operator."""
+    """A depth-K DMN with its phase laws, holding the explicit gradient operator.
+
+    Weights and normals may be complex (complex-step differentiation): every
+    decision is then taken on real parts and linear systems are solved without
+    conjugation."""
 
     def __init__(self, K, w, normals, fiber, matrix):
         self.K = K
         self.nL = 2 ** K
         self.L = 2 ** K - 1
-        self.w = np.asarray(w, dtype=np.float64)
-        self.normals = np.asarray(normals, dtype=np.float64)
-        self.valid = bool(np.all(self.w >= 0.0))
+        self.w = np.asarray(w)
+        self.normals = np.asarray(normals)
+        self.dtype = np.result_type(self.w, self.normals, 1.0)
+        self.valid = bool(np.all(np.real(self.w) >= 0.0))
         for (k, i) in laminates(K):
             lo, hi = lam_leaves(K, k, i)
-            if not self.w[lo:hi].sum() > 0.0:
+            if not np.real(self.w[lo:hi].sum()) > 0.0:
                 self.valid = False
         self.wt = self.w / self.w.sum() if self.valid else None
         self.A = gradient_operator(K, self.w, self.normals) if self.valid else None
@@ -70,9 +79,10 @@ class DmnModel:
     def evaluate(self, E, z_n, a):
         """Leaf strains, stresses, tangents and the residual at jumps a."""
         eps = E[None, :] + (self.A @ a).reshape(self.nL, 6)
-        sig = np.zeros((self.nL, 6))
-        D = np.zeros((self.nL, 6, 6))
-        z = np.array(z_n, dtype=np.float64, copy=True)
+        dt = np.result_type(self.dtype, eps, z_n)
+        sig = np.zeros((self.nL, 6), dtype=dt)
+        D = np.zeros((self.nL, 6, 6), dtype=dt)
+        z = np.array(z_n, dtype=dt, copy=True)
         margin = np.inf
         local_ok = True
         for j in range(self.nL):
@@ -97,12 +107,20 @@ class DmnModel:
         H = (self.A.T @ (WD @ self.A)).toarray()
         return H, WD
 
+    def solve(self, H, rhs):
+        """H^-1 rhs with a Cholesky factorisation of (the real part of) H; raises
+        LinAlgError when H is not positive definite.  Complex H (complex step) is
+        solved by LU without conjugation."""
+        cho = sla.cho_factor(np.real(H), lower=True)
+        if np.iscomplexobj(H) or np.iscomplexobj(rhs):
+            return np.linalg.solve(H, rhs)
+        return sla.cho_solve(cho, rhs)
+
     def tangent(self, D):
         """Algorithmic tangent of Sec. 3.2 at the given leaf tangents."""
         H, WD = self.hessian(D)
         rhs = -(self.A.T @ (WD @ self.B))
-        cho = sla.cho_factor(H, lower=True)
-        X = sla.cho_solve(cho, rhs)
+        X = self.solve(H, rhs)
         return self.B.T @ (WD @ (self.B + self.A @ X))
 
 
@@ -117,9 +135,9 @@ def gp_update(model: DmnModel, E, z_n, a_n, opts: NewtonOptions = NewtonOptions(
     matrix leaves (plastic strain in Mandel, then p); a_n: [3L] jumps in
     paper order.  Returns dict(sigma, C, z, a, iters, status, margin).
     """
-    E = np.asarray(E, dtype=np.float64)
-    z_n = np.asarray(z_n, dtype=np.float64)
-    a_n = np.asarray(a_n, dtype=np.float64)
+    E = np.asarray(E)
+    z_n = np.asarray(z_n)
+    a_n = np.asarray(a_n)
     fail = dict(sigma=np.full(6, np.nan), C=np.full((6, 6), np.nan), z=z_n.copy(),
                 a=a_n.copy(), iters=0, margin=np.inf)
     if not model.valid:
@@ -132,6 +150,7 @@ def gp_update(model: DmnModel, E, z_n, a_n, opts: NewtonOptions = NewtonOptions(
     margin = ev["margin"]
     iters = 0
     status = OK
+    polish = opts.polish
     while True:
         if not ev["local_ok"]:
             status = LOCALFAIL
@@ -141,17 +160,22 @@ def gp_update(model: DmnModel, E, z_n, a_n, opts: NewtonOptions = NewtonOptions(
             break
         rn = np.linalg.norm(ev["r"])
         if rn == 0.0 or rn <= scale * np.linalg.norm(ev["sbar"]):
-            break
+            if polish == 0:
+                break
+            polish -= 1
+            H, _ = model.hessian(ev["D"])
+            a = a - model.solve(H, ev["r"])
+            ev = model.evaluate(E, z_n, a)
+            continue
         if iters == opts.max_iter:
             status = MAXITER
             break
         H, _ = model.hessian(ev["D"])
         try:
-            cho = sla.cho_factor(H, lower=True)
+            da = -model.solve(H, ev["r"])
         except np.linalg.LinAlgError:
             status = NOTSPD
             break
-        da = -sla.cho_solve(cho, ev["r"])
         s = 1.0
         for bt in range(opts.max_backtrack + 1):
             trial = model.evaluate(E, z_n, a + s * da)
@@ -177,8 +201,8 @@ def gp_update(model: DmnModel, E, z_n, a_n, opts: NewtonOptions = NewtonOptions(
 def run_path(model, E_path, opts=NewtonOptions(), z0=None, a0=None):
     """Apply a macro strain path E_path [T, 6] from the initial state z = 0, a = 0."""
     M = model.nL // 2
-    z = np.zeros((M, 7)) if z0 is None else z0
-    a = np.zeros(3 * model.L) if a0 is None else a0
+    z = np.zeros((M, 7), dtype=model.dtype) if z0 is None else z0
+    a = np.zeros(3 * model.L, dtype=model.dtype) if a0 is None else a0
     outs = []
     for E in E_path:
         out = gp_update(model, E, z, a, opts)

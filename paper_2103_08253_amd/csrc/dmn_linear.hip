@@ -314,12 +314,12 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
     }
     __syncthreads();  // nodeC is rewritten by the next sample group
   }
-  // partial sums of this wave slot: [slot][pos][4]
+  // partial sums of this wave slot, stored [pos * 4 + c][slot]
   const size_t pslot = (size_t)blockIdx.x * C::PPW + slot;
-  double* P = partials + pslot * C::L * 4;
+  const size_t nslots = (size_t)gridDim.x * C::PPW;
   auto put = [&](int pos, const double* v) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) P[(size_t)pos * 4 + c] = v[c];
+    for (int c = 0; c < 4; ++c) partials[((size_t)pos * 4 + c) * nslots + pslot] = v[c];
   };
   [&] {
     if constexpr (C::NLAM >= 1) {
@@ -348,15 +348,24 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
   if (lane == 0 && (fail || *flag)) atomicOr(err, (*flag ? 1 : 0) | (fail ? 2 : 0));
 }
 
-// Sum the partials over wave slots in a fixed order: gsum[pos][4].
+// Sum the partials over wave slots in a fixed order: one workgroup per
+// (laminate, component) row; each thread sums a strided subset, then a
+// fixed-shape tree in LDS.  gsum[pos * 4 + c].
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials,
                                                               long long nslots, int L4,
                                                               double* __restrict__ gsum) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L4) return;
+  __shared__ double part[256];
+  const int i = blockIdx.x;
+  const double* row = partials + (size_t)i * nslots;
   double s = 0.0;
-  for (long long q = 0; q < nslots; ++q) s += partials[(size_t)q * L4 + i];
-  gsum[i] = s;
+  for (long long q = threadIdx.x; q < nslots; q += blockDim.x) s += row[q];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && i < L4) gsum[i] = part[0];
 }
 
 // Leaf-weight and normal gradients from the per-laminate sums: a leaf
@@ -387,7 +396,7 @@ __global__ __launch_bounds__(256) void finish_grads_kernel(const double* __restr
   }
 }
 
-constexpr int kMaxBwdWaves = 1024;
+constexpr int kMaxBwdWaves = 2048;
 
 }  // namespace
 
@@ -454,7 +463,7 @@ static int bwd_k(const void* tab, const int32_t* flag, long long B, const void* 
                      (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar, (T*)gC1,
                      (T*)gC2, partials, err);
   const int L4 = C::L * 4;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((L4 + 255) / 256), dim3(256), 0, s,
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(L4), dim3(256), 0, s,
                      (const double*)partials, nslots, L4, gsum);
   const int nleaf = 1 << K;
   hipLaunchKernelGGL((finish_grads_kernel<T>), dim3((nleaf + 255) / 256), dim3(256), 0, s,

@@ -8,8 +8,8 @@
 //   rfac = W_L W_R / ((W_L + W_R) sum(w))  (scale of the laminate's block of A^T W sigma)
 //   dc1/dW_L = W_R / W^2, dc1/dW_R = -W_L / W^2
 // and flags the DMN as invalid when a weight is negative or not finite, or a
-// laminate's children carry no weight.  Subtree sums run sequentially over
-// the leaves, so the table is bit-identical run to run.
+// laminate's children carry no weight.  Subtree sums are formed pairwise in
+// a fixed order, so the table is bit-identical run to run.
 #include "dmn_internal.hpp"
 
 namespace dmn {
@@ -20,41 +20,48 @@ __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, cons
                                                    int K, T* __restrict__ tab,
                                                    int32_t* __restrict__ flag,
                                                    int32_t* __restrict__ err) {
+  // node sums of the whole tree in LDS, heap order: node 1 = root, leaves at
+  // 2^K ... 2^(K+1)-1; each internal node is the sum of its two children
+  __shared__ T W[2 << DMN_MAX_DEPTH];
   __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
   const int nleaf = 1 << K;
   const int L = nleaf - 1;
-  T wtot = T(0);
-  for (int j = 0; j < nleaf; ++j) wtot += w[j];
+  if (threadIdx.x == 0) bad = 0;
   int mybad = 0;
-  for (int j = threadIdx.x; j < nleaf; j += blockDim.x)
-    if (!(w[j] >= T(0)) || !isfinite(w[j])) mybad = 1;
+  for (int j = threadIdx.x; j < nleaf; j += blockDim.x) {
+    const T v = w[j];
+    if (!(v >= T(0)) || !isfinite(v)) mybad = 1;
+    W[nleaf + j] = v;
+  }
+  __syncthreads();
+  for (int k = K; k >= 1; --k) {  // heap level k holds 2^(k-1) laminates
+    const int first = 1 << (k - 1);
+    for (int h = first + threadIdx.x; h < 2 * first; h += blockDim.x)
+      W[h] = W[2 * h] + W[2 * h + 1];
+    __syncthreads();
+  }
+  const T wtot = W[1];
   for (int pos = threadIdx.x; pos < L; pos += blockDim.x) {
-    // level k and 1-based index i of the laminate at paper position pos
+    // level k and 0-based index i0 of the laminate at paper position pos
     int k = K, base = 0;
     while (pos >= base + (1 << (k - 1))) {
       base += 1 << (k - 1);
       --k;
     }
-    const int i0 = pos - base;           // 0-based index within level k
-    const int span = 1 << (K - k + 1);   // leaves below the laminate
-    const int lo = i0 * span, mid = lo + span / 2, hi = lo + span;
-    T WL = T(0), WR = T(0);
-    for (int j = lo; j < mid; ++j) WL += w[j];
-    for (int j = mid; j < hi; ++j) WR += w[j];
-    const T W = WL + WR;
-    if (!(W > T(0))) mybad = 1;
+    const int h = (1 << (k - 1)) + (pos - base);  // heap index
+    const T WL = W[2 * h], WR = W[2 * h + 1];
+    const T Wn = WL + WR;
+    if (!(Wn > T(0))) mybad = 1;
     T* r = tab + (size_t)pos * kTabStride;
-    const T c1 = WL / W;
+    const T c1 = WL / Wn;
     r[0] = c1;
     r[1] = T(1) - c1;
     r[2] = n[(size_t)pos * 3 + 0];
     r[3] = n[(size_t)pos * 3 + 1];
     r[4] = n[(size_t)pos * 3 + 2];
-    r[5] = WL * WR / (W * wtot);
-    r[6] = WR / (W * W);
-    r[7] = -WL / (W * W);
+    r[5] = WL * WR / (Wn * wtot);
+    r[6] = WR / (Wn * Wn);
+    r[7] = -WL / (Wn * Wn);
   }
   if (mybad) atomicOr(&bad, 1);
   __syncthreads();
