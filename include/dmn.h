@@ -182,6 +182,50 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                             const dmn_newton_opts* opts, void* ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/* One batch of points for the load-step adjoint.  With M = 2^(K-1), L = 2^K - 1
+ * (FP64, point-major, device memory):
+ *   E        [P][6]     macro strain of the step
+ *   z_in     [P][M][7]  internal variables entering the step (z^n)
+ *   a_conv   [P][L][3]  converged jumps of the step (a^{n+1}, as returned by
+ *                       dmn_update_gauss_points from the same inputs)
+ *   g_sigma  [P][6]     cotangent of the step's effective stress, or NULL (zero)
+ *   g_z_next [P][M][7]  cotangent of the step's new internal variables z^{n+1},
+ *                       or NULL (zero)
+ *   g_z_prev [P][M][7]  out: cotangent of z_in
+ *   gw [2^K], gn [L][3] accumulated (+=): cotangents of the DMN's leaf weights
+ *                       and normals (n as passed), summed over the points */
+typedef struct dmn_adjoint_group {
+  dmn_net net;
+  int64_t P;
+  const void* E;
+  const void* z_in;
+  const void* a_conv;
+  const void* g_sigma;
+  const void* g_z_next;
+  void* g_z_prev;
+  void* gw;
+  void* gn;
+} dmn_adjoint_group;
+
+/* Workspace bytes for dmn_update_adjoint. */
+size_t dmn_update_adjoint_workspace_size(const dmn_adjoint_group* groups, int32_t n_groups,
+                                         int prec);
+
+/* Reverse-mode sensitivity of one Newton-converged load step (implicit-function
+ * adjoint of the Euler-Lagrange equation of Sec. 3.2): given the cotangents of
+ * the step's outputs (effective stress, new internal variables), accumulate the
+ * cotangents of the DMN parameters and return the cotangent of the internal
+ * variables entering the step.  Chaining calls backwards over the steps of a
+ * load path (with the states of the forward path, e.g. recomputed from
+ * checkpoints) gives the gradient of any function of the path's stresses.
+ * The leaf laws are re-evaluated at (E, z_in, a_conv); a_conv must be the
+ * converged jumps for those inputs.  Batch sums use a fixed reduction order.
+ * prec: DMN_F64.  An invalid DMN, a non-SPD pivot or a failed J2 return set
+ * bits 1, 2, 4 of the device error word at the start of the workspace. */
+int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
+                       const dmn_elastic* fiber, const dmn_j2* matrix, int prec, void* ws,
+                       size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

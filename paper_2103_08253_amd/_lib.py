@@ -41,6 +41,13 @@ class DmnPointGroup(ctypes.Structure):
                 ("iters", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
+class DmnAdjointGroup(ctypes.Structure):
+    _fields_ = [("net", DmnNet), ("P", ctypes.c_int64),
+                ("E", ctypes.c_void_p), ("z_in", ctypes.c_void_p), ("a_conv", ctypes.c_void_p),
+                ("g_sigma", ctypes.c_void_p), ("g_z_next", ctypes.c_void_p),
+                ("g_z_prev", ctypes.c_void_p), ("gw", ctypes.c_void_p), ("gn", ctypes.c_void_p)]
+
+
 # exported functions and their signatures
 _SIGS = {
     "dmn_version": (ctypes.c_char_p, []),
@@ -60,6 +67,12 @@ _SIGS = {
                                                ctypes.POINTER(DmnElastic), ctypes.POINTER(DmnJ2),
                                                ctypes.c_int, ctypes.POINTER(DmnNewtonOpts),
                                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dmn_update_adjoint_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(DmnAdjointGroup),
+                                                            ctypes.c_int32, ctypes.c_int]),
+    "dmn_update_adjoint": (ctypes.c_int, [ctypes.POINTER(DmnAdjointGroup), ctypes.c_int32,
+                                          ctypes.POINTER(DmnElastic), ctypes.POINTER(DmnJ2),
+                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_void_p]),
 }
 
 _lib = None

@@ -186,3 +186,53 @@ def dmn_update_gauss_points(groups: List[PointGroup], fiber: dict, matrix: dict,
                                      _stream())
     L.check(rc, "dmn_update_gauss_points")
     return ws
+
+
+@dataclass
+class AdjointGroup:
+    """Device arrays of one batch of points for dmn_update_adjoint (include/dmn.h)."""
+    w: torch.Tensor
+    n: torch.Tensor
+    E: torch.Tensor
+    z_in: torch.Tensor
+    a_conv: torch.Tensor
+    g_sigma: Optional[torch.Tensor]
+    g_z_next: Optional[torch.Tensor]
+    g_z_prev: torch.Tensor
+    gw: torch.Tensor
+    gn: torch.Tensor
+
+    def to_c(self):
+        net, K = _net(self.w, self.n, torch.float64)
+        P = self.E.shape[0]
+        M, Lm = 2 ** (K - 1), 2 ** K - 1
+        _need(self.E, "E", torch.float64, (P, 6))
+        _need(self.z_in, "z_in", torch.float64, (P, M, 7))
+        _need(self.a_conv, "a_conv", torch.float64, (P, Lm, 3))
+        _need(self.g_z_prev, "g_z_prev", torch.float64, (P, M, 7))
+        if self.g_sigma is not None:
+            _need(self.g_sigma, "g_sigma", torch.float64, (P, 6))
+        if self.g_z_next is not None:
+            _need(self.g_z_next, "g_z_next", torch.float64, (P, M, 7))
+        _need(self.gw, "gw", torch.float64, (2 ** K,))
+        _need(self.gn, "gn", torch.float64, (Lm, 3))
+        ptr = lambda t: None if t is None else t.data_ptr()
+        return L.DmnAdjointGroup(net, P, self.E.data_ptr(), self.z_in.data_ptr(),
+                                 self.a_conv.data_ptr(), ptr(self.g_sigma), ptr(self.g_z_next),
+                                 self.g_z_prev.data_ptr(), self.gw.data_ptr(), self.gn.data_ptr())
+
+
+def dmn_update_adjoint(groups: List[AdjointGroup], fiber: dict, matrix: dict, ws=None):
+    """Adjoint of one converged load step for every group; gw, gn accumulate (+=)."""
+    arr = (L.DmnAdjointGroup * len(groups))(*[g.to_c() for g in groups])
+    fib, mat = _materials(fiber, matrix)
+    lib = L.lib()
+    nbytes = lib.dmn_update_adjoint_workspace_size(arr, len(groups), L.DMN_F64)
+    if nbytes == 0:
+        raise L.DmnError("dmn_update_adjoint_workspace_size rejected the groups")
+    if ws is None or ws.numel() < nbytes:
+        ws = workspace(nbytes, groups[0].E.device)
+    rc = lib.dmn_update_adjoint(arr, len(groups), ctypes.byref(fib), ctypes.byref(mat),
+                                L.DMN_F64, _ptr(ws), ws.numel(), _stream())
+    L.check(rc, "dmn_update_adjoint")
+    return ws

@@ -17,8 +17,7 @@ inline size_t elt_size(int prec) { return prec == DMN_F32 ? sizeof(float) : size
 // Workspace layout: [header 256 B: int32 error word at 0]
 //                   then per table: [flag 256 B][rows L x 8 elements, aligned]
 inline size_t table_bytes(int depth, int prec) {
-  const size_t L = ((size_t)1 << depth) - 1;
-  return kAlign + align_up(L * dmn::kTabStride * elt_size(prec));
+  return kAlign + align_up(dmn::table_elems(depth) * elt_size(prec));
 }
 
 inline bool depth_ok(int32_t d) { return d >= 1 && d <= DMN_MAX_DEPTH; }
@@ -203,6 +202,83 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
     }
     if (blocks > 0x7fffffff) return DMN_EINVAL;
     if (dmn::launch_gp_update(K, lp, args, (int)blocks, stream)) return DMN_EHIP;
+  }
+  return DMN_OK;
+}
+
+static size_t adjoint_group_bytes(const dmn_adjoint_group& g) {
+  const size_t K = g.net.depth;
+  const size_t rows = 4 * (((size_t)1 << K) - 1) + ((size_t)1 << K);
+  const size_t slots = (size_t)dmn::adjoint_partial_slots((int)K, g.P);
+  return table_bytes((int)K, DMN_F64) + align_up(rows * sizeof(double)) +
+         align_up(rows * slots * sizeof(double));
+}
+
+size_t dmn_update_adjoint_workspace_size(const dmn_adjoint_group* groups, int32_t n_groups,
+                                         int prec) {
+  if (!groups || n_groups < 1 || n_groups > 64 || prec != DMN_F64) return 0;
+  size_t total = kAlign;
+  for (int i = 0; i < n_groups; ++i) {
+    if (!depth_ok(groups[i].net.depth) || groups[i].P < 0) return 0;
+    total += adjoint_group_bytes(groups[i]);
+  }
+  return total;
+}
+
+int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
+                       const dmn_elastic* fiber, const dmn_j2* matrix, int prec, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  if (!groups || n_groups < 1 || n_groups > 64) return DMN_EINVAL;
+  if (prec != DMN_F64) return DMN_EUNSUPPORTED;
+  if (!phase_ok(fiber) || !j2_ok(matrix)) return DMN_EINVAL;
+  for (int i = 0; i < n_groups; ++i) {
+    const dmn_adjoint_group& g = groups[i];
+    if (!depth_ok(g.net.depth) || g.P < 0 || !g.net.w || !g.net.n || !g.gw || !g.gn)
+      return DMN_EINVAL;
+    if (g.P > 0 && (!g.E || !g.z_in || !g.a_conv || !g.g_z_prev)) return DMN_EINVAL;
+    if (g.P > 0 && g.g_z_next != nullptr && g.g_z_next == g.g_z_prev) return DMN_EINVAL;
+  }
+  const size_t need = dmn_update_adjoint_workspace_size(groups, n_groups, prec);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
+  int32_t* err = (int32_t*)ws;
+  size_t off = kAlign;
+  for (int i = 0; i < n_groups; ++i) {
+    const dmn_adjoint_group& g = groups[i];
+    const int K = g.net.depth;
+    const size_t rows = 4 * (((size_t)1 << K) - 1) + ((size_t)1 << K);
+    Table tb = table_at(ws, off);
+    double* gsum = (double*)((char*)ws + off + table_bytes(K, DMN_F64));
+    double* partials = (double*)((char*)gsum + align_up(rows * sizeof(double)));
+    off += adjoint_group_bytes(g);
+    if (dmn::launch_prep_tables(g.net.w, g.net.n, K, DMN_F64, tb.rows, tb.flag,
+                                i == 0 ? err : nullptr, stream))
+      return DMN_EHIP;
+    if (g.P == 0) continue;
+    dmn::AdjointLaunch a;
+    memset(&a, 0, sizeof(a));
+    a.E = (const double*)g.E;
+    a.z_in = (const double*)g.z_in;
+    a.a_conv = (const double*)g.a_conv;
+    a.g_sigma = (const double*)g.g_sigma;
+    a.g_z_next = (const double*)g.g_z_next;
+    a.g_z_prev = (double*)g.g_z_prev;
+    a.tab = (const double*)tb.rows;
+    a.flag = tb.flag;
+    a.partials = partials;
+    a.gsum = gsum;
+    a.gw = (double*)g.gw;
+    a.gn = (double*)g.gn;
+    a.err = err;
+    a.P = g.P;
+    a.fib.K = fiber->E / (3.0 * (1.0 - 2.0 * fiber->nu));
+    a.fib.G = fiber->E / (2.0 * (1.0 + fiber->nu));
+    a.mat.K = matrix->E / (3.0 * (1.0 - 2.0 * matrix->nu));
+    a.mat.G = matrix->E / (2.0 * (1.0 + matrix->nu));
+    a.mat.sigma0 = matrix->sigma0;
+    a.mat.k_inf = matrix->k_inf;
+    a.mat.dsigma = matrix->dsigma;
+    a.mat.b = matrix->b;
+    if (dmn::launch_adjoint(K, a, stream)) return DMN_EHIP;
   }
   return DMN_OK;
 }

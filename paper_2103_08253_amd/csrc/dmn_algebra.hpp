@@ -503,4 +503,120 @@ __device__ __forceinline__ bool j2_return(const J2Law& m, const double eps[6], c
   return ok;
 }
 
+
+// Vector-Jacobian product of the J2 return mapping (j2_return).  Given the
+// cotangents psi of the stress and zeta = (zeta_e, zeta_p) of the new internal
+// variables (plastic strain, p), returns the cotangents of the strain (geps)
+// and of the old internal variables (gz = (gz_e, gz_p)).  The forward state is
+// recomputed.  With e = eps - ep_n, q = |s_tr|, nh = s_tr / q, dg the plastic
+// multiplier, kappa = 1 / (2G + 2/3 H'(p)), beta = 2G / q, c = sqrt(2/3):
+//   ge  = K (1.psi) 1 + 2G dev(psi)                         (elastic part)
+//       + 2G kappa gbar nh + beta (dev(nu) - nh (nh.nu))    (plastic only)
+//   gbar = -2G psi.nh + zeta_e.nh + c zeta_p,  nu = dg (zeta_e - 2G psi)
+//   geps = ge,  gz_e = zeta_e - ge,  gz_p = zeta_p - c H' kappa gbar (plastic)
+__device__ __forceinline__ void j2_vjp(const J2Law& m, const double eps[6], const double epn[6],
+                                       double pn, const double psi[6], const double ze[6],
+                                       double zp, double geps[6], double gz[7]) {
+  double e[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) e[s] = eps[s] - epn[s];
+  const double tr3 = (e[0] + e[1] + e[2]) * (1.0 / 3.0);
+  double str[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) str[s] = 2.0 * m.G * (s < 3 ? e[s] - tr3 : e[s]);
+  double q2 = 0.0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) q2 += str[s] * str[s];
+  const double q = sqrt(q2);
+  const double syn = m.sigma0 + m.k_inf * pn + m.dsigma * (1.0 - exp(-m.b * pn));
+  const double f = q - kSqrt23 * syn;
+  const double ipsi = psi[0] + psi[1] + psi[2];
+  double ge[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+    ge[s] = (s < 3 ? m.K * ipsi + 2.0 * m.G * (psi[s] - ipsi / 3.0) : 2.0 * m.G * psi[s]);
+  double gpn = zp;
+  if (f > 0.0) {
+    const double xtol = kLocalTol * q / (2.0 * m.G);
+    double x = 0.0;
+    for (int it = 0; it < kLocalMaxIt; ++it) {
+      const double pp = pn + kSqrt23 * x;
+      const double ex = exp(-m.b * pp);
+      const double sy = m.sigma0 + m.k_inf * pp + m.dsigma * (1.0 - ex);
+      const double dsy = m.k_inf + m.dsigma * m.b * ex;
+      const double dx = (q - 2.0 * m.G * x - kSqrt23 * sy) / (2.0 * m.G + (2.0 / 3.0) * dsy);
+      x += dx;
+      if (fabs(dx) <= xtol) break;
+    }
+    const double pp = pn + kSqrt23 * x;
+    const double Hp = m.k_inf + m.dsigma * m.b * exp(-m.b * pp);
+    const double kappa = 1.0 / (2.0 * m.G + (2.0 / 3.0) * Hp);
+    const double beta = 2.0 * m.G / q;
+    double nh[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) nh[s] = str[s] / q;
+    double psin = 0.0, zen = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      psin += psi[s] * nh[s];
+      zen += ze[s] * nh[s];
+    }
+    const double gbar = -2.0 * m.G * psin + zen + kSqrt23 * zp;
+    double nu[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) nu[s] = x * (ze[s] - 2.0 * m.G * psi[s]);
+    const double nu3 = (nu[0] + nu[1] + nu[2]) * (1.0 / 3.0);
+    double nun = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) nun += nu[s] * nh[s];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const double dnu = s < 3 ? nu[s] - nu3 : nu[s];
+      ge[s] += 2.0 * m.G * kappa * gbar * nh[s] + beta * (dnu - nh[s] * nun);
+    }
+    gpn = zp - kSqrt23 * Hp * kappa * gbar;
+  }
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    geps[s] = ge[s];
+    gz[s] = ze[s] - ge[s];
+  }
+  gz[6] = gpn;
+}
+
+// Parameter cotangents of one laminate in the path adjoint: with subtree sums
+// Sm_X of mu and Ss_X of w~ sigma over its children X = L, R, jumps a and
+// adjoint jumps lam,
+//   dJ/dn  = N(a)^T (-c2 Sm_L + c1 Sm_R) - N(lam)^T (-c2 Ss_L + c1 Ss_R)
+//   dJ/dc1 = (N(n) a).(Sm_L + Sm_R) - (N(n) lam).(Ss_L + Ss_R)
+// using N(n) x = N(x) n.  g4 = {dJ/dc1, dJ/dn}.
+__device__ __forceinline__ void laminate_param_grad(const Normal<double>& nv, double c1, double c2,
+                                                    const double a[3], const double lam[3],
+                                                    const double SmL[6], const double SsL[6],
+                                                    const double SmR[6], const double SsR[6],
+                                                    double g4[4]) {
+  double Mm[6], Ms[6], Tm[6], Ts[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    Mm[k] = -c2 * SmL[k] + c1 * SmR[k];
+    Ms[k] = -c2 * SsL[k] + c1 * SsR[k];
+    Tm[k] = SmL[k] + SmR[k];
+    Ts[k] = SsL[k] + SsR[k];
+  }
+  const Normal<double> na{a[0], a[1], a[2]}, nl{lam[0], lam[1], lam[2]};
+  double ga[3], gl[3];
+  na.applyT(Mm, ga);
+  nl.applyT(Ms, gl);
+  double Na[6], Nl[6];
+  nv.apply(a, Na);
+  nv.apply(lam, Nl);
+  double gc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) gc += Na[k] * Tm[k] - Nl[k] * Ts[k];
+  g4[0] = gc;
+  g4[1] = ga[0] - gl[0];
+  g4[2] = ga[1] - gl[1];
+  g4[3] = ga[2] - gl[2];
+}
+
 }  // namespace dmn

@@ -21,317 +21,12 @@
 // of the kernel performs exactly one evaluation, at a + s da (s = 0 for the
 // initial state, s = 1, 1/2, ... for backtracking trials), followed by the
 // per-point decision; all shuffles run in wave-uniform code.
-#include "dmn_internal.hpp"
+#include "dmn_tree.hpp"
 
 namespace dmn {
 namespace {
 
-template <int K, int D>
-struct Cfg {
-  static_assert(D >= 1 && D <= K, "subtree depth");
-  static constexpr int LP = 1 << (K - D);  // lanes per point
-  static_assert(LP <= 64, "at most one point per wave is split over lanes");
-  static constexpr int PPW = 64 / LP;      // points per wave
-  static constexpr int NLEAF = 1 << D;     // leaves per lane
-  static constexpr int NLAM = NLEAF - 1;   // laminates per lane
-  static constexpr int NUP = LP - 1;       // laminates above the lane subtrees
-  static constexpr int NUPS = NUP > 0 ? NUP : 1;
-  static constexpr int L = (1 << K) - 1;
-  static constexpr int M = 1 << (K - 1);   // matrix leaves per point
-  static constexpr int UP0 = (1 << K) - LP;  // paper position of the first upper laminate
-  static constexpr int UPLEV = K - D;
-  static constexpr int SLOTS = PPW * NUPS;
-};
-
-__host__ __device__ constexpr int ilog2(int h) { return h <= 1 ? 0 : 1 + ilog2(h / 2); }
-
-// paper position of the lane subtree's heap node H (1-based heap) of lane t
-template <int K, int D, int H>
-__device__ __forceinline__ int lane_pos(int t) {
-  constexpr int m = ilog2(H);
-  constexpr int k = K - D + 1 + m;
-  return (1 << K) - (1 << k) + t * (1 << m) + (H - (1 << m));
-}
-
-// paper position of the upper laminate computed by lane t at upper step m
-template <int K, int D>
-__device__ __forceinline__ int upper_pos(int m, int t) {
-  const int k = K - D + 1 - m;
-  return (1 << K) - (1 << k) + (t >> m);
-}
-
-struct LamRow {
-  Normal<double> nv;
-  double c1, c2, rf;
-};
-
-__device__ __forceinline__ LamRow load_row(const double* __restrict__ tab, int pos) {
-  const double* r = tab + (size_t)pos * kTabStride;
-  LamRow o;
-  o.c1 = r[0];
-  o.c2 = r[1];
-  o.nv.n0 = r[2];
-  o.nv.n1 = r[3];
-  o.nv.n2 = r[4];
-  o.rf = r[5];
-  return o;
-}
-
-// LDS storage of the upper laminates of all points of a wave (SoA by field).
-template <int K, int D>
-struct UpperLds {
-  double G[18][Cfg<K, D>::SLOTS];
-  double g[3][Cfg<K, D>::SLOTS];
-  double a[3][Cfg<K, D>::SLOTS];
-  double da[3][Cfg<K, D>::SLOTS];
-};
-
-// Lane-resident state of one point's lane subtree.
-template <int K, int D>
-struct LaneState {
-  using C = Cfg<K, D>;
-  double a[C::NLAM][3];   // accepted jumps
-  double da[C::NLAM][3];  // Newton increments
-  double G[C::NLAM][18];  // top-down factors of the last evaluation
-  double g[C::NLAM][3];
-};
-
-struct EvalOut {
-  double C[21];  // condensed tangent (meaningful on the point's lane 0)
-  double sb[6];  // plain stress average (lane 0)
-  double rr;     // squared residual norm (reduced over the point's lanes)
-  double sn2;    // squared norm of the effective stress (broadcast)
-  int lfail;     // J2 return failed somewhere in the point
-  int spdfail;   // a laminate pivot was not positive
-};
-
-template <int K, int D>
-struct Ctx {
-  const double* __restrict__ tab;
-  const double* __restrict__ zin;  // this point's z_in
-  IsoElastic fib;
-  J2Law mat;
-  int t;
-  int slot;
-  int base;  // first lane of this point in the wave
-};
-
-__device__ __forceinline__ double shfl_down_d(double v, int o, int width) {
-  return __shfl_down(v, (unsigned)o, width);
-}
-__device__ __forceinline__ double shfl_up_d(double v, int o, int width) {
-  return __shfl_up(v, (unsigned)o, width);
-}
-
-__device__ __forceinline__ bool upper_active(int t, int m) { return (t & ((1 << m) - 1)) == 0; }
-__device__ __forceinline__ bool upper_right(int t, int m) {
-  return (t & ((1 << m) - 1)) == (1 << (m - 1));
-}
-
-// ------------------------------------------------------- strain localisation
-
-template <int K, int D, int H>
-__device__ __forceinline__ void loc_node(const Ctx<K, D>& cx, const LaneState<K, D>& st, double s,
-                                         const double (&e)[6],
-                                         double (&eps)[Cfg<K, D>::NLEAF][6]) {
-  using C = Cfg<K, D>;
-  if constexpr (H >= C::NLEAF) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) eps[H - C::NLEAF][k] = e[k];
-  } else {
-    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
-    double aj[3], eL[6], eR[6];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) aj[k] = st.a[H - 1][k] + s * st.da[H - 1][k];
-    laminate_localize(aj, e, row.nv, row.c1, row.c2, eL, eR);
-    loc_node<K, D, 2 * H>(cx, st, s, eL, eps);
-    loc_node<K, D, 2 * H + 1>(cx, st, s, eR, eps);
-  }
-}
-
-// Leaf strains at jumps a + s da (wave-uniform: contains shuffles).
-template <int K, int D>
-__device__ __forceinline__ void localize(const Ctx<K, D>& cx, const LaneState<K, D>& st,
-                                         const UpperLds<K, D>& up, const double (&E)[6], double s,
-                                         double (&eps)[Cfg<K, D>::NLEAF][6]) {
-  using C = Cfg<K, D>;
-  double e[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) e[k] = E[k];
-#pragma unroll 1
-  for (int m = C::UPLEV; m >= 1; --m) {
-    const int o = 1 << (m - 1);
-    double eR[6] = {0, 0, 0, 0, 0, 0};
-    if (upper_active(cx.t, m)) {
-      const int pos = upper_pos<K, D>(m, cx.t);
-      const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row(cx.tab, pos);
-      double aj[3], eL[6];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) aj[k] = up.a[k][u] + s * up.da[k][u];
-      laminate_localize(aj, e, row.nv, row.c1, row.c2, eL, eR);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = eL[k];
-    }
-    double rcv[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
-    if (upper_right(cx.t, m)) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = rcv[k];
-    }
-  }
-  loc_node<K, D, 1>(cx, st, s, e, eps);
-}
-
-// ---------------------------------------------------------------- bottom-up
-
-template <int K, int D, int H>
-__device__ __forceinline__ void up_node(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                        const double (&eps)[Cfg<K, D>::NLEAF][6],
-                                        double (&Cn)[21], double (&tn)[6], double (&sn)[6],
-                                        double& rr, int& lfail, int& spdfail) {
-  using C = Cfg<K, D>;
-  if constexpr (H >= C::NLEAF) {
-    constexpr int q = H - C::NLEAF;
-    if constexpr (q % 2 == 0) {  // fibre leaf
-      iso_stress(cx.fib, eps[q], sn);
-      iso_packed(cx.fib, Cn);
-    } else {                     // matrix leaf
-      const int mloc = cx.t * (C::NLEAF / 2) + q / 2;
-      const double* z = cx.zin + (size_t)mloc * 7;
-      double epn[6], ep[6], p;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) epn[k] = z[k];
-      const bool ok = j2_return(cx.mat, eps[q], epn, z[6], sn, Cn, ep, p);
-      lfail |= ok ? 0 : 1;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) tn[k] = sn[k];
-  } else {
-    up_node<K, D, 2 * H>(cx, st, eps, Cn, tn, sn, rr, lfail, spdfail);
-    double CR[21], tR[6], sR[6];
-    up_node<K, D, 2 * H + 1>(cx, st, eps, CR, tR, sR, rr, lfail, spdfail);
-    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
-    const bool ok = laminate_newton(Cn, tn, sn, CR, tR, sR, row.nv, row.c1, row.c2, row.rf,
-                                    st.G[H - 1], st.g[H - 1], rr);
-    spdfail |= ok ? 0 : 1;
-  }
-}
-
-// Leaf laws, bottom-up condensation and per-point reductions at leaf strains
-// eps (wave-uniform: contains shuffles).
-template <int K, int D>
-__device__ __forceinline__ void evaluate_full(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                              UpperLds<K, D>& up,
-                                              const double (&eps)[Cfg<K, D>::NLEAF][6],
-                                              EvalOut& out) {
-  using C = Cfg<K, D>;
-  double rr = 0.0;
-  int lfail = 0, spdfail = 0;
-  double cT[6];
-  up_node<K, D, 1>(cx, st, eps, out.C, cT, out.sb, rr, lfail, spdfail);
-#pragma unroll 1
-  for (int m = 1; m <= C::UPLEV; ++m) {
-    const int o = 1 << (m - 1);
-    double rC[21], rT[6], rS[6];
-#pragma unroll
-    for (int k = 0; k < 21; ++k) rC[k] = shfl_down_d(out.C[k], o, C::LP);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      rT[k] = shfl_down_d(cT[k], o, C::LP);
-      rS[k] = shfl_down_d(out.sb[k], o, C::LP);
-    }
-    if (upper_active(cx.t, m)) {
-      const int pos = upper_pos<K, D>(m, cx.t);
-      const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row(cx.tab, pos);
-      double Gu[18], gu[3];
-      const bool ok = laminate_newton(out.C, cT, out.sb, rC, rT, rS, row.nv, row.c1, row.c2,
-                                      row.rf, Gu, gu, rr);
-      spdfail |= ok ? 0 : 1;
-#pragma unroll
-      for (int k = 0; k < 18; ++k) up.G[k][u] = Gu[k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) up.g[k][u] = gu[k];
-    }
-  }
-  // reductions over the LP lanes of each point; broadcast of the root average
-#pragma unroll
-  for (int o = 1; o < C::LP; o <<= 1) {
-    rr += __shfl_xor(rr, o, C::LP);
-    lfail |= __shfl_xor(lfail, o, C::LP);
-    spdfail |= __shfl_xor(spdfail, o, C::LP);
-  }
-  double sn2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const double v = __shfl(out.sb[k], cx.base, 64);
-    sn2 += v * v;
-  }
-  out.rr = rr;
-  out.sn2 = sn2;
-  out.lfail = lfail;
-  out.spdfail = spdfail;
-}
-
-// ---------------------------------------------------------------- top-down
-
-template <int K, int D, int H>
-__device__ __forceinline__ void down_node(const Ctx<K, D>& cx, LaneState<K, D>& st, bool commit,
-                                          const double (&e)[6]) {
-  using C = Cfg<K, D>;
-  if constexpr (H < C::NLEAF) {
-    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
-    double eL[6], eR[6], dah[3];
-    laminate_descend(st.G[H - 1], st.g[H - 1], e, row.nv, row.c1, row.c2, dah, eL, eR);
-    if (commit) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) st.da[H - 1][k] = dah[k];
-    }
-    down_node<K, D, 2 * H>(cx, st, commit, eL);
-    down_node<K, D, 2 * H + 1>(cx, st, commit, eR);
-  }
-}
-
-// Newton increments da for all laminates of the points with commit set
-// (wave-uniform: contains shuffles).
-template <int K, int D>
-__device__ __forceinline__ void direction(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                          UpperLds<K, D>& up, bool commit) {
-  using C = Cfg<K, D>;
-  double e[6] = {0, 0, 0, 0, 0, 0};  // the macro strain is fixed during Newton
-#pragma unroll 1
-  for (int m = C::UPLEV; m >= 1; --m) {
-    const int o = 1 << (m - 1);
-    double eR[6] = {0, 0, 0, 0, 0, 0};
-    if (upper_active(cx.t, m)) {
-      const int pos = upper_pos<K, D>(m, cx.t);
-      const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row(cx.tab, pos);
-      double Gu[18], gu[3], dau[3], eL[6];
-#pragma unroll
-      for (int k = 0; k < 18; ++k) Gu[k] = up.G[k][u];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) gu[k] = up.g[k][u];
-      laminate_descend(Gu, gu, e, row.nv, row.c1, row.c2, dau, eL, eR);
-      if (commit) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) up.da[k][u] = dau[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = eL[k];
-    }
-    double rcv[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
-    if (upper_right(cx.t, m)) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = rcv[k];
-    }
-  }
-  down_node<K, D, 1>(cx, st, commit, e);
-}
+using namespace tree;
 
 // ---------------------------------------------------------------- outputs
 

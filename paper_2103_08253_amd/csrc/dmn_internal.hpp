@@ -13,6 +13,10 @@ namespace dmn {
 // rfac = W_L W_R / (W sum(w)) scales the laminate's residual block; the last
 // two entries are the derivatives of c1 = W_L / (W_L + W_R).
 constexpr int kTabStride = 8;
+// After the L rows: normalised leaf weights [2^K], then 1 / sum(w).
+__host__ __device__ inline size_t table_elems(int depth) {
+  return ((size_t)1 << depth) * (kTabStride + 1) - kTabStride + 1;
+}
 
 // Point-group description passed by value to the Gauss-point kernel.
 struct GroupArgs {
@@ -63,5 +67,28 @@ int launch_linear_backward(int depth, int prec, const void* tab, const int32_t* 
                            double* gsum, int32_t* err, hipStream_t stream);
 // number of partial-sum slots (waves x samples per wave) the backward uses
 long long linear_backward_partials(int depth, long long B);
+
+// One point group of the path adjoint (device pointers).
+struct AdjointLaunch {
+  const double* E;
+  const double* z_in;
+  const double* a_conv;
+  const double* g_sigma;
+  const double* g_z_next;
+  double* g_z_prev;
+  const double* tab;
+  const int32_t* flag;
+  double* partials;  // [4 L + 2^K][slots]
+  double* gsum;      // [4 L + 2^K]
+  double* gw;
+  double* gn;
+  int32_t* err;
+  long long P;
+  IsoElastic fib;
+  J2Law mat;
+};
+
+long long adjoint_partial_slots(int depth, long long P);
+int launch_adjoint(int depth, const AdjointLaunch& args, hipStream_t stream);
 
 }  // namespace dmn

@@ -7,7 +7,7 @@
 //   n                                      (copied as passed)
 //   rfac = W_L W_R / ((W_L + W_R) sum(w))  (scale of the laminate's block of A^T W sigma)
 //   dc1/dW_L = W_R / W^2, dc1/dW_R = -W_L / W^2
-// and flags the DMN as invalid when a weight is negative or not finite, or a
+// followed by the leaf section w / sum(w) [2^K] and 1 / sum(w), and flags the DMN as invalid when a weight is negative or not finite, or a
 // laminate's children carry no weight.  Subtree sums are formed pairwise in
 // a fixed order, so the table is bit-identical run to run.
 #include "dmn_internal.hpp"
@@ -63,6 +63,10 @@ __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, cons
     r[6] = WR / (Wn * Wn);
     r[7] = -WL / (Wn * Wn);
   }
+  // leaf section: normalised weights w / sum(w), then 1 / sum(w)
+  T* leafw = tab + (size_t)L * kTabStride;
+  for (int j = threadIdx.x; j < nleaf; j += blockDim.x) leafw[j] = W[nleaf + j] / wtot;
+  if (threadIdx.x == 0) leafw[nleaf] = T(1) / wtot;
   if (mybad) atomicOr(&bad, 1);
   __syncthreads();
   if (threadIdx.x == 0) {

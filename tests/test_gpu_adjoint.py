@@ -1,0 +1,217 @@
+"""GPU parity of the path adjoint (dmn_update_adjoint swept over a load path).
+
+References:
+* the oracle's complex-step derivative through the whole path (independent:
+  forward-mode differentiation of the dense-Hessian Newton path, no adjoint);
+* on an elastic path, the linear map's hand-written backward (two GPU paths
+  that share no kernel);
+* central finite differences (h = 1e-6) of the GPU forward path itself.
+Both GPU and oracle paths run with the tight Newton tolerance 1e-13 so that
+the derivative of the converged path is compared, not stopping noise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synthetic as S
+from oracle.adjoint import TIGHT, path_directional_derivative
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-13
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def angle_grads(gn, alpha, beta):
+    da = np.stack([np.cos(alpha) * np.cos(beta), np.cos(alpha) * np.sin(beta), -np.sin(alpha)], -1)
+    db = np.stack([-np.sin(alpha) * np.sin(beta), np.sin(alpha) * np.cos(beta),
+                   np.zeros_like(alpha)], -1)
+    return np.sum(gn * da, -1), np.sum(gn * db, -1)
+
+
+def gpu_gradient(net, E, g, ck=10, tol=TOL):
+    from paper_2103_08253_amd.path import path_gradient
+    d = dev()
+    sigma, gw, gn = path_gradient(torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d),
+                                  torch.tensor(E, device=d), torch.tensor(g, device=d),
+                                  S.FIBER, S.MATRIX, checkpoint_every=ck, tol=tol, max_iter=50)
+    torch.cuda.synchronize()
+    return sigma.cpu().numpy(), gw.cpu().numpy(), gn.cpu().numpy()
+
+
+def case(K, seed, n_points, steps, mag=0.02, frac=0.25, noise=1e-3):
+    rs = S.streams(seed)
+    net = S.random_dmn(rs["dmn"], K, frac)
+    E = S.ramp_with_noise(rs, n_points, steps, mag, noise)
+    g = S.unit_directions(rs["cotangent"], n_points)
+    return net, E, g
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_adjoint_full_gradient_small_depth(K):
+    say(f"case: path adjoint depth {K}, all parameters")
+    net, E, g = case(K, 400 + K, 3, 5)
+    _, gw, gn = gpu_gradient(net, E, g, ck=2)
+    alpha, beta = S.normals_to_angles(net.normals)
+    ga, gb = angle_grads(gn, alpha, beta)
+    nl, L = 2 ** K, 2 ** K - 1
+    worst = 0.0
+    scale = max(np.abs(gw).max(), np.abs(ga).max(), np.abs(gb).max())
+    for k in range(nl + 2 * L):
+        vw, va, vb = np.zeros(nl), np.zeros(L), np.zeros(L)
+        if k < nl:
+            vw[k] = 1.0
+            got = gw[k]
+        elif k < nl + L:
+            va[k - nl] = 1.0
+            got = ga[k - nl]
+        else:
+            vb[k - nl - L] = 1.0
+            got = gb[k - nl - L]
+        ref = path_directional_derivative(K, net.w, alpha, beta, S.FIBER, S.MATRIX, E, g, vw, va, vb)
+        worst = max(worst, abs(got - ref) / scale)
+    say(f"  worst rel err {worst:.2e}")
+    assert worst <= 1e-9
+
+
+def test_adjoint_depth8_random_directions():
+    say("case: path adjoint depth 8, 2 points x 6 steps, 2 random directions")
+    net, E, g = case(8, 410, 2, 6, mag=0.015)
+    _, gw, gn = gpu_gradient(net, E, g, ck=4)
+    alpha, beta = S.normals_to_angles(net.normals)
+    ga, gb = angle_grads(gn, alpha, beta)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        vw, va, vb = rng.standard_normal(256), rng.standard_normal(255), rng.standard_normal(255)
+        got = gw @ vw + ga @ va + gb @ vb
+        ref = path_directional_derivative(8, net.w, alpha, beta, S.FIBER, S.MATRIX, E, g, vw, va, vb)
+        say(f"  directional derivative gpu {got:.12e} oracle {ref:.12e}")
+        assert abs(got - ref) <= 1e-8 * abs(ref)
+
+
+def test_adjoint_elastic_path_equals_linear_backward():
+    """Elastic path: J = sum_p g_p . C_lin E_p, so the path adjoint must equal the
+    linear map's backward with cotangent sum_p g_p E_p^T."""
+    from paper_2103_08253_amd import dmn_homogenize_backward
+    from oracle.mandel import iso_from_E_nu
+    say("case: path adjoint on an elastic path vs linear backward")
+    d = dev()
+    net, E, g = case(6, 420, 16, 3, mag=2e-4, noise=0.0)
+    _, gw, gn = gpu_gradient(net, E, g, ck=2)
+    C1 = torch.tensor(iso_from_E_nu(S.FIBER["E"], S.FIBER["nu"])[None], device=d)
+    C2 = torch.tensor(iso_from_E_nu(S.MATRIX["E"], S.MATRIX["nu"])[None], device=d)
+    G = torch.tensor(np.einsum("pi,pj->ij", g, E[-1])[None], device=d)
+    lw, ln, _, _, _ = dmn_homogenize_backward(torch.tensor(net.w, device=d),
+                                              torch.tensor(net.normals, device=d), C1, C2, G)
+    lw, ln = lw.cpu().numpy(), ln.cpu().numpy()
+    ew = np.abs(gw - lw).max() / np.abs(lw).max()
+    en = np.abs(gn - ln).max() / np.abs(ln).max()
+    say(f"  rel err w {ew:.2e} n {en:.2e}")
+    assert ew <= 1e-9 and en <= 1e-9
+
+
+def plastic_pattern_and_J(net_w, normals, E_path, g, picks_np):
+    """GPU forward along the path; returns J = sum g . sigma(final) over the picked
+    points and, per picked point, the plastic/elastic pattern of every matrix leaf
+    at every step (p grew or not)."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    d = dev()
+    picks = torch.tensor(picks_np, device=d)
+    grp = PointGroup.allocate(net_w, normals, E_path[0])
+    pats = []
+    ws = None
+    for step in range(E_path.shape[0]):
+        grp.E = E_path[step]
+        ws = dmn_update_gauss_points([grp], S.FIBER, S.MATRIX, ws=ws, tol=TOL, max_iter=50)
+        assert bool((grp.status == 0).all())
+        pats.append((grp.z_out[picks, :, 6] > grp.z_in[picks, :, 6]).cpu().numpy())
+        if step + 1 < E_path.shape[0]:
+            grp.advance()
+    J = (grp.sigma[picks] * torch.tensor(g[picks_np], device=d)).sum(dim=1).cpu().numpy()
+    return J, np.stack(pats, 1)
+
+
+def test_adjoint_production_size_checkpointed():
+    """16,384 points x 50 steps, checkpoints every 10 steps: the adjoint against
+    the oracle's complex-step path derivative on 2 sampled points, and against
+    GPU central differences (h = 1e-6) on 32 sampled points, excluding points
+    whose elastic/plastic pattern differs between the +h and -h paths (a kink of
+    the path there makes the difference quotient meaningless)."""
+    from oracle.grad import normals_from_angles
+    say("case: path adjoint depth 8, 16384 points x 50 steps")
+    d = dev()
+    wl = S.config4()
+    net = wl.nets[0]
+    P = wl.n_points
+    picks = S.streams(4)["picks"].choice(P, 32, replace=False)
+    alpha, beta = S.normals_to_angles(net.normals)
+    rng = np.random.default_rng(6)
+    vw, va, vb = rng.standard_normal(256), rng.standard_normal(255), rng.standard_normal(255)
+    # two points against the oracle (strict)
+    two = picks[:2]
+    g2 = np.zeros((P, 6))
+    g2[two] = wl.g_sigma[two]
+    _, gw2, gn2 = gpu_gradient(net, wl.E, g2, ck=10)
+    ga2, gb2 = angle_grads(gn2, alpha, beta)
+    got2 = gw2 @ vw + ga2 @ va + gb2 @ vb
+    ref2 = path_directional_derivative(8, net.w, alpha, beta, S.FIBER, S.MATRIX,
+                                       wl.E[:, two, :], wl.g_sigma[two], vw, va, vb)
+    say(f"  2 points: adjoint {got2:.12e} oracle {ref2:.12e}")
+    assert abs(got2 - ref2) <= 1e-8 * abs(ref2)
+    # 32 points against GPU central differences, kinked points excluded
+    E_t = torch.tensor(wl.E, device=d)
+    h = 1e-6
+    runs = []
+    for s in (h, -h):
+        w = torch.tensor(net.w + s * vw, device=d)
+        n = torch.tensor(normals_from_angles(alpha + s * va, beta + s * vb), device=d)
+        runs.append(plastic_pattern_and_J(w, n, E_t, wl.g_sigma, picks))
+    same = np.array([np.array_equal(runs[0][1][i], runs[1][1][i]) for i in range(32)])
+    keep = picks[same]
+    say(f"  {same.sum()} of 32 points keep their elastic/plastic pattern under +-h")
+    assert same.sum() >= 8
+    fd = float(np.sum((runs[0][0] - runs[1][0])[same]) / (2 * h))
+    gk = np.zeros((P, 6))
+    gk[keep] = wl.g_sigma[keep]
+    _, gwk, gnk = gpu_gradient(net, wl.E, gk, ck=10)
+    gak, gbk = angle_grads(gnk, alpha, beta)
+    got = gwk @ vw + gak @ va + gbk @ vb
+    say(f"  {len(keep)} points: adjoint {got:.10e} FD {fd:.10e}")
+    assert abs(got - fd) <= 1e-5 * abs(fd)
+
+
+def test_autograd_wrappers():
+    from paper_2103_08253_amd.autograd import dmn_linear, dmn_path_stress, normals_from_angles
+    say("case: autograd wrappers")
+    d = dev()
+    tw = S.config3(batch=8, depth=4)
+    a0 = torch.tensor(tw.alpha0[:15], device=d, requires_grad=True)
+    b0 = torch.tensor(tw.beta0[:15], device=d, requires_grad=True)
+    w = torch.tensor(tw.v0[:16] / tw.v0[:16].sum(), device=d, requires_grad=True)
+    C1 = torch.tensor(tw.C1, device=d)
+    C2 = torch.tensor(tw.C2, device=d)
+    T = torch.tensor(S.config3(batch=8, depth=4).C1, device=d)
+    Cbar = dmn_linear(w, normals_from_angles(a0, b0), C1, C2)
+    loss = (torch.linalg.matrix_norm(Cbar - T) / torch.linalg.matrix_norm(T)).mean()
+    loss.backward()
+    assert torch.isfinite(w.grad).all() and torch.isfinite(a0.grad).all()
+    net, E, g = case(3, 430, 4, 4)
+    w2 = torch.tensor(net.w, device=d, requires_grad=True)
+    n2 = torch.tensor(net.normals, device=d, requires_grad=True)
+    sig = dmn_path_stress(w2, n2, torch.tensor(E, device=d), S.FIBER, S.MATRIX, 2)
+    (sig * torch.tensor(g, device=d)).sum().backward()
+    _, gw, gn = gpu_gradient(net, E, g, ck=2, tol=1e-10)
+    assert np.allclose(w2.grad.cpu().numpy(), gw, rtol=1e-12, atol=1e-14)
+    assert np.allclose(n2.grad.cpu().numpy(), gn, rtol=1e-12, atol=1e-14)
