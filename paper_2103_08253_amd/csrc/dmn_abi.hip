@@ -107,7 +107,7 @@ int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void*
 size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int32_t n_groups,
                                               int prec) {
   if (!groups || n_groups < 1 || n_groups > 64 || prec != DMN_F64) return 0;
-  size_t total = kAlign;
+  size_t total = kAlign + kAlign;  // header, then one work counter per launch
   for (int i = 0; i < n_groups; ++i) {
     if (!depth_ok(groups[i].net.depth)) return 0;
     total += table_bytes(groups[i].net.depth, prec);
@@ -138,9 +138,11 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
 
-  // tables, one per group
+  // work counters (at most one launch per group), then tables, one per group
+  int32_t* counters = (int32_t*)((char*)ws + kAlign);
+  if (dmn::launch_zero_ints(counters, n_groups, stream)) return DMN_EHIP;
   std::vector<Table> tabs(n_groups);
-  size_t off = kAlign;
+  size_t off = 2 * kAlign;
   for (int i = 0; i < n_groups; ++i) {
     tabs[i] = table_at(ws, off);
     off += table_bytes(groups[i].net.depth, prec);
@@ -172,6 +174,8 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
     return groups[a].net.depth > groups[b].net.depth;
   });
   size_t pos = 0;
+  int launch = 0;
+  const long long persistent = (long long)dmn::device_cu_count() * 8;
   while (pos < order.size()) {
     const int K = groups[order[pos]].net.depth;
     const int lp = dmn::gp_default_lanes_per_point(K);
@@ -201,7 +205,10 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
       ++pos;
     }
     if (blocks > 0x7fffffff) return DMN_EINVAL;
-    if (dmn::launch_gp_update(K, lp, args, (int)blocks, stream)) return DMN_EHIP;
+    args.counter = counters + launch++;
+    args.total = (int)blocks;
+    const long long waves = blocks < persistent ? blocks : persistent;
+    if (dmn::launch_gp_update(K, lp, args, (int)waves, stream)) return DMN_EHIP;
   }
   return DMN_OK;
 }

@@ -112,7 +112,7 @@ __device__ __forceinline__ void sum_node(const Ctx<K, D>& cx, const LaneState<K,
     double SmR[6], SsR[6];
     sum_node<K, D, 2 * H>(cx, st, mu, ws, live, acc, Sm, Ss);
     sum_node<K, D, 2 * H + 1>(cx, st, mu, ws, live, acc, SmR, SsR);
-    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, lane_pos<K, D, H>(cx.t));
     double a[3], lam[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -138,12 +138,13 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
   using C = Cfg<K, D>;
   __shared__ UpperLds<K, D> up;
   __shared__ double accU[4][C::SLOTS];
+  __shared__ TableLds<K> tlds;
   const int lane = threadIdx.x;
   Ctx<K, D> cx;
   cx.slot = lane / C::LP;
   cx.t = lane % C::LP;
   cx.base = cx.slot * C::LP;
-  cx.tab = args.tab;
+  cx.tab = stage_table<K>(tlds, args.tab + table_soa_offset(K));
   cx.fib = args.fib;
   cx.mat = args.mat;
   const double* leafw = args.tab + (size_t)C::L * kTabStride;
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
       if (upper_active(cx.t, m)) {
         const int pos = upper_pos<K, D>(m, cx.t);
         const int u = cx.slot * C::NUPS + (pos - C::UP0);
-        const LamRow row = load_row(cx.tab, pos);
+        const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, pos);
         double a[3], lam[3], g4[4];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {

@@ -103,25 +103,43 @@ __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K,
 
 // ---------------------------------------------------------------- kernel
 
+// Persistent waves: each 64-lane workgroup takes batches of PPW points from an
+// atomic counter until the launch's batches are exhausted, so points with
+// more Newton iterations do not leave SIMDs idle; the DMN table of the
+// current group is staged in the wave's LDS when the group changes.
 template <int K, int D>
 __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   using C = Cfg<K, D>;
   __shared__ UpperLds<K, D> up;
-  const int blk = blockIdx.x;
+  __shared__ TableLds<K> tlds;
+  const int lane = threadIdx.x;
+  int cur = -1;
+  const double* tabp = nullptr;
+#pragma unroll 1
+  while (true) {
+  int item = 0;
+  if (lane == 0) item = atomicAdd(args.counter, 1);
+  item = __shfl(item, 0, 64);
+  if (item >= args.total) break;
   int gi = 0;
 #pragma unroll 1
   for (int q = 1; q < args.ng; ++q)
-    if (blk >= args.g[q].block0) gi = q;
+    if (item >= args.g[q].block0) gi = q;
   const GroupArgs& G = args.g[gi];
-  const int lane = threadIdx.x;
+  if (gi != cur) {
+    __syncthreads();
+    tabp = stage_table<K>(tlds, G.tab + table_soa_offset(K));
+    __syncthreads();
+    cur = gi;
+  }
   Ctx<K, D> cx;
   cx.slot = lane / C::LP;
   cx.t = lane % C::LP;
   cx.base = cx.slot * C::LP;
-  cx.tab = G.tab;
+  cx.tab = tabp;
   cx.fib = args.fib;
   cx.mat = args.mat;
-  const long long pt_raw = (long long)(blk - G.block0) * C::PPW + cx.slot;
+  const long long pt_raw = (long long)(item - G.block0) * C::PPW + cx.slot;
   const bool in_range = pt_raw < G.P;
   const long long pt = in_range ? pt_raw : G.P - 1;  // tail lanes shadow the last point
   cx.zin = G.z_in + (size_t)pt * C::M * 7;
@@ -174,7 +192,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) ev.sb[k] = __builtin_nan("");
     if (in_range) finalize(cx, st, up, G, pt, eps, ev, DMN_STATUS_BADPARAM, 0);
-    return;
+    continue;
   }
 
   const double scale = args.tol * (double)C::L;
@@ -253,6 +271,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
       }
     }
   }
+  }  // persistent loop
 }
 
 }  // namespace

@@ -13,13 +13,18 @@ namespace dmn {
 // rfac = W_L W_R / (W sum(w)) scales the laminate's residual block; the last
 // two entries are the derivatives of c1 = W_L / (W_L + W_R).
 constexpr int kTabStride = 8;
-// After the L rows: normalised leaf weights [2^K], then 1 / sum(w).
+// After the L rows: normalised leaf weights [2^K], then 1 / sum(w), then a
+// field-major copy [6][L] of c1, c2, n0, n1, n2, rfac (8-element aligned).
+__host__ __device__ inline size_t table_soa_offset(int depth) {
+  const size_t L = ((size_t)1 << depth) - 1;
+  return (L * kTabStride + ((size_t)1 << depth) + 1 + 7) / 8 * 8;
+}
 __host__ __device__ inline size_t table_elems(int depth) {
-  return ((size_t)1 << depth) * (kTabStride + 1) - kTabStride + 1;
+  return table_soa_offset(depth) + 6 * (((size_t)1 << depth) - 1);
 }
 
 // Point-group description passed by value to the Gauss-point kernel.
-struct GroupArgs {
+struct GroupArgs {  // tab points at the table start (AoS rows first)
   const double* E;
   const double* z_in;
   double* z_out;
@@ -32,7 +37,7 @@ struct GroupArgs {
   const double* tab;   // [L][kTabStride]
   const int32_t* flag; // nonzero: invalid DMN parameters
   long long P;
-  int block0;          // first workgroup index of this group in the launch
+  int block0;          // first batch index of this group in the launch
   int pad;
 };
 
@@ -40,6 +45,8 @@ constexpr int kMaxGroupsPerLaunch = 12;
 
 struct GpLaunch {
   GroupArgs g[kMaxGroupsPerLaunch];
+  int* counter;  // zeroed before the launch; batches are taken with atomicAdd
+  int total;     // batches in this launch
   int ng;
   int max_iter;
   int max_bt;
@@ -55,6 +62,9 @@ int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* 
                        int32_t* err, hipStream_t stream);
 int launch_gp_update(int depth, int lanes_per_point, const GpLaunch& args, int n_blocks,
                      hipStream_t stream);
+int launch_zero_ints(int32_t* p, int n, hipStream_t stream);
+// compute units of the current device (cached per device)
+int device_cu_count();
 int gp_points_per_block(int depth, int lanes_per_point);
 int gp_default_lanes_per_point(int depth);
 

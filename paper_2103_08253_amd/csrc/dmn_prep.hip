@@ -7,7 +7,8 @@
 //   n                                      (copied as passed)
 //   rfac = W_L W_R / ((W_L + W_R) sum(w))  (scale of the laminate's block of A^T W sigma)
 //   dc1/dW_L = W_R / W^2, dc1/dW_R = -W_L / W^2
-// followed by the leaf section w / sum(w) [2^K] and 1 / sum(w), and flags the DMN as invalid when a weight is negative or not finite, or a
+// followed by the leaf section w / sum(w) [2^K] and 1 / sum(w), and a
+// field-major copy of the first six fields; flags the DMN as invalid when a weight is negative or not finite, or a
 // laminate's children carry no weight.  Subtree sums are formed pairwise in
 // a fixed order, so the table is bit-identical run to run.
 #include "dmn_internal.hpp"
@@ -62,6 +63,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, cons
     r[5] = WL * WR / (Wn * wtot);
     r[6] = WR / (Wn * Wn);
     r[7] = -WL / (Wn * Wn);
+    T* soa = tab + table_soa_offset(K);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) soa[(size_t)f * L + pos] = r[f];
   }
   // leaf section: normalised weights w / sum(w), then 1 / sum(w)
   T* leafw = tab + (size_t)L * kTabStride;
@@ -75,7 +79,31 @@ __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, cons
   }
 }
 
+__global__ void zero_ints_kernel(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace
+
+int launch_zero_ints(int32_t* p, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n);
+  return (int)hipGetLastError();
+}
+
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
 
 int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
                        int32_t* err, hipStream_t stream) {

@@ -48,16 +48,37 @@ struct LamRow {
   double c1, c2, rf;
 };
 
-__device__ __forceinline__ LamRow load_row(const double* __restrict__ tab, int pos) {
-  const double* r = tab + (size_t)pos * kTabStride;
+// Row of the laminate table, field-major copy [6][L] (c1, c2, n0, n1, n2, rfac):
+// in LDS for depths up to 9, in global memory above.
+template <int L>
+__device__ __forceinline__ LamRow load_row_soa(const double* __restrict__ tab, int pos) {
   LamRow o;
-  o.c1 = r[0];
-  o.c2 = r[1];
-  o.nv.n0 = r[2];
-  o.nv.n1 = r[3];
-  o.nv.n2 = r[4];
-  o.rf = r[5];
+  o.c1 = tab[0 * L + pos];
+  o.c2 = tab[1 * L + pos];
+  o.nv.n0 = tab[2 * L + pos];
+  o.nv.n1 = tab[3 * L + pos];
+  o.nv.n2 = tab[4 * L + pos];
+  o.rf = tab[5 * L + pos];
   return o;
+}
+
+template <int K>
+struct TableLds {
+  static constexpr int L = (1 << K) - 1;
+  static constexpr bool kInLds = L <= 511;
+  double v[kInLds ? 6 * L : 1];
+};
+
+// Cooperative copy of the field-major table into LDS (all threads of the
+// workgroup; the caller synchronises).
+template <int K>
+__device__ __forceinline__ const double* stage_table(TableLds<K>& lds, const double* soa_global) {
+  if constexpr (TableLds<K>::kInLds) {
+    for (int i = threadIdx.x; i < 6 * TableLds<K>::L; i += blockDim.x) lds.v[i] = soa_global[i];
+    return lds.v;
+  } else {
+    return soa_global;
+  }
 }
 
 // LDS storage of the upper laminates of all points of a wave (SoA by field).
@@ -122,7 +143,7 @@ __device__ __forceinline__ void loc_node(const Ctx<K, D>& cx, const LaneState<K,
 #pragma unroll
     for (int k = 0; k < 6; ++k) eps[H - C::NLEAF][k] = e[k];
   } else {
-    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, lane_pos<K, D, H>(cx.t));
     double aj[3], eL[6], eR[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) aj[k] = st.a[H - 1][k] + s * st.da[H - 1][k];
@@ -148,7 +169,7 @@ __device__ __forceinline__ void localize(const Ctx<K, D>& cx, const LaneState<K,
     if (upper_active(cx.t, m)) {
       const int pos = upper_pos<K, D>(m, cx.t);
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row(cx.tab, pos);
+      const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, pos);
       double aj[3], eL[6];
 #pragma unroll
       for (int k = 0; k < 3; ++k) aj[k] = up.a[k][u] + s * up.da[k][u];
@@ -206,7 +227,7 @@ __device__ __forceinline__ void up_node(const Ctx<K, D>& cx, LaneState<K, D>& st
     up_node<K, D, 2 * H>(cx, st, leaf, eps, Cn, tn, sn, rr, lfail, spdfail);
     double CR[21], tR[6], sR[6];
     up_node<K, D, 2 * H + 1>(cx, st, leaf, eps, CR, tR, sR, rr, lfail, spdfail);
-    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, lane_pos<K, D, H>(cx.t));
     const bool ok = laminate_newton(Cn, tn, sn, CR, tR, sR, row.nv, row.c1, row.c2, row.rf,
                                     st.G[H - 1], st.g[H - 1], rr);
     spdfail |= ok ? 0 : 1;
@@ -239,7 +260,7 @@ __device__ __forceinline__ void evaluate_full(const Ctx<K, D>& cx, LaneState<K, 
     if (upper_active(cx.t, m)) {
       const int pos = upper_pos<K, D>(m, cx.t);
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row(cx.tab, pos);
+      const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, pos);
       double Gu[18], gu[3];
       const bool ok = laminate_newton(out.C, cT, out.sb, rC, rT, rS, row.nv, row.c1, row.c2,
                                       row.rf, Gu, gu, rr);
@@ -277,7 +298,7 @@ __device__ __forceinline__ void down_node(const Ctx<K, D>& cx, LaneState<K, D>& 
                                           double (*leaf_de)[6] /* [NLEAF][6] or null */) {
   using C = Cfg<K, D>;
   if constexpr (H < C::NLEAF) {
-    const LamRow row = load_row(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, lane_pos<K, D, H>(cx.t));
     double eL[6], eR[6], dah[3];
     laminate_descend(st.G[H - 1], st.g[H - 1], e, row.nv, row.c1, row.c2, dah, eL, eR);
     if (commit) {
@@ -309,7 +330,7 @@ __device__ __forceinline__ void direction(const Ctx<K, D>& cx, LaneState<K, D>& 
     if (upper_active(cx.t, m)) {
       const int pos = upper_pos<K, D>(m, cx.t);
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row(cx.tab, pos);
+      const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, pos);
       double Gu[18], gu[3], dau[3], eL[6];
 #pragma unroll
       for (int k = 0; k < 18; ++k) Gu[k] = up.G[k][u];
