@@ -81,7 +81,8 @@ __device__ __forceinline__ const double* stage_table(TableLds<K>& lds, const dou
   }
 }
 
-// LDS storage of the upper laminates of all points of a wave (SoA by field).
+// LDS storage of the upper laminates of all points of a wave (SoA by field):
+// top-down factors and jumps per upper laminate.
 template <int K, int D>
 struct UpperLds {
   double G[18][Cfg<K, D>::SLOTS];
@@ -153,37 +154,33 @@ __device__ __forceinline__ void loc_node(const Ctx<K, D>& cx, const LaneState<K,
   }
 }
 
-// Leaf strains at jumps a + s da (wave-uniform: contains shuffles).
+// Leaf strains at jumps a + s da.  The macro strain reaching a lane's subtree
+// root is E plus one term per upper ancestor (-c2 N a on the left of it,
+// +c1 N a on the right), so every lane sums its ancestors' contributions
+// directly, without a chain through the levels.  Reads jumps written by other
+// lanes of the wave: synchronises first.
 template <int K, int D>
 __device__ __forceinline__ void localize(const Ctx<K, D>& cx, const LaneState<K, D>& st,
                                          const UpperLds<K, D>& up, const double (&E)[6], double s,
                                          double (&eps)[Cfg<K, D>::NLEAF][6]) {
   using C = Cfg<K, D>;
+  __syncthreads();
   double e[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) e[k] = E[k];
 #pragma unroll 1
   for (int m = C::UPLEV; m >= 1; --m) {
-    const int o = 1 << (m - 1);
-    double eR[6] = {0, 0, 0, 0, 0, 0};
-    if (upper_active(cx.t, m)) {
-      const int pos = upper_pos<K, D>(m, cx.t);
-      const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, pos);
-      double aj[3], eL[6];
+    const int lead = cx.t & ~((1 << m) - 1);
+    const int pos = upper_pos<K, D>(m, lead);
+    const int u = cx.slot * C::NUPS + (pos - C::UP0);
+    const LamRow row = load_row_soa<C::L>(cx.tab, pos);
+    double aj[3], Na[6];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) aj[k] = up.a[k][u] + s * up.da[k][u];
-      laminate_localize(aj, e, row.nv, row.c1, row.c2, eL, eR);
+    for (int k = 0; k < 3; ++k) aj[k] = up.a[k][u] + s * up.da[k][u];
+    row.nv.apply(aj, Na);
+    const double f = ((cx.t >> (m - 1)) & 1) ? row.c1 : -row.c2;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = eL[k];
-    }
-    double rcv[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
-    if (upper_right(cx.t, m)) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = rcv[k];
-    }
+    for (int k = 0; k < 6; ++k) e[k] += f * Na[k];
   }
   loc_node<K, D, 1>(cx, st, s, e, eps);
 }
@@ -315,46 +312,40 @@ __device__ __forceinline__ void down_node(const Ctx<K, D>& cx, LaneState<K, D>& 
   }
 }
 
-// Newton increments da for all laminates of the points with commit set
-// (wave-uniform: contains shuffles).
+// Newton increments da for all laminates of the points with commit set.
+// Every lane walks its own root path through the upper levels (lanes of a
+// group repeat their shared ancestors' small top-down step instead of
+// exchanging it); the group leader stores the upper increments.  Reads
+// factors written by other lanes: synchronises first.
 template <int K, int D>
 __device__ __forceinline__ void direction(const Ctx<K, D>& cx, LaneState<K, D>& st,
                                           UpperLds<K, D>& up, bool commit,
                                           double (*leaf_de)[6] = nullptr) {
   using C = Cfg<K, D>;
+  __syncthreads();
   double e[6] = {0, 0, 0, 0, 0, 0};  // the macro strain is fixed during Newton
 #pragma unroll 1
   for (int m = C::UPLEV; m >= 1; --m) {
-    const int o = 1 << (m - 1);
-    double eR[6] = {0, 0, 0, 0, 0, 0};
-    if (upper_active(cx.t, m)) {
-      const int pos = upper_pos<K, D>(m, cx.t);
-      const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, pos);
-      double Gu[18], gu[3], dau[3], eL[6];
+    const int lead = cx.t & ~((1 << m) - 1);
+    const int pos = upper_pos<K, D>(m, lead);
+    const int u = cx.slot * C::NUPS + (pos - C::UP0);
+    const LamRow row = load_row_soa<C::L>(cx.tab, pos);
+    double Gu[18], gu[3], dau[3], eL[6], eR[6];
 #pragma unroll
-      for (int k = 0; k < 18; ++k) Gu[k] = up.G[k][u];
+    for (int k = 0; k < 18; ++k) Gu[k] = up.G[k][u];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) gu[k] = up.g[k][u];
-      laminate_descend(Gu, gu, e, row.nv, row.c1, row.c2, dau, eL, eR);
-      if (commit) {
+    for (int k = 0; k < 3; ++k) gu[k] = up.g[k][u];
+    laminate_descend(Gu, gu, e, row.nv, row.c1, row.c2, dau, eL, eR);
+    if (commit && cx.t == lead) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) up.da[k][u] = dau[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = eL[k];
+      for (int k = 0; k < 3; ++k) up.da[k][u] = dau[k];
     }
-    double rcv[6];
+    const bool right = (cx.t >> (m - 1)) & 1;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) rcv[k] = shfl_up_d(eR[k], o, C::LP);
-    if (upper_right(cx.t, m)) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = rcv[k];
-    }
+    for (int k = 0; k < 6; ++k) e[k] = right ? eR[k] : eL[k];
   }
   down_node<K, D, 1>(cx, st, commit, e, leaf_de);
 }
-
 
 }  // namespace tree
 }  // namespace dmn
