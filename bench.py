@@ -5,9 +5,11 @@ One bench step is one pass of the whole hot path over one batch:
   * one load step of the depth-8 production workload: 65,536 Gauss points,
     FP64 (parameter prep, localisation, J2 leaves, tree Newton with
     backtracking, stress + tangent + state), taken in order along the seeded
-    20-step strain path; and
+    20-step strain path;
   * one training forward + backward of the depth-8 linear DMN map on a batch
-    of 4,096 phase-stiffness pairs (FP64) with a seeded cotangent.
+    of 4,096 phase-stiffness pairs (FP64) with a seeded cotangent; and
+  * one load-step adjoint of the depth-8 path-sensitivity workload (16,384
+    points at step 25 of their 50-step path, cotangents of stress and state).
 
 Inputs are synthetic (see synthetic/), resident on the GPU before timing.
 Prints one JSON line.  `value` is Gauss-point updates per second of whole
@@ -30,6 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "DMN Gauss-point updates/s (stress+tangent, depth 8, FP64) + train fwd+bwd samples/s"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gp_update_depth8_traffic.json")
 GP_SOURCES = ["paper_2103_08253_amd/csrc/dmn_gp.hip", "paper_2103_08253_amd/csrc/dmn_algebra.hpp",
+              "paper_2103_08253_amd/csrc/dmn_tree.hpp",
               "paper_2103_08253_amd/csrc/dmn_internal.hpp"]
 
 
@@ -112,8 +115,9 @@ def main():
     import torch
 
     import synthetic as S
-    from paper_2103_08253_amd import (PointGroup, dmn_homogenize_backward,
-                                      dmn_homogenize_linear, dmn_update_gauss_points)
+    from paper_2103_08253_amd import (AdjointGroup, PointGroup, dmn_homogenize_backward,
+                                      dmn_homogenize_linear, dmn_update_adjoint,
+                                      dmn_update_gauss_points)
     from paper_2103_08253_amd import roofline as R
     from paper_2103_08253_amd import _lib
 
@@ -134,6 +138,38 @@ def main():
     Gc = torch.tensor(S.streams(3)["cotangent"].standard_normal((B, 6, 6)), device=dev)
     wt = torch.tensor(tw.v0, device=dev)
     nt = torch.tensor(S.angles_to_normals(tw.alpha0, tw.beta0), device=dev)
+
+    # adjoint workload: state of the 16,384-point path at its step 25
+    wa = S.config4()
+    neta = wa.nets[0]
+    Ea = torch.tensor(wa.E[:26], device=dev)
+    wadj = torch.tensor(neta.w, device=dev)
+    nadj = torch.tensor(neta.normals, device=dev)
+    ga = PointGroup.allocate(wadj, nadj, Ea[0])
+    ws_a = None
+    for k in range(25):
+        ga.E = Ea[k]
+        ws_a = dmn_update_gauss_points([ga], S.FIBER, S.MATRIX, ws=ws_a)
+        ga.advance()
+    z25 = ga.z_in.clone()
+    ga.E = Ea[25]
+    dmn_update_gauss_points([ga], S.FIBER, S.MATRIX, ws=ws_a)
+    Pa = wa.n_points
+    rs_a = S.streams(4)
+    g_sig = torch.tensor(wa.g_sigma, device=dev)
+    g_znext = torch.tensor(1e3 * rs_a["cotangent"].standard_normal((Pa, 128, 7)), device=dev)
+    g_zprev = torch.empty_like(g_znext)
+    gw_a = torch.zeros(256, dtype=torch.float64, device=dev)
+    gn_a = torch.zeros((255, 3), dtype=torch.float64, device=dev)
+    adj = AdjointGroup(wadj, nadj, Ea[25], z25, ga.a_out.clone(), g_sig, g_znext, g_zprev,
+                       gw_a, gn_a)
+    ws_adj = None
+
+    # one-off device copy of a known size (calibrates HBM byte counters in profiles)
+    calib_src = torch.empty(256 * 2 ** 20, dtype=torch.uint8, device=dev)
+    calib_dst = torch.empty_like(calib_src)
+    calib_dst.copy_(calib_src)
+    del calib_src, calib_dst
 
     ws_gp = None
     ws_lin = ws_bwd = None
@@ -156,15 +192,20 @@ def main():
         out = dmn_homogenize_backward(wt, nt, C1, C2, Gc, ws=ws_bwd)
         ws_bwd = out[-1]
 
+    def adjoint_step():
+        nonlocal ws_adj
+        ws_adj = dmn_update_adjoint([adj], S.FIBER, S.MATRIX, ws=ws_adj)
+
     for k in range(args.warmup):
         gp_step(k)
         train_step()
+        adjoint_step()
     torch.cuda.synchronize()
     reset_state()
 
     K = args.steps
     iters_log = torch.empty((K, P), dtype=torch.int32, device=dev)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
@@ -175,11 +216,15 @@ def main():
         ev[k][2].record()
         train_step()
         ev[k][3].record()
+        ev[k][4].record()
+        adjoint_step()
+        ev[k][5].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     gp_ms = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)])
     tr_ms = np.array([ev[k][2].elapsed_time(ev[k][3]) for k in range(K)])
+    ad_ms = np.array([ev[k][4].elapsed_time(ev[k][5]) for k in range(K)])
     status_ok = bool((g.status == 0).all().item())
     it = iters_log.cpu().numpy()
     flops = np.array([sum(int(c) * R.gp_update_flops(8, int(v))
@@ -201,7 +246,8 @@ def main():
         dtype="f64", data="synthetic",
         config=dict(workload="depth8_production: 65536 Gauss points, 20-step strain path "
                              "(ramp to 1.5 % + N(0,1e-3) walk), J2 matrix + elastic fibre; "
-                             "plus depth-8 linear fwd+bwd on 4096 SPD phase pairs",
+                             "plus depth-8 linear fwd+bwd on 4096 SPD phase pairs and one "
+                             "load-step adjoint on 16384 points",
                     depth=8, gauss_points=P, load_steps_in_path=T, train_batch=B,
                     newton_tol=1e-10),
         train_samples_per_s=B * K / (tr_ms.sum() * 1e-3),
@@ -214,7 +260,9 @@ def main():
                            algorithmic_bytes_per_launch=bytes_launch),
             train_fwd_bwd=dict(ms_mean=float(tr_ms.mean()),
                                samples_per_s=float(B / (tr_ms.mean() * 1e-3)),
-                               tflops=float(train_flops / (tr_ms.mean() * 1e-3) / 1e12))),
+                               tflops=float(train_flops / (tr_ms.mean() * 1e-3) / 1e12)),
+            path_adjoint_step=dict(ms_mean=float(ad_ms.mean()), points=Pa,
+                                   point_steps_per_s=float(Pa / (ad_ms.mean() * 1e-3)))),
         roofline=dict(bound="alu", achieved=float(achieved_tf), peak=R.FP64_PEAK_TFLOPS,
                       unit="TFLOP/s", frac=float(achieved_tf / R.FP64_PEAK_TFLOPS),
                       traffic=traffic, kernel="gp_update_kernel<8,2> (FP64 VALU)"),

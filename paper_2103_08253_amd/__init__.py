@@ -6,6 +6,7 @@ linear DMN homogenisation used in offline training and its hand-written
 backward.  All computation runs in the HIP kernels of libdmn.so; this package
 only marshals arguments.
 """
-from .api import (PointGroup, dmn_homogenize_backward, dmn_homogenize_linear,  # noqa: F401
-                  dmn_update_gauss_points, error_word, workspace)
+from .api import (AdjointGroup, PointGroup, dmn_homogenize_backward,  # noqa: F401
+                  dmn_homogenize_linear, dmn_update_adjoint, dmn_update_gauss_points,
+                  error_word, workspace)
 from ._lib import DmnError, STATUS  # noqa: F401
