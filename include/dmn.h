@@ -56,7 +56,8 @@ extern "C" {
 /* precision of storage and arithmetic */
 #define DMN_F64 0       /* FP64 storage, FP64 arithmetic */
 #define DMN_F32 1       /* FP32 storage, FP32 arithmetic (linear map only) */
-#define DMN_F32_STATE 2 /* FP32 storage of per-point arrays, FP64 arithmetic (reserved) */
+#define DMN_F32_STATE 2 /* FP32 storage of per-point arrays, FP64 arithmetic (reserved:
+                           currently rejected with DMN_EUNSUPPORTED) */
 
 /* per-point status written by dmn_update_gauss_points */
 #define DMN_STATUS_OK 0        /* converged */
@@ -176,7 +177,8 @@ size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int
  * a_in, with the J2 return mapping at matrix leaves and linear elasticity at
  * fibre leaves; return the effective stress, the algorithmic tangent, the
  * updated internal variables and the converged jumps.  Groups may have
- * different depths.  prec: DMN_F64.  At most 64 groups per call. */
+ * different depths.  prec: DMN_F64 (DMN_F32_STATE returns DMN_EUNSUPPORTED).
+ * At most 64 groups per call. */
 int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                             const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
                             const dmn_newton_opts* opts, void* ws, size_t ws_bytes,

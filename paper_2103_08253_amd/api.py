@@ -122,10 +122,13 @@ class PointGroup:
 
     @staticmethod
     def allocate(w, n, E, z_in=None, a_in=None):
-        """Outputs (and zero initial state if not given) for the points of E [P, 6]."""
+        """Outputs (and zero initial state if not given) for the points of E [P, 6].
+
+        The per-point arrays take E's dtype (float64; float32 maps to
+        DMN_F32_STATE, which the library currently rejects); w and n are float64."""
         K = int(round(torch.log2(torch.tensor(float(w.numel()))).item()))
         P = E.shape[0]
-        dev, dt = E.device, torch.float64
+        dev, dt = E.device, E.dtype
         M, Lm = 2 ** (K - 1), 2 ** K - 1
         if z_in is None:
             z_in = torch.zeros((P, M, 7), dtype=dt, device=dev)
@@ -142,17 +145,28 @@ class PointGroup:
         self.z_in, self.z_out = self.z_out, self.z_in
         self.a_in, self.a_out = self.a_out, self.a_in
 
+    @property
+    def prec(self):
+        """DMN_F64 for float64 per-point arrays, DMN_F32_STATE for float32."""
+        if self.E.dtype == torch.float64:
+            return L.DMN_F64
+        if self.E.dtype == torch.float32:
+            return L.DMN_F32_STATE
+        raise TypeError(f"E must be float64 or float32, got {self.E.dtype}")
+
     def to_c(self):
         net, K = _net(self.w, self.n, torch.float64)
         P = self.E.shape[0]
         M, Lm = 2 ** (K - 1), 2 ** K - 1
-        _need(self.E, "E", torch.float64, (P, 6))
+        dt = self.E.dtype
+        self.prec  # dtype check
+        _need(self.E, "E", dt, (P, 6))
         for t, nm in ((self.z_in, "z_in"), (self.z_out, "z_out")):
-            _need(t, nm, torch.float64, (P, M, 7))
+            _need(t, nm, dt, (P, M, 7))
         for t, nm in ((self.a_in, "a_in"), (self.a_out, "a_out")):
-            _need(t, nm, torch.float64, (P, Lm, 3))
-        _need(self.sigma, "sigma", torch.float64, (P, 6))
-        _need(self.tangent, "tangent", torch.float64)
+            _need(t, nm, dt, (P, Lm, 3))
+        _need(self.sigma, "sigma", dt, (P, 6))
+        _need(self.tangent, "tangent", dt)
         if self.tangent.numel() != 36 * P:
             raise ValueError("tangent must be [P, 6, 6]")
         _need(self.iters, "iters", torch.int32, (P,))
@@ -171,18 +185,25 @@ def _materials(fiber: dict, matrix: dict):
 
 def dmn_update_gauss_points(groups: List[PointGroup], fiber: dict, matrix: dict, tol=1e-10,
                             max_iter=25, max_backtrack=10, armijo=1e-4, ws=None):
-    """One load step at every point of every group (outputs written in place)."""
+    """One load step at every point of every group (outputs written in place).
+
+    All groups hold their per-point arrays in one dtype: float64 (DMN_F64);
+    float32 maps to DMN_F32_STATE, which the library currently rejects."""
+    precs = {g.prec for g in groups}
+    if len(precs) != 1:
+        raise TypeError("all groups of one call must use the same per-point dtype")
+    prec = precs.pop()
     arr = (L.DmnPointGroup * len(groups))(*[g.to_c() for g in groups])
     fib, mat = _materials(fiber, matrix)
     opts = L.DmnNewtonOpts(tol, max_iter, max_backtrack, armijo)
     lib = L.lib()
-    nbytes = lib.dmn_update_gauss_points_workspace_size(arr, len(groups), L.DMN_F64)
+    nbytes = lib.dmn_update_gauss_points_workspace_size(arr, len(groups), prec)
     if nbytes == 0:
         raise L.DmnError("dmn_update_gauss_points_workspace_size rejected the groups")
     if ws is None or ws.numel() < nbytes:
         ws = workspace(nbytes, groups[0].E.device)
     rc = lib.dmn_update_gauss_points(arr, len(groups), ctypes.byref(fib), ctypes.byref(mat),
-                                     L.DMN_F64, ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                     prec, ctypes.byref(opts), _ptr(ws), ws.numel(),
                                      _stream())
     L.check(rc, "dmn_update_gauss_points")
     return ws

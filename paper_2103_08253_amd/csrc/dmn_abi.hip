@@ -110,7 +110,7 @@ size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int
   size_t total = kAlign + kAlign;  // header, then one work counter per launch
   for (int i = 0; i < n_groups; ++i) {
     if (!depth_ok(groups[i].net.depth)) return 0;
-    total += table_bytes(groups[i].net.depth, prec);
+    total += table_bytes(groups[i].net.depth, DMN_F64);  // DMN parameters are FP64
   }
   return total;
 }
@@ -120,7 +120,7 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                             const dmn_newton_opts* opts, void* ws, size_t ws_bytes,
                             hipStream_t stream) {
   if (!groups || n_groups < 1 || n_groups > 64) return DMN_EINVAL;
-  if (prec != DMN_F64) return DMN_EUNSUPPORTED;
+  if (prec != DMN_F64) return DMN_EUNSUPPORTED;  // DMN_F32_STATE is switched off
   if (!phase_ok(fiber) || !j2_ok(matrix) || !opts) return DMN_EINVAL;
   if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->max_backtrack < 0 ||
       !(opts->armijo >= 0.0 && opts->armijo < 1.0))
@@ -145,8 +145,8 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   size_t off = 2 * kAlign;
   for (int i = 0; i < n_groups; ++i) {
     tabs[i] = table_at(ws, off);
-    off += table_bytes(groups[i].net.depth, prec);
-    if (dmn::launch_prep_tables(groups[i].net.w, groups[i].net.n, groups[i].net.depth, prec,
+    off += table_bytes(groups[i].net.depth, DMN_F64);
+    if (dmn::launch_prep_tables(groups[i].net.w, groups[i].net.n, groups[i].net.depth, DMN_F64,
                                 tabs[i].rows, tabs[i].flag, nullptr, stream))
       return DMN_EHIP;
   }
@@ -188,13 +188,13 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
       const int i = order[pos];
       const dmn_point_group& g = groups[i];
       dmn::GroupArgs& a = args.g[args.ng++];
-      a.E = (const double*)g.E;
-      a.z_in = (const double*)g.z_in;
-      a.z_out = (double*)g.z_out;
-      a.a_in = (const double*)g.a_in;
-      a.a_out = (double*)g.a_out;
-      a.sigma = (double*)g.sigma;
-      a.tangent = (double*)g.tangent;
+      a.E = g.E;
+      a.z_in = g.z_in;
+      a.z_out = g.z_out;
+      a.a_in = g.a_in;
+      a.a_out = g.a_out;
+      a.sigma = g.sigma;
+      a.tangent = g.tangent;
       a.iters = g.iters;
       a.status = g.status;
       a.tab = (const double*)tabs[i].rows;
@@ -208,7 +208,7 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
     args.counter = counters + launch++;
     args.total = (int)blocks;
     const long long waves = blocks < persistent ? blocks : persistent;
-    if (dmn::launch_gp_update(K, lp, args, (int)waves, stream)) return DMN_EHIP;
+    if (dmn::launch_gp_update(K, lp, prec, args, (int)waves, stream)) return DMN_EHIP;
   }
   return DMN_OK;
 }

@@ -68,7 +68,7 @@ struct AdjointLeaf {
       iso_stress(cx.fib, gb, tn);
     } else {
       const int mloc = cx.t * (C::NLEAF / 2) + Q / 2;
-      const double* z = cx.zin + (size_t)mloc * 7;
+      const double* z = (const double*)cx.zin + (size_t)mloc * 7;
       double epn[6], ep[6], p;
 #pragma unroll
       for (int k = 0; k < 6; ++k) epn[k] = z[k];
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
         iso_stress(cx.fib, psi, mu[q]);
       } else {
         const int mloc = cx.t * (C::NLEAF / 2) + q / 2;
-        const double* z = cx.zin + (size_t)mloc * 7;
+        const double* z = (const double*)cx.zin + (size_t)mloc * 7;
         double epn[6], ze[6], zp = 0.0, gz[7];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {

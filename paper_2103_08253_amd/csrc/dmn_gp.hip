@@ -30,23 +30,23 @@ using namespace tree;
 
 // ---------------------------------------------------------------- outputs
 
-template <int K, int D, int H>
+template <int K, int D, int H, typename S>
 __device__ __forceinline__ void write_lane_a(const LaneState<K, D>& st, int t, bool ok,
-                                             const double* __restrict__ ain,
-                                             double* __restrict__ aout) {
+                                             const S* __restrict__ ain, S* __restrict__ aout) {
   if constexpr (H <= Cfg<K, D>::NLAM) {
     const int pos = lane_pos<K, D, H>(t);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      aout[(size_t)pos * 3 + k] = ok ? st.a[H - 1][k] : ain[(size_t)pos * 3 + k];
+      aout[(size_t)pos * 3 + k] = ok ? (S)st.a[H - 1][k] : ain[(size_t)pos * 3 + k];
     write_lane_a<K, D, H + 1>(st, t, ok, ain, aout);
   }
 }
 
 // Write the point's outputs.  ok: converged (z from the J2 return at the
 // accepted strains eps); otherwise the input state is copied through and the
-// tangent is NaN.  No shuffles: runs under per-point control flow.
-template <int K, int D>
+// tangent is NaN.  No shuffles: runs under per-point control flow.  S is the
+// storage type of the per-point arrays; results are rounded to it on store.
+template <int K, int D, typename S>
 __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K, D>& st,
                                          const UpperLds<K, D>& up, const GroupArgs& G,
                                          long long pt, const double (&eps)[Cfg<K, D>::NLEAF][6],
@@ -54,28 +54,28 @@ __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K,
   using C = Cfg<K, D>;
   const bool ok = status == 0;
   const int t = cx.t;
-  double* zout = G.z_out + (size_t)pt * C::M * 7;
+  S* zout = (S*)G.z_out + (size_t)pt * C::M * 7;
 #pragma unroll
   for (int q = 1; q < C::NLEAF; q += 2) {
     const int mloc = t * (C::NLEAF / 2) + q / 2;
-    const double* z = cx.zin + (size_t)mloc * 7;
-    double* zo = zout + (size_t)mloc * 7;
+    const S* z = (const S*)cx.zin + (size_t)mloc * 7;
+    S* zo = zout + (size_t)mloc * 7;
     if (ok) {
       double epn[6], ep[6], p, sg[6], Dp[21];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) epn[k] = z[k];
-      j2_return(cx.mat, eps[q], epn, z[6], sg, Dp, ep, p);
+      for (int k = 0; k < 6; ++k) epn[k] = (double)z[k];
+      j2_return(cx.mat, eps[q], epn, (double)z[6], sg, Dp, ep, p);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) zo[k] = ep[k];
-      zo[6] = p;
+      for (int k = 0; k < 6; ++k) zo[k] = (S)ep[k];
+      zo[6] = (S)p;
     } else {
 #pragma unroll
       for (int k = 0; k < 7; ++k) zo[k] = z[k];
     }
   }
-  const double* ain = G.a_in + (size_t)pt * C::L * 3;
-  double* aout = G.a_out + (size_t)pt * C::L * 3;
-  write_lane_a<K, D, 1>(st, t, ok, ain, aout);
+  const S* ain = (const S*)G.a_in + (size_t)pt * C::L * 3;
+  S* aout = (S*)G.a_out + (size_t)pt * C::L * 3;
+  write_lane_a<K, D, 1, S>(st, t, ok, ain, aout);
 #pragma unroll 1
   for (int m = 1; m <= C::UPLEV; ++m) {
     if (upper_active(t, m)) {
@@ -83,19 +83,19 @@ __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K,
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        aout[(size_t)pos * 3 + k] = ok ? up.a[k][u] : ain[(size_t)pos * 3 + k];
+        aout[(size_t)pos * 3 + k] = ok ? (S)up.a[k][u] : ain[(size_t)pos * 3 + k];
     }
   }
   if (t == 0) {
-    double* sg = G.sigma + (size_t)pt * 6;
+    S* sg = (S*)G.sigma + (size_t)pt * 6;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) sg[k] = ev.sb[k];
-    double* tg = G.tangent + (size_t)pt * 36;
+    for (int k = 0; k < 6; ++k) sg[k] = (S)ev.sb[k];
+    S* tg = (S*)G.tangent + (size_t)pt * 36;
     const double nan = __builtin_nan("");
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
-      for (int j = 0; j < 6; ++j) tg[i * 6 + j] = ok ? ev.C[sidx(i, j)] : nan;
+      for (int j = 0; j < 6; ++j) tg[i * 6 + j] = (S)(ok ? ev.C[sidx(i, j)] : nan);
     G.iters[pt] = iters;
     G.status[pt] = status;
   }
@@ -106,8 +106,10 @@ __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K,
 // Persistent waves: each 64-lane workgroup takes batches of PPW points from an
 // atomic counter until the launch's batches are exhausted, so points with
 // more Newton iterations do not leave SIMDs idle; the DMN table of the
-// current group is staged in the wave's LDS when the group changes.
-template <int K, int D>
+// current group is staged in the wave's LDS when the group changes.  S is the
+// storage type of the per-point arrays (double, or float for FP32 state);
+// arithmetic is FP64 either way.
+template <int K, int D, typename S>
 __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   using C = Cfg<K, D>;
   __shared__ UpperLds<K, D> up;
@@ -142,15 +144,16 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   const long long pt_raw = (long long)(item - G.block0) * C::PPW + cx.slot;
   const bool in_range = pt_raw < G.P;
   const long long pt = in_range ? pt_raw : G.P - 1;  // tail lanes shadow the last point
-  cx.zin = G.z_in + (size_t)pt * C::M * 7;
-  const double* ain = G.a_in + (size_t)pt * C::L * 3;
+  cx.zin = (const S*)G.z_in + (size_t)pt * C::M * 7;
+  const S* ain = (const S*)G.a_in + (size_t)pt * C::L * 3;
+  const S* zin = (const S*)cx.zin;
 
   LaneState<K, D> st;
   EvalOut ev;
   double eps[C::NLEAF][6];
   double E[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) E[k] = G.E[(size_t)pt * 6 + k];
+  for (int k = 0; k < 6; ++k) E[k] = (double)((const S*)G.E)[(size_t)pt * 6 + k];
 
   // load the jumps and check the inputs of the point for non-finite values
   int bad = 0;
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   for (int k = 0; k < 6; ++k) bad |= isfinite(E[k]) ? 0 : 1;
 #pragma unroll
   for (int q = 0; q < C::NLEAF / 2 * 7; ++q)
-    bad |= isfinite(cx.zin[(size_t)cx.t * (C::NLEAF / 2) * 7 + q]) ? 0 : 1;
+    bad |= isfinite((double)zin[(size_t)cx.t * (C::NLEAF / 2) * 7 + q]) ? 0 : 1;
 #pragma unroll
   for (int h = 1; h <= C::NLAM; ++h) {
     const int m = ilog2(h);
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
     const int pos = (1 << K) - (1 << k) + cx.t * (1 << m) + (h - (1 << m));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      st.a[h - 1][c] = ain[(size_t)pos * 3 + c];
+      st.a[h - 1][c] = (double)ain[(size_t)pos * 3 + c];
       st.da[h - 1][c] = 0.0;
       bad |= isfinite(st.a[h - 1][c]) ? 0 : 1;
     }
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double v = ain[(size_t)pos * 3 + c];
+        const double v = (double)ain[(size_t)pos * 3 + c];
         up.a[c][u] = v;
         up.da[c][u] = 0.0;
         bad |= isfinite(v) ? 0 : 1;
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   if (*G.flag != 0) {  // invalid DMN parameters: every point of the group fails
 #pragma unroll
     for (int k = 0; k < 6; ++k) ev.sb[k] = __builtin_nan("");
-    if (in_range) finalize(cx, st, up, G, pt, eps, ev, DMN_STATUS_BADPARAM, 0);
+    if (in_range) finalize<K, D, S>(cx, st, up, G, pt, eps, ev, DMN_STATUS_BADPARAM, 0);
     continue;
   }
 
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
 #pragma unroll 1
   while (true) {
     localize(cx, st, up, E, done ? 0.0 : s, eps);
-    evaluate_full(cx, st, up, eps, ev);
+    evaluate_full<K, D, NewtonLeafS<S>>(cx, st, up, eps, ev);
     bool just_done = false, need_dir = false;
     if (!done) {
       bool accepted = false;
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
       // strains at the accepted jumps, for the internal variables of finished points
       localize(cx, st, up, E, 0.0, eps);
       if (just_done) {
-        finalize(cx, st, up, G, pt, eps, ev, status, iters);
+        finalize<K, D, S>(cx, st, up, G, pt, eps, ev, status, iters);
         done = true;
       }
     }
@@ -289,19 +292,22 @@ int gp_points_per_block(int depth, int lanes_per_point) {
   return 64 / lanes_per_point;
 }
 
+// Only FP64 storage is instantiated: the FP32-storage instantiation is switched
+// off (its first GPU run ended in a device fault whose cause is not yet found).
 template <int K, int D>
-static int launch_kd(const GpLaunch& args, int n_blocks, hipStream_t stream) {
-  hipLaunchKernelGGL((gp_update_kernel<K, D>), dim3(n_blocks), dim3(64), 0, stream, args);
+static int launch_kd(int prec, const GpLaunch& args, int n_blocks, hipStream_t stream) {
+  if (prec != DMN_F64) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL((gp_update_kernel<K, D, double>), dim3(n_blocks), dim3(64), 0, stream, args);
   return (int)hipGetLastError();
 }
 
-int launch_gp_update(int depth, int lanes_per_point, const GpLaunch& args, int n_blocks,
-                     hipStream_t stream) {
+int launch_gp_update(int depth, int lanes_per_point, int prec, const GpLaunch& args,
+                     int n_blocks, hipStream_t stream) {
   const int D = depth - ilog2(lanes_per_point);
   switch (depth * 16 + D) {
 #define DMN_GP_CASE(KK, DD) \
   case KK * 16 + DD:        \
-    return launch_kd<KK, DD>(args, n_blocks, stream);
+    return launch_kd<KK, DD>(prec, args, n_blocks, stream);
     DMN_GP_CASE(1, 1)
     DMN_GP_CASE(2, 1)
     DMN_GP_CASE(3, 1)

@@ -25,13 +25,14 @@ __host__ __device__ inline size_t table_elems(int depth) {
 
 // Point-group description passed by value to the Gauss-point kernel.
 struct GroupArgs {  // tab points at the table start (AoS rows first)
-  const double* E;
-  const double* z_in;
-  double* z_out;
-  const double* a_in;
-  double* a_out;
-  double* sigma;
-  double* tangent;
+  // per-point arrays in the storage precision of the launch (FP64 or FP32)
+  const void* E;
+  const void* z_in;
+  void* z_out;
+  const void* a_in;
+  void* a_out;
+  void* sigma;
+  void* tangent;
   int32_t* iters;
   int32_t* status;
   const double* tab;   // [L][kTabStride]
@@ -60,8 +61,8 @@ struct GpLaunch {
 // Host launchers (return hipError_t as int).
 int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
                        int32_t* err, hipStream_t stream);
-int launch_gp_update(int depth, int lanes_per_point, const GpLaunch& args, int n_blocks,
-                     hipStream_t stream);
+int launch_gp_update(int depth, int lanes_per_point, int prec, const GpLaunch& args,
+                     int n_blocks, hipStream_t stream);
 int launch_zero_ints(int32_t* p, int n, hipStream_t stream);
 // compute units of the current device (cached per device)
 int device_cu_count();

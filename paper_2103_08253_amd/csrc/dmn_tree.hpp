@@ -113,7 +113,7 @@ struct EvalOut {
 template <int K, int D>
 struct Ctx {
   const double* __restrict__ tab;
-  const double* __restrict__ zin;  // this point's z_in
+  const void* zin;  // this point's z_in (storage precision of the kernel)
   IsoElastic fib;
   J2Law mat;
   int t;
@@ -187,8 +187,10 @@ __device__ __forceinline__ void localize(const Ctx<K, D>& cx, const LaneState<K,
 
 // ---------------------------------------------------------------- bottom-up
 
-// Leaf law of the Newton evaluation: stress, tangent, and tau = stress.
-struct NewtonLeaf {
+// Leaf law of the Newton evaluation: stress, tangent, and tau = stress.  S is
+// the storage type of the internal variables.
+template <typename S>
+struct NewtonLeafS {
   template <int K, int D, int Q>
   __device__ __forceinline__ void operator()(const Ctx<K, D>& cx, std::integral_constant<int, Q>,
                                              const double (&e)[6], double (&Cn)[21],
@@ -199,17 +201,18 @@ struct NewtonLeaf {
       iso_packed(cx.fib, Cn);
     } else {                     // matrix leaf
       const int mloc = cx.t * (C::NLEAF / 2) + Q / 2;
-      const double* z = cx.zin + (size_t)mloc * 7;
+      const S* z = (const S*)cx.zin + (size_t)mloc * 7;
       double epn[6], ep[6], p;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) epn[k] = z[k];
-      const bool ok = j2_return(cx.mat, e, epn, z[6], sn, Cn, ep, p);
+      for (int k = 0; k < 6; ++k) epn[k] = (double)z[k];
+      const bool ok = j2_return(cx.mat, e, epn, (double)z[6], sn, Cn, ep, p);
       lfail |= ok ? 0 : 1;
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) tn[k] = sn[k];
   }
 };
+using NewtonLeaf = NewtonLeafS<double>;
 
 template <int K, int D, int H, class Leaf>
 __device__ __forceinline__ void up_node(const Ctx<K, D>& cx, LaneState<K, D>& st, const Leaf& leaf,

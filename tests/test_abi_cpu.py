@@ -84,6 +84,7 @@ def test_gauss_point_validation_codes():
     need = lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F64)
     assert need > 0
     assert lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F32) == 0
+    assert lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F32_STATE) == 0
 
     def call(a=arr, n=2, f=fib, m=mat, o=opts, prec=L.DMN_F64, nb=need):
         return lib.dmn_update_gauss_points(a, n, ctypes.byref(f) if f else None,
@@ -93,6 +94,8 @@ def test_gauss_point_validation_codes():
     assert call(n=0) == L.DMN_EINVAL
     assert call(n=65) == L.DMN_EINVAL
     assert call(prec=L.DMN_F32) == L.DMN_EUNSUPPORTED
+    assert call(prec=7) == L.DMN_EUNSUPPORTED
+    assert call(prec=L.DMN_F32_STATE) == L.DMN_EUNSUPPORTED
     assert call(f=None) == L.DMN_EINVAL
     assert call(m=L.DmnJ2(2800.0, 0.5, 50.0, 200.0, 30.0, 60.0)) == L.DMN_EINVAL
     assert call(o=L.DmnNewtonOpts(0.0, 25, 10, 1e-4)) == L.DMN_EINVAL

@@ -168,6 +168,123 @@ def test_gp_mixed_depth_groups_one_call():
         compare_paths(net, Em, range(min(len(sel), 2)), gpu)
 
 
+F32_STATE_RTOL = 1e-4
+
+
+def gpu_groups_path(nets, E_path, idx, dtype):
+    """Run one call per step over several groups; per-step, per-group host copies."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    d = dev()
+    groups = [PointGroup.allocate(torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d),
+                                  torch.tensor(E_path[0, sel], device=d, dtype=dtype))
+              for net, sel in zip(nets, idx)]
+    outs = []
+    for step in range(E_path.shape[0]):
+        for g, sel in zip(groups, idx):
+            g.E.copy_(torch.tensor(E_path[step, sel], device=d, dtype=dtype))
+        dmn_update_gauss_points(groups, S.FIBER, S.MATRIX)
+        torch.cuda.synchronize()
+        outs.append([dict(sigma=g.sigma.double().cpu().numpy(), C=g.tangent.double().cpu().numpy(),
+                          z=g.z_out.double().cpu().numpy(), status=g.status.cpu().numpy())
+                     for g in groups])
+        for g in groups:
+            g.advance()
+    return outs
+
+
+@pytest.mark.skip(reason="DMN_F32_STATE is switched off: its first GPU run ended in a device "
+                  "fault with no cause found yet (a CPU emulation of the kernel under "
+                  "AddressSanitizer shows no out-of-bounds access on this case)")
+def test_gp_f32_state_mixed_groups():
+    """FP32-stored state (DMN_F32_STATE) over 16 mixed-depth groups, 6 steps.
+
+    Against the FP64 oracle on the FP32-rounded strains (2 points per group) and
+    against the GPU FP64 path on every point: sigma within 1e-4 everywhere, the
+    tangent within 1e-4 wherever both paths take the same elastic/plastic
+    decision at every matrix leaf (a decision within FP32 rounding of the
+    yield surface may flip, and the tangent jumps there)."""
+    say("case: gp FP32 state, 16 mixed-depth groups, 256 points x 6 steps")
+    wl = S.config2(n_points=256, n_steps=6)
+    E32 = wl.E.astype(np.float32).astype(np.float64)
+    idx = [np.nonzero(wl.dmn_id == m)[0] for m in range(len(wl.nets))]
+    f32 = gpu_groups_path(wl.nets, E32, idx, torch.float32)
+    f64 = gpu_groups_path(wl.nets, E32, idx, torch.float64)
+    worst_o, worst_s, worst_c, flips = 0.0, 0.0, 0.0, 0
+    for m, net in enumerate(wl.nets):
+        sel = idx[m]
+        if len(sel) == 0:
+            continue
+        model = DmnModel(net.depth, net.w, net.normals, S.FIBER, S.MATRIX)
+        for p in range(min(len(sel), 2)):
+            ref = run_path(model, E32[:, sel[p], :], NewtonOptions())
+            if min(r["margin"] for r in ref) < 1e-5:
+                continue
+            for step, r in enumerate(ref):
+                g = f32[step][m]
+                assert g["status"][p] == 0 and r["status"] == 0
+                e = max(rel(g["sigma"][p], r["sigma"]), rel(g["C"][p], r["C"]))
+                worst_o = max(worst_o, e)
+                assert e <= F32_STATE_RTOL, (m, p, step, e)
+        same = np.ones(len(sel), bool)
+        for step in range(wl.n_steps):
+            a, b = f32[step][m], f64[step][m]
+            assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+            zin_a = f32[step - 1][m]["z"][..., 6] if step else 0.0
+            zin_b = f64[step - 1][m]["z"][..., 6] if step else 0.0
+            same &= np.all((a["z"][..., 6] > zin_a) == (b["z"][..., 6] > zin_b), axis=1)
+            for p in range(len(sel)):
+                es = rel(a["sigma"][p], b["sigma"][p])
+                worst_s = max(worst_s, es)
+                assert es <= F32_STATE_RTOL, (m, p, step, es)
+                if same[p]:
+                    ec = rel(a["C"][p], b["C"][p])
+                    worst_c = max(worst_c, ec)
+                    assert ec <= F32_STATE_RTOL, (m, p, step, ec)
+        flips += int((~same).sum())
+    say(f"  worst rel vs oracle {worst_o:.2e}; vs GPU FP64 sigma {worst_s:.2e} C {worst_c:.2e}; "
+        f"{flips} points with a flipped leaf decision")
+    assert flips <= 8
+
+
+@pytest.mark.skip(reason="DMN_F32_STATE is switched off: its first GPU run ended in a device "
+                  "fault with no cause found yet (a CPU emulation of the kernel under "
+                  "AddressSanitizer shows no out-of-bounds access on this case)")
+def test_gp_f32_state_depth8_production_size_sampled():
+    """FP32 state at the production size (depth 8, 65,536 points, 20 steps);
+    the FP64 oracle follows 4 sampled points on the FP32-rounded strains."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    say("case: gp FP32 state, depth 8, 65536 points x 20 steps, 4 sampled")
+    d = dev()
+    wl = S.config1()
+    net = wl.nets[0]
+    E32 = torch.tensor(wl.E, device=d, dtype=torch.float32)
+    picks = S.streams(1)["picks"].choice(wl.n_points, 4, replace=False)
+    g = PointGroup.allocate(torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d),
+                            E32[0].clone())
+    sig, tan = [], []
+    pk = torch.tensor(picks, device=d)
+    ws = None
+    for step in range(wl.n_steps):
+        g.E.copy_(E32[step])
+        ws = dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws)
+        assert bool((g.status == 0).all())
+        sig.append(g.sigma[pk].double().cpu().numpy())
+        tan.append(g.tangent[pk].double().cpu().numpy())
+        g.advance()
+    model = DmnModel(net.depth, net.w, net.normals, S.FIBER, S.MATRIX)
+    E_ref = E32.double().cpu().numpy()
+    worst = 0.0
+    for i, p in enumerate(picks):
+        ref = run_path(model, E_ref[:, p, :], NewtonOptions())
+        if min(r["margin"] for r in ref) < 1e-5:
+            continue
+        for step, r in enumerate(ref):
+            e = max(rel(sig[step][i], r["sigma"]), rel(tan[step][i], r["C"]))
+            worst = max(worst, e)
+            assert e <= F32_STATE_RTOL, (p, step, e)
+    say(f"  worst rel vs oracle {worst:.2e}")
+
+
 def test_gp_status_codes_and_failure_state():
     from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
     say("case: gp status codes")
