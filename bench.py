@@ -11,6 +11,13 @@ One bench step is one pass of the whole hot path over one batch:
   * one load-step adjoint of the depth-8 path-sensitivity workload (16,384
     points at step 25 of their 50-step path, cotangents of stress and state).
 
+The launch of each depth is autotuned first (lanes per point, persistent
+waves; cached on disk).  Reported beside the headline, outside its timed
+region: the mixed-depth batch (131,072 points over 16 DMNs of depths 5-9,
+the 20-step path captured as one HIP graph and replayed), and the plain
+one-launch-per-point and one-launch-per-sample forms of the same library on
+the same GPU, for comparison with the batched launches.
+
 Inputs are synthetic (see synthetic/), resident on the GPU before timing.
 Prints one JSON line.  `value` is Gauss-point updates per second of whole
 step time; the training rate and per-component times are reported beside it,
@@ -18,6 +25,7 @@ together with the roofline of the dominant kernel and the FP64 CPU oracle
 timed on a bounded sample on the host cores.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2] [--no-cpu-baseline]
+                    [--no-autotune] [--no-extras]
 """
 import argparse
 import hashlib
@@ -104,6 +112,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=24)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-batch graph and the one-launch-per-point forms")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single "
@@ -118,6 +129,7 @@ def main():
     from paper_2103_08253_amd import (AdjointGroup, PointGroup, dmn_homogenize_backward,
                                       dmn_homogenize_linear, dmn_update_adjoint,
                                       dmn_update_gauss_points)
+    from paper_2103_08253_amd import autotune as A
     from paper_2103_08253_amd import roofline as R
     from paper_2103_08253_amd import _lib
 
@@ -173,6 +185,12 @@ def main():
 
     ws_gp = None
     ws_lin = ws_bwd = None
+    tuned = {}
+    if not args.no_autotune:
+        tuned = A.tune_gauss_points([g], S.FIBER, S.MATRIX)
+        g.z_in.zero_()
+        g.a_in.zero_()
+    lanes8, waves8 = A.get_tuning(8)
 
     def reset_state():
         g.z_in.zero_()
@@ -252,7 +270,8 @@ def main():
                     newton_tol=1e-10),
         train_samples_per_s=B * K / (tr_ms.sum() * 1e-3),
         components=dict(
-            gp_update=dict(ms_mean=float(gp_ms.mean()), ms_min=float(gp_ms.min()),
+            gp_update=dict(tuning=[lanes8, waves8], ms_mean=float(gp_ms.mean()),
+                           ms_min=float(gp_ms.min()),
                            ms_max=float(gp_ms.max()),
                            updates_per_s=float(P / (gp_ms.mean() * 1e-3)),
                            mean_newton_iters=float(it.mean()), all_converged=status_ok,
@@ -267,9 +286,141 @@ def main():
                       unit="TFLOP/s", frac=float(achieved_tf / R.FP64_PEAK_TFLOPS),
                       traffic=traffic, kernel="gp_update_kernel<8,2> (FP64 VALU)"),
     )
+    rec["roofline"]["kernel"] = (f"gp_update_kernel<8,{8 - (lanes8.bit_length() - 1)}> "
+                                 f"({lanes8} lanes per point, {waves8} waves/CU; FP64 VALU)")
+    if not args.no_extras:
+        rec["components"].update(extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2,
+                                        Gc, wt, nt, tuned))
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args.cpu_points)
     print(json.dumps(rec), flush=True)
+
+
+def _graph_of(fn):
+    """Capture fn's library calls into a HIP graph (removes the host-side cost
+    of issuing many small calls from the timing)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(graph, stream=stream):
+        fn()
+    torch.cuda.current_stream().wait_stream(stream)
+    return graph
+
+
+def _event_ms(fn, reps=1):
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b)
+
+
+def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tuned):
+    """Mixed-depth batch as a replayed HIP graph, and the plain one-launch-per-
+    point / per-sample forms of the same calls (timed apart from the headline)."""
+    import numpy as np
+    import torch
+    import synthetic as S
+    from paper_2103_08253_amd import (LoadStepGraph, PointGroup, dmn_homogenize_backward,
+                                      dmn_homogenize_linear, dmn_update_gauss_points)
+    from paper_2103_08253_amd import autotune as A
+    out = {}
+
+    # batched vs one launch per point, both at load step 10 of the production path
+    reset_state()
+    for k in range(10):
+        gp_step(k)
+    g.E = E_path[10]
+    torch.cuda.synchronize()
+    ws = dmn_update_gauss_points([g], S.FIBER, S.MATRIX)
+    P = g.E.shape[0]
+    batched_ms = _event_ms(lambda: dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws), 3) / 3
+    n_plain = 512
+    picks = np.linspace(0, P - 1, n_plain).astype(int)
+    singles = [PointGroup(g.w, g.n, g.E[p:p + 1], g.z_in[p:p + 1], g.z_out[p:p + 1],
+                          g.a_in[p:p + 1], g.a_out[p:p + 1], g.sigma[p:p + 1],
+                          g.tangent[p:p + 1], g.iters[p:p + 1], g.status[p:p + 1])
+                for p in picks]
+    ws1 = dmn_update_gauss_points([singles[0]], S.FIBER, S.MATRIX)
+
+    def plain():
+        for sg in singles:
+            dmn_update_gauss_points([sg], S.FIBER, S.MATRIX, ws=ws1)
+    plain_graph = _graph_of(plain)
+    plain_graph.replay()
+    plain_ms = _event_ms(plain_graph.replay) / n_plain
+    out["gp_update_one_launch_per_point"] = dict(
+        points_sampled=n_plain, load_step=10, issued_as="one library call per point, "
+        "replayed from a HIP graph (device time only)", us_per_point=plain_ms * 1e3,
+        updates_per_s=1e3 / plain_ms, batched_updates_per_s=P / (batched_ms * 1e-3),
+        batched_speedup=(plain_ms * P) / batched_ms)
+
+    # training: one launch per sample vs the batch
+    n_s = 128
+    singles_t = [(C1[b:b + 1], C2[b:b + 1], Gc[b:b + 1]) for b in range(n_s)]
+    _, wsf = dmn_homogenize_linear(wt, nt, C1[:1], C2[:1])
+    wsb = dmn_homogenize_backward(wt, nt, C1[:1], C2[:1], Gc[:1])[-1]
+
+    def plain_train():
+        for c1, c2, gc in singles_t:
+            dmn_homogenize_linear(wt, nt, c1, c2, ws=wsf)
+            dmn_homogenize_backward(wt, nt, c1, c2, gc, ws=wsb)
+    train_graph = _graph_of(plain_train)
+    train_graph.replay()
+    pt_ms = _event_ms(train_graph.replay) / n_s
+    _, wsf_b = dmn_homogenize_linear(wt, nt, C1, C2)
+    wsb_b = dmn_homogenize_backward(wt, nt, C1, C2, Gc)[-1]
+
+    def batch_train():
+        dmn_homogenize_linear(wt, nt, C1, C2, ws=wsf_b)
+        dmn_homogenize_backward(wt, nt, C1, C2, Gc, ws=wsb_b)
+    batch_train()
+    bt_ms = _event_ms(batch_train, 5) / 5
+    out["train_one_launch_per_sample"] = dict(
+        samples_sampled=n_s, issued_as="forward + backward call per sample, replayed from a "
+        "HIP graph (device time only)", us_per_sample=pt_ms * 1e3, samples_per_s=1e3 / pt_ms,
+        batched_samples_per_s=B / (bt_ms * 1e-3), batched_speedup=(pt_ms * B) / bt_ms)
+
+    # mixed-depth batch: 16 DMNs, 131,072 points, the 20-step path as one graph
+    wl = S.config2()
+    groups, E_steps = [], []
+    for m, net in enumerate(wl.nets):
+        sel = np.nonzero(wl.dmn_id == m)[0]
+        Em = torch.tensor(np.ascontiguousarray(wl.E[:, sel, :]), device=dev)
+        E_steps.append(Em)
+        groups.append(PointGroup.allocate(torch.tensor(net.w, device=dev),
+                                          torch.tensor(net.normals, device=dev), Em[0].clone()))
+    mixed_tuned = {} if args.no_autotune else A.tune_gauss_points(groups, S.FIBER, S.MATRIX)
+    for gr in groups:
+        gr.z_in.zero_()
+        gr.a_in.zero_()
+    graph = LoadStepGraph(groups, S.FIBER, S.MATRIX, E_steps, keep_sigma=False)
+
+    def replay():
+        for z, a in graph.start_state:
+            z.zero_()
+            a.zero_()
+        graph.replay()
+    replay()
+    torch.cuda.synchronize()
+    ok = all(bool((gr.status == 0).all().item()) for gr in groups)
+    ms = _event_ms(replay, 2) / 2
+    Pm = wl.n_points
+    out["mixed_batch_graph"] = dict(
+        points=Pm, dmns=len(wl.nets), depths=sorted({n.depth for n in wl.nets}),
+        load_steps_per_replay=wl.n_steps, ms_per_load_step=ms / wl.n_steps,
+        updates_per_s=Pm * wl.n_steps / (ms * 1e-3), last_step_all_converged=ok,
+        tuning={int(k): [v["lanes_per_point"], v["waves_per_cu"]]
+                for k, v in mixed_tuned.items()})
+    return out
 
 
 if __name__ == "__main__":

@@ -184,6 +184,34 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                             const dmn_newton_opts* opts, void* ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/* Launch tuning of dmn_update_gauss_points for one DMN depth.  The kernels
+ * split a point's laminate tree across lanes_per_point lanes of a 64-lane
+ * wavefront (each lane owns a subtree of depth K - log2(lanes_per_point), the
+ * levels above are combined across lanes), so 64 / lanes_per_point points
+ * share a wavefront; waves_per_cu persistent wavefronts per compute unit take
+ * batches of points from a work counter.  Tuning changes speed only: every
+ * variant computes the same per-point result. */
+typedef struct dmn_gp_tuning {
+  int32_t lanes_per_point; /* a value listed by dmn_gp_lane_variants; 0 = default */
+  int32_t waves_per_cu;    /* 1..64; 0 = default (8) */
+} dmn_gp_tuning;
+
+/* Set the process-wide tuning for depth (NULL restores the defaults).  Calls
+ * read the table once when they start, so it may be changed from any thread;
+ * it affects calls made afterwards.  DMN_EINVAL for a depth outside [1,10] or
+ * a negative / too large value, DMN_EUNSUPPORTED if no kernel variant with
+ * that lane count is compiled for the depth. */
+int dmn_gp_set_tuning(int32_t depth, const dmn_gp_tuning* t);
+
+/* The tuning in effect for depth (defaults resolved).  DMN_EINVAL for a depth
+ * outside [1,10] or t == NULL. */
+int dmn_gp_get_tuning(int32_t depth, dmn_gp_tuning* t);
+
+/* Lane counts per point of the kernel variants compiled for depth: writes up
+ * to cap of them to lanes (host memory) and returns how many exist (0 for a
+ * depth outside [1,10]). */
+int32_t dmn_gp_lane_variants(int32_t depth, int32_t* lanes, int32_t cap);
+
 /* One batch of points for the load-step adjoint.  With M = 2^(K-1), L = 2^K - 1
  * (FP64, point-major, device memory):
  *   E        [P][6]     macro strain of the step

@@ -48,6 +48,10 @@ class DmnAdjointGroup(ctypes.Structure):
                 ("g_z_prev", ctypes.c_void_p), ("gw", ctypes.c_void_p), ("gn", ctypes.c_void_p)]
 
 
+class DmnGpTuning(ctypes.Structure):
+    _fields_ = [("lanes_per_point", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+
+
 # exported functions and their signatures
 _SIGS = {
     "dmn_version": (ctypes.c_char_p, []),
@@ -67,6 +71,10 @@ _SIGS = {
                                                ctypes.POINTER(DmnElastic), ctypes.POINTER(DmnJ2),
                                                ctypes.c_int, ctypes.POINTER(DmnNewtonOpts),
                                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dmn_gp_set_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(DmnGpTuning)]),
+    "dmn_gp_get_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(DmnGpTuning)]),
+    "dmn_gp_lane_variants": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.c_int32]),
     "dmn_update_adjoint_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(DmnAdjointGroup),
                                                             ctypes.c_int32, ctypes.c_int]),
     "dmn_update_adjoint": (ctypes.c_int, [ctypes.POINTER(DmnAdjointGroup), ctypes.c_int32,

@@ -1,0 +1,150 @@
+"""Autotuner of the Gauss-point launch: lanes per point and persistent waves.
+
+For every DMN depth of a workload it times each compiled lane variant
+(``dmn_gp_lane_variants``) at a few persistent-wave counts on the workload
+itself, keeps the fastest with ``dmn_gp_set_tuning`` and records the choice
+in a JSON cache, keyed by device, library version, depth and point count
+(rounded to a power of two), so later processes set it without timing.
+
+The update is functional (inputs are never written), so timing repeated calls
+on the caller's groups leaves their inputs intact; their outputs end up as
+one call would leave them.  Tuning never changes what a call computes per
+point, only how fast.
+"""
+import ctypes
+import json
+import math
+import os
+import tempfile
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+from . import _lib as L
+
+WAVES_PER_CU = (4, 8, 16)
+
+
+def default_cache_path() -> str:
+    return os.environ.get("DMN_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "libdmn",
+                                       "autotune.json"))
+
+
+def lane_variants(depth: int) -> List[int]:
+    """Lane counts per point compiled for a depth."""
+    lib = L.lib()
+    n = lib.dmn_gp_lane_variants(depth, None, 0)
+    buf = (ctypes.c_int32 * max(n, 1))()
+    lib.dmn_gp_lane_variants(depth, buf, n)
+    return list(buf[:n])
+
+
+def get_tuning(depth: int) -> Tuple[int, int]:
+    t = L.DmnGpTuning()
+    L.check(L.lib().dmn_gp_get_tuning(depth, ctypes.byref(t)), "dmn_gp_get_tuning")
+    return t.lanes_per_point, t.waves_per_cu
+
+
+def set_tuning(depth: int, lanes_per_point: int = 0, waves_per_cu: int = 0):
+    """Set the tuning of a depth (0 = default for either field)."""
+    t = L.DmnGpTuning(lanes_per_point, waves_per_cu)
+    L.check(L.lib().dmn_gp_set_tuning(depth, ctypes.byref(t)), "dmn_gp_set_tuning")
+
+
+def reset_tuning():
+    for k in range(1, 11):
+        L.check(L.lib().dmn_gp_set_tuning(k, None), "dmn_gp_set_tuning")
+
+
+def device_tag(device=None) -> str:
+    import torch
+    p = torch.cuda.get_device_properties(device if device is not None else 0)
+    return f"{p.name}|{p.multi_processor_count}CU|{L.lib().dmn_version().decode()}"
+
+
+def cache_key(tag: str, depth: int, n_points: int) -> str:
+    bucket = 2 ** int(round(math.log2(max(n_points, 1))))
+    return f"{tag}|K{depth}|P{bucket}"
+
+
+def load_cache(path: str) -> Dict[str, dict]:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(path: str, cache: Dict[str, dict]):
+    """Write atomically (rename of a temporary file in the same folder)."""
+    folder = os.path.dirname(os.path.abspath(path))
+    os.makedirs(folder, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=folder, suffix=".tmp")
+    with os.fdopen(fd, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _gpu_timer(groups, fiber, matrix, reps: int, newton: dict) -> float:
+    """Median milliseconds of one dmn_update_gauss_points call on the groups."""
+    import torch
+    from .api import dmn_update_gauss_points
+    ws = dmn_update_gauss_points(groups, fiber, matrix, **newton)  # warm-up
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dmn_update_gauss_points(groups, fiber, matrix, ws=ws, **newton)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def tune_gauss_points(groups: Sequence, fiber: dict, matrix: dict,
+                      cache_path: Optional[str] = None, reps: int = 3,
+                      waves: Sequence[int] = WAVES_PER_CU, retune: bool = False,
+                      timer: Optional[Callable] = None, tag: Optional[str] = None,
+                      **newton) -> Dict[int, dict]:
+    """Tune every depth present in ``groups`` and set the winners.
+
+    Returns {depth: {"lanes_per_point", "waves_per_cu", "ms", "cached"}}.
+    ``timer(groups, fiber, matrix, reps, newton) -> ms`` and ``tag`` replace
+    the GPU timing and device tag (for tests of the cache logic).
+    """
+    timer = timer or _gpu_timer
+    path = cache_path or default_cache_path()
+    tag = tag or device_tag()
+    by_depth: Dict[int, list] = {}
+    for g in groups:
+        by_depth.setdefault(int(round(math.log2(g.w.numel()))), []).append(g)
+    cache = load_cache(path)
+    chosen: Dict[int, dict] = {}
+    dirty = False
+    for K in sorted(by_depth, reverse=True):
+        gs = [g for g in by_depth[K] if g.E.shape[0] > 0]
+        P = sum(g.E.shape[0] for g in gs)
+        key = cache_key(tag, K, P)
+        hit = cache.get(key)
+        if hit and not retune and hit.get("lanes_per_point") in lane_variants(K):
+            set_tuning(K, hit["lanes_per_point"], hit["waves_per_cu"])
+            chosen[K] = dict(hit, cached=True)
+            continue
+        if not gs:
+            continue
+        best = None
+        for lanes in lane_variants(K):
+            for w in waves:
+                set_tuning(K, lanes, w)
+                ms = float(timer(gs, fiber, matrix, reps, newton))
+                if best is None or ms < best[0]:
+                    best = (ms, lanes, w)
+        set_tuning(K, best[1], best[2])
+        cache[key] = dict(lanes_per_point=best[1], waves_per_cu=best[2], ms=best[0])
+        chosen[K] = dict(cache[key], cached=False)
+        dirty = True
+    if dirty:
+        save_cache(path, cache)
+    return chosen

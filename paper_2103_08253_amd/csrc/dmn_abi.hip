@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "dmn_internal.hpp"
@@ -38,6 +39,30 @@ inline bool phase_ok(const dmn_elastic* f) {
 inline bool j2_ok(const dmn_j2* m) {
   return m && m->E > 0.0 && m->nu > -1.0 && m->nu < 0.5 && m->sigma0 > 0.0 && m->k_inf >= 0.0 &&
          m->dsigma >= 0.0 && m->b >= 0.0;
+}
+
+// Process-wide launch tuning of the Gauss-point update per depth (0 = default).
+std::atomic<int> g_tune_lanes[DMN_MAX_DEPTH + 1];
+std::atomic<int> g_tune_waves[DMN_MAX_DEPTH + 1];
+
+struct GpTune {
+  int lanes;         // lanes per point
+  int waves_per_cu;  // persistent waves per compute unit
+};
+
+inline GpTune gp_tuning(int depth) {
+  const int l = g_tune_lanes[depth].load(std::memory_order_relaxed);
+  const int w = g_tune_waves[depth].load(std::memory_order_relaxed);
+  return GpTune{l ? l : dmn::gp_default_lanes_per_point(depth),
+                w ? w : dmn::kDefaultWavesPerCu};
+}
+
+inline bool gp_variant_exists(int depth, int lanes) {
+  int v[16];
+  const int n = dmn::gp_lane_variants(depth, v, 16);
+  for (int i = 0; i < n && i < 16; ++i)
+    if (v[i] == lanes) return true;
+  return false;
 }
 
 }  // namespace
@@ -132,8 +157,13 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                     !g.tangent || !g.iters || !g.status))
       return DMN_EINVAL;
     if (g.P > 0 && (g.z_in == g.z_out || g.a_in == g.a_out)) return DMN_EINVAL;
-    const int lp = dmn::gp_default_lanes_per_point(g.net.depth);
-    if ((g.P + 63) / 64 * lp > (int64_t)0x7fffffff) return DMN_EINVAL;
+  }
+  // one snapshot of the tuning table per call
+  GpTune tune[DMN_MAX_DEPTH + 1];
+  for (int k = 1; k <= DMN_MAX_DEPTH; ++k) tune[k] = gp_tuning(k);
+  for (int i = 0; i < n_groups; ++i) {
+    const dmn_point_group& g = groups[i];
+    if ((g.P + 63) / 64 * tune[g.net.depth].lanes > (int64_t)0x7fffffff) return DMN_EINVAL;
   }
   const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
@@ -175,10 +205,11 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   });
   size_t pos = 0;
   int launch = 0;
-  const long long persistent = (long long)dmn::device_cu_count() * 8;
+  const long long cus = dmn::device_cu_count();
   while (pos < order.size()) {
     const int K = groups[order[pos]].net.depth;
-    const int lp = dmn::gp_default_lanes_per_point(K);
+    const int lp = tune[K].lanes;
+    const long long persistent = cus * tune[K].waves_per_cu;
     const int ppb = dmn::gp_points_per_block(K, lp);
     dmn::GpLaunch args = base;
     args.ng = 0;
@@ -288,6 +319,30 @@ int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
     if (dmn::launch_adjoint(K, a, stream)) return DMN_EHIP;
   }
   return DMN_OK;
+}
+
+int dmn_gp_set_tuning(int32_t depth, const dmn_gp_tuning* t) {
+  if (!depth_ok(depth)) return DMN_EINVAL;
+  const int lanes = t ? t->lanes_per_point : 0;
+  const int waves = t ? t->waves_per_cu : 0;
+  if (lanes < 0 || waves < 0 || waves > 64) return DMN_EINVAL;
+  if (lanes != 0 && !gp_variant_exists(depth, lanes)) return DMN_EUNSUPPORTED;
+  g_tune_lanes[depth].store(lanes, std::memory_order_relaxed);
+  g_tune_waves[depth].store(waves, std::memory_order_relaxed);
+  return DMN_OK;
+}
+
+int dmn_gp_get_tuning(int32_t depth, dmn_gp_tuning* t) {
+  if (!depth_ok(depth) || !t) return DMN_EINVAL;
+  const GpTune u = gp_tuning(depth);
+  t->lanes_per_point = u.lanes;
+  t->waves_per_cu = u.waves_per_cu;
+  return DMN_OK;
+}
+
+int32_t dmn_gp_lane_variants(int32_t depth, int32_t* lanes, int32_t cap) {
+  if (!depth_ok(depth) || cap < 0) return 0;
+  return dmn::gp_lane_variants(depth, lanes, cap);
 }
 
 }  // extern "C"

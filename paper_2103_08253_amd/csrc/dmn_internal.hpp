@@ -68,6 +68,10 @@ int launch_zero_ints(int32_t* p, int n, hipStream_t stream);
 int device_cu_count();
 int gp_points_per_block(int depth, int lanes_per_point);
 int gp_default_lanes_per_point(int depth);
+// lane counts per point of the compiled variants for a depth (writes up to cap,
+// returns how many exist)
+int gp_lane_variants(int depth, int* lanes, int cap);
+constexpr int kDefaultWavesPerCu = 8;
 
 int launch_linear_forward(int depth, int prec, const void* tab, const int32_t* flag, long long B,
                           const void* C1, const void* C2, void* Cbar, int32_t* err,
