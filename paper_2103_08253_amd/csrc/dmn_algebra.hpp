@@ -55,36 +55,29 @@ struct Normal {
   }
 };
 
-// 3x3 SPD inverse by Cholesky. Returns false if a pivot is not positive
-// (or not finite); M is then left unspecified.
+// Inverse M of a symmetric 3x3 matrix K from its cofactors and one reciprocal
+// of the determinant.  Returns false unless K is positive definite by
+// Sylvester's criterion (k00, k00 k11 - k01^2 and det K all positive; false
+// for non-finite entries); M is then left unspecified.
 template <typename T>
 __device__ __forceinline__ bool spd3_inverse(T k00, T k01, T k02, T k11, T k12, T k22,
                                              T& m00, T& m01, T& m02, T& m11, T& m12,
                                              T& m22) {
-  bool ok = k00 > T(0);
-  T l00 = sqrt(ok ? k00 : T(1));
-  T i00 = T(1) / l00;
-  T l10 = k01 * i00, l20 = k02 * i00;
-  T d1 = k11 - l10 * l10;
-  ok = ok && d1 > T(0);
-  T l11 = sqrt(d1 > T(0) ? d1 : T(1));
-  T i11 = T(1) / l11;
-  T l21 = (k12 - l20 * l10) * i11;
-  T d2 = k22 - l20 * l20 - l21 * l21;
-  ok = ok && d2 > T(0);
-  T l22 = sqrt(d2 > T(0) ? d2 : T(1));
-  T i22 = T(1) / l22;
-  // L^-1 (lower triangular)
-  T j10 = -l10 * i00 * i11;
-  T j21 = -l21 * i11 * i22;
-  T j20 = -(l20 * i00 + l21 * j10) * i22;
-  // M = L^-T L^-1
-  m00 = i00 * i00 + j10 * j10 + j20 * j20;
-  m01 = j10 * i11 + j20 * j21;
-  m02 = j20 * i22;
-  m11 = i11 * i11 + j21 * j21;
-  m12 = j21 * i22;
-  m22 = i22 * i22;
+  const T c00 = k11 * k22 - k12 * k12;
+  const T c01 = k02 * k12 - k01 * k22;
+  const T c02 = k01 * k12 - k02 * k11;
+  const T c11 = k00 * k22 - k02 * k02;
+  const T c12 = k01 * k02 - k00 * k12;
+  const T c22 = k00 * k11 - k01 * k01;
+  const T det = k00 * c00 + k01 * c01 + k02 * c02;
+  const bool ok = k00 > T(0) && c22 > T(0) && det > T(0);
+  const T inv = T(1) / (ok ? det : T(1));
+  m00 = c00 * inv;
+  m01 = c01 * inv;
+  m02 = c02 * inv;
+  m11 = c11 * inv;
+  m12 = c12 * inv;
+  m22 = c22 * inv;
   return ok;
 }
 
