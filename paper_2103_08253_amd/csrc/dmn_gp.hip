@@ -31,60 +31,48 @@ using namespace tree;
 // ---------------------------------------------------------------- outputs
 
 template <int K, int D, int H, typename S>
-__device__ __forceinline__ void write_lane_a(const LaneState<K, D>& st, int t, bool ok,
-                                             const S* __restrict__ ain, S* __restrict__ aout) {
+__device__ __forceinline__ void write_lane_a(const LaneState<K, D>& st, int t,
+                                             S* __restrict__ aout) {
   if constexpr (H <= Cfg<K, D>::NLAM) {
     const int pos = lane_pos<K, D, H>(t);
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      aout[(size_t)pos * 3 + k] = ok ? (S)st.a[H - 1][k] : ain[(size_t)pos * 3 + k];
-    write_lane_a<K, D, H + 1>(st, t, ok, ain, aout);
+    for (int k = 0; k < 3; ++k) aout[(size_t)pos * 3 + k] = (S)st.a[H - 1][k];
+    write_lane_a<K, D, H + 1>(st, t, aout);
   }
 }
 
-// Write the point's outputs.  ok: converged (z from the J2 return at the
-// accepted strains eps); otherwise the input state is copied through and the
-// tangent is NaN.  No shuffles: runs under per-point control flow.  S is the
-// storage type of the per-point arrays; results are rounded to it on store.
+// Write the point's outputs.  ok: converged (z_out was written by the leaf
+// laws of the last evaluation, which is the accepted state); otherwise the
+// input state is copied through and the tangent is NaN.  No shuffles: runs
+// under per-point control flow.  S is the storage type of the per-point
+// arrays; results are rounded to it on store.
 template <int K, int D, typename S>
 __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K, D>& st,
                                          const UpperLds<K, D>& up, const GroupArgs& G,
-                                         long long pt, const double (&eps)[Cfg<K, D>::NLEAF][6],
-                                         const EvalOut& ev, int status, int iters) {
+                                         long long pt, const EvalOut& ev, int status, int iters) {
   using C = Cfg<K, D>;
   const bool ok = status == 0;
   const int t = cx.t;
-  S* zout = (S*)G.z_out + (size_t)pt * C::M * 7;
-#pragma unroll
-  for (int q = 1; q < C::NLEAF; q += 2) {
-    const int mloc = t * (C::NLEAF / 2) + q / 2;
-    const S* z = (const S*)cx.zin + (size_t)mloc * 7;
-    S* zo = zout + (size_t)mloc * 7;
-    if (ok) {
-      double epn[6], ep[6], p, sg[6], Dp[21];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) epn[k] = (double)z[k];
-      j2_return(cx.mat, eps[q], epn, (double)z[6], sg, Dp, ep, p);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) zo[k] = (S)ep[k];
-      zo[6] = (S)p;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 7; ++k) zo[k] = z[k];
-    }
-  }
-  const S* ain = (const S*)G.a_in + (size_t)pt * C::L * 3;
   S* aout = (S*)G.a_out + (size_t)pt * C::L * 3;
-  write_lane_a<K, D, 1, S>(st, t, ok, ain, aout);
+  if (ok) {
+    write_lane_a<K, D, 1, S>(st, t, aout);
 #pragma unroll 1
-  for (int m = 1; m <= C::UPLEV; ++m) {
-    if (upper_active(t, m)) {
-      const int pos = upper_pos<K, D>(m, t);
-      const int u = cx.slot * C::NUPS + (pos - C::UP0);
+    for (int m = 1; m <= C::UPLEV; ++m) {
+      if (upper_active(t, m)) {
+        const int pos = upper_pos<K, D>(m, t);
+        const int u = cx.slot * C::NUPS + (pos - C::UP0);
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        aout[(size_t)pos * 3 + k] = ok ? (S)up.a[k][u] : ain[(size_t)pos * 3 + k];
+        for (int k = 0; k < 3; ++k) aout[(size_t)pos * 3 + k] = (S)up.a[k][u];
+      }
     }
+  } else {
+    // failure: this lane copies its share of the input state through
+    const S* zi = (const S*)cx.zin + (size_t)t * (C::NLEAF / 2) * 7;
+    S* zo = (S*)G.z_out + (size_t)pt * C::M * 7 + (size_t)t * (C::NLEAF / 2) * 7;
+#pragma unroll
+    for (int q = 0; q < C::NLEAF / 2 * 7; ++q) zo[q] = zi[q];
+    const S* ain = (const S*)G.a_in + (size_t)pt * C::L * 3;
+    for (int i = t; i < C::L * 3; i += C::LP) aout[i] = ain[i];
   }
   if (t == 0) {
     S* sg = (S*)G.sigma + (size_t)pt * 6;
@@ -145,6 +133,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   const bool in_range = pt_raw < G.P;
   const long long pt = in_range ? pt_raw : G.P - 1;  // tail lanes shadow the last point
   cx.zin = (const S*)G.z_in + (size_t)pt * C::M * 7;
+  cx.zout = (S*)G.z_out + (size_t)pt * C::M * 7;
   const S* ain = (const S*)G.a_in + (size_t)pt * C::L * 3;
   const S* zin = (const S*)cx.zin;
 
@@ -194,7 +183,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   if (*G.flag != 0) {  // invalid DMN parameters: every point of the group fails
 #pragma unroll
     for (int k = 0; k < 6; ++k) ev.sb[k] = __builtin_nan("");
-    if (in_range) finalize<K, D, S>(cx, st, up, G, pt, eps, ev, DMN_STATUS_BADPARAM, 0);
+    if (in_range) finalize<K, D, S>(cx, st, up, G, pt, ev, DMN_STATUS_BADPARAM, 0);
     continue;
   }
 
@@ -206,6 +195,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
 #pragma unroll 1
   while (true) {
     localize(cx, st, up, E, done ? 0.0 : s, eps);
+    cx.wz = !done;
     evaluate_full<K, D, NewtonLeafS<S>>(cx, st, up, eps, ev);
     bool just_done = false, need_dir = false;
     if (!done) {
@@ -257,13 +247,9 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
         }
       }
     }
-    if (__any(just_done)) {
-      // strains at the accepted jumps, for the internal variables of finished points
-      localize(cx, st, up, E, 0.0, eps);
-      if (just_done) {
-        finalize<K, D, S>(cx, st, up, G, pt, eps, ev, status, iters);
-        done = true;
-      }
+    if (just_done) {
+      finalize<K, D, S>(cx, st, up, G, pt, ev, status, iters);
+      done = true;
     }
     if (!__any(!done)) break;
     if (__any(need_dir)) {

@@ -113,12 +113,14 @@ struct EvalOut {
 template <int K, int D>
 struct Ctx {
   const double* __restrict__ tab;
-  const void* zin;  // this point's z_in (storage precision of the kernel)
+  const void* zin;       // this point's z_in (storage precision of the kernel)
+  void* zout = nullptr;  // this point's z_out, written by the leaf law when wz is set
   IsoElastic fib;
   J2Law mat;
   int t;
   int slot;
   int base;  // first lane of this point in the wave
+  bool wz = false;
 };
 
 __device__ __forceinline__ double shfl_down_d(double v, int o, int width) {
@@ -188,7 +190,9 @@ __device__ __forceinline__ void localize(const Ctx<K, D>& cx, const LaneState<K,
 // ---------------------------------------------------------------- bottom-up
 
 // Leaf law of the Newton evaluation: stress, tangent, and tau = stress.  S is
-// the storage type of the internal variables.
+// the storage type of the internal variables.  With cx.wz set, the updated
+// internal variables of the matrix leaves go to z_out (the last evaluation of
+// a converged point is its accepted state, so z_out then holds the result).
 template <typename S>
 struct NewtonLeafS {
   template <int K, int D, int Q>
@@ -207,6 +211,12 @@ struct NewtonLeafS {
       for (int k = 0; k < 6; ++k) epn[k] = (double)z[k];
       const bool ok = j2_return(cx.mat, e, epn, (double)z[6], sn, Cn, ep, p);
       lfail |= ok ? 0 : 1;
+      if (cx.wz) {
+        S* zo = (S*)cx.zout + (size_t)mloc * 7;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) zo[k] = (S)ep[k];
+        zo[6] = (S)p;
+      }
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) tn[k] = sn[k];
