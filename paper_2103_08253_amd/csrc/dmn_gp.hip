@@ -11,7 +11,9 @@
 // the lane that computes the laminate.
 //
 // One evaluation at jumps a:
-//   localisation: leaf strains eps = E + A a, top-down through the tree;
+//   localisation: leaf strains eps = E + A a: each lane sums its upper
+//                 ancestors' terms for its subtree root, then localises down
+//                 its subtree while condensing it (one pass);
 //   leaves:       fibre sigma = C_f eps; matrix J2 radial return -> sigma, D;
 //   bottom-up:    block-Cholesky condensation of A^T W D A in postorder (no
 //                 fill-in): condensed C, tau, plain average, residual blocks;
@@ -139,7 +141,6 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
 
   LaneState<K, D> st;
   EvalOut ev;
-  double eps[C::NLEAF][6];
   double E[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) E[k] = (double)((const S*)G.E)[(size_t)pt * 6 + k];
@@ -194,9 +195,8 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   double s = 0.0, rn = 0.0;
 #pragma unroll 1
   while (true) {
-    localize(cx, st, up, E, done ? 0.0 : s, eps);
     cx.wz = !done;
-    evaluate_full<K, D, NewtonLeafS<S>>(cx, st, up, eps, ev);
+    evaluate_at<K, D, NewtonLeafS<S>>(cx, st, up, E, done ? 0.0 : s, ev);
     bool just_done = false, need_dir = false;
     if (!done) {
       bool accepted = false;

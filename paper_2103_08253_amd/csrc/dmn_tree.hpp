@@ -244,18 +244,39 @@ __device__ __forceinline__ void up_node(const Ctx<K, D>& cx, LaneState<K, D>& st
   }
 }
 
-// Leaf laws, bottom-up condensation and per-point reductions at leaf strains
-// eps (wave-uniform: contains shuffles).
-template <int K, int D, class Leaf = NewtonLeaf>
-__device__ __forceinline__ void evaluate_full(const Ctx<K, D>& cx, LaneState<K, D>& st,
-                                              UpperLds<K, D>& up,
-                                              const double (&eps)[Cfg<K, D>::NLEAF][6],
-                                              EvalOut& out, const Leaf& leaf = Leaf()) {
+// Lane subtree with the strains localised on the way down: node H receives
+// its strain e, its children e -/+ c N (a + s da); leaf laws at the leaves,
+// condensation on the way up.  Each laminate row is read once.
+template <int K, int D, int H, class Leaf>
+__device__ __forceinline__ void up_node_loc(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                            const Leaf& leaf, double s, const double (&e)[6],
+                                            double (&Cn)[21], double (&tn)[6], double (&sn)[6],
+                                            double& rr, int& lfail, int& spdfail) {
   using C = Cfg<K, D>;
-  double rr = 0.0;
-  int lfail = 0, spdfail = 0;
-  double cT[6];
-  up_node<K, D, 1>(cx, st, leaf, eps, out.C, cT, out.sb, rr, lfail, spdfail);
+  if constexpr (H >= C::NLEAF) {
+    leaf(cx, std::integral_constant<int, H - C::NLEAF>{}, e, Cn, tn, sn, lfail);
+  } else {
+    const LamRow row = load_row_soa<C::L>(cx.tab, lane_pos<K, D, H>(cx.t));
+    double aj[3], eL[6], eR[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) aj[k] = st.a[H - 1][k] + s * st.da[H - 1][k];
+    laminate_localize(aj, e, row.nv, row.c1, row.c2, eL, eR);
+    up_node_loc<K, D, 2 * H>(cx, st, leaf, s, eL, Cn, tn, sn, rr, lfail, spdfail);
+    double CR[21], tR[6], sR[6];
+    up_node_loc<K, D, 2 * H + 1>(cx, st, leaf, s, eR, CR, tR, sR, rr, lfail, spdfail);
+    const bool ok = laminate_newton(Cn, tn, sn, CR, tR, sR, row.nv, row.c1, row.c2, row.rf,
+                                    st.G[H - 1], st.g[H - 1], rr);
+    spdfail |= ok ? 0 : 1;
+  }
+}
+
+// Upper levels of the bottom-up condensation (shuffles between lanes) and the
+// per-point reductions, after the lane subtrees (wave-uniform).
+template <int K, int D>
+__device__ __forceinline__ void evaluate_upper(const Ctx<K, D>& cx, UpperLds<K, D>& up,
+                                               EvalOut& out, double (&cT)[6], double rr,
+                                               int lfail, int spdfail) {
+  using C = Cfg<K, D>;
 #pragma unroll 1
   for (int m = 1; m <= C::UPLEV; ++m) {
     const int o = 1 << (m - 1);
@@ -298,6 +319,54 @@ __device__ __forceinline__ void evaluate_full(const Ctx<K, D>& cx, LaneState<K, 
   out.sn2 = sn2;
   out.lfail = lfail;
   out.spdfail = spdfail;
+}
+
+// Leaf laws, bottom-up condensation and per-point reductions at leaf strains
+// eps (wave-uniform: contains shuffles).
+template <int K, int D, class Leaf = NewtonLeaf>
+__device__ __forceinline__ void evaluate_full(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                              UpperLds<K, D>& up,
+                                              const double (&eps)[Cfg<K, D>::NLEAF][6],
+                                              EvalOut& out, const Leaf& leaf = Leaf()) {
+  double rr = 0.0;
+  int lfail = 0, spdfail = 0;
+  double cT[6];
+  up_node<K, D, 1>(cx, st, leaf, eps, out.C, cT, out.sb, rr, lfail, spdfail);
+  evaluate_upper(cx, up, out, cT, rr, lfail, spdfail);
+}
+
+// One whole evaluation at jumps a + s da: strain of each lane subtree's root
+// (E plus its upper ancestors' terms), then the lane subtree with
+// localisation fused into the condensation, then the upper levels and
+// reductions.  Reads upper jumps written by other lanes: synchronises first.
+template <int K, int D, class Leaf>
+__device__ __forceinline__ void evaluate_at(const Ctx<K, D>& cx, LaneState<K, D>& st,
+                                            UpperLds<K, D>& up, const double (&E)[6], double s,
+                                            EvalOut& out, const Leaf& leaf = Leaf()) {
+  using C = Cfg<K, D>;
+  __syncthreads();
+  double e[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) e[k] = E[k];
+#pragma unroll 1
+  for (int m = C::UPLEV; m >= 1; --m) {
+    const int lead = cx.t & ~((1 << m) - 1);
+    const int pos = upper_pos<K, D>(m, lead);
+    const int u = cx.slot * C::NUPS + (pos - C::UP0);
+    const LamRow row = load_row_soa<C::L>(cx.tab, pos);
+    double aj[3], Na[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) aj[k] = up.a[k][u] + s * up.da[k][u];
+    row.nv.apply(aj, Na);
+    const double f = ((cx.t >> (m - 1)) & 1) ? row.c1 : -row.c2;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) e[k] += f * Na[k];
+  }
+  double rr = 0.0;
+  int lfail = 0, spdfail = 0;
+  double cT[6];
+  up_node_loc<K, D, 1>(cx, st, leaf, s, e, out.C, cT, out.sb, rr, lfail, spdfail);
+  evaluate_upper(cx, up, out, cT, rr, lfail, spdfail);
 }
 
 // ---------------------------------------------------------------- top-down
