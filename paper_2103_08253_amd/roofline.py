@@ -19,10 +19,13 @@ DMN) are excluded.
 from dataclasses import dataclass
 
 # ---- per-item flop counts (see the kernels' formulas) ----------------------
+# 3x3 inverse by cofactors: six cofactors (18), determinant (5), reciprocal (1),
+# scaling (6)
+INVERSE3 = 30
 # laminate step of the Newton bottom-up: S and C_R - C_L (84), S N and U (216),
-# K = N^T S N (54), 3x3 Cholesky inverse (40), V = U K^-1 (90), condensed C (211),
-# g and tau (99), plain average and residual block (50)
-LAMINATE_NEWTON = 844
+# K = N^T S N (54), 3x3 inverse, V = U K^-1 (90), condensed C (211), g and tau
+# (99), plain average and residual block (50)
+LAMINATE_NEWTON = 804 + INVERSE3
 # top-down step: da = -(g + G e) (39), N da (15), children strains (24)
 LAMINATE_DESCEND = 78
 # strain localisation through a laminate from stored jumps: N a (15) + 24
@@ -33,12 +36,12 @@ J2_LEAF = 145
 # fibre leaf: isotropic stress
 FIBER_LEAF = 15
 # linear laminate (forward of the training map): S, dC (84), S N and U (216),
-# K (54), inverse (40), V (90), C (211)
-LAMINATE_LINEAR = 695
-# laminate VJP: recompute (695 - 211 + 63 for T), X = Gt V (126), G_K (36),
+# K (54), inverse, V (90), C (211)
+LAMINATE_LINEAR = 655 + INVERSE3
+# laminate VJP: recompute (forward - 211 + 63 for T), X = Gt V (126), G_K (36),
 # N G_K and G_S (108 + 108), Y (90), G_CL / G_CR / inner products (378),
 # G_N (324), g_n (18)
-LAMINATE_LINEAR_VJP = 547 + 126 + 36 + 216 + 90 + 378 + 324 + 18
+LAMINATE_LINEAR_VJP = (LAMINATE_LINEAR - 211 + 63) + 126 + 36 + 216 + 90 + 378 + 324 + 18
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak
@@ -59,11 +62,13 @@ class DmnSizes:
 
 
 def gp_update_flops(depth: int, iters: int) -> int:
-    """Algorithmic flops of one Gauss-point update that took `iters` Newton steps."""
+    """Algorithmic flops of one Gauss-point update that took `iters` Newton steps:
+    per evaluation the localisation eps = E + A a, the leaf laws and the
+    bottom-up condensation; per Newton step the top-down solve."""
     s = DmnSizes(depth)
-    per_eval = s.L * LAMINATE_NEWTON + s.M * (J2_LEAF + FIBER_LEAF)
-    return ((iters + 1) * per_eval + iters * s.L * LAMINATE_DESCEND
-            + s.L * LAMINATE_LOCALIZE + s.M * J2_LEAF)
+    per_eval = (s.L * (LAMINATE_NEWTON + LAMINATE_LOCALIZE)
+                + s.M * (J2_LEAF + FIBER_LEAF))
+    return (iters + 1) * per_eval + iters * s.L * LAMINATE_DESCEND
 
 
 def gp_update_bytes(depth: int, elt: int = 8) -> int:
