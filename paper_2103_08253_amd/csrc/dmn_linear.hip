@@ -8,7 +8,9 @@
 // are combined with shuffles.  Leaves alternate between C1 (even) and C2
 // (odd).  The backward pass recomputes the forward, keeping the lane
 // subtree's node stiffnesses in registers and the lane roots and upper nodes
-// in LDS, then runs the laminate VJPs from the root down.  Parameter
+// in LDS, then runs the laminate VJPs from the root down.  A sample's two
+// phase stiffnesses are the same for all its lanes and sit in LDS (broadcast
+// reads) rather than in every lane's registers.  Parameter
 // cotangents are accumulated per lane over the samples a wave processes and
 // reduced over waves in a fixed order (bit-reproducible).
 #include "dmn_internal.hpp"
@@ -82,8 +84,8 @@ __device__ __forceinline__ void store_full(T* __restrict__ A, const T P[21]) {
 
 // bottom-up over the lane subtree; stores the laminate outputs when Store
 template <typename T, int K, int D, int H, bool Store>
-__device__ __forceinline__ void lin_up(const T* __restrict__ tab, int t, const T (&C1)[21],
-                                       const T (&C2)[21], T (&Cn)[21], int& fail,
+__device__ __forceinline__ void lin_up(const T* __restrict__ tab, int t, const T* C1,
+                                       const T* C2, T (&Cn)[21], int& fail,
                                        T (&nodes)[LCfg<K, D>::NLAM][21]) {
   using C = LCfg<K, D>;
   if constexpr (H >= C::NLEAF) {
@@ -120,18 +122,21 @@ __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ ta
                                                         T* __restrict__ Cbar,
                                                         int32_t* __restrict__ err) {
   using C = LCfg<K, D>;
+  __shared__ T leafC[C::PPW][2][21];
   const int lane = threadIdx.x;
   const int slot = lane / C::LP, t = lane % C::LP;
   const long long braw = (long long)blockIdx.x * C::PPW + slot;
   const bool in_range = braw < B;
   const long long b = in_range ? braw : B - 1;
-  T A1[21], A2[21];
-  load_sym(C1 + (size_t)b * 36, A1);
-  load_sym(C2 + (size_t)b * 36, A2);
+  if (t == 0) {
+    load_sym(C1 + (size_t)b * 36, leafC[slot][0]);
+    load_sym(C2 + (size_t)b * 36, leafC[slot][1]);
+  }
+  __syncthreads();
   int fail = 0;
   T cC[21];
   T dummy[C::NLAM][21];
-  lin_up<T, K, D, 1, false>(tab, t, A1, A2, cC, fail, dummy);
+  lin_up<T, K, D, 1, false>(tab, t, leafC[slot][0], leafC[slot][1], cC, fail, dummy);
 #pragma unroll
   for (int m = 1; m <= C::UPLEV; ++m) {
     const int o = 1 << (m - 1);
@@ -159,20 +164,23 @@ __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ ta
   }
 }
 
-// backward over the lane subtree: cotangent Gm of heap node H
-template <typename T, int K, int D, int H>
+// backward over the lane subtree: cotangent Gm of heap node H; the phase
+// stiffness cotangents g1, g2 are accumulated only if IG
+template <typename T, int K, int D, int H, bool IG>
 __device__ __forceinline__ void lin_back(const T* __restrict__ tab, int t, bool live,
-                                         const T (&C1)[21], const T (&C2)[21],
+                                         const T* C1, const T* C2,
                                          const T (&nodes)[LCfg<K, D>::NLAM][21],
                                          const T (&Gm)[21], double (&acc)[LCfg<K, D>::NLAM][4],
-                                         T (&g1)[21], T (&g2)[21]) {
+                                         T (&g1)[IG ? 21 : 1], T (&g2)[IG ? 21 : 1]) {
   using C = LCfg<K, D>;
   if constexpr (H >= C::NLEAF) {
-    constexpr int q = H - C::NLEAF;
+    if constexpr (IG) {
+      constexpr int q = H - C::NLEAF;
 #pragma unroll
-    for (int k = 0; k < 21; ++k) {
-      if constexpr (q % 2 == 0) g1[k] += Gm[k];
-      else g2[k] += Gm[k];
+      for (int k = 0; k < 21; ++k) {
+        if constexpr (q % 2 == 0) g1[k] += Gm[k];
+        else g2[k] += Gm[k];
+      }
     }
   } else {
     const T* CL;
@@ -193,12 +201,12 @@ __device__ __forceinline__ void lin_back(const T* __restrict__ tab, int t, bool 
       acc[H - 1][2] += (double)gn[1];
       acc[H - 1][3] += (double)gn[2];
     }
-    lin_back<T, K, D, 2 * H>(tab, t, live, C1, C2, nodes, GL, acc, g1, g2);
-    lin_back<T, K, D, 2 * H + 1>(tab, t, live, C1, C2, nodes, GR, acc, g1, g2);
+    lin_back<T, K, D, 2 * H, IG>(tab, t, live, C1, C2, nodes, GL, acc, g1, g2);
+    lin_back<T, K, D, 2 * H + 1, IG>(tab, t, live, C1, C2, nodes, GR, acc, g1, g2);
   }
 }
 
-template <typename T, int K, int D>
+template <typename T, int K, int D, bool IG>
 __global__ __launch_bounds__(64) void linear_bwd_kernel(
     const T* __restrict__ tab, const int32_t* __restrict__ flag, long long B,
     const T* __restrict__ C1, const T* __restrict__ C2, const T* __restrict__ gCbar,
@@ -207,6 +215,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
   using C = LCfg<K, D>;
   static_assert(C::NLAM >= 1, "lane subtree needs a laminate");
   __shared__ T nodeC[21][C::PPW * C::NODES];
+  __shared__ T leafC[C::PPW][2][21];
   __shared__ double accU[4][C::PPW * (C::NUP > 0 ? C::NUP : 1)];
   const int lane = threadIdx.x;
   const int slot = lane / C::LP, t = lane % C::LP;
@@ -223,9 +232,13 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
     const long long braw = sg * C::PPW + slot;
     const bool live = braw < B;
     const long long b = live ? braw : B - 1;
-    T A1[21], A2[21];
-    load_sym(C1 + (size_t)b * 36, A1);
-    load_sym(C2 + (size_t)b * 36, A2);
+    if (t == 0) {
+      load_sym(C1 + (size_t)b * 36, leafC[slot][0]);
+      load_sym(C2 + (size_t)b * 36, leafC[slot][1]);
+    }
+    __syncthreads();
+    const T* A1 = leafC[slot][0];
+    const T* A2 = leafC[slot][1];
     // forward, keeping node stiffnesses
     T nodes[C::NLAM][21];
     T cC[21];
@@ -292,14 +305,14 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
         for (int k = 0; k < 21; ++k) Gm[k] = rcv[k];
       }
     }
-    T g1[21], g2[21];
+    T g1[IG ? 21 : 1], g2[IG ? 21 : 1];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) {
+    for (int k = 0; k < (IG ? 21 : 1); ++k) {
       g1[k] = T(0);
       g2[k] = T(0);
     }
-    lin_back<T, K, D, 1>(tab, t, live, A1, A2, nodes, Gm, acc, g1, g2);
-    if (gC1 != nullptr) {
+    lin_back<T, K, D, 1, IG>(tab, t, live, A1, A2, nodes, Gm, acc, g1, g2);
+    if constexpr (IG) {
 #pragma unroll
       for (int o = 1; o < C::LP; o <<= 1)
 #pragma unroll
@@ -312,7 +325,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
         store_full(gC2 + (size_t)b * 36, g2);
       }
     }
-    __syncthreads();  // nodeC is rewritten by the next sample group
+    __syncthreads();  // nodeC and leafC are rewritten by the next sample group
   }
   // partial sums of this wave slot, stored [pos * 4 + c][slot]
   const size_t pslot = (size_t)blockIdx.x * C::PPW + slot;
@@ -459,9 +472,14 @@ static int bwd_k(const void* tab, const int32_t* flag, long long B, const void* 
   using C = LCfg<K, D>;
   const long long nslots = linear_backward_partials(K, B);
   const long long waves = nslots / C::PPW;
-  hipLaunchKernelGGL((linear_bwd_kernel<T, K, D>), dim3((unsigned)waves), dim3(64), 0, s,
-                     (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar, (T*)gC1,
-                     (T*)gC2, partials, err);
+  if (gC1 != nullptr)
+    hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, true>), dim3((unsigned)waves), dim3(64), 0, s,
+                       (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar,
+                       (T*)gC1, (T*)gC2, partials, err);
+  else
+    hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, false>), dim3((unsigned)waves), dim3(64), 0,
+                       s, (const T*)tab, flag, B, (const T*)C1, (const T*)C2,
+                       (const T*)gCbar, (T*)gC1, (T*)gC2, partials, err);
   const int L4 = C::L * 4;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(L4), dim3(256), 0, s,
                      (const double*)partials, nslots, L4, gsum);
