@@ -137,7 +137,7 @@ __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ ta
   T cC[21];
   T dummy[C::NLAM][21];
   lin_up<T, K, D, 1, false>(tab, t, leafC[slot][0], leafC[slot][1], cC, fail, dummy);
-#pragma unroll
+#pragma unroll 1
   for (int m = 1; m <= C::UPLEV; ++m) {
     const int o = 1 << (m - 1);
     T rC[21];
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
     const int nbase = slot * C::NODES;
 #pragma unroll
     for (int k = 0; k < 21; ++k) nodeC[k][nbase + t] = cC[k];
-#pragma unroll
+#pragma unroll 1
     for (int m = 1; m <= C::UPLEV; ++m) {
       const int o = 1 << (m - 1);
       T rC[21];
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
     // backward: root cotangent is the symmetric part of gCbar
     T Gm[21];
     load_sym(gCbar + (size_t)b * 36, Gm);
-#pragma unroll
+#pragma unroll 1
     for (int m = C::UPLEV; m >= 1; --m) {
       const int o = 1 << (m - 1);
       T GRs[21];
