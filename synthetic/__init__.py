@@ -235,3 +235,56 @@ def angles_to_normals(alpha: np.ndarray, beta: np.ndarray) -> np.ndarray:
     """n = (sin a cos b, sin a sin b, cos a): the spherical parameterisation of Sec. 2.3."""
     return np.stack([np.sin(alpha) * np.cos(beta), np.sin(alpha) * np.sin(beta),
                      np.cos(alpha)], axis=-1)
+
+
+# ---------------------------------------------------------------- orientation
+
+SHAPE_COUNTS = {"linear": 3, "trilinear": 4, "quadratic": 6}
+
+
+@dataclass
+class InterpolatedDmn:
+    """A DMN whose normals depend on the fibre orientation (l1, l2): shared
+    leaf weights w [2^K] and, per laminate (paper order), coefficient vectors
+    p, q [2^K - 1, M] of the spherical angles over M shape functions."""
+    depth: int
+    w: np.ndarray
+    p: np.ndarray
+    q: np.ndarray
+    kind: str
+
+
+def interpolated_dmn(rng: np.random.Generator, depth: int, fiber_fraction: float, kind: str,
+                     spread: float = 0.3) -> InterpolatedDmn:
+    """Weights and base angles as random_dmn; each shape-function coefficient is
+    the base angle plus N(0, spread^2), so the normals vary with orientation."""
+    net = random_dmn(rng, depth, fiber_fraction)
+    alpha, beta = normals_to_angles(net.normals)
+    M = SHAPE_COUNTS[kind]
+    L = net.n_laminates
+    p = alpha[:, None] + spread * rng.standard_normal((L, M))
+    q = beta[:, None] + spread * rng.standard_normal((L, M))
+    return InterpolatedDmn(depth, net.w, p, q, kind)
+
+
+def triangle_points(rng: np.random.Generator, count: int) -> np.ndarray:
+    """[count, 2] points (l1, l2) uniform in the fibre orientation triangle
+    1/3 <= l1 <= 1, 1 - 2 l1 <= l2 <= l1 (rejection from the bounding box)."""
+    out = np.empty((0, 2))
+    while out.shape[0] < count:
+        c = np.column_stack([rng.uniform(1.0 / 3.0, 1.0, 4 * count),
+                             rng.uniform(0.0, 1.0, 4 * count)])
+        ok = (c[:, 1] >= 1.0 - 2.0 * c[:, 0]) & (c[:, 1] <= c[:, 0])
+        out = np.vstack([out, c[ok]])
+    return out[:count].copy()
+
+
+def orientation_workload(n_points: int = 65536, n_steps: int = 20, kind: str = "quadratic",
+                         depth: int = 8):
+    """Depth-8 orientation-interpolated DMN, every point with its own (l1, l2);
+    strain paths as the production workload.  Returns (net, lam [P, 2], E)."""
+    rs = streams(5)
+    net = interpolated_dmn(rs["dmn"], depth, 0.25, kind)
+    lam = triangle_points(rs["assignment"], n_points)
+    E = ramp_with_noise(rs, n_points, n_steps, 0.015, 1e-3)
+    return net, lam, E
