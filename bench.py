@@ -14,9 +14,11 @@ One bench step is one pass of the whole hot path over one batch:
 The launch of each depth is autotuned first (lanes per point, persistent
 waves; cached on disk).  Reported beside the headline, outside its timed
 region: the mixed-depth batch (131,072 points over 16 DMNs of depths 5-9,
-the 20-step path captured as one HIP graph and replayed), and the plain
-one-launch-per-point and one-launch-per-sample forms of the same library on
-the same GPU, for comparison with the batched launches.
+the 20-step path captured as one HIP graph and replayed), the depth-8 update
+with orientation-interpolated normals (every point its own fibre
+orientation), and the plain one-launch-per-point and one-launch-per-sample
+forms of the same library on the same GPU, for comparison with the batched
+launches.
 
 Inputs are synthetic (see synthetic/), resident on the GPU before timing.
 Prints one JSON line.  `value` is Gauss-point updates per second of whole
@@ -362,6 +364,27 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         "replayed from a HIP graph (device time only)", us_per_point=plain_ms * 1e3,
         updates_per_s=1e3 / plain_ms, batched_updates_per_s=P / (batched_ms * 1e-3),
         batched_speedup=(plain_ms * P) / batched_ms)
+
+    # orientation-interpolated normals: depth 8, quadratic shape functions, every
+    # point its own (l1, l2); load step 10 of the same kind of path
+    from paper_2103_08253_amd import Orientation
+    net_o, lam_o, E_o = S.orientation_workload()
+    ori = Orientation(net_o.kind, torch.tensor(net_o.p, device=dev),
+                      torch.tensor(net_o.q, device=dev), torch.tensor(lam_o, device=dev))
+    E_ot = torch.tensor(E_o, device=dev)
+    go = PointGroup.allocate(torch.tensor(net_o.w, device=dev), None, E_ot[0].clone(), ori=ori)
+    ws_o = None
+    for k in range(10):
+        go.E = E_ot[k]
+        ws_o = dmn_update_gauss_points([go], S.FIBER, S.MATRIX, ws=ws_o)
+        go.advance()
+    go.E = E_ot[10]
+    ori_ms = _event_ms(lambda: dmn_update_gauss_points([go], S.FIBER, S.MATRIX, ws=ws_o), 3) / 3
+    out["gp_update_orientation_interpolated"] = dict(
+        points=E_o.shape[1], depth=8, shape_functions=net_o.kind, load_step=10,
+        ms=ori_ms, updates_per_s=E_o.shape[1] / (ori_ms * 1e-3),
+        all_converged=bool((go.status == 0).all().item()),
+        fixed_normals_ms_same_step=batched_ms)
 
     # training: one launch per sample vs the batch
     n_s = 128

@@ -69,14 +69,37 @@ extern "C" {
 
 #define DMN_MAX_DEPTH 10
 
+/* Fibre-orientation interpolation of the normals (Sec. 2.3): shape-function
+ * family of the orientation-interpolation table and its number M of
+ * functions. */
+#define DMN_ORI_NONE 0      /* fixed normals n */
+#define DMN_ORI_LINEAR 1    /* M = 3 */
+#define DMN_ORI_TRILINEAR 2 /* M = 4 (linear plus the cubic bubble) */
+#define DMN_ORI_QUADRATIC 3 /* M = 6 */
+
 /* A direct DMN: depth K, leaf weights w[2^K] (non-negative, need not sum to
- * one: fractions are weight ratios and averages use w / sum(w)), normals
- * n[2^K - 1][3] in paper order (unit length expected; used as passed).
- * Both arrays are device memory in the precision of the call. */
+ * one: fractions are weight ratios and averages use w / sum(w)), and either
+ *   ori_shape = DMN_ORI_NONE: normals n[2^K - 1][3] in paper order (unit
+ *     length expected; used as passed); or
+ *   ori_shape = DMN_ORI_LINEAR / TRILINEAR / QUADRATIC: normals that depend
+ *     on each point's fibre orientation (l1, l2), the two largest eigenvalues
+ *     of its second-order orientation tensor (Sec. 2.3).  (l1, l2) is mapped
+ *     to barycentric coordinates of the orientation triangle with vertices
+ *     unidirectional (1, 0), isotropic (1/3, 1/3), planar isotropic (1/2, 1/2);
+ *     with the M shape functions s of the family, laminate i has angles
+ *     alpha = ori_p[i] . s, beta = ori_q[i] . s and normal
+ *     (sin alpha cos beta, sin alpha sin beta, cos alpha).  ori_p, ori_q are
+ *     [2^K - 1][M] in paper order; n is not read.  Points outside the
+ *     triangle extrapolate the polynomials.  Supported by
+ *     dmn_update_gauss_points only (the other calls return DMN_EUNSUPPORTED).
+ * All arrays are device memory in the precision of the call. */
 typedef struct dmn_net {
   int32_t depth;
   const void* w;
   const void* n;
+  int32_t ori_shape;
+  const void* ori_p;
+  const void* ori_q;
 } dmn_net;
 
 /* Isotropic linear elastic phase 1 (the fibre): Young's modulus, Poisson ratio. */
@@ -115,6 +138,8 @@ typedef struct dmn_newton_opts {
  *   tangent [P][36]    algorithmic tangent d sigma / d E
  *   iters   [P]        Newton steps taken
  *   status  [P]        DMN_STATUS_*
+ *   lam     [P][2]     fibre orientation (l1, l2) of each point when
+ *                      net.ori_shape is not DMN_ORI_NONE (else not read)
  * The update is functional: z_in and a_in are never written, and must not
  * alias z_out / a_out.  On a non-zero status z_out = z_in and a_out = a_in so
  * the caller can retry with a smaller increment; sigma then holds the last
@@ -131,6 +156,7 @@ typedef struct dmn_point_group {
   void* tangent;
   int32_t* iters;
   int32_t* status;
+  const void* lam;
 } dmn_point_group;
 
 /* Version string of the library. */
@@ -177,8 +203,11 @@ size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int
  * a_in, with the J2 return mapping at matrix leaves and linear elasticity at
  * fibre leaves; return the effective stress, the algorithmic tangent, the
  * updated internal variables and the converged jumps.  Groups may have
- * different depths.  prec: DMN_F64 (DMN_F32_STATE returns DMN_EUNSUPPORTED).
- * At most 64 groups per call. */
+ * different depths and normal interpolations.  prec: DMN_F64 (DMN_F32_STATE
+ * returns DMN_EUNSUPPORTED).  At most 64 groups per call.  Groups with
+ * orientation-interpolated normals use the default lane split of their depth
+ * whatever the tuning table says.  A non-finite (l1, l2) gives
+ * DMN_STATUS_NONFINITE. */
 int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                             const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
                             const dmn_newton_opts* opts, void* ws, size_t ws_bytes,

@@ -10,13 +10,17 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdmn.so")
 
 DMN_OK, DMN_EINVAL, DMN_EWORKSPACE, DMN_EHIP, DMN_EUNSUPPORTED = 0, -1, -2, -3, -4
 DMN_F64, DMN_F32, DMN_F32_STATE = 0, 1, 2
+DMN_ORI = {"none": 0, "linear": 1, "trilinear": 2, "quadratic": 3}
+ORI_COUNT = {"linear": 3, "trilinear": 4, "quadratic": 6}
 STATUS = {0: "ok", 1: "maxiter", 2: "nonfinite", 3: "notspd", 4: "local", 5: "badparam"}
 ERRORS = {DMN_EINVAL: "DMN_EINVAL", DMN_EWORKSPACE: "DMN_EWORKSPACE", DMN_EHIP: "DMN_EHIP",
           DMN_EUNSUPPORTED: "DMN_EUNSUPPORTED"}
 
 
 class DmnNet(ctypes.Structure):
-    _fields_ = [("depth", ctypes.c_int32), ("w", ctypes.c_void_p), ("n", ctypes.c_void_p)]
+    _fields_ = [("depth", ctypes.c_int32), ("w", ctypes.c_void_p), ("n", ctypes.c_void_p),
+                ("ori_shape", ctypes.c_int32), ("ori_p", ctypes.c_void_p),
+                ("ori_q", ctypes.c_void_p)]
 
 
 class DmnElastic(ctypes.Structure):
@@ -38,7 +42,8 @@ class DmnPointGroup(ctypes.Structure):
                 ("E", ctypes.c_void_p), ("z_in", ctypes.c_void_p), ("z_out", ctypes.c_void_p),
                 ("a_in", ctypes.c_void_p), ("a_out", ctypes.c_void_p),
                 ("sigma", ctypes.c_void_p), ("tangent", ctypes.c_void_p),
-                ("iters", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+                ("iters", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p)]
 
 
 class DmnAdjointGroup(ctypes.Structure):

@@ -43,6 +43,21 @@ def _net(w: torch.Tensor, n: torch.Tensor, dtype):
     return L.DmnNet(K, w.data_ptr(), n.data_ptr()), K
 
 
+def _net_ori(w: torch.Tensor, ori: "Orientation"):
+    """dmn_net with orientation-interpolated normals."""
+    K = int(round(torch.log2(torch.tensor(float(w.numel()))).item()))
+    if 2 ** K != w.numel() or not 1 <= K <= 10:
+        raise ValueError("w must hold 2^K leaf weights with 1 <= K <= 10")
+    if ori.kind not in L.ORI_COUNT:
+        raise ValueError(f"unknown shape functions {ori.kind!r}")
+    M = L.ORI_COUNT[ori.kind]
+    _need(w, "w", torch.float64, (2 ** K,))
+    _need(ori.p, "p", torch.float64, (2 ** K - 1, M))
+    _need(ori.q, "q", torch.float64, (2 ** K - 1, M))
+    return L.DmnNet(K, w.data_ptr(), None, L.DMN_ORI[ori.kind], ori.p.data_ptr(),
+                    ori.q.data_ptr()), K
+
+
 def workspace(nbytes: int, device) -> torch.Tensor:
     """Device workspace (torch's allocator returns 512-byte aligned blocks)."""
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -106,10 +121,24 @@ def dmn_homogenize_backward(w, n, C1, C2, gCbar, want_input_grads=False, ws=None
 
 
 @dataclass
+class Orientation:
+    """Normals interpolated over the fibre orientation triangle: shape-function
+    family ("linear", "trilinear", "quadratic"), angle coefficients p, q
+    [L, M] (float64, device) and per-point (l1, l2) lam [P, 2]."""
+    kind: str
+    p: torch.Tensor
+    q: torch.Tensor
+    lam: torch.Tensor
+
+
+@dataclass
 class PointGroup:
-    """Device arrays of one batch of Gauss points sharing a DMN (see include/dmn.h)."""
+    """Device arrays of one batch of Gauss points sharing a DMN (see include/dmn.h).
+
+    With ``ori`` set the normals follow each point's fibre orientation and
+    ``n`` is not read (it may be None)."""
     w: torch.Tensor
-    n: torch.Tensor
+    n: Optional[torch.Tensor]
     E: torch.Tensor
     z_in: torch.Tensor
     z_out: torch.Tensor
@@ -119,9 +148,10 @@ class PointGroup:
     tangent: torch.Tensor
     iters: torch.Tensor
     status: torch.Tensor
+    ori: Optional[Orientation] = None
 
     @staticmethod
-    def allocate(w, n, E, z_in=None, a_in=None):
+    def allocate(w, n, E, z_in=None, a_in=None, ori=None):
         """Outputs (and zero initial state if not given) for the points of E [P, 6].
 
         The per-point arrays take E's dtype (float64; float32 maps to
@@ -138,7 +168,7 @@ class PointGroup:
                           torch.empty((P, 6), dtype=dt, device=dev),
                           torch.empty((P, 6, 6), dtype=dt, device=dev),
                           torch.empty(P, dtype=torch.int32, device=dev),
-                          torch.empty(P, dtype=torch.int32, device=dev))
+                          torch.empty(P, dtype=torch.int32, device=dev), ori)
 
     def advance(self):
         """Make the outputs the next step's inputs (swap the state buffers)."""
@@ -155,7 +185,10 @@ class PointGroup:
         raise TypeError(f"E must be float64 or float32, got {self.E.dtype}")
 
     def to_c(self):
-        net, K = _net(self.w, self.n, torch.float64)
+        if self.ori is None:
+            net, K = _net(self.w, self.n, torch.float64)
+        else:
+            net, K = _net_ori(self.w, self.ori)
         P = self.E.shape[0]
         M, Lm = 2 ** (K - 1), 2 ** K - 1
         dt = self.E.dtype
@@ -171,10 +204,14 @@ class PointGroup:
             raise ValueError("tangent must be [P, 6, 6]")
         _need(self.iters, "iters", torch.int32, (P,))
         _need(self.status, "status", torch.int32, (P,))
+        lam = None
+        if self.ori is not None:
+            _need(self.ori.lam, "lam", torch.float64, (P, 2))
+            lam = self.ori.lam.data_ptr()
         return L.DmnPointGroup(net, P, self.E.data_ptr(), self.z_in.data_ptr(),
                                self.z_out.data_ptr(), self.a_in.data_ptr(), self.a_out.data_ptr(),
                                self.sigma.data_ptr(), self.tangent.data_ptr(),
-                               self.iters.data_ptr(), self.status.data_ptr())
+                               self.iters.data_ptr(), self.status.data_ptr(), lam)
 
 
 def _materials(fiber: dict, matrix: dict):

@@ -119,6 +119,8 @@ def tune_gauss_points(groups: Sequence, fiber: dict, matrix: dict,
     tag = tag or device_tag()
     by_depth: Dict[int, list] = {}
     for g in groups:
+        if getattr(g, "ori", None) is not None:
+            continue  # orientation-interpolated groups always use the default split
         by_depth.setdefault(int(round(math.log2(g.w.numel()))), []).append(g)
     cache = load_cache(path)
     chosen: Dict[int, dict] = {}

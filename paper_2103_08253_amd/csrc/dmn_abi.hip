@@ -23,6 +23,25 @@ inline size_t table_bytes(int depth, int prec) {
 
 inline bool depth_ok(int32_t d) { return d >= 1 && d <= DMN_MAX_DEPTH; }
 
+// shape functions of an orientation interpolation, 0 for fixed normals, -1 invalid
+inline int ori_count(int32_t shape) {
+  switch (shape) {
+    case DMN_ORI_NONE: return 0;
+    case DMN_ORI_LINEAR: return 3;
+    case DMN_ORI_TRILINEAR: return 4;
+    case DMN_ORI_QUADRATIC: return 6;
+    default: return -1;
+  }
+}
+
+// a net with fixed normals (the calls other than the Gauss-point update)
+inline int fixed_net_check(const dmn_net* net) {
+  if (!net || !net->w) return DMN_EINVAL;
+  if (net->ori_shape != DMN_ORI_NONE) return ori_count(net->ori_shape) < 0 ? DMN_EINVAL
+                                                                           : DMN_EUNSUPPORTED;
+  return net->n ? DMN_OK : DMN_EINVAL;
+}
+
 struct Table {
   int32_t* flag;
   void* rows;
@@ -81,7 +100,7 @@ int dmn_homogenize_linear(const dmn_net* net, int64_t B, int prec, const void* C
                           hipStream_t stream) {
   if (!net || !depth_ok(net->depth) || B < 0) return DMN_EINVAL;
   if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
-  if (!net->w || !net->n) return DMN_EINVAL;
+  if (const int rc = fixed_net_check(net)) return rc;
   if (B > 0 && (!C1 || !C2 || !Cbar)) return DMN_EINVAL;
   const size_t need = dmn_homogenize_linear_workspace_size(net->depth, B, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
@@ -109,7 +128,8 @@ int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void*
                             void* gC2, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!net || !depth_ok(net->depth) || B < 0) return DMN_EINVAL;
   if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
-  if (!net->w || !net->n || !gw || !gn) return DMN_EINVAL;
+  if (const int rc = fixed_net_check(net)) return rc;
+  if (!gw || !gn) return DMN_EINVAL;
   if (B > 0 && (!C1 || !C2 || !gCbar)) return DMN_EINVAL;
   if ((gC1 == nullptr) != (gC2 == nullptr)) return DMN_EINVAL;
   const size_t need = dmn_homogenize_backward_workspace_size(net->depth, B, prec);
@@ -152,7 +172,11 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
     return DMN_EINVAL;
   for (int i = 0; i < n_groups; ++i) {
     const dmn_point_group& g = groups[i];
-    if (!depth_ok(g.net.depth) || g.P < 0 || !g.net.w || !g.net.n) return DMN_EINVAL;
+    if (!depth_ok(g.net.depth) || g.P < 0 || !g.net.w) return DMN_EINVAL;
+    const int m = ori_count(g.net.ori_shape);
+    if (m < 0) return DMN_EINVAL;
+    if (m == 0 && !g.net.n) return DMN_EINVAL;
+    if (m > 0 && (!g.net.ori_p || !g.net.ori_q || (g.P > 0 && !g.lam))) return DMN_EINVAL;
     if (g.P > 0 && (!g.E || !g.z_in || !g.z_out || !g.a_in || !g.a_out || !g.sigma ||
                     !g.tangent || !g.iters || !g.status))
       return DMN_EINVAL;
@@ -163,7 +187,10 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   for (int k = 1; k <= DMN_MAX_DEPTH; ++k) tune[k] = gp_tuning(k);
   for (int i = 0; i < n_groups; ++i) {
     const dmn_point_group& g = groups[i];
-    if ((g.P + 63) / 64 * tune[g.net.depth].lanes > (int64_t)0x7fffffff) return DMN_EINVAL;
+    const int lanes = g.net.ori_shape != DMN_ORI_NONE
+                          ? dmn::gp_default_lanes_per_point(g.net.depth)
+                          : tune[g.net.depth].lanes;
+    if ((g.P + 63) / 64 * lanes > (int64_t)0x7fffffff) return DMN_EINVAL;
   }
   const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
@@ -176,7 +203,8 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   for (int i = 0; i < n_groups; ++i) {
     tabs[i] = table_at(ws, off);
     off += table_bytes(groups[i].net.depth, DMN_F64);
-    if (dmn::launch_prep_tables(groups[i].net.w, groups[i].net.n, groups[i].net.depth, DMN_F64,
+    const void* nfix = groups[i].net.ori_shape == DMN_ORI_NONE ? groups[i].net.n : nullptr;
+    if (dmn::launch_prep_tables(groups[i].net.w, nfix, groups[i].net.depth, DMN_F64,
                                 tabs[i].rows, tabs[i].flag, nullptr, stream))
       return DMN_EHIP;
   }
@@ -196,26 +224,31 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   base.mat.dsigma = matrix->dsigma;
   base.mat.b = matrix->b;
 
-  // one launch per depth (deepest first), up to kMaxGroupsPerLaunch groups each
+  // one launch per depth (deepest first) and kind of normals, up to
+  // kMaxGroupsPerLaunch groups each
   std::vector<int> order;
   for (int i = 0; i < n_groups; ++i)
     if (groups[i].P > 0) order.push_back(i);
+  auto is_ori = [&](int i) { return groups[i].net.ori_shape != DMN_ORI_NONE; };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return groups[a].net.depth > groups[b].net.depth;
+    if (groups[a].net.depth != groups[b].net.depth)
+      return groups[a].net.depth > groups[b].net.depth;
+    return (int)is_ori(a) < (int)is_ori(b);
   });
   size_t pos = 0;
   int launch = 0;
   const long long cus = dmn::device_cu_count();
   while (pos < order.size()) {
     const int K = groups[order[pos]].net.depth;
-    const int lp = tune[K].lanes;
+    const bool ori = is_ori(order[pos]);
+    const int lp = ori ? dmn::gp_default_lanes_per_point(K) : tune[K].lanes;
     const long long persistent = cus * tune[K].waves_per_cu;
     const int ppb = dmn::gp_points_per_block(K, lp);
     dmn::GpLaunch args = base;
     args.ng = 0;
     long long blocks = 0;
     while (pos < order.size() && groups[order[pos]].net.depth == K &&
-           args.ng < dmn::kMaxGroupsPerLaunch) {
+           is_ori(order[pos]) == ori && args.ng < dmn::kMaxGroupsPerLaunch) {
       const int i = order[pos];
       const dmn_point_group& g = groups[i];
       dmn::GroupArgs& a = args.g[args.ng++];
@@ -230,6 +263,10 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
       a.status = g.status;
       a.tab = (const double*)tabs[i].rows;
       a.flag = tabs[i].flag;
+      a.ori_p = (const double*)g.net.ori_p;
+      a.ori_q = (const double*)g.net.ori_q;
+      a.lam = (const double*)g.lam;
+      a.ori_m = ori_count(g.net.ori_shape);
       a.P = g.P;
       a.block0 = (int)blocks;
       blocks += (g.P + ppb - 1) / ppb;
@@ -239,7 +276,7 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
     args.counter = counters + launch++;
     args.total = (int)blocks;
     const long long waves = blocks < persistent ? blocks : persistent;
-    if (dmn::launch_gp_update(K, lp, prec, args, (int)waves, stream)) return DMN_EHIP;
+    if (dmn::launch_gp_update(K, lp, prec, ori, args, (int)waves, stream)) return DMN_EHIP;
   }
   return DMN_OK;
 }
@@ -271,8 +308,8 @@ int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
   if (!phase_ok(fiber) || !j2_ok(matrix)) return DMN_EINVAL;
   for (int i = 0; i < n_groups; ++i) {
     const dmn_adjoint_group& g = groups[i];
-    if (!depth_ok(g.net.depth) || g.P < 0 || !g.net.w || !g.net.n || !g.gw || !g.gn)
-      return DMN_EINVAL;
+    if (!depth_ok(g.net.depth) || g.P < 0 || !g.gw || !g.gn) return DMN_EINVAL;
+    if (const int rc = fixed_net_check(&g.net)) return rc;
     if (g.P > 0 && (!g.E || !g.z_in || !g.a_conv || !g.g_z_prev)) return DMN_EINVAL;
     if (g.P > 0 && g.g_z_next != nullptr && g.g_z_next == g.g_z_prev) return DMN_EINVAL;
   }

@@ -112,7 +112,7 @@ __device__ __forceinline__ void sum_node(const Ctx<K, D>& cx, const LaneState<K,
     double SmR[6], SsR[6];
     sum_node<K, D, 2 * H>(cx, st, mu, ws, live, acc, Sm, Ss);
     sum_node<K, D, 2 * H + 1>(cx, st, mu, ws, live, acc, SmR, SsR);
-    const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row(cx, lane_pos<K, D, H>(cx.t));
     double a[3], lam[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -145,6 +145,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
   cx.t = lane % C::LP;
   cx.base = cx.slot * C::LP;
   cx.tab = stage_table<K>(tlds, args.tab + table_soa_offset(K));
+  cx.nrm = cx.tab + 2 * C::L;
   cx.fib = args.fib;
   cx.mat = args.mat;
   const double* leafw = args.tab + (size_t)C::L * kTabStride;
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
       if (upper_active(cx.t, m)) {
         const int pos = upper_pos<K, D>(m, cx.t);
         const int u = cx.slot * C::NUPS + (pos - C::UP0);
-        const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, pos);
+        const LamRow row = load_row(cx, pos);
         double a[3], lam[3], g4[4];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {

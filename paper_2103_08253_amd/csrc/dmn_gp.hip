@@ -98,12 +98,14 @@ __device__ __forceinline__ void finalize(const Ctx<K, D>& cx, const LaneState<K,
 // more Newton iterations do not leave SIMDs idle; the DMN table of the
 // current group is staged in the wave's LDS when the group changes.  S is the
 // storage type of the per-point arrays (double, or float for FP32 state);
-// arithmetic is FP64 either way.
-template <int K, int D, typename S>
+// arithmetic is FP64 either way.  ORI: the groups' normals follow each point's
+// fibre orientation and are computed into LDS when the wave takes a batch.
+template <int K, int D, typename S, bool ORI>
 __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   using C = Cfg<K, D>;
   __shared__ UpperLds<K, D> up;
   __shared__ TableLds<K> tlds;
+  __shared__ NormalLds<K, D, ORI> nlds;
   const int lane = threadIdx.x;
   int cur = -1;
   const double* tabp = nullptr;
@@ -129,6 +131,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
   cx.t = lane % C::LP;
   cx.base = cx.slot * C::LP;
   cx.tab = tabp;
+  cx.nrm = tabp + 2 * C::L;
   cx.fib = args.fib;
   cx.mat = args.mat;
   const long long pt_raw = (long long)(item - G.block0) * C::PPW + cx.slot;
@@ -147,6 +150,13 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
 
   // load the jumps and check the inputs of the point for non-finite values
   int bad = 0;
+  if constexpr (ORI) {
+    const double l1 = G.lam[(size_t)pt * 2], l2 = G.lam[(size_t)pt * 2 + 1];
+    bad |= (isfinite(l1) && isfinite(l2)) ? 0 : 1;
+    double* nrm = nlds.v + cx.slot * 3 * C::L;
+    orientation_normals<K, D>(G.ori_p, G.ori_q, G.ori_m, l1, l2, cx.t, nrm);
+    cx.nrm = nrm;  // read by the point's other lanes after the next barrier
+  }
 #pragma unroll
   for (int k = 0; k < 6; ++k) bad |= isfinite(E[k]) ? 0 : 1;
 #pragma unroll
@@ -299,21 +309,32 @@ int gp_points_per_block(int depth, int lanes_per_point) {
 
 // Only FP64 storage is instantiated: the FP32-storage instantiation is switched
 // off (its first GPU run ended in a device fault whose cause is not yet found).
+// Orientation-interpolated normals are compiled for the default split of
+// each depth only.
 template <int K, int D>
-static int launch_kd(int prec, const GpLaunch& args, int n_blocks, hipStream_t stream) {
+static int launch_kd(int prec, bool ori, const GpLaunch& args, int n_blocks, hipStream_t stream) {
   if (prec != DMN_F64) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL((gp_update_kernel<K, D, double>), dim3(n_blocks), dim3(64), 0, stream, args);
+  if (ori) {
+    if constexpr (D == (K - 6 < 1 ? 1 : K - 6))
+      hipLaunchKernelGGL((gp_update_kernel<K, D, double, true>), dim3(n_blocks), dim3(64), 0,
+                         stream, args);
+    else
+      return (int)hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((gp_update_kernel<K, D, double, false>), dim3(n_blocks), dim3(64), 0,
+                       stream, args);
+  }
   return (int)hipGetLastError();
 }
 
-int launch_gp_update(int depth, int lanes_per_point, int prec, const GpLaunch& args,
+int launch_gp_update(int depth, int lanes_per_point, int prec, bool ori, const GpLaunch& args,
                      int n_blocks, hipStream_t stream) {
   if (lanes_per_point < 1 || lanes_per_point > 64) return (int)hipErrorInvalidValue;
   const int D = depth - ilog2(lanes_per_point);
   switch (depth * 16 + D) {
 #define DMN_GP_CASE(KK, DD) \
   case KK * 16 + DD:        \
-    return launch_kd<KK, DD>(prec, args, n_blocks, stream);
+    return launch_kd<KK, DD>(prec, ori, args, n_blocks, stream);
     DMN_GP_VARIANTS(DMN_GP_CASE)
 #undef DMN_GP_CASE
     default:

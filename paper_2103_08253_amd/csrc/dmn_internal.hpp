@@ -35,6 +35,11 @@ struct GroupArgs {  // tab points at the table start (AoS rows first)
   void* tangent;
   int32_t* iters;
   int32_t* status;
+  const double* ori_p;  // [L][ori_m] angle coefficients (orientation launches)
+  const double* ori_q;
+  const double* lam;    // [P][2] per-point (l1, l2)
+  int ori_m;            // number of shape functions (3, 4, 6), 0 without interpolation
+  int ori_pad;
   const double* tab;   // [L][kTabStride]
   const int32_t* flag; // nonzero: invalid DMN parameters
   long long P;
@@ -61,7 +66,7 @@ struct GpLaunch {
 // Host launchers (return hipError_t as int).
 int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
                        int32_t* err, hipStream_t stream);
-int launch_gp_update(int depth, int lanes_per_point, int prec, const GpLaunch& args,
+int launch_gp_update(int depth, int lanes_per_point, int prec, bool ori, const GpLaunch& args,
                      int n_blocks, hipStream_t stream);
 int launch_zero_ints(int32_t* p, int n, hipStream_t stream);
 // compute units of the current device (cached per device)

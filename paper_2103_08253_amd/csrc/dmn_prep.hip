@@ -4,7 +4,8 @@
 // From the leaf weights w[2^K] and the normals n[2^K-1][3] (paper order) one
 // workgroup builds the laminate table used by every kernel:
 //   c1 = W_L / (W_L + W_R), c2 = 1 - c1   (W_X: summed leaf weights of a child)
-//   n                                      (copied as passed)
+//   n                                      (copied as passed; zero if n is null,
+//                                           for normals interpolated per point)
 //   rfac = W_L W_R / ((W_L + W_R) sum(w))  (scale of the laminate's block of A^T W sigma)
 //   dc1/dW_L = W_R / W^2, dc1/dW_R = -W_L / W^2
 // followed by the leaf section w / sum(w) [2^K] and 1 / sum(w), and a
@@ -57,9 +58,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, cons
     const T c1 = WL / Wn;
     r[0] = c1;
     r[1] = T(1) - c1;
-    r[2] = n[(size_t)pos * 3 + 0];
-    r[3] = n[(size_t)pos * 3 + 1];
-    r[4] = n[(size_t)pos * 3 + 2];
+    r[2] = n ? n[(size_t)pos * 3 + 0] : T(0);  // no fixed normals: filled per point
+    r[3] = n ? n[(size_t)pos * 3 + 1] : T(0);
+    r[4] = n ? n[(size_t)pos * 3 + 2] : T(0);
     r[5] = WL * WR / (Wn * wtot);
     r[6] = WR / (Wn * Wn);
     r[7] = -WL / (Wn * Wn);

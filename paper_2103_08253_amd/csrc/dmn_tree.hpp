@@ -48,20 +48,6 @@ struct LamRow {
   double c1, c2, rf;
 };
 
-// Row of the laminate table, field-major copy [6][L] (c1, c2, n0, n1, n2, rfac):
-// in LDS for depths up to 9, in global memory above.
-template <int L>
-__device__ __forceinline__ LamRow load_row_soa(const double* __restrict__ tab, int pos) {
-  LamRow o;
-  o.c1 = tab[0 * L + pos];
-  o.c2 = tab[1 * L + pos];
-  o.nv.n0 = tab[2 * L + pos];
-  o.nv.n1 = tab[3 * L + pos];
-  o.nv.n2 = tab[4 * L + pos];
-  o.rf = tab[5 * L + pos];
-  return o;
-}
-
 template <int K>
 struct TableLds {
   static constexpr int L = (1 << K) - 1;
@@ -113,6 +99,7 @@ struct EvalOut {
 template <int K, int D>
 struct Ctx {
   const double* __restrict__ tab;
+  const double* nrm;     // normals [3][L] of this point (the table's or its own)
   const void* zin;       // this point's z_in (storage precision of the kernel)
   void* zout = nullptr;  // this point's z_out, written by the leaf law when wz is set
   IsoElastic fib;
@@ -122,6 +109,70 @@ struct Ctx {
   int base;  // first lane of this point in the wave
   bool wz = false;
 };
+
+// Laminate row of the point: fractions and residual scale from the table,
+// normal from the point's normal array.
+template <int K, int D>
+__device__ __forceinline__ LamRow load_row(const Ctx<K, D>& cx, int pos) {
+  constexpr int L = Cfg<K, D>::L;
+  LamRow o;
+  o.c1 = cx.tab[0 * L + pos];
+  o.c2 = cx.tab[1 * L + pos];
+  o.rf = cx.tab[5 * L + pos];
+  o.nv.n0 = cx.nrm[0 * L + pos];
+  o.nv.n1 = cx.nrm[1 * L + pos];
+  o.nv.n2 = cx.nrm[2 * L + pos];
+  return o;
+}
+
+// LDS normals of the points of a wave, [slot][3][L], for orientation launches.
+template <int K, int D, bool ORI>
+struct NormalLds {
+  double v[ORI ? Cfg<K, D>::PPW * 3 * Cfg<K, D>::L : 1];
+};
+
+// Normals of one point from its fibre orientation (l1, l2) (FE-DMN paper,
+// Sec. 2.3): barycentric coordinates of the orientation triangle (vertices
+// unidirectional (1, 0), isotropic (1/3, 1/3), planar isotropic (1/2, 1/2)),
+// the m shape functions of the orientation-interpolation table (3 linear,
+// 4 tri-linear, 6 quadratic), angles alpha = p . s, beta = q . s per laminate,
+// n = (sin a cos b, sin a sin b, cos a).  Lane t of the point's LP lanes
+// writes laminates t, t + LP, ... of nrm [3][L].
+template <int K, int D>
+__device__ __forceinline__ void orientation_normals(const double* __restrict__ p,
+                                                    const double* __restrict__ q, int m,
+                                                    double l1, double l2, int t, double* nrm) {
+  using C = Cfg<K, D>;
+  constexpr int L = C::L;
+  const double f1 = l1 - l2;
+  const double f2 = 3.0 - 3.0 * l1 - 3.0 * l2;
+  const double f3 = 2.0 * l1 + 4.0 * l2 - 2.0;
+  double s[6];
+  if (m == 3) {
+    s[0] = f1; s[1] = f2; s[2] = f3;
+  } else if (m == 4) {
+    const double b = f1 * f2 * f3;
+    s[0] = f1 - 9.0 * b; s[1] = f2 - 9.0 * b; s[2] = f3 - 9.0 * b; s[3] = 27.0 * b;
+  } else {
+    s[0] = f1 * (2.0 * f1 - 1.0); s[1] = f2 * (2.0 * f2 - 1.0); s[2] = f3 * (2.0 * f3 - 1.0);
+    s[3] = 4.0 * f1 * f2; s[4] = 4.0 * f1 * f3; s[5] = 4.0 * f2 * f3;
+  }
+#pragma unroll 1
+  for (int pos = t; pos < L; pos += C::LP) {
+    double a = 0.0, b = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < m; ++j) {
+      a += p[(size_t)pos * m + j] * s[j];
+      b += q[(size_t)pos * m + j] * s[j];
+    }
+    double sa, ca, sb, cb;
+    sincos(a, &sa, &ca);
+    sincos(b, &sb, &cb);
+    nrm[0 * L + pos] = sa * cb;
+    nrm[1 * L + pos] = sa * sb;
+    nrm[2 * L + pos] = ca;
+  }
+}
 
 __device__ __forceinline__ double shfl_down_d(double v, int o, int width) {
   return __shfl_down(v, (unsigned)o, width);
@@ -146,7 +197,7 @@ __device__ __forceinline__ void loc_node(const Ctx<K, D>& cx, const LaneState<K,
 #pragma unroll
     for (int k = 0; k < 6; ++k) eps[H - C::NLEAF][k] = e[k];
   } else {
-    const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row(cx, lane_pos<K, D, H>(cx.t));
     double aj[3], eL[6], eR[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) aj[k] = st.a[H - 1][k] + s * st.da[H - 1][k];
@@ -175,7 +226,7 @@ __device__ __forceinline__ void localize(const Ctx<K, D>& cx, const LaneState<K,
     const int lead = cx.t & ~((1 << m) - 1);
     const int pos = upper_pos<K, D>(m, lead);
     const int u = cx.slot * C::NUPS + (pos - C::UP0);
-    const LamRow row = load_row_soa<C::L>(cx.tab, pos);
+    const LamRow row = load_row(cx, pos);
     double aj[3], Na[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) aj[k] = up.a[k][u] + s * up.da[k][u];
@@ -237,7 +288,7 @@ __device__ __forceinline__ void up_node(const Ctx<K, D>& cx, LaneState<K, D>& st
     up_node<K, D, 2 * H>(cx, st, leaf, eps, Cn, tn, sn, rr, lfail, spdfail);
     double CR[21], tR[6], sR[6];
     up_node<K, D, 2 * H + 1>(cx, st, leaf, eps, CR, tR, sR, rr, lfail, spdfail);
-    const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row(cx, lane_pos<K, D, H>(cx.t));
     const bool ok = laminate_newton(Cn, tn, sn, CR, tR, sR, row.nv, row.c1, row.c2, row.rf,
                                     st.G[H - 1], st.g[H - 1], rr);
     spdfail |= ok ? 0 : 1;
@@ -256,7 +307,7 @@ __device__ __forceinline__ void up_node_loc(const Ctx<K, D>& cx, LaneState<K, D>
   if constexpr (H >= C::NLEAF) {
     leaf(cx, std::integral_constant<int, H - C::NLEAF>{}, e, Cn, tn, sn, lfail);
   } else {
-    const LamRow row = load_row_soa<C::L>(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row(cx, lane_pos<K, D, H>(cx.t));
     double aj[3], eL[6], eR[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) aj[k] = st.a[H - 1][k] + s * st.da[H - 1][k];
@@ -291,7 +342,7 @@ __device__ __forceinline__ void evaluate_upper(const Ctx<K, D>& cx, UpperLds<K, 
     if (upper_active(cx.t, m)) {
       const int pos = upper_pos<K, D>(m, cx.t);
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
-      const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, pos);
+      const LamRow row = load_row(cx, pos);
       double Gu[18], gu[3];
       const bool ok = laminate_newton(out.C, cT, out.sb, rC, rT, rS, row.nv, row.c1, row.c2,
                                       row.rf, Gu, gu, rr);
@@ -353,7 +404,7 @@ __device__ __forceinline__ void evaluate_at(const Ctx<K, D>& cx, LaneState<K, D>
     const int lead = cx.t & ~((1 << m) - 1);
     const int pos = upper_pos<K, D>(m, lead);
     const int u = cx.slot * C::NUPS + (pos - C::UP0);
-    const LamRow row = load_row_soa<C::L>(cx.tab, pos);
+    const LamRow row = load_row(cx, pos);
     double aj[3], Na[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) aj[k] = up.a[k][u] + s * up.da[k][u];
@@ -377,7 +428,7 @@ __device__ __forceinline__ void down_node(const Ctx<K, D>& cx, LaneState<K, D>& 
                                           double (*leaf_de)[6] /* [NLEAF][6] or null */) {
   using C = Cfg<K, D>;
   if constexpr (H < C::NLEAF) {
-    const LamRow row = load_row_soa<Cfg<K, D>::L>(cx.tab, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row(cx, lane_pos<K, D, H>(cx.t));
     double eL[6], eR[6], dah[3];
     laminate_descend(st.G[H - 1], st.g[H - 1], e, row.nv, row.c1, row.c2, dah, eL, eR);
     if (commit) {
@@ -411,7 +462,7 @@ __device__ __forceinline__ void direction(const Ctx<K, D>& cx, LaneState<K, D>& 
     const int lead = cx.t & ~((1 << m) - 1);
     const int pos = upper_pos<K, D>(m, lead);
     const int u = cx.slot * C::NUPS + (pos - C::UP0);
-    const LamRow row = load_row_soa<C::L>(cx.tab, pos);
+    const LamRow row = load_row(cx, pos);
     double Gu[18], gu[3], dau[3], eL[6], eR[6];
 #pragma unroll
     for (int k = 0; k < 18; ++k) Gu[k] = up.G[k][u];

@@ -110,3 +110,38 @@ def test_gauss_point_validation_codes():
     assert call(a=neg, n=1) == L.DMN_EINVAL
     nul = (L.DmnPointGroup * 1)(group(2, sigma=None))
     assert call(a=nul, n=1) == L.DMN_EINVAL
+
+
+def test_orientation_validation_codes():
+    lib = L.lib()
+    fib = L.DmnElastic(72000.0, 0.22)
+    mat = L.DmnJ2(2800.0, 0.35, 50.0, 200.0, 30.0, 60.0)
+    opts = L.DmnNewtonOpts(1e-10, 25, 10, 1e-4)
+
+    def ori_group(shape, p=FAKE.value, q=FAKE.value, lam=FAKE.value, P=5):
+        g = group(3, P=P)
+        g.net = L.DmnNet(3, FAKE.value, None, shape, p, q)
+        g.lam = lam
+        return (L.DmnPointGroup * 1)(g)
+
+    arr = ori_group(L.DMN_ORI["quadratic"])
+    need = lib.dmn_update_gauss_points_workspace_size(arr, 1, L.DMN_F64)
+    assert need > 0
+
+    def call(a):
+        return lib.dmn_update_gauss_points(a, 1, ctypes.byref(fib), ctypes.byref(mat), L.DMN_F64,
+                                           ctypes.byref(opts), ALIGNED, need, None)
+
+    assert call(ori_group(7)) == L.DMN_EINVAL
+    assert call(ori_group(L.DMN_ORI["linear"], p=None)) == L.DMN_EINVAL
+    assert call(ori_group(L.DMN_ORI["trilinear"], q=None)) == L.DMN_EINVAL
+    assert call(ori_group(L.DMN_ORI["quadratic"], lam=None)) == L.DMN_EINVAL
+    assert call(ori_group(L.DMN_ORI["none"])) == L.DMN_EINVAL  # fixed normals need n
+    # the other calls take fixed normals only
+    net = L.DmnNet(3, FAKE.value, None, L.DMN_ORI["linear"], FAKE.value, FAKE.value)
+    nb = lib.dmn_homogenize_linear_workspace_size(3, 4, L.DMN_F64)
+    assert lib.dmn_homogenize_linear(ctypes.byref(net), 4, L.DMN_F64, FAKE, FAKE, FAKE, ALIGNED,
+                                     nb, None) == L.DMN_EUNSUPPORTED
+    nbb = lib.dmn_homogenize_backward_workspace_size(3, 4, L.DMN_F64)
+    assert lib.dmn_homogenize_backward(ctypes.byref(net), 4, L.DMN_F64, FAKE, FAKE, FAKE, FAKE,
+                                       FAKE, None, None, ALIGNED, nbb, None) == L.DMN_EUNSUPPORTED
