@@ -16,7 +16,8 @@ waves; cached on disk).  Reported beside the headline, outside its timed
 region: the mixed-depth batch (131,072 points over 16 DMNs of depths 5-9,
 the 20-step path captured as one HIP graph and replayed), the depth-8 update
 with orientation-interpolated normals (every point its own fibre
-orientation), and the plain one-launch-per-point and one-launch-per-sample
+orientation), the paper's six uniaxial strain hystereses with its material
+constants (80 steps, one graph), and the plain one-launch-per-point and one-launch-per-sample
 forms of the same library on the same GPU, for comparison with the batched
 launches.
 
@@ -385,6 +386,31 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         ms=ori_ms, updates_per_s=E_o.shape[1] / (ori_ms * 1e-3),
         all_converged=bool((go.status == 0).all().item()),
         fixed_normals_ms_same_step=batched_ms)
+
+    # the paper's inelastic load cases: six uniaxial strain hystereses (2.5 %,
+    # 80 steps, the paper's material constants) over 65,536 points, each with
+    # its own fibre orientation; the 80-step path captured as one graph
+    net_h, lam_h, E_h, _ = S.hysteresis_workload()
+    ori_h = Orientation(net_h.kind, torch.tensor(net_h.p, device=dev),
+                        torch.tensor(net_h.q, device=dev), torch.tensor(lam_h, device=dev))
+    E_ht = torch.tensor(E_h, device=dev)
+    gh = PointGroup.allocate(torch.tensor(net_h.w, device=dev), None, E_ht[0].clone(), ori=ori_h)
+    graph_h = LoadStepGraph([gh], S.FIBER_PAPER, S.MATRIX_PAPER, [E_ht], keep_sigma=False)
+
+    def replay_h():
+        for z, a in graph_h.start_state:
+            z.zero_()
+            a.zero_()
+        graph_h.replay()
+    replay_h()
+    torch.cuda.synchronize()
+    hyst_ms = _event_ms(replay_h)
+    out["hysteresis_paper_constants_graph"] = dict(
+        points=E_h.shape[1], depth=8, shape_functions=net_h.kind, load_steps=E_h.shape[0],
+        ms_per_load_step=hyst_ms / E_h.shape[0],
+        updates_per_s=E_h.shape[1] * E_h.shape[0] / (hyst_ms * 1e-3),
+        last_step_all_converged=bool((gh.status == 0).all().item()))
+    del graph_h, gh, E_ht
 
     # training: one launch per sample vs the batch
     n_s = 128

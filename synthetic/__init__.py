@@ -288,3 +288,40 @@ def orientation_workload(n_points: int = 65536, n_steps: int = 20, kind: str = "
     lam = triangle_points(rs["assignment"], n_points)
     E = ramp_with_noise(rs, n_points, n_steps, 0.015, 1e-3)
     return net, lam, E
+
+
+# ---------------------------------------------------------------- hysteresis
+
+# Mandel components of the six uniaxial strain directions e_i (x) e_j
+# (i, j) = 11, 22, 33, 23, 13, 12: the symmetric part of e_i (x) e_j, whose
+# Mandel entry is sqrt(2) * 1/2 for i != j.
+UNIAXIAL_DIRECTIONS = np.array([
+    [1.0, 0.0, 0.0, 0.0, 0.0, 0.0],
+    [0.0, 1.0, 0.0, 0.0, 0.0, 0.0],
+    [0.0, 0.0, 1.0, 0.0, 0.0, 0.0],
+    [0.0, 0.0, 0.0, np.sqrt(0.5), 0.0, 0.0],
+    [0.0, 0.0, 0.0, 0.0, np.sqrt(0.5), 0.0],
+    [0.0, 0.0, 0.0, 0.0, 0.0, np.sqrt(0.5)],
+])
+
+
+def hysteresis_factor(n_steps: int = 80) -> np.ndarray:
+    """Scalar load factor of a full cycle in n_steps equidistant steps:
+    0 -> +1 in a quarter, +1 -> -1 in a half, -1 -> 0 in the last quarter."""
+    t = np.arange(1, n_steps + 1, dtype=np.float64) / n_steps
+    return np.where(t <= 0.25, 4.0 * t, np.where(t <= 0.75, 2.0 - 4.0 * t, 4.0 * t - 4.0))
+
+
+def hysteresis_workload(n_points: int = 65536, n_steps: int = 80, amplitude: float = 0.025,
+                        kind: str = "linear", depth: int = 8, fiber_fraction: float = 0.16):
+    """The paper's inelastic load cases on an orientation-interpolated DMN:
+    point p runs the uniaxial strain hysteresis of direction p mod 6 with the
+    given amplitude and has its own fibre orientation (l1, l2).  Use with
+    FIBER_PAPER and MATRIX_PAPER.  Returns (net, lam [P, 2], E [T, P, 6],
+    case [P])."""
+    rs = streams(6)
+    net = interpolated_dmn(rs["dmn"], depth, fiber_fraction, kind)
+    lam = triangle_points(rs["assignment"], n_points)
+    case = np.arange(n_points) % 6
+    E = (amplitude * hysteresis_factor(n_steps))[:, None, None] * UNIAXIAL_DIRECTIONS[case][None]
+    return net, lam, E, case
