@@ -63,3 +63,27 @@ def interpolated_normals(p, q, l1, l2, kind):
     """Lamination normals [L, 3] of the DMN at orientation (l1, l2)."""
     a, b = interpolated_angles(p, q, l1, l2, kind)
     return normals_from_angles(a, b)
+
+
+def oriented_linear(K, w, p, q, kind, lam, C1, C2):
+    """DMN^L (Sec. 3.1) of every sample with the normals of its own orientation
+    lam[b] = (l1, l2): [B, 6, 6].  Complex-safe in w, p, q."""
+    from .linear import dmn_linear
+    out = []
+    for b in range(len(lam)):
+        n = interpolated_normals(p, q, lam[b][0], lam[b][1], kind)
+        out.append(dmn_linear(K, w, n, C1[b:b + 1], C2[b:b + 1])[0])
+    return np.stack(out)
+
+
+def oriented_functional(K, w, p, q, kind, lam, C1, C2, G):
+    """J = sum_b <G_b, DMN^L_b>."""
+    return np.sum(G * oriented_linear(K, w, p, q, kind, lam, C1, C2))
+
+
+def oriented_directional_derivative(K, w, p, q, kind, lam, C1, C2, G, vw, vp, vq, h=1e-30):
+    """dJ/d(w, p, q) . (vw, vp, vq) by one complex step of size h."""
+    J = oriented_functional(K, np.asarray(w) + 1j * h * np.asarray(vw),
+                            np.asarray(p) + 1j * h * np.asarray(vp),
+                            np.asarray(q) + 1j * h * np.asarray(vq), kind, lam, C1, C2, G)
+    return J.imag / h

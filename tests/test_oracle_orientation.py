@@ -112,3 +112,64 @@ def test_normals_are_unit_and_constant_angles_give_fixed_normals(kind):
     pr, qr = rng.normal(size=(15, M)), rng.normal(size=(15, M))
     n = interpolated_normals(pr, qr, 0.6, 0.3, kind)
     assert np.allclose(np.linalg.norm(n, axis=1), 1.0)
+
+
+def _training_case(K=2, B=3, kind="quadratic", seed=11):
+    import synthetic as S
+    rs = S.streams(seed)
+    net = S.interpolated_dmn(rs["dmn"], K, 0.3, kind)
+    lam = S.triangle_points(rs["assignment"], B)
+    C1 = S.random_spd(rs["stiffness"], B)
+    C2 = S.random_spd(rs["stiffness"], B)
+    G = rs["cotangent"].standard_normal((B, 6, 6))
+    return net, lam, C1, C2, G
+
+
+def test_oriented_linear_with_constant_coefficients_is_the_fixed_map():
+    """Equal shape coefficients give orientation-independent normals (partition
+    of unity), so every sample sees the fixed-normal map."""
+    from oracle.linear import dmn_linear
+    net, lam, C1, C2, _ = _training_case(K=3, B=4)
+    a0, b0 = net.p[:, 0], net.q[:, 0]
+    M = net.p.shape[1]
+    p = np.repeat(a0[:, None], M, 1)
+    q = np.repeat(b0[:, None], M, 1)
+    from oracle.orientation import oriented_linear
+    got = oriented_linear(3, net.w, p, q, net.kind, lam, C1, C2)
+    ref = dmn_linear(3, net.w, normals_from_angles(a0, b0), C1, C2)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("kind", list(SHAPES))
+def test_oriented_directional_derivative_matches_central_differences(kind):
+    from oracle.orientation import oriented_directional_derivative, oriented_functional
+    net, lam, C1, C2, G = _training_case(K=2, B=3, kind=kind)
+    rng = np.random.default_rng(2)
+    vw, vp, vq = rng.standard_normal(4), rng.standard_normal(net.p.shape), rng.standard_normal(net.q.shape)
+    d = oriented_directional_derivative(2, net.w, net.p, net.q, kind, lam, C1, C2, G, vw, vp, vq)
+    def central(h):
+        Jp = oriented_functional(2, net.w + h * vw, net.p + h * vp, net.q + h * vq, kind, lam,
+                                 C1, C2, G)
+        Jm = oriented_functional(2, net.w - h * vw, net.p - h * vp, net.q - h * vq, kind, lam,
+                                 C1, C2, G)
+        return (Jp - Jm) / (2 * h)
+    h = 1e-4
+    fd = (4.0 * central(h / 2) - central(h)) / 3.0   # Richardson: O(h^4)
+    assert abs(d - fd) <= 1e-8 * max(abs(d), 1.0)
+
+
+def test_coefficient_gradients_sum_to_the_angle_gradient():
+    """Partition of unity: at fixed orientation, the derivative along v_p = 1 for
+    every shape coefficient of one laminate equals the derivative along its angle."""
+    from oracle.grad import linear_gradients
+    from oracle.orientation import interpolated_angles, oriented_directional_derivative
+    net, lam, C1, C2, G = _training_case(K=2, B=1, kind="trilinear")
+    L, M = net.p.shape
+    a, b = interpolated_angles(net.p, net.q, lam[0, 0], lam[0, 1], net.kind)
+    ref = linear_gradients(2, net.w, a, b, C1, C2, G)
+    for i in range(L):
+        vp = np.zeros((L, M))
+        vp[i] = 1.0
+        d = oriented_directional_derivative(2, net.w, net.p, net.q, net.kind, lam, C1, C2, G,
+                                            np.zeros(4), vp, np.zeros((L, M)))
+        assert abs(d - ref["galpha"][i]) <= 1e-10 * max(1.0, abs(ref["galpha"][i]))
