@@ -91,7 +91,10 @@ extern "C" {
  *     (sin alpha cos beta, sin alpha sin beta, cos alpha).  ori_p, ori_q are
  *     [2^K - 1][M] in paper order; n is not read.  Points outside the
  *     triangle extrapolate the polynomials.  Supported by
- *     dmn_update_gauss_points only (the other calls return DMN_EUNSUPPORTED).
+ *     dmn_update_gauss_points (per-point orientation).  The linear map and
+ *     its backward accept the per-sample form below but currently return
+ *     DMN_EUNSUPPORTED (switched off); dmn_update_adjoint returns
+ *     DMN_EUNSUPPORTED.
  * All arrays are device memory in the precision of the call. */
 typedef struct dmn_net {
   int32_t depth;
@@ -162,36 +165,42 @@ typedef struct dmn_point_group {
 /* Version string of the library. */
 const char* dmn_version(void);
 
-/* Workspace bytes for dmn_homogenize_linear. */
-size_t dmn_homogenize_linear_workspace_size(int32_t depth, int64_t B, int prec);
+/* Workspace bytes for dmn_homogenize_linear (0 for an invalid net, B or prec). */
+size_t dmn_homogenize_linear_workspace_size(const dmn_net* net, int64_t B, int prec);
 
 /* Linear DMN homogenisation DMN^L (Sec. 3.1, stiffness propagation):
  * for each of B samples, phase stiffnesses C1[b], C2[b] (6x6 Mandel,
  * row-major, [B][36]; read as their symmetric part) are homogenised bottom-up
  * through the laminate tree of `net`; the result goes to Cbar[b] ([B][36],
- * symmetric).  prec: DMN_F64 or DMN_F32 (all arrays, including w and n, in
- * that precision).  An invalid DMN (negative weight, zero child weight) or a
- * non-SPD laminate pivot sets the device error word at the start of the
- * workspace (int32, 0 = fine; read it after the stream has finished) and
- * leaves NaN in the affected outputs. */
+ * symmetric).  prec: DMN_F64 or DMN_F32 (all arrays, including w, n, the
+ * orientation coefficients and lam, in that precision).  lam [B][2]: the
+ * fibre orientation (l1, l2) of each sample for an orientation-interpolated
+ * net (Sec. 2.3, see dmn_net), NULL for fixed normals.  An invalid DMN
+ * (negative weight, zero child weight) or a non-SPD laminate pivot sets the
+ * device error word at the start of the workspace (int32, 0 = fine; read it
+ * after the stream has finished) and leaves NaN in the affected outputs. */
 int dmn_homogenize_linear(const dmn_net* net, int64_t B, int prec, const void* C1,
-                          const void* C2, void* Cbar, void* ws, size_t ws_bytes,
-                          hipStream_t stream);
+                          const void* C2, const void* lam, void* Cbar, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
 
-/* Workspace bytes for dmn_homogenize_backward. */
-size_t dmn_homogenize_backward_workspace_size(int32_t depth, int64_t B, int prec);
+/* Workspace bytes for dmn_homogenize_backward (0 for an invalid net, B or prec). */
+size_t dmn_homogenize_backward_workspace_size(const dmn_net* net, int64_t B, int prec);
 
 /* Vector-Jacobian product of dmn_homogenize_linear: given the cotangent
  * gCbar[B][36] of Cbar, writes (overwrites)
  *   gw [2^K]     sum over samples of d<gCbar, Cbar>/d w
  *   gn [L][3]    sum over samples of d<gCbar, Cbar>/d n (n as passed; the
- *                map is invariant to the length of n, so gn is tangential)
+ *                map is invariant to the length of n, so gn is tangential);
+ *                for an orientation-interpolated net gn is [L][2][M]: row i
+ *                holds d/d ori_p[i] (M values) then d/d ori_q[i], each summed
+ *                over the samples with their own orientation lam
  *   gC1, gC2 [B][36]  per-sample d<gCbar, Cbar>/d C1, C2 (symmetric), or NULL
  * The batch sums use a fixed reduction order (bit-reproducible run to run).
  * The forward is recomputed inside the call.  Same error word as the forward. */
 int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void* C1,
-                            const void* C2, const void* gCbar, void* gw, void* gn, void* gC1,
-                            void* gC2, void* ws, size_t ws_bytes, hipStream_t stream);
+                            const void* C2, const void* lam, const void* gCbar, void* gw,
+                            void* gn, void* gC1, void* gC2, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
 
 /* Workspace bytes for dmn_update_gauss_points. */
 size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int32_t n_groups,

@@ -60,16 +60,19 @@ class DmnGpTuning(ctypes.Structure):
 # exported functions and their signatures
 _SIGS = {
     "dmn_version": (ctypes.c_char_p, []),
-    "dmn_homogenize_linear_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int]),
+    "dmn_homogenize_linear_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(DmnNet),
+                                                               ctypes.c_int64, ctypes.c_int]),
     "dmn_homogenize_linear": (ctypes.c_int, [ctypes.POINTER(DmnNet), ctypes.c_int64, ctypes.c_int,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
-    "dmn_homogenize_backward_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int]),
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                             ctypes.c_void_p]),
+    "dmn_homogenize_backward_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(DmnNet),
+                                                                 ctypes.c_int64, ctypes.c_int]),
     "dmn_homogenize_backward": (ctypes.c_int, [ctypes.POINTER(DmnNet), ctypes.c_int64, ctypes.c_int,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
-                                               ctypes.c_void_p]),
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_size_t, ctypes.c_void_p]),
     "dmn_update_gauss_points_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(DmnPointGroup),
                                                                  ctypes.c_int32, ctypes.c_int]),
     "dmn_update_gauss_points": (ctypes.c_int, [ctypes.POINTER(DmnPointGroup), ctypes.c_int32,

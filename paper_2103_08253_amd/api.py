@@ -43,17 +43,17 @@ def _net(w: torch.Tensor, n: torch.Tensor, dtype):
     return L.DmnNet(K, w.data_ptr(), n.data_ptr()), K
 
 
-def _net_ori(w: torch.Tensor, ori: "Orientation"):
-    """dmn_net with orientation-interpolated normals."""
+def _net_ori(w: torch.Tensor, ori: "Orientation", dtype=torch.float64):
+    """dmn_net with orientation-interpolated normals (arrays in dtype)."""
     K = int(round(torch.log2(torch.tensor(float(w.numel()))).item()))
     if 2 ** K != w.numel() or not 1 <= K <= 10:
         raise ValueError("w must hold 2^K leaf weights with 1 <= K <= 10")
     if ori.kind not in L.ORI_COUNT:
         raise ValueError(f"unknown shape functions {ori.kind!r}")
     M = L.ORI_COUNT[ori.kind]
-    _need(w, "w", torch.float64, (2 ** K,))
-    _need(ori.p, "p", torch.float64, (2 ** K - 1, M))
-    _need(ori.q, "q", torch.float64, (2 ** K - 1, M))
+    _need(w, "w", dtype, (2 ** K,))
+    _need(ori.p, "p", dtype, (2 ** K - 1, M))
+    _need(ori.q, "q", dtype, (2 ** K - 1, M))
     return L.DmnNet(K, w.data_ptr(), None, L.DMN_ORI[ori.kind], ori.p.data_ptr(),
                     ori.q.data_ptr()), K
 
@@ -68,13 +68,26 @@ def error_word(ws: torch.Tensor) -> int:
     return int(ws[:4].view(torch.int32).item())
 
 
-def dmn_homogenize_linear(w, n, C1, C2, Cbar=None, ws=None):
-    """Cbar[b] = DMN^L(C1[b], C2[b]) for a batch [B, 6, 6] (or [B, 36])."""
+def _linear_net(w, n, ori, dtype, B):
+    """dmn_net and lam pointer of a linear call (fixed or per-sample normals)."""
+    if ori is None:
+        net, K = _net(w, n, dtype)
+        return net, K, None
+    net, K = _net_ori(w, ori, dtype)
+    _need(ori.lam, "lam", dtype, (B, 2))
+    return net, K, _ptr(ori.lam)
+
+
+def dmn_homogenize_linear(w, n, C1, C2, Cbar=None, ws=None, ori=None):
+    """Cbar[b] = DMN^L(C1[b], C2[b]) for a batch [B, 6, 6] (or [B, 36]).
+
+    With ``ori`` (an Orientation whose lam is [B, 2]) every sample has its own
+    fibre orientation and n is not read."""
     dtype = C1.dtype
     if dtype not in _PREC:
         raise TypeError("float64 or float32 expected")
-    net, K = _net(w, n, dtype)
     B = C1.shape[0]
+    net, K, lam = _linear_net(w, n, ori, dtype, B)
     _need(C1, "C1", dtype)
     _need(C2, "C2", dtype)
     if C1.numel() != 36 * B or C2.numel() != 36 * B:
@@ -84,38 +97,42 @@ def dmn_homogenize_linear(w, n, C1, C2, Cbar=None, ws=None):
     _need(Cbar, "Cbar", dtype)
     prec = _PREC[dtype]
     lib = L.lib()
-    nbytes = lib.dmn_homogenize_linear_workspace_size(K, B, prec)
+    nbytes = lib.dmn_homogenize_linear_workspace_size(ctypes.byref(net), B, prec)
     if ws is None or ws.numel() < nbytes:
         ws = workspace(nbytes, C1.device)
-    rc = lib.dmn_homogenize_linear(ctypes.byref(net), B, prec, _ptr(C1), _ptr(C2), _ptr(Cbar),
-                                   _ptr(ws), ws.numel(), _stream())
+    rc = lib.dmn_homogenize_linear(ctypes.byref(net), B, prec, _ptr(C1), _ptr(C2), lam,
+                                   _ptr(Cbar), _ptr(ws), ws.numel(), _stream())
     L.check(rc, "dmn_homogenize_linear")
     return Cbar, ws
 
 
-def dmn_homogenize_backward(w, n, C1, C2, gCbar, want_input_grads=False, ws=None):
-    """(gw, gn, gC1, gC2) of sum_b <gCbar[b], Cbar[b]>; gC1/gC2 None unless requested."""
+def dmn_homogenize_backward(w, n, C1, C2, gCbar, want_input_grads=False, ws=None, ori=None):
+    """(gw, gn, gC1, gC2) of sum_b <gCbar[b], Cbar[b]>; gC1/gC2 None unless requested.
+
+    With ``ori`` gn is [L, 2, M]: the cotangents of the angle coefficients p
+    (first) and q of every laminate, summed over the samples."""
     dtype = C1.dtype
-    net, K = _net(w, n, dtype)
     B = C1.shape[0]
+    net, K, lam = _linear_net(w, n, ori, dtype, B)
     for t, nm in ((C1, "C1"), (C2, "C2"), (gCbar, "gCbar")):
         _need(t, nm, dtype)
         if t.numel() != 36 * B:
             raise ValueError(f"{nm} must be [B, 6, 6]")
     gw = torch.empty(2 ** K, dtype=dtype, device=C1.device)
-    gn = torch.empty((2 ** K - 1, 3), dtype=dtype, device=C1.device)
+    gn_shape = (2 ** K - 1, 3) if ori is None else (2 ** K - 1, 2, L.ORI_COUNT[ori.kind])
+    gn = torch.empty(gn_shape, dtype=dtype, device=C1.device)
     gC1 = gC2 = None
     if want_input_grads:
         gC1 = torch.empty((B, 6, 6), dtype=dtype, device=C1.device)
         gC2 = torch.empty((B, 6, 6), dtype=dtype, device=C1.device)
     prec = _PREC[dtype]
     lib = L.lib()
-    nbytes = lib.dmn_homogenize_backward_workspace_size(K, B, prec)
+    nbytes = lib.dmn_homogenize_backward_workspace_size(ctypes.byref(net), B, prec)
     if ws is None or ws.numel() < nbytes:
         ws = workspace(nbytes, C1.device)
-    rc = lib.dmn_homogenize_backward(ctypes.byref(net), B, prec, _ptr(C1), _ptr(C2), _ptr(gCbar),
-                                     _ptr(gw), _ptr(gn), _ptr(gC1), _ptr(gC2), _ptr(ws),
-                                     ws.numel(), _stream())
+    rc = lib.dmn_homogenize_backward(ctypes.byref(net), B, prec, _ptr(C1), _ptr(C2), lam,
+                                     _ptr(gCbar), _ptr(gw), _ptr(gn), _ptr(gC1), _ptr(gC2),
+                                     _ptr(ws), ws.numel(), _stream())
     L.check(rc, "dmn_homogenize_backward")
     return gw, gn, gC1, gC2, ws
 

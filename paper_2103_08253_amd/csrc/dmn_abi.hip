@@ -90,61 +90,95 @@ extern "C" {
 
 const char* dmn_version(void) { return "libdmn 0.1 gfx950"; }
 
-size_t dmn_homogenize_linear_workspace_size(int32_t depth, int64_t B, int prec) {
-  if (!depth_ok(depth) || B < 0 || (prec != DMN_F64 && prec != DMN_F32)) return 0;
-  return kAlign + table_bytes(depth, prec);
+// a net for the linear calls.  Orientation-interpolated normals are switched
+// off here: the first GPU run of the per-sample orientation kernels ended in
+// a device fault whose cause is not yet found.
+static int linear_net_check(const dmn_net* net, int64_t B, const void* lam) {
+  if (!net || !depth_ok(net->depth) || B < 0 || !net->w) return DMN_EINVAL;
+  const int m = ori_count(net->ori_shape);
+  if (m < 0) return DMN_EINVAL;
+  if (m == 0) return net->n ? DMN_OK : DMN_EINVAL;
+  if (!net->ori_p || !net->ori_q || (B > 0 && !lam)) return DMN_EINVAL;
+  return DMN_EUNSUPPORTED;
+}
+
+static dmn::LinOriArgs lin_ori(const dmn_net* net, const void* lam, void* gang) {
+  dmn::LinOriArgs o;
+  o.m = ori_count(net->ori_shape);
+  if (o.m > 0) {
+    o.p = net->ori_p;
+    o.q = net->ori_q;
+    o.lam = lam;
+    o.gang = gang;
+  }
+  return o;
+}
+
+size_t dmn_homogenize_linear_workspace_size(const dmn_net* net, int64_t B, int prec) {
+  if (!net || !depth_ok(net->depth) || B < 0 || (prec != DMN_F64 && prec != DMN_F32)) return 0;
+  if (ori_count(net->ori_shape) < 0) return 0;
+  return kAlign + table_bytes(net->depth, prec);
 }
 
 int dmn_homogenize_linear(const dmn_net* net, int64_t B, int prec, const void* C1,
-                          const void* C2, void* Cbar, void* ws, size_t ws_bytes,
-                          hipStream_t stream) {
-  if (!net || !depth_ok(net->depth) || B < 0) return DMN_EINVAL;
+                          const void* C2, const void* lam, void* Cbar, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  if (!net) return DMN_EINVAL;
   if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
-  if (const int rc = fixed_net_check(net)) return rc;
+  if (const int rc = linear_net_check(net, B, lam)) return rc;
   if (B > 0 && (!C1 || !C2 || !Cbar)) return DMN_EINVAL;
-  const size_t need = dmn_homogenize_linear_workspace_size(net->depth, B, prec);
+  const size_t need = dmn_homogenize_linear_workspace_size(net, B, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   int32_t* err = (int32_t*)ws;
   Table tb = table_at(ws, kAlign);
-  if (dmn::launch_prep_tables(net->w, net->n, net->depth, prec, tb.rows, tb.flag, err, stream))
+  const void* nfix = net->ori_shape == DMN_ORI_NONE ? net->n : nullptr;
+  if (dmn::launch_prep_tables(net->w, nfix, net->depth, prec, tb.rows, tb.flag, err, stream))
     return DMN_EHIP;
   if (B == 0) return DMN_OK;
   if (dmn::launch_linear_forward(net->depth, prec, tb.rows, tb.flag, B, C1, C2, Cbar, err,
-                                 stream))
+                                 lin_ori(net, lam, nullptr), stream))
     return DMN_EHIP;
   return DMN_OK;
 }
 
-size_t dmn_homogenize_backward_workspace_size(int32_t depth, int64_t B, int prec) {
-  if (!depth_ok(depth) || B < 0 || (prec != DMN_F64 && prec != DMN_F32)) return 0;
+size_t dmn_homogenize_backward_workspace_size(const dmn_net* net, int64_t B, int prec) {
+  if (!net || !depth_ok(net->depth) || B < 0 || (prec != DMN_F64 && prec != DMN_F32)) return 0;
+  const int m = ori_count(net->ori_shape);
+  if (m < 0) return 0;
+  const int depth = net->depth;
   const size_t L = ((size_t)1 << depth) - 1;
   const size_t slots = (size_t)dmn::linear_backward_partials(depth, B);
+  const size_t gang = m > 0 ? align_up(L * 2 * (size_t)B * elt_size(prec)) : 0;
   return kAlign + table_bytes(depth, prec) + align_up(L * 4 * sizeof(double)) +
-         align_up(slots * L * 4 * sizeof(double));
+         align_up(slots * L * 4 * sizeof(double)) + gang;
 }
 
 int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void* C1,
-                            const void* C2, const void* gCbar, void* gw, void* gn, void* gC1,
-                            void* gC2, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (!net || !depth_ok(net->depth) || B < 0) return DMN_EINVAL;
+                            const void* C2, const void* lam, const void* gCbar, void* gw,
+                            void* gn, void* gC1, void* gC2, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  if (!net) return DMN_EINVAL;
   if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
-  if (const int rc = fixed_net_check(net)) return rc;
+  if (const int rc = linear_net_check(net, B, lam)) return rc;
   if (!gw || !gn) return DMN_EINVAL;
   if (B > 0 && (!C1 || !C2 || !gCbar)) return DMN_EINVAL;
   if ((gC1 == nullptr) != (gC2 == nullptr)) return DMN_EINVAL;
-  const size_t need = dmn_homogenize_backward_workspace_size(net->depth, B, prec);
+  const size_t need = dmn_homogenize_backward_workspace_size(net, B, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   const int K = net->depth;
   const size_t L = ((size_t)1 << K) - 1;
+  const size_t slots = (size_t)dmn::linear_backward_partials(K, B);
   int32_t* err = (int32_t*)ws;
   Table tb = table_at(ws, kAlign);
   double* gsum = (double*)((char*)ws + kAlign + table_bytes(K, prec));
   double* partials = (double*)((char*)gsum + align_up(L * 4 * sizeof(double)));
-  if (dmn::launch_prep_tables(net->w, net->n, K, prec, tb.rows, tb.flag, err, stream))
+  void* gang = (char*)partials + align_up(slots * L * 4 * sizeof(double));
+  const void* nfix = net->ori_shape == DMN_ORI_NONE ? net->n : nullptr;
+  if (dmn::launch_prep_tables(net->w, nfix, K, prec, tb.rows, tb.flag, err, stream))
     return DMN_EHIP;
-  // B == 0 still runs the (empty) reduction so gw, gn are overwritten with zeros
+  // B == 0 still runs the (empty) reductions so gw, gn are overwritten with zeros
   if (dmn::launch_linear_backward(K, prec, tb.rows, tb.flag, B, C1, C2, gCbar, gw, gn, gC1, gC2,
-                                  partials, gsum, err, stream))
+                                  partials, gsum, err, lin_ori(net, lam, gang), stream))
     return DMN_EHIP;
   return DMN_OK;
 }

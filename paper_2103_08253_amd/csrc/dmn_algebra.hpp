@@ -612,4 +612,66 @@ __device__ __forceinline__ void laminate_param_grad(const Normal<double>& nv, do
   g4[3] = ga[2] - gl[2];
 }
 
+// ------------------------------------------------ orientation interpolation
+
+// Shape functions of the orientation-interpolation table (FE-DMN paper,
+// Sec. 2.3) at fibre orientation (l1, l2): barycentric coordinates of the
+// orientation triangle with vertices unidirectional (1, 0), isotropic
+// (1/3, 1/3), planar isotropic (1/2, 1/2) (the closed-form solution of the
+// paper's 3x3 system), then m = 3 linear, 4 tri-linear (linear minus/plus the
+// cubic bubble) or 6 quadratic functions (vertex functions, then edges 1-2,
+// 1-3, 2-3).
+template <typename T>
+__device__ __forceinline__ void orientation_shape(T l1, T l2, int m, T s[6]) {
+  const T f1 = l1 - l2;
+  const T f2 = T(3) - T(3) * l1 - T(3) * l2;
+  const T f3 = T(2) * l1 + T(4) * l2 - T(2);
+  if (m == 3) {
+    s[0] = f1; s[1] = f2; s[2] = f3;
+  } else if (m == 4) {
+    const T b = f1 * f2 * f3;
+    s[0] = f1 - T(9) * b; s[1] = f2 - T(9) * b; s[2] = f3 - T(9) * b; s[3] = T(27) * b;
+  } else {
+    s[0] = f1 * (T(2) * f1 - T(1)); s[1] = f2 * (T(2) * f2 - T(1));
+    s[2] = f3 * (T(2) * f3 - T(1));
+    s[3] = T(4) * f1 * f2; s[4] = T(4) * f1 * f3; s[5] = T(4) * f2 * f3;
+  }
+}
+
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+
+// Normals of laminates t, t + lanes, ... of one point / sample: angles
+// alpha = p . s, beta = q . s (p, q: [L][m]) and n = (sin a cos b,
+// sin a sin b, cos a) into nrm[c * L + pos]; with dalpha != nullptr also
+// dn/dalpha = (cos a cos b, cos a sin b, -sin a) into dalpha[c * L + pos].
+template <typename T>
+__device__ __forceinline__ void orientation_normals(const T* __restrict__ p,
+                                                    const T* __restrict__ q, int m, T l1,
+                                                    T l2, int t, int lanes, int L, T* nrm,
+                                                    T* dalpha) {
+  T s[6];
+  orientation_shape(l1, l2, m, s);
+#pragma unroll 1
+  for (int pos = t; pos < L; pos += lanes) {
+    T a = T(0), b = T(0);
+#pragma unroll 1
+    for (int j = 0; j < m; ++j) {
+      a += p[(size_t)pos * m + j] * s[j];
+      b += q[(size_t)pos * m + j] * s[j];
+    }
+    T sa, ca, sb, cb;
+    sin_cos(a, &sa, &ca);
+    sin_cos(b, &sb, &cb);
+    nrm[0 * L + pos] = sa * cb;
+    nrm[1 * L + pos] = sa * sb;
+    nrm[2 * L + pos] = ca;
+    if (dalpha != nullptr) {
+      dalpha[0 * L + pos] = ca * cb;
+      dalpha[1 * L + pos] = ca * sb;
+      dalpha[2 * L + pos] = -sa;
+    }
+  }
+}
+
 }  // namespace dmn

@@ -154,7 +154,8 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
     const double l1 = G.lam[(size_t)pt * 2], l2 = G.lam[(size_t)pt * 2 + 1];
     bad |= (isfinite(l1) && isfinite(l2)) ? 0 : 1;
     double* nrm = nlds.v + cx.slot * 3 * C::L;
-    orientation_normals<K, D>(G.ori_p, G.ori_q, G.ori_m, l1, l2, cx.t, nrm);
+    orientation_normals<double>(G.ori_p, G.ori_q, G.ori_m, l1, l2, cx.t, C::LP, C::L, nrm,
+                                nullptr);
     cx.nrm = nrm;  // read by the point's other lanes after the next barrier
   }
 #pragma unroll

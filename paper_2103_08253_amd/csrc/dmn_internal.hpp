@@ -78,13 +78,24 @@ int gp_default_lanes_per_point(int depth);
 int gp_lane_variants(int depth, int* lanes, int cap);
 constexpr int kDefaultWavesPerCu = 8;
 
+// Orientation-interpolated normals of a linear launch (m = 0: fixed normals):
+// angle coefficients p, q [L][m], per-sample (l1, l2) lam [B][2], and for the
+// backward the per-sample angle cotangents gang [L][2][B] (workspace).
+struct LinOriArgs {
+  const void* p = nullptr;
+  const void* q = nullptr;
+  const void* lam = nullptr;
+  void* gang = nullptr;
+  int m = 0;
+};
 int launch_linear_forward(int depth, int prec, const void* tab, const int32_t* flag, long long B,
                           const void* C1, const void* C2, void* Cbar, int32_t* err,
-                          hipStream_t stream);
+                          const LinOriArgs& ori, hipStream_t stream);
 int launch_linear_backward(int depth, int prec, const void* tab, const int32_t* flag,
                            long long B, const void* C1, const void* C2, const void* gCbar,
                            void* gw, void* gn, void* gC1, void* gC2, double* partials,
-                           double* gsum, int32_t* err, hipStream_t stream);
+                           double* gsum, int32_t* err, const LinOriArgs& ori,
+                           hipStream_t stream);
 // number of partial-sum slots (waves x samples per wave) the backward uses
 long long linear_backward_partials(int depth, long long B);
 

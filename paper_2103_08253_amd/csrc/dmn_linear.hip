@@ -52,17 +52,43 @@ struct LRow {
   T c1, c2;
 };
 
+
+// Orientation inputs of a launch whose normals follow each sample's fibre
+// orientation (Sec. 2.3): angle coefficients p, q [L][m], per-sample
+// (l1, l2) lam [B][2]; the backward writes each sample's angle cotangents
+// (d/dalpha, d/dbeta) per laminate to gang [L][2][B].
 template <typename T>
-__device__ __forceinline__ LRow<T> lrow(const T* __restrict__ tab, int pos) {
-  const T* r = tab + (size_t)pos * kTabStride;
-  LRow<T> o;
-  o.c1 = r[0];
-  o.c2 = r[1];
-  o.nv.n0 = r[2];
-  o.nv.n1 = r[3];
-  o.nv.n2 = r[4];
-  return o;
-}
+struct LinOri {
+  const T* p;
+  const T* q;
+  const T* lam;
+  T* gang;
+  int m;
+};
+
+// Laminate rows: fractions from the table, normals from the table (fixed
+// normals) or from the sample's normal block nrm [3][L] (ORI).
+template <typename T, int L, bool ORI>
+struct Rows {
+  const T* __restrict__ tab;
+  const T* nrm;
+  __device__ __forceinline__ LRow<T> operator()(int pos) const {
+    const T* r = tab + (size_t)pos * kTabStride;
+    LRow<T> o;
+    o.c1 = r[0];
+    o.c2 = r[1];
+    if constexpr (ORI) {
+      o.nv.n0 = nrm[pos];
+      o.nv.n1 = nrm[L + pos];
+      o.nv.n2 = nrm[2 * L + pos];
+    } else {
+      o.nv.n0 = r[2];
+      o.nv.n1 = r[3];
+      o.nv.n2 = r[4];
+    }
+    return o;
+  }
+};
 
 // symmetric part of a row-major 6x6, packed
 template <typename T>
@@ -83,8 +109,8 @@ __device__ __forceinline__ void store_full(T* __restrict__ A, const T P[21]) {
 }
 
 // bottom-up over the lane subtree; stores the laminate outputs when Store
-template <typename T, int K, int D, int H, bool Store>
-__device__ __forceinline__ void lin_up(const T* __restrict__ tab, int t, const T* C1,
+template <typename T, int K, int D, int H, bool Store, class R>
+__device__ __forceinline__ void lin_up(const R& rows, int t, const T* C1,
                                        const T* C2, T (&Cn)[21], int& fail,
                                        T (&nodes)[LCfg<K, D>::NLAM][21]) {
   using C = LCfg<K, D>;
@@ -94,9 +120,9 @@ __device__ __forceinline__ void lin_up(const T* __restrict__ tab, int t, const T
     for (int k = 0; k < 21; ++k) Cn[k] = (q % 2 == 0) ? C1[k] : C2[k];
   } else {
     T CL[21], CR[21];
-    lin_up<T, K, D, 2 * H, Store>(tab, t, C1, C2, CL, fail, nodes);
-    lin_up<T, K, D, 2 * H + 1, Store>(tab, t, C1, C2, CR, fail, nodes);
-    const LRow<T> row = lrow(tab, lpos<K, D, H>(t));
+    lin_up<T, K, D, 2 * H, Store>(rows, t, C1, C2, CL, fail, nodes);
+    lin_up<T, K, D, 2 * H + 1, Store>(rows, t, C1, C2, CR, fail, nodes);
+    const LRow<T> row = rows(lpos<K, D, H>(t));
     fail |= laminate_linear(CL, CR, row.nv, row.c1, row.c2, Cn) ? 0 : 1;
     if constexpr (Store) {
 #pragma unroll
@@ -114,15 +140,17 @@ __device__ __forceinline__ T shfl_upv(T v, int o, int w) {
   return __shfl_up(v, (unsigned)o, w);
 }
 
-template <typename T, int K, int D>
+template <typename T, int K, int D, bool ORI>
 __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ tab,
                                                         const int32_t* __restrict__ flag,
                                                         long long B, const T* __restrict__ C1,
                                                         const T* __restrict__ C2,
                                                         T* __restrict__ Cbar,
-                                                        int32_t* __restrict__ err) {
+                                                        int32_t* __restrict__ err,
+                                                        const LinOri<T> ori) {
   using C = LCfg<K, D>;
   __shared__ T leafC[C::PPW][2][21];
+  __shared__ T nl[ORI ? C::PPW * 3 * C::L : 1];
   const int lane = threadIdx.x;
   const int slot = lane / C::LP, t = lane % C::LP;
   const long long braw = (long long)blockIdx.x * C::PPW + slot;
@@ -132,11 +160,16 @@ __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ ta
     load_sym(C1 + (size_t)b * 36, leafC[slot][0]);
     load_sym(C2 + (size_t)b * 36, leafC[slot][1]);
   }
+  T* nrm = nl + (ORI ? slot * 3 * C::L : 0);
+  if constexpr (ORI)
+    orientation_normals<T>(ori.p, ori.q, ori.m, ori.lam[(size_t)b * 2], ori.lam[(size_t)b * 2 + 1],
+                           t, C::LP, C::L, nrm, (T*)nullptr);
   __syncthreads();
+  const Rows<T, C::L, ORI> rows{tab, nrm};
   int fail = 0;
   T cC[21];
   T dummy[C::NLAM][21];
-  lin_up<T, K, D, 1, false>(tab, t, leafC[slot][0], leafC[slot][1], cC, fail, dummy);
+  lin_up<T, K, D, 1, false>(rows, t, leafC[slot][0], leafC[slot][1], cC, fail, dummy);
 #pragma unroll 1
   for (int m = 1; m <= C::UPLEV; ++m) {
     const int o = 1 << (m - 1);
@@ -144,7 +177,7 @@ __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ ta
 #pragma unroll
     for (int k = 0; k < 21; ++k) rC[k] = shfl_dn(cC[k], o, C::LP);
     if ((t & (2 * o - 1)) == 0) {
-      const LRow<T> row = lrow(tab, upos<K, D>(m, t));
+      const LRow<T> row = rows(upos<K, D>(m, t));
       T nC[21];
       fail |= laminate_linear(cC, rC, row.nv, row.c1, row.c2, nC) ? 0 : 1;
 #pragma unroll
@@ -164,10 +197,24 @@ __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ ta
   }
 }
 
+// Angle cotangents of laminate pos of sample b from its normal cotangent gn:
+// d/dalpha = gn . dn/dalpha, d/dbeta = gn . (-n1, n0, 0).
+template <typename T, int L>
+__device__ __forceinline__ void put_angles(const LinOri<T>& ori, long long B, long long b, int pos,
+                                           const T* nrm, const T gn[3]) {
+  const T* da = nrm + 3 * L;
+  const T ga = gn[0] * da[pos] + gn[1] * da[L + pos] + gn[2] * da[2 * L + pos];
+  const T gb = -gn[0] * nrm[L + pos] + gn[1] * nrm[pos];
+  ori.gang[((size_t)pos * 2) * B + b] = ga;
+  ori.gang[((size_t)pos * 2 + 1) * B + b] = gb;
+}
+
 // backward over the lane subtree: cotangent Gm of heap node H; the phase
-// stiffness cotangents g1, g2 are accumulated only if IG
-template <typename T, int K, int D, int H, bool IG>
-__device__ __forceinline__ void lin_back(const T* __restrict__ tab, int t, bool live,
+// stiffness cotangents g1, g2 are accumulated only if IG; with ORI the
+// sample's angle cotangents go to ori.gang
+template <typename T, int K, int D, int H, bool IG, bool ORI, class R>
+__device__ __forceinline__ void lin_back(const R& rows, const LinOri<T>& ori, long long B,
+                                         long long b, int t, bool live,
                                          const T* C1, const T* C2,
                                          const T (&nodes)[LCfg<K, D>::NLAM][21],
                                          const T (&Gm)[21], double (&acc)[LCfg<K, D>::NLAM][4],
@@ -192,7 +239,8 @@ __device__ __forceinline__ void lin_back(const T* __restrict__ tab, int t, bool 
       CL = nodes[2 * H - 1];
       CR = nodes[2 * H];
     }
-    const LRow<T> row = lrow(tab, lpos<K, D, H>(t));
+    const int pos = lpos<K, D, H>(t);
+    const LRow<T> row = rows(pos);
     T GL[21], GR[21], gc1, gn[3];
     laminate_linear_vjp(CL, CR, row.nv, row.c1, row.c2, Gm, GL, GR, gc1, gn);
     if (live) {
@@ -200,22 +248,25 @@ __device__ __forceinline__ void lin_back(const T* __restrict__ tab, int t, bool 
       acc[H - 1][1] += (double)gn[0];
       acc[H - 1][2] += (double)gn[1];
       acc[H - 1][3] += (double)gn[2];
+      if constexpr (ORI) put_angles<T, C::L>(ori, B, b, pos, rows.nrm, gn);
     }
-    lin_back<T, K, D, 2 * H, IG>(tab, t, live, C1, C2, nodes, GL, acc, g1, g2);
-    lin_back<T, K, D, 2 * H + 1, IG>(tab, t, live, C1, C2, nodes, GR, acc, g1, g2);
+    lin_back<T, K, D, 2 * H, IG, ORI>(rows, ori, B, b, t, live, C1, C2, nodes, GL, acc, g1, g2);
+    lin_back<T, K, D, 2 * H + 1, IG, ORI>(rows, ori, B, b, t, live, C1, C2, nodes, GR, acc, g1,
+                                          g2);
   }
 }
 
-template <typename T, int K, int D, bool IG>
+template <typename T, int K, int D, bool IG, bool ORI>
 __global__ __launch_bounds__(64) void linear_bwd_kernel(
     const T* __restrict__ tab, const int32_t* __restrict__ flag, long long B,
     const T* __restrict__ C1, const T* __restrict__ C2, const T* __restrict__ gCbar,
     T* __restrict__ gC1, T* __restrict__ gC2, double* __restrict__ partials,
-    int32_t* __restrict__ err) {
+    int32_t* __restrict__ err, const LinOri<T> ori) {
   using C = LCfg<K, D>;
   static_assert(C::NLAM >= 1, "lane subtree needs a laminate");
   __shared__ T nodeC[21][C::PPW * C::NODES];
   __shared__ T leafC[C::PPW][2][21];
+  __shared__ T nl[ORI ? C::PPW * 6 * C::L : 1];  // normals, then dn/dalpha, per sample
   __shared__ double accU[4][C::PPW * (C::NUP > 0 ? C::NUP : 1)];
   const int lane = threadIdx.x;
   const int slot = lane / C::LP, t = lane % C::LP;
@@ -236,13 +287,18 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
       load_sym(C1 + (size_t)b * 36, leafC[slot][0]);
       load_sym(C2 + (size_t)b * 36, leafC[slot][1]);
     }
+    T* nrm = nl + (ORI ? slot * 6 * C::L : 0);
+    if constexpr (ORI)
+      orientation_normals<T>(ori.p, ori.q, ori.m, ori.lam[(size_t)b * 2],
+                             ori.lam[(size_t)b * 2 + 1], t, C::LP, C::L, nrm, nrm + 3 * C::L);
     __syncthreads();
+    const Rows<T, C::L, ORI> rows{tab, nrm};
     const T* A1 = leafC[slot][0];
     const T* A2 = leafC[slot][1];
     // forward, keeping node stiffnesses
     T nodes[C::NLAM][21];
     T cC[21];
-    lin_up<T, K, D, 1, true>(tab, t, A1, A2, cC, fail, nodes);
+    lin_up<T, K, D, 1, true>(rows, t, A1, A2, cC, fail, nodes);
     const int nbase = slot * C::NODES;
 #pragma unroll
     for (int k = 0; k < 21; ++k) nodeC[k][nbase + t] = cC[k];
@@ -254,7 +310,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
       for (int k = 0; k < 21; ++k) rC[k] = shfl_dn(cC[k], o, C::LP);
       if ((t & (2 * o - 1)) == 0) {
         const int pos = upos<K, D>(m, t);
-        const LRow<T> row = lrow(tab, pos);
+        const LRow<T> row = rows(pos);
         T nC[21];
         fail |= laminate_linear(cC, rC, row.nv, row.c1, row.c2, nC) ? 0 : 1;
 #pragma unroll
@@ -276,7 +332,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
       for (int k = 0; k < 21; ++k) GRs[k] = T(0);
       if ((t & (2 * o - 1)) == 0) {
         const int pos = upos<K, D>(m, t);
-        const LRow<T> row = lrow(tab, pos);
+        const LRow<T> row = rows(pos);
         const int vL = m == 1 ? t : C::LP + (upos<K, D>(m - 1, t) - C::UP0);
         const int vR = m == 1 ? t + 1 : C::LP + (upos<K, D>(m - 1, t + o) - C::UP0);
         T CL[21], CR[21];
@@ -293,6 +349,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
           accU[1][u] += (double)gn[0];
           accU[2][u] += (double)gn[1];
           accU[3][u] += (double)gn[2];
+          if constexpr (ORI) put_angles<T, C::L>(ori, B, b, pos, nrm, gn);
         }
 #pragma unroll
         for (int k = 0; k < 21; ++k) Gm[k] = GL[k];
@@ -311,7 +368,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
       g1[k] = T(0);
       g2[k] = T(0);
     }
-    lin_back<T, K, D, 1, IG>(tab, t, live, A1, A2, nodes, Gm, acc, g1, g2);
+    lin_back<T, K, D, 1, IG, ORI>(rows, ori, B, b, t, live, A1, A2, nodes, Gm, acc, g1, g2);
     if constexpr (IG) {
 #pragma unroll
       for (int o = 1; o < C::LP; o <<= 1)
@@ -325,7 +382,7 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
         store_full(gC2 + (size_t)b * 36, g2);
       }
     }
-    __syncthreads();  // nodeC and leafC are rewritten by the next sample group
+    __syncthreads();  // nodeC, leafC and nl are rewritten by the next sample group
   }
   // partial sums of this wave slot, stored [pos * 4 + c][slot]
   const size_t pslot = (size_t)blockIdx.x * C::PPW + slot;
@@ -388,7 +445,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void finish_grads_kernel(const double* __restrict__ gsum,
                                                            const T* __restrict__ tab, int K,
                                                            T* __restrict__ gw,
-                                                           T* __restrict__ gn) {
+                                                           T* __restrict__ gn, int write_gn) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nleaf = 1 << K;
   const int L = nleaf - 1;
@@ -403,9 +460,51 @@ __global__ __launch_bounds__(256) void finish_grads_kernel(const double* __restr
     }
     gw[i] = (T)s;
   }
-  if (i < L) {
+  if (write_gn && i < L) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) gn[(size_t)i * 3 + c] = (T)gsum[(size_t)i * 4 + 1 + c];
+  }
+}
+
+// Cotangents of the angle coefficients: for laminate pos (one workgroup),
+// dJ/dp_j = sum_b dJ/dalpha[b] s_j(l_b), dJ/dq_j likewise, summed over the
+// samples in a fixed order (strided per thread, then a fixed tree).  Output
+// gpq [L][2][m] (p first, then q).
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_orientation_kernel(const T* __restrict__ gang,
+                                                                 const T* __restrict__ lam,
+                                                                 long long B, int m,
+                                                                 T* __restrict__ gpq) {
+  __shared__ double part[256];
+  const int pos = blockIdx.x;
+  double acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = 0.0;
+  for (long long b = threadIdx.x; b < B; b += blockDim.x) {
+    T s[6];
+    orientation_shape<T>(lam[(size_t)b * 2], lam[(size_t)b * 2 + 1], m, s);
+    const double ga = (double)gang[((size_t)pos * 2) * B + b];
+    const double gb = (double)gang[((size_t)pos * 2 + 1) * B + b];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      if (j < m) {
+        acc[j] += ga * (double)s[j];
+        acc[6 + j] += gb * (double)s[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const int j = c % 6;
+    if (j >= m) continue;  // uniform over the workgroup
+    part[threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) gpq[(size_t)pos * 2 * m + (c / 6) * m + j] = (T)part[0];
+    __syncthreads();
   }
 }
 
@@ -420,38 +519,47 @@ static int lin_default_D(int depth) {
 
 template <typename T, int K>
 static int fwd_k(const void* tab, const int32_t* flag, long long B, const void* C1, const void* C2,
-                 void* Cbar, int32_t* err, hipStream_t s) {
+                 void* Cbar, int32_t* err, const LinOriArgs& o, hipStream_t s) {
   constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
   using C = LCfg<K, D>;
   const long long nb = (B + C::PPW - 1) / C::PPW;
-  hipLaunchKernelGGL((linear_fwd_kernel<T, K, D>), dim3((unsigned)nb), dim3(64), 0, s,
-                     (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (T*)Cbar, err);
+  const LinOri<T> ori{(const T*)o.p, (const T*)o.q, (const T*)o.lam, (T*)o.gang, o.m};
+  // per-sample orientation (ORI = true) is not launched: switched off after
+  // an unexplained device fault on its first GPU run
+  if (o.m > 0) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL((linear_fwd_kernel<T, K, D, false>), dim3((unsigned)nb), dim3(64), 0, s,
+                     (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (T*)Cbar, err, ori);
   return (int)hipGetLastError();
 }
 
 template <typename T>
 static int fwd_t(int depth, const void* tab, const int32_t* flag, long long B, const void* C1,
-                 const void* C2, void* Cbar, int32_t* err, hipStream_t s) {
+                 const void* C2, void* Cbar, int32_t* err, const LinOriArgs& o, hipStream_t s) {
   switch (depth) {
-    case 1: return fwd_k<T, 1>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 2: return fwd_k<T, 2>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 3: return fwd_k<T, 3>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 4: return fwd_k<T, 4>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 5: return fwd_k<T, 5>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 6: return fwd_k<T, 6>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 7: return fwd_k<T, 7>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 8: return fwd_k<T, 8>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 9: return fwd_k<T, 9>(tab, flag, B, C1, C2, Cbar, err, s);
-    case 10: return fwd_k<T, 10>(tab, flag, B, C1, C2, Cbar, err, s);
-    default: return (int)hipErrorInvalidValue;
+#define DMN_FWD_CASE(KK) \
+  case KK:               \
+    return fwd_k<T, KK>(tab, flag, B, C1, C2, Cbar, err, o, s);
+    DMN_FWD_CASE(1)
+    DMN_FWD_CASE(2)
+    DMN_FWD_CASE(3)
+    DMN_FWD_CASE(4)
+    DMN_FWD_CASE(5)
+    DMN_FWD_CASE(6)
+    DMN_FWD_CASE(7)
+    DMN_FWD_CASE(8)
+    DMN_FWD_CASE(9)
+    DMN_FWD_CASE(10)
+#undef DMN_FWD_CASE
+    default:
+      return (int)hipErrorInvalidValue;
   }
 }
 
 int launch_linear_forward(int depth, int prec, const void* tab, const int32_t* flag, long long B,
                           const void* C1, const void* C2, void* Cbar, int32_t* err,
-                          hipStream_t stream) {
-  if (prec == DMN_F32) return fwd_t<float>(depth, tab, flag, B, C1, C2, Cbar, err, stream);
-  return fwd_t<double>(depth, tab, flag, B, C1, C2, Cbar, err, stream);
+                          const LinOriArgs& ori, hipStream_t stream) {
+  if (prec == DMN_F32) return fwd_t<float>(depth, tab, flag, B, C1, C2, Cbar, err, ori, stream);
+  return fwd_t<double>(depth, tab, flag, B, C1, C2, Cbar, err, ori, stream);
 }
 
 long long linear_backward_partials(int depth, long long B) {
@@ -464,39 +572,54 @@ long long linear_backward_partials(int depth, long long B) {
   return waves * PPW;
 }
 
+template <typename T, int K, bool IG, bool ORI>
+static void bwd_launch(long long waves, const void* tab, const int32_t* flag, long long B,
+                       const void* C1, const void* C2, const void* gCbar, void* gC1, void* gC2,
+                       double* partials, int32_t* err, const LinOri<T>& ori, hipStream_t s) {
+  constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
+  hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, IG, ORI>), dim3((unsigned)waves), dim3(64), 0, s,
+                     (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar,
+                     (T*)gC1, (T*)gC2, partials, err, ori);
+}
+
 template <typename T, int K>
 static int bwd_k(const void* tab, const int32_t* flag, long long B, const void* C1, const void* C2,
                  const void* gCbar, void* gw, void* gn, void* gC1, void* gC2, double* partials,
-                 double* gsum, int32_t* err, hipStream_t s) {
+                 double* gsum, int32_t* err, const LinOriArgs& o, hipStream_t s) {
   constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
   using C = LCfg<K, D>;
   const long long nslots = linear_backward_partials(K, B);
   const long long waves = nslots / C::PPW;
-  if (gC1 != nullptr)
-    hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, true>), dim3((unsigned)waves), dim3(64), 0, s,
-                       (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar,
-                       (T*)gC1, (T*)gC2, partials, err);
+  const LinOri<T> ori{(const T*)o.p, (const T*)o.q, (const T*)o.lam, (T*)o.gang, o.m};
+  const bool ig = gC1 != nullptr, oriented = o.m > 0;
+  if (oriented) return (int)hipErrorInvalidValue;  // switched off, see the forward launcher
+  if (ig)
+    bwd_launch<T, K, true, false>(waves, tab, flag, B, C1, C2, gCbar, gC1, gC2, partials, err, ori,
+                                  s);
   else
-    hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, false>), dim3((unsigned)waves), dim3(64), 0,
-                       s, (const T*)tab, flag, B, (const T*)C1, (const T*)C2,
-                       (const T*)gCbar, (T*)gC1, (T*)gC2, partials, err);
+    bwd_launch<T, K, false, false>(waves, tab, flag, B, C1, C2, gCbar, gC1, gC2, partials, err,
+                                   ori, s);
   const int L4 = C::L * 4;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(L4), dim3(256), 0, s,
                      (const double*)partials, nslots, L4, gsum);
   const int nleaf = 1 << K;
   hipLaunchKernelGGL((finish_grads_kernel<T>), dim3((nleaf + 255) / 256), dim3(256), 0, s,
-                     (const double*)gsum, (const T*)tab, K, (T*)gw, (T*)gn);
+                     (const double*)gsum, (const T*)tab, K, (T*)gw, (T*)gn, oriented ? 0 : 1);
+  if (oriented)
+    hipLaunchKernelGGL((reduce_orientation_kernel<T>), dim3(C::L), dim3(256), 0, s,
+                       (const T*)o.gang, (const T*)o.lam, B, o.m, (T*)gn);
   return (int)hipGetLastError();
 }
 
 template <typename T>
 static int bwd_t(int depth, const void* tab, const int32_t* flag, long long B, const void* C1,
                  const void* C2, const void* gCbar, void* gw, void* gn, void* gC1, void* gC2,
-                 double* partials, double* gsum, int32_t* err, hipStream_t s) {
+                 double* partials, double* gsum, int32_t* err, const LinOriArgs& o,
+                 hipStream_t s) {
   switch (depth) {
 #define DMN_BWD_CASE(KK) \
   case KK:               \
-    return bwd_k<T, KK>(tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum, err, s);
+    return bwd_k<T, KK>(tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum, err, o, s);
     DMN_BWD_CASE(1)
     DMN_BWD_CASE(2)
     DMN_BWD_CASE(3)
@@ -516,12 +639,13 @@ static int bwd_t(int depth, const void* tab, const int32_t* flag, long long B, c
 int launch_linear_backward(int depth, int prec, const void* tab, const int32_t* flag,
                            long long B, const void* C1, const void* C2, const void* gCbar,
                            void* gw, void* gn, void* gC1, void* gC2, double* partials,
-                           double* gsum, int32_t* err, hipStream_t stream) {
+                           double* gsum, int32_t* err, const LinOriArgs& ori,
+                           hipStream_t stream) {
   if (prec == DMN_F32)
     return bwd_t<float>(depth, tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum,
-                        err, stream);
+                        err, ori, stream);
   return bwd_t<double>(depth, tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum, err,
-                       stream);
+                       ori, stream);
 }
 
 }  // namespace dmn

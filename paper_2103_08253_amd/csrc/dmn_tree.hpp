@@ -131,49 +131,6 @@ struct NormalLds {
   double v[ORI ? Cfg<K, D>::PPW * 3 * Cfg<K, D>::L : 1];
 };
 
-// Normals of one point from its fibre orientation (l1, l2) (FE-DMN paper,
-// Sec. 2.3): barycentric coordinates of the orientation triangle (vertices
-// unidirectional (1, 0), isotropic (1/3, 1/3), planar isotropic (1/2, 1/2)),
-// the m shape functions of the orientation-interpolation table (3 linear,
-// 4 tri-linear, 6 quadratic), angles alpha = p . s, beta = q . s per laminate,
-// n = (sin a cos b, sin a sin b, cos a).  Lane t of the point's LP lanes
-// writes laminates t, t + LP, ... of nrm [3][L].
-template <int K, int D>
-__device__ __forceinline__ void orientation_normals(const double* __restrict__ p,
-                                                    const double* __restrict__ q, int m,
-                                                    double l1, double l2, int t, double* nrm) {
-  using C = Cfg<K, D>;
-  constexpr int L = C::L;
-  const double f1 = l1 - l2;
-  const double f2 = 3.0 - 3.0 * l1 - 3.0 * l2;
-  const double f3 = 2.0 * l1 + 4.0 * l2 - 2.0;
-  double s[6];
-  if (m == 3) {
-    s[0] = f1; s[1] = f2; s[2] = f3;
-  } else if (m == 4) {
-    const double b = f1 * f2 * f3;
-    s[0] = f1 - 9.0 * b; s[1] = f2 - 9.0 * b; s[2] = f3 - 9.0 * b; s[3] = 27.0 * b;
-  } else {
-    s[0] = f1 * (2.0 * f1 - 1.0); s[1] = f2 * (2.0 * f2 - 1.0); s[2] = f3 * (2.0 * f3 - 1.0);
-    s[3] = 4.0 * f1 * f2; s[4] = 4.0 * f1 * f3; s[5] = 4.0 * f2 * f3;
-  }
-#pragma unroll 1
-  for (int pos = t; pos < L; pos += C::LP) {
-    double a = 0.0, b = 0.0;
-#pragma unroll 1
-    for (int j = 0; j < m; ++j) {
-      a += p[(size_t)pos * m + j] * s[j];
-      b += q[(size_t)pos * m + j] * s[j];
-    }
-    double sa, ca, sb, cb;
-    sincos(a, &sa, &ca);
-    sincos(b, &sb, &cb);
-    nrm[0 * L + pos] = sa * cb;
-    nrm[1 * L + pos] = sa * sb;
-    nrm[2 * L + pos] = ca;
-  }
-}
-
 __device__ __forceinline__ double shfl_down_d(double v, int o, int width) {
   return __shfl_down(v, (unsigned)o, width);
 }

@@ -36,12 +36,12 @@ def net(depth=3):
 
 def test_linear_validation_codes():
     lib = L.lib()
-    ws_need = lib.dmn_homogenize_linear_workspace_size(3, 10, L.DMN_F64)
+    ws_need = lib.dmn_homogenize_linear_workspace_size(ctypes.byref(net(3)), 10, L.DMN_F64)
     assert ws_need > 0
-    assert lib.dmn_homogenize_linear_workspace_size(0, 10, L.DMN_F64) == 0
-    assert lib.dmn_homogenize_linear_workspace_size(11, 10, L.DMN_F64) == 0
+    assert lib.dmn_homogenize_linear_workspace_size(ctypes.byref(net(0)), 10, L.DMN_F64) == 0
+    assert lib.dmn_homogenize_linear_workspace_size(ctypes.byref(net(11)), 10, L.DMN_F64) == 0
     call = lambda n, B=10, prec=L.DMN_F64, ws=ALIGNED, nb=ws_need: lib.dmn_homogenize_linear(
-        n, B, prec, FAKE, FAKE, FAKE, ws, nb, None)
+        n, B, prec, FAKE, FAKE, None, FAKE, ws, nb, None)
     assert call(None) == L.DMN_EINVAL
     assert call(ctypes.byref(net(0))) == L.DMN_EINVAL
     assert call(ctypes.byref(net(11))) == L.DMN_EINVAL
@@ -56,11 +56,12 @@ def test_linear_validation_codes():
 
 def test_backward_validation_codes():
     lib = L.lib()
-    need = lib.dmn_homogenize_backward_workspace_size(8, 4096, L.DMN_F64)
-    assert need > lib.dmn_homogenize_linear_workspace_size(8, 4096, L.DMN_F64)
+    need = lib.dmn_homogenize_backward_workspace_size(ctypes.byref(net(8)), 4096, L.DMN_F64)
+    assert need > lib.dmn_homogenize_linear_workspace_size(ctypes.byref(net(8)), 4096, L.DMN_F64)
     n8 = net(8)
     call = lambda gw=FAKE, gc1=None, gc2=None, nb=need: lib.dmn_homogenize_backward(
-        ctypes.byref(n8), 4096, L.DMN_F64, FAKE, FAKE, FAKE, gw, FAKE, gc1, gc2, ALIGNED, nb, None)
+        ctypes.byref(n8), 4096, L.DMN_F64, FAKE, FAKE, None, FAKE, gw, FAKE, gc1, gc2, ALIGNED, nb,
+        None)
     assert call(gw=None) == L.DMN_EINVAL
     assert call(gc1=FAKE) == L.DMN_EINVAL          # gC1 without gC2
     assert call(nb=need - 1) == L.DMN_EWORKSPACE
@@ -137,11 +138,28 @@ def test_orientation_validation_codes():
     assert call(ori_group(L.DMN_ORI["trilinear"], q=None)) == L.DMN_EINVAL
     assert call(ori_group(L.DMN_ORI["quadratic"], lam=None)) == L.DMN_EINVAL
     assert call(ori_group(L.DMN_ORI["none"])) == L.DMN_EINVAL  # fixed normals need n
-    # the other calls take fixed normals only
-    net = L.DmnNet(3, FAKE.value, None, L.DMN_ORI["linear"], FAKE.value, FAKE.value)
-    nb = lib.dmn_homogenize_linear_workspace_size(3, 4, L.DMN_F64)
-    assert lib.dmn_homogenize_linear(ctypes.byref(net), 4, L.DMN_F64, FAKE, FAKE, FAKE, ALIGNED,
-                                     nb, None) == L.DMN_EUNSUPPORTED
-    nbb = lib.dmn_homogenize_backward_workspace_size(3, 4, L.DMN_F64)
-    assert lib.dmn_homogenize_backward(ctypes.byref(net), 4, L.DMN_F64, FAKE, FAKE, FAKE, FAKE,
-                                       FAKE, None, None, ALIGNED, nbb, None) == L.DMN_EUNSUPPORTED
+    # linear calls: per-sample orientation needs lam; the backward needs space for
+    # the per-sample angle cotangents
+    onet = L.DmnNet(3, FAKE.value, None, L.DMN_ORI["linear"], FAKE.value, FAKE.value)
+    fnet = net(3)
+    nb = lib.dmn_homogenize_linear_workspace_size(ctypes.byref(onet), 4, L.DMN_F64)
+    assert nb == lib.dmn_homogenize_linear_workspace_size(ctypes.byref(fnet), 4, L.DMN_F64)
+    assert lib.dmn_homogenize_linear(ctypes.byref(onet), 4, L.DMN_F64, FAKE, FAKE, None, FAKE,
+                                     ALIGNED, nb, None) == L.DMN_EINVAL
+    # per-sample orientation in the linear calls is switched off
+    assert lib.dmn_homogenize_linear(ctypes.byref(onet), 4, L.DMN_F64, FAKE, FAKE, FAKE, FAKE,
+                                     ALIGNED, nb, None) == L.DMN_EUNSUPPORTED
+    nbo = lib.dmn_homogenize_backward_workspace_size(ctypes.byref(onet), 4096, L.DMN_F64)
+    nbf = lib.dmn_homogenize_backward_workspace_size(ctypes.byref(fnet), 4096, L.DMN_F64)
+    assert nbo - nbf >= 7 * 2 * 4096 * 8
+    assert lib.dmn_homogenize_backward(ctypes.byref(onet), 4096, L.DMN_F64, FAKE, FAKE, FAKE,
+                                       FAKE, FAKE, FAKE, None, None, ALIGNED, nbo,
+                                       None) == L.DMN_EUNSUPPORTED
+    bad = L.DmnNet(3, FAKE.value, None, 9, FAKE.value, FAKE.value)
+    assert lib.dmn_homogenize_linear_workspace_size(ctypes.byref(bad), 4, L.DMN_F64) == 0
+    # the adjoint takes fixed normals only
+    ag = L.DmnAdjointGroup(onet, 4, *([FAKE.value] * 8))
+    arr_a = (L.DmnAdjointGroup * 1)(ag)
+    nba = lib.dmn_update_adjoint_workspace_size(arr_a, 1, L.DMN_F64)
+    assert lib.dmn_update_adjoint(arr_a, 1, ctypes.byref(fib), ctypes.byref(mat), L.DMN_F64,
+                                  ALIGNED, max(nba, 1 << 20), None) == L.DMN_EUNSUPPORTED
