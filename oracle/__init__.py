@@ -23,6 +23,9 @@ gp         Online evaluation at one Gauss point: Newton on the jumps with the
            dense Hessian, backtracking, convergence test of Sec. 4.6,
            effective stress and algorithmic tangent (Sec. 3.2).
 grad       Gradients of the linear map by complex-step differentiation.
+orientation  Fibre-orientation interpolation of the normals (Sec. 2.3).
+training   Offline-training objective (Sec. 3.1), AMSGrad with the modulated
+           learning rate (Sec. 4.5) and the stiffness sampler (Sec. 4.4).
 
 Readings of points the paper leaves open are listed in each function's
 docstring and in the design notes of the repository.
