@@ -438,6 +438,38 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         "HIP graph (device time only)", us_per_sample=pt_ms * 1e3, samples_per_s=1e3 / pt_ms,
         batched_samples_per_s=B / (bt_ms * 1e-3), batched_speedup=(pt_ms * B) / bt_ms)
 
+    # the paper's training objective end to end: forward, data term and cotangent,
+    # backward, AMSGrad update as one graph per step, at the 4096-sample batch and
+    # at the paper's mini-batch of 32 samples
+    from paper_2103_08253_amd import (AmsgradOpts, TrainParams, TrainingStepGraph,
+                                      dmn_sample_stiffness)
+    tw = S.config3()
+    tgt, _ = dmn_homogenize_linear(torch.tensor(tw.truth.w, device=dev),
+                                   torch.tensor(tw.truth.normals, device=dev), C1, C2)
+    train = {}
+    for nb in (B, 32):
+        Pt = TrainParams.create(torch.tensor(tw.v0, device=dev),
+                                torch.tensor(tw.alpha0, device=dev),
+                                torch.tensor(tw.beta0, device=dev))
+        gstep = TrainingStepGraph(Pt, C1[:nb].contiguous(), C2[:nb].contiguous(),
+                                  tgt[:nb].contiguous(), opts=AmsgradOpts(steps_per_epoch=10))
+        gstep.replay()
+        torch.cuda.synchronize()
+        j0 = float(gstep.stats[3].item())
+        reps = 50
+        ms = _event_ms(gstep.replay, reps) / reps
+        train[nb] = dict(ms_per_step=ms, samples_per_s=nb / (ms * 1e-3),
+                         objective_first=j0, objective_after=float(gstep.stats[3].item()),
+                         steps_taken=int(Pt.step.item()))
+    u = torch.rand((B, 8), dtype=torch.float64, device=dev)
+    dmn_sample_stiffness(u)
+    torch.cuda.synchronize()
+    samp_ms = _event_ms(lambda: dmn_sample_stiffness(u), 5) / 5
+    out["training_objective_step_graph"] = dict(
+        depth=8, p=1.0, q=10.0, optimiser="AMSGrad, modulated learning rate",
+        batch_4096=train[B], batch_32=train[32],
+        stiffness_sampler=dict(samples=B, ms=samp_ms, samples_per_s=B / (samp_ms * 1e-3)))
+
     # mixed-depth batch: 16 DMNs, 131,072 points, the 20-step path as one graph
     wl = S.config2()
     groups, E_steps = [], []

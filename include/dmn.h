@@ -294,6 +294,119 @@ int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
                        const dmn_elastic* fiber, const dmn_j2* matrix, int prec, void* ws,
                        size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Offline training of a DMN with fixed normals (Sec. 3.1 objective and
+ * parameterisation, Sec. 4.4 stiffness sampling, Sec. 4.5 optimiser).  One
+ * training step is dmn_homogenize_linear -> dmn_training_loss ->
+ * dmn_homogenize_backward -> dmn_training_update; every call only enqueues
+ * kernels, so the step can be captured into a HIP graph.
+ * ------------------------------------------------------------------------- */
+
+/* Exponents of the objective (Sec. 3.1): the error of sample s is
+ *   e_s = ||V(target_s - Cbar_s)||_p / ||V target_s||_p,
+ * the l^p norm over the 36 Voigt components V of the 6x6 stiffness (Voigt
+ * components are the Mandel entries divided by s_I s_J with
+ * s = (1, 1, 1, sqrt 2, sqrt 2, sqrt 2)); the batch of B samples contributes
+ * the data term (1/B) (sum_s e_s^q)^(1/q).  The paper trains with p = 1 and
+ * q = 10.  Requires 1 <= p, q (finite). */
+typedef struct dmn_loss_opts {
+  double p;
+  double q;
+} dmn_loss_opts;
+
+/* The training calls share a device block of DMN_TRAIN_STATS doubles:
+ *   [0] data term   [1] max_s e_s   [2] sum_s (e_s / max e)^q
+ *   [3] objective = data term + penalty      [4] penalty
+ *   [5] learning rate of the update          [6] sum_i <v_i>_+ before it
+ *   [7] unused
+ * dmn_training_loss writes [0..2], dmn_training_update writes [3..6]. */
+#define DMN_TRAIN_STATS 8
+
+/* Workspace bytes for dmn_training_loss (3 B doubles and a header). */
+size_t dmn_training_loss_workspace_size(int64_t B);
+
+/* Data term of the objective and its cotangent.  Cbar, target [B][36] are
+ * Mandel stiffnesses (target: the reference effective stiffness of each
+ * sample, nonzero); writes stats[0..2], the per-sample errors e [B] (NULL:
+ * not stored) and gCbar [B][36] = d(data term)/d Cbar entry by entry (the
+ * cotangent dmn_homogenize_backward takes).  Derivatives of |x| at 0 are
+ * taken as 0; a batch with no error gets a zero cotangent.  prec: DMN_F64 or
+ * DMN_F32 for Cbar, target, e, gCbar (sums in FP64); stats is FP64.  Batch
+ * sums use a fixed order.  B = 0 writes zeros to stats[0..2]. */
+int dmn_training_loss(int64_t B, int prec, const void* Cbar, const void* target,
+                      const dmn_loss_opts* opts, void* e, void* gCbar, double* stats, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* Optimiser of Sec. 4.5: AMSGrad (Adam with the running maximum of the
+ * second moment; Adam's bias corrections on the first moment and on that
+ * maximum) with the learning rate of epoch m
+ *   lr_decay^m (lr_min + (lr_max - lr_min) (1 + cos(pi m / half_period)) / 2),
+ * m = (updates taken so far) / steps_per_epoch (integer division).  The
+ * paper's values: lr_min = 1.5e-3, lr_max = 1.5e-2, lr_decay = 0.999,
+ * half_period = 50, penalty (lambda of the mixing penalty
+ * lambda (sum_i <v_i>_+ - 1)^2, Sec. 3.1) = 1e3; beta1 = 0.9,
+ * beta2 = 0.999, eps = 1e-8 are Adam's customary values (the paper gives
+ * none).  Requires 0 <= lr_min, lr_max; 0 < lr_decay; half_period,
+ * steps_per_epoch >= 1; 0 <= beta1, beta2 < 1; eps > 0; penalty >= 0. */
+typedef struct dmn_amsgrad_opts {
+  double lr_min;
+  double lr_max;
+  double lr_decay;
+  int32_t half_period;
+  int32_t steps_per_epoch;
+  double beta1;
+  double beta2;
+  double eps;
+  double penalty;
+} dmn_amsgrad_opts;
+
+/* Trainable parameters of a depth-K DMN with fixed normals (Sec. 3.1):
+ * unconstrained weights v [2^K] with leaf weights w = <v>_+ (Macaulay
+ * bracket) and normal angles alpha, beta [L] with
+ * n = (sin alpha cos beta, sin alpha sin beta, cos alpha) (Sec. 2.3).
+ * All arrays are device memory in the precision of the call. */
+typedef struct dmn_train_params {
+  int32_t depth;
+  void* v;         /* [2^K], updated in place */
+  void* alpha;     /* [L], updated in place */
+  void* beta;      /* [L], updated in place */
+  void* w;         /* [2^K] out: <v>_+ of the current v */
+  void* n;         /* [L][3] out: n(alpha, beta) of the current angles */
+  void* state;     /* [3][2^K + 2L]: first moments, second moments, their
+                      running maxima, for the slots v, alpha, beta in that
+                      order; zero before the first update */
+  int64_t* step;   /* device counter of updates taken (0 before the first) */
+} dmn_train_params;
+
+/* One optimiser step: with gw [2^K], gn [L][3] from dmn_homogenize_backward
+ * of the current (w, n) and the cotangent of dmn_training_loss, the
+ * gradients of the objective are
+ *   dJ/dv_i = (gw_i + 2 lambda (sum_j <v_j>_+ - 1)) [v_i > 0],
+ *   dJ/dalpha_l = gn_l . dn_l/dalpha_l,  dJ/dbeta_l = gn_l . dn_l/dbeta_l;
+ * the call applies AMSGrad to v, alpha, beta, advances *step, writes
+ * stats[3..6] (the objective of the parameters before the step) and
+ * refreshes w, n for the next forward.  prec: DMN_F64 or DMN_F32 for every
+ * array of params, gw and gn (arithmetic in FP64). */
+int dmn_training_update(const dmn_train_params* params, int prec, const void* gw, const void* gn,
+                        const dmn_amsgrad_opts* opts, double* stats, hipStream_t stream);
+
+/* Writes w = <v>_+ and n(alpha, beta) of params without a step (the inputs of
+ * the first forward). */
+int dmn_training_refresh(const dmn_train_params* params, int prec, hipStream_t stream);
+
+/* Stiffness sampler of Sec. 4.4: for each of B points u [B][8] (FP64) of
+ * the unit cube, the eight parameters (a, e1, e2, e3, beta, theta, psi, phi)
+ * are a = u0, e_i = -3 + 6 u_i, beta = 2 pi u4, theta in [0, pi] with
+ * theta - sin(theta) = pi u5, psi = pi u6, phi = 2 pi u7, and
+ *   C1 = 3 K1 P1 + 2 G1 P2,  C2 = 3 K2 P1 + 2 G2 (P2 - a N' (x) N'),
+ * with K1 = 1, G1 = 10^e1, K2 = 10^e2, G2 = 10^e3 (GPa), P1, P2 the
+ * spherical and deviatoric projectors, N' = Q N Q^T for the trace-free unit
+ * diagonal N(beta) and Q the rotation by theta about the axis
+ * (sin psi cos phi, sin psi sin phi, cos psi).  C1, C2 [B][36] Mandel in
+ * prec (DMN_F64 or DMN_F32). */
+int dmn_sample_stiffness(int64_t B, int prec, const double* u, void* C1, void* C2,
+                         hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

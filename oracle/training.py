@@ -50,8 +50,10 @@ H = 1e-30
 
 def cabs(x):
     """|x| for real x, continued analytically from the sign of the real part
-    (complex-step safe)."""
-    return np.where(np.real(x) >= 0, x, -x)
+    (complex-step safe); at x = 0 the continuation is 0, so the derivative
+    there is 0 (reading T2)."""
+    r = np.real(x)
+    return np.where(r > 0, x, np.where(r < 0, -x, 0.0 * x))
 
 
 def macaulay(v):

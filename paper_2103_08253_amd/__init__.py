@@ -2,8 +2,9 @@
 
 Batched online evaluation of direct deep material networks at Gauss points
 (J2 leaves, Newton on the laminate jumps with a tree block-Cholesky), the
-linear DMN homogenisation used in offline training and its hand-written
-backward, and the adjoint of a Newton-converged load path.  All computation
+linear DMN homogenisation used in offline training, its hand-written
+backward, the training objective, optimiser and stiffness sampler, and the
+adjoint of a Newton-converged load path.  All computation
 runs in the HIP kernels of libdmn.so; this package only marshals arguments
 (and captures sequences of calls into HIP graphs).
 """
@@ -12,3 +13,6 @@ from .api import (AdjointGroup, Orientation, PointGroup, dmn_homogenize_backward
                   error_word, workspace)
 from ._lib import DmnError, STATUS  # noqa: F401
 from .graph import LinearStepGraph, LoadStepGraph  # noqa: F401
+from .training import (AmsgradOpts, TrainParams, TrainingStepGraph,  # noqa: F401
+                       dmn_sample_stiffness, dmn_training_loss, dmn_training_refresh,
+                       dmn_training_update)

@@ -57,8 +57,41 @@ class DmnGpTuning(ctypes.Structure):
     _fields_ = [("lanes_per_point", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
 
 
+class DmnLossOpts(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_double), ("q", ctypes.c_double)]
+
+
+class DmnAmsgradOpts(ctypes.Structure):
+    _fields_ = [("lr_min", ctypes.c_double), ("lr_max", ctypes.c_double),
+                ("lr_decay", ctypes.c_double), ("half_period", ctypes.c_int32),
+                ("steps_per_epoch", ctypes.c_int32), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("penalty", ctypes.c_double)]
+
+
+class DmnTrainParams(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("v", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+                ("beta", ctypes.c_void_p), ("w", ctypes.c_void_p), ("n", ctypes.c_void_p),
+                ("state", ctypes.c_void_p), ("step", ctypes.c_void_p)]
+
+
+DMN_TRAIN_STATS = 8
+
 # exported functions and their signatures
 _SIGS = {
+    "dmn_training_loss_workspace_size": (ctypes.c_size_t, [ctypes.c_int64]),
+    "dmn_training_loss": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(DmnLossOpts),
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dmn_training_update": (ctypes.c_int, [ctypes.POINTER(DmnTrainParams), ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.POINTER(DmnAmsgradOpts), ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "dmn_training_refresh": (ctypes.c_int, [ctypes.POINTER(DmnTrainParams), ctypes.c_int,
+                                            ctypes.c_void_p]),
+    "dmn_sample_stiffness": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "dmn_version": (ctypes.c_char_p, []),
     "dmn_homogenize_linear_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(DmnNet),
                                                                ctypes.c_int64, ctypes.c_int]),

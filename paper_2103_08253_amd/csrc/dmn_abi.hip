@@ -416,4 +416,90 @@ int32_t dmn_gp_lane_variants(int32_t depth, int32_t* lanes, int32_t cap) {
   return dmn::gp_lane_variants(depth, lanes, cap);
 }
 
+size_t dmn_training_loss_workspace_size(int64_t B) {
+  if (B < 0) return 0;
+  return kAlign + align_up(3 * (size_t)B * sizeof(double));
+}
+
+int dmn_training_loss(int64_t B, int prec, const void* Cbar, const void* target,
+                      const dmn_loss_opts* opts, void* e, void* gCbar, double* stats, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  if (B < 0 || !opts || !stats) return DMN_EINVAL;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!(opts->p >= 1.0 && opts->p < 1e300) || !(opts->q >= 1.0 && opts->q < 1e300))
+    return DMN_EINVAL;
+  if (B > 0 && (!Cbar || !target || !gCbar)) return DMN_EINVAL;
+  if (!ws || ws_bytes < dmn_training_loss_workspace_size(B) || ((uintptr_t)ws % kAlign) != 0)
+    return DMN_EWORKSPACE;
+  double* scratch = (double*)((char*)ws + kAlign);
+  if (dmn::launch_training_loss(prec, B, opts->p, opts->q, Cbar, target, e, gCbar, stats, scratch,
+                                stream))
+    return DMN_EHIP;
+  return DMN_OK;
+}
+
+static int train_params_check(const dmn_train_params* t) {
+  if (!t || !depth_ok(t->depth)) return DMN_EINVAL;
+  if (!t->v || !t->alpha || !t->beta || !t->w || !t->n || !t->state || !t->step)
+    return DMN_EINVAL;
+  return DMN_OK;
+}
+
+static dmn::TrainUpdateArgs train_args(const dmn_train_params* t) {
+  dmn::TrainUpdateArgs a = {};
+  a.v = t->v;
+  a.alpha = t->alpha;
+  a.beta = t->beta;
+  a.w = t->w;
+  a.n = t->n;
+  a.state = t->state;
+  a.step = (long long*)t->step;
+  a.half_period = 1;
+  a.steps_per_epoch = 1;
+  return a;
+}
+
+int dmn_training_update(const dmn_train_params* params, int prec, const void* gw, const void* gn,
+                        const dmn_amsgrad_opts* opts, double* stats, hipStream_t stream) {
+  if (const int rc = train_params_check(params)) return rc;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!gw || !gn || !opts || !stats) return DMN_EINVAL;
+  const dmn_amsgrad_opts& o = *opts;
+  if (!(o.lr_min >= 0.0) || !(o.lr_max >= 0.0) || !(o.lr_decay > 0.0) || o.half_period < 1 ||
+      o.steps_per_epoch < 1 || !(o.beta1 >= 0.0 && o.beta1 < 1.0) ||
+      !(o.beta2 >= 0.0 && o.beta2 < 1.0) || !(o.eps > 0.0) || !(o.penalty >= 0.0))
+    return DMN_EINVAL;
+  dmn::TrainUpdateArgs a = train_args(params);
+  a.gw = gw;
+  a.gn = gn;
+  a.stats = stats;
+  a.lr_min = o.lr_min;
+  a.lr_max = o.lr_max;
+  a.lr_decay = o.lr_decay;
+  a.beta1 = o.beta1;
+  a.beta2 = o.beta2;
+  a.eps = o.eps;
+  a.penalty = o.penalty;
+  a.half_period = o.half_period;
+  a.steps_per_epoch = o.steps_per_epoch;
+  a.take_step = 1;
+  return dmn::launch_training_update(prec, params->depth, a, stream) ? DMN_EHIP : DMN_OK;
+}
+
+int dmn_training_refresh(const dmn_train_params* params, int prec, hipStream_t stream) {
+  if (const int rc = train_params_check(params)) return rc;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  dmn::TrainUpdateArgs a = train_args(params);
+  a.take_step = 0;
+  return dmn::launch_training_update(prec, params->depth, a, stream) ? DMN_EHIP : DMN_OK;
+}
+
+int dmn_sample_stiffness(int64_t B, int prec, const double* u, void* C1, void* C2,
+                         hipStream_t stream) {
+  if (B < 0) return DMN_EINVAL;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (B > 0 && (!u || !C1 || !C2)) return DMN_EINVAL;
+  return dmn::launch_sample_stiffness(prec, B, u, C1, C2, stream) ? DMN_EHIP : DMN_OK;
+}
+
 }  // extern "C"

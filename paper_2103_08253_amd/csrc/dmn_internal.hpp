@@ -120,6 +120,30 @@ struct AdjointLaunch {
 };
 
 long long adjoint_partial_slots(int depth, long long P);
+
+// Training: data term and cotangent of the objective (scratch: 3 B doubles),
+// optimiser step and parameter refresh, stiffness sampler.
+int launch_training_loss(int prec, long long B, double p, double q, const void* Cbar,
+                         const void* target, void* e_out, void* gCbar, double* stats,
+                         double* scratch, hipStream_t stream);
+struct TrainUpdateArgs {
+  void* v;
+  void* alpha;
+  void* beta;
+  void* w;
+  void* n;
+  void* state;
+  long long* step;
+  const void* gw;
+  const void* gn;
+  double* stats;
+  double lr_min, lr_max, lr_decay, beta1, beta2, eps, penalty;
+  int half_period, steps_per_epoch;
+  int take_step;  // 0: only refresh w and n from v, alpha, beta
+};
+int launch_training_update(int prec, int depth, const TrainUpdateArgs& args, hipStream_t stream);
+int launch_sample_stiffness(int prec, long long B, const double* u, void* C1, void* C2,
+                            hipStream_t stream);
 int launch_adjoint(int depth, const AdjointLaunch& args, hipStream_t stream);
 
 }  // namespace dmn

@@ -1,0 +1,361 @@
+// Offline training of a DMN with fixed normals: the objective's data term and
+// its cotangent (Sec. 3.1), the parameter update (Macaulay weights, normal
+// angles, mixing penalty of Sec. 3.1; AMSGrad with the modulated learning
+// rate of Sec. 4.5) and the stiffness sampler of Sec. 4.4.
+//
+// All of it is bandwidth- or latency-bound work next to the linear map and its
+// VJP: per-sample kernels read and write whole 36-entry stiffness records,
+// the batch reductions and the parameter update run in one workgroup with a
+// fixed summation order, so results are bit-reproducible run to run.
+#include "dmn_internal.hpp"
+
+namespace dmn {
+namespace {
+
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+constexpr double kSqrt2 = 1.41421356237309504880;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kReduceThreads = 1024;
+constexpr int kUpdateThreads = 512;
+
+// Voigt component of a Mandel stiffness entry (I, J): C_IJ / (s_I s_J) with
+// s = (1, 1, 1, sqrt 2, sqrt 2, sqrt 2).
+__device__ __forceinline__ double voigt_factor(int k) {
+  const int shear = (k / 6 >= 3) + (k % 6 >= 3);
+  return shear == 0 ? 1.0 : (shear == 1 ? kInvSqrt2 : 0.5);
+}
+
+__device__ __forceinline__ double pow_p(double x, double p, bool p1) { return p1 ? x : pow(x, p); }
+
+// Per sample: nd = ||V(target - Cbar)||_p, nt = ||V target||_p, e = nd / nt.
+template <typename T>
+__global__ __launch_bounds__(256) void loss_norms_kernel(long long B, double p,
+                                                         const T* __restrict__ Cbar,
+                                                         const T* __restrict__ target,
+                                                         double* __restrict__ nd,
+                                                         double* __restrict__ nt,
+                                                         double* __restrict__ e, T* e_out) {
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= B) return;
+  const bool p1 = p == 1.0;
+  const T* c = Cbar + (size_t)s * 36;
+  const T* t = target + (size_t)s * 36;
+  double sd = 0.0, st = 0.0;
+#pragma unroll
+  for (int k = 0; k < 36; ++k) {
+    const double f = voigt_factor(k);
+    const double tv = (double)t[k];
+    sd += pow_p(fabs((tv - (double)c[k]) * f), p, p1);
+    st += pow_p(fabs(tv * f), p, p1);
+  }
+  const double a = p1 ? sd : pow(sd, 1.0 / p);
+  const double b = p1 ? st : pow(st, 1.0 / p);
+  nd[s] = a;
+  nt[s] = b;
+  e[s] = a / b;
+  if (e_out) e_out[s] = (T)(a / b);
+}
+
+// One workgroup: M = max e (NaN propagates), S = sum (e / M)^q in a fixed
+// order, data term M S^(1/q) / B.  stats[0..2] = data term, M, S.
+__global__ __launch_bounds__(kReduceThreads) void loss_reduce_kernel(long long B, double q,
+                                                                     const double* __restrict__ e,
+                                                                     double* __restrict__ stats) {
+  __shared__ double red[kReduceThreads];
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  for (long long s = tid; s < B; s += kReduceThreads) {
+    const double x = e[s];
+    m = (x > m || x != x) ? x : m;
+  }
+  red[tid] = m;
+  __syncthreads();
+  for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      const double x = red[tid + h], y = red[tid];
+      red[tid] = (x > y || x != x) ? x : y;
+    }
+    __syncthreads();
+  }
+  const double M = red[0];
+  __syncthreads();
+  double acc = 0.0;
+  if (M > 0.0 || M != M)
+    for (long long s = tid; s < B; s += kReduceThreads) acc += pow(e[s] / M, q);
+  red[tid] = acc;
+  __syncthreads();
+  for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double S = red[0];
+    stats[0] = (M > 0.0 || M != M) ? M * pow(S, 1.0 / q) / (double)B : 0.0;
+    stats[1] = M;
+    stats[2] = S;
+  }
+}
+
+// gCbar_s = d(data term)/d Cbar_s
+//         = (1/B) S^(1/q - 1) (e_s / M)^(q - 1) * (-1 / nt_s) d||D||_p/dD * f
+// with D = V(target - Cbar); zero where the batch or the sample has no error.
+template <typename T>
+__global__ __launch_bounds__(256) void loss_cotangent_kernel(long long B, double p, double q,
+                                                             const T* __restrict__ Cbar,
+                                                             const T* __restrict__ target,
+                                                             const double* __restrict__ nd,
+                                                             const double* __restrict__ nt,
+                                                             const double* __restrict__ e,
+                                                             const double* __restrict__ stats,
+                                                             T* __restrict__ gC) {
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= B) return;
+  const double M = stats[1], S = stats[2];
+  const double ds = nd[s];
+  double coef = 0.0;
+  if (M > 0.0 && ds > 0.0)
+    coef = pow(S, 1.0 / q - 1.0) * pow(e[s] / M, q - 1.0) / ((double)B * nt[s]);
+  else if (M != M || ds != ds)
+    coef = M + ds;  // NaN in, NaN out
+  const bool p1 = p == 1.0;
+  const T* c = Cbar + (size_t)s * 36;
+  const T* t = target + (size_t)s * 36;
+  T* g = gC + (size_t)s * 36;
+#pragma unroll
+  for (int k = 0; k < 36; ++k) {
+    const double f = voigt_factor(k);
+    const double d = ((double)t[k] - (double)c[k]) * f;
+    const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+    const double dn = p1 ? sg : (ds > 0.0 ? pow(fabs(d) / ds, p - 1.0) * sg : 0.0);
+    g[k] = (T)(-coef * dn * f);
+  }
+}
+
+struct AmsArgs {
+  double lr_min, lr_max, lr_decay, beta1, beta2, eps, penalty;
+  int half_period, steps_per_epoch;
+};
+
+// Learning rate of epoch m: decay^m (lr_min + (lr_max - lr_min)(1 + cos(pi m / M)) / 2).
+__device__ __forceinline__ double modulated_rate(const AmsArgs& o, long long m) {
+  return pow(o.lr_decay, (double)m) *
+         (o.lr_min + 0.5 * (o.lr_max - o.lr_min) * (1.0 + cos(kPi * (double)m / o.half_period)));
+}
+
+// One workgroup.  Reads sum <v>_+ (fixed order), then (step != 0) takes one
+// AMSGrad step on (v, alpha, beta) with the gradients
+//   dJ/dv_i     = (gw_i + 2 lambda (sum <v>_+ - 1)) [v_i > 0]
+//   dJ/dalpha_l = gn_l . dn/dalpha,   dJ/dbeta_l = gn_l . dn/dbeta,
+// and finally writes w = <v>_+ and n(alpha, beta) for the next forward.
+template <typename T>
+__global__ __launch_bounds__(kUpdateThreads) void train_update_kernel(
+    int K, T* __restrict__ v, T* __restrict__ alpha, T* __restrict__ beta, T* __restrict__ w,
+    T* __restrict__ n, T* __restrict__ state, long long* __restrict__ step,
+    const T* __restrict__ gw, const T* __restrict__ gn, AmsArgs o, double* __restrict__ stats,
+    int take_step) {
+  __shared__ double red[kUpdateThreads];
+  const int tid = threadIdx.x;
+  const int NL = 1 << K, L = NL - 1, NP = NL + 2 * L;
+  double acc = 0.0;
+  for (int i = tid; i < NL; i += kUpdateThreads) acc += fmax((double)v[i], 0.0);
+  red[tid] = acc;
+  __syncthreads();
+  for (int h = kUpdateThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  const double sw = red[0];
+  if (take_step) {
+    const long long t0 = *step;
+    const double pen_g = 2.0 * o.penalty * (sw - 1.0);
+    const double lr = modulated_rate(o, t0 / o.steps_per_epoch);
+    const double t = (double)(t0 + 1);
+    const double step_size = lr / (1.0 - pow(o.beta1, t));
+    const double bc2 = 1.0 - pow(o.beta2, t);
+    T* m1 = state;
+    T* m2 = state + NP;
+    T* mx = state + 2 * NP;
+    // one AMSGrad update of parameter slot i with gradient g
+    auto amsgrad = [&](int i, double th, double g) {
+      const double a1 = o.beta1 * (double)m1[i] + (1.0 - o.beta1) * g;
+      const double a2 = o.beta2 * (double)m2[i] + (1.0 - o.beta2) * g * g;
+      const double ax = fmax((double)mx[i], a2);
+      m1[i] = (T)a1;
+      m2[i] = (T)a2;
+      mx[i] = (T)ax;
+      return th - step_size * a1 / (sqrt(ax / bc2) + o.eps);
+    };
+    // a thread owns a weight, or both angles of one laminate (each angle's
+    // gradient needs the other's old value)
+    for (int i = tid; i < NL + L; i += kUpdateThreads) {
+      if (i < NL) {
+        const double th = (double)v[i];
+        v[i] = (T)amsgrad(i, th, th > 0.0 ? (double)gw[i] + pen_g : 0.0);
+      } else {
+        const int l = i - NL;
+        const double a = (double)alpha[l], b = (double)beta[l];
+        double sa, ca, sb, cb;
+        sincos(a, &sa, &ca);
+        sincos(b, &sb, &cb);
+        const double g0 = (double)gn[3 * l], g1 = (double)gn[3 * l + 1], g2 = (double)gn[3 * l + 2];
+        alpha[l] = (T)amsgrad(NL + l, a, g0 * ca * cb + g1 * ca * sb - g2 * sa);
+        beta[l] = (T)amsgrad(NL + L + l, b, -g0 * sa * sb + g1 * sa * cb);
+      }
+    }
+    if (tid == 0) {
+      const double pen = o.penalty * (sw - 1.0) * (sw - 1.0);
+      stats[3] = stats[0] + pen;
+      stats[4] = pen;
+      stats[5] = lr;
+      stats[6] = sw;
+    }
+    __syncthreads();  // every read of *step and of the old parameters is done
+    if (tid == 0) *step = t0 + 1;
+  }
+  for (int i = tid; i < NL; i += kUpdateThreads) w[i] = (T)fmax((double)v[i], 0.0);
+  for (int l = tid; l < L; l += kUpdateThreads) {
+    double sa, ca, sb, cb;
+    sincos((double)alpha[l], &sa, &ca);
+    sincos((double)beta[l], &sb, &cb);
+    n[3 * l] = (T)(sa * cb);
+    n[3 * l + 1] = (T)(sa * sb);
+    n[3 * l + 2] = (T)ca;
+  }
+}
+
+// theta in [0, pi] with theta - sin(theta) = pi u: Newton from the small-angle
+// estimate (6 pi u)^(1/3), which lies left of the root; the function is
+// convex and increasing, so after the first step the iterates decrease
+// monotonically onto the root.
+__device__ double theta_from_unit(double u) {
+  const double rhs = kPi * u;
+  if (!(rhs > 0.0)) return 0.0;
+  double th = fmin(cbrt(6.0 * rhs), kPi);
+  for (int it = 0; it < 8; ++it) {
+    const double d = 1.0 - cos(th);
+    if (!(d > 0.0)) break;
+    th = fmin(fmax(th - (th - sin(th) - rhs) / d, 0.0), kPi);
+  }
+  return th;
+}
+
+// Phase stiffnesses of Sec. 4.4 from a unit-cube point u[8]:
+//   C1 = 3 K1 P1 + 2 G1 P2, C2 = 3 K2 P1 + 2 G2 (P2 - a N' (x) N'),
+// K1 = 1, G1 = 10^e1, K2 = 10^e2, G2 = 10^e3, N' = Q diag(d) Q^T with the
+// trace-free unit diagonal d(beta) = (c, s, -(c + s)) / sqrt(2 + 2 c s)
+// (c = cos beta, s = sin beta) and Q the rotation by theta about
+// (sin psi cos phi, sin psi sin phi, cos psi).
+template <typename T>
+__global__ __launch_bounds__(256) void sample_stiffness_kernel(long long B,
+                                                               const double* __restrict__ u,
+                                                               T* __restrict__ C1,
+                                                               T* __restrict__ C2) {
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= B) return;
+  const double* x = u + (size_t)s * 8;
+  const double a = x[0];
+  const double G1 = exp10(-3.0 + 6.0 * x[1]);
+  const double K2 = exp10(-3.0 + 6.0 * x[2]);
+  const double G2 = exp10(-3.0 + 6.0 * x[3]);
+  const double bt = 2.0 * kPi * x[4];
+  const double th = theta_from_unit(x[5]);
+  const double psi = kPi * x[6], phi = 2.0 * kPi * x[7];
+  double cb, sb, ct, st, cp, sp, cf, sf;
+  sincos(bt, &sb, &cb);
+  sincos(th, &st, &ct);
+  sincos(psi, &sp, &cp);
+  sincos(phi, &sf, &cf);
+  const double inv = 1.0 / sqrt(2.0 + 2.0 * cb * sb);
+  const double d[3] = {cb * inv, sb * inv, -(cb + sb) * inv};
+  const double ax[3] = {sp * cf, sp * sf, cp};
+  // Rodrigues: R = cos(th) I + sin(th) [ax]_x + (1 - cos th) ax ax^T
+  double R[3][3];
+  const double oc = 1.0 - ct;
+  R[0][0] = ct + oc * ax[0] * ax[0];
+  R[1][1] = ct + oc * ax[1] * ax[1];
+  R[2][2] = ct + oc * ax[2] * ax[2];
+  R[0][1] = oc * ax[0] * ax[1] - st * ax[2];
+  R[1][0] = oc * ax[0] * ax[1] + st * ax[2];
+  R[0][2] = oc * ax[0] * ax[2] + st * ax[1];
+  R[2][0] = oc * ax[0] * ax[2] - st * ax[1];
+  R[1][2] = oc * ax[1] * ax[2] - st * ax[0];
+  R[2][1] = oc * ax[1] * ax[2] + st * ax[0];
+  auto Nr = [&](int i, int j) {
+    return R[i][0] * d[0] * R[j][0] + R[i][1] * d[1] * R[j][1] + R[i][2] * d[2] * R[j][2];
+  };
+  const double nv[6] = {Nr(0, 0), Nr(1, 1), Nr(2, 2), kSqrt2 * Nr(1, 2), kSqrt2 * Nr(0, 2),
+                        kSqrt2 * Nr(0, 1)};
+  T* c1 = C1 + (size_t)s * 36;
+  T* c2 = C2 + (size_t)s * 36;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const double p1 = (i < 3 && j < 3) ? 1.0 / 3.0 : 0.0;
+      const double p2 = (i == j ? 1.0 : 0.0) - p1;
+      c1[i * 6 + j] = (T)(3.0 * p1 + 2.0 * G1 * p2);
+      c2[i * 6 + j] = (T)(3.0 * K2 * p1 + 2.0 * G2 * (p2 - a * nv[i] * nv[j]));
+    }
+}
+
+inline unsigned blocks_for(long long B, int threads) {
+  return (unsigned)((B + threads - 1) / threads);
+}
+
+template <typename T>
+int loss_t(long long B, double p, double q, const void* Cbar, const void* target, void* e_out,
+           void* gCbar, double* stats, double* scratch, hipStream_t s) {
+  double* nd = scratch;
+  double* nt = scratch + B;
+  double* e = scratch + 2 * B;
+  if (B > 0)
+    hipLaunchKernelGGL((loss_norms_kernel<T>), dim3(blocks_for(B, 256)), dim3(256), 0, s, B, p,
+                       (const T*)Cbar, (const T*)target, nd, nt, e, (T*)e_out);
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, B, q,
+                     (const double*)e, stats);
+  if (B > 0)
+    hipLaunchKernelGGL((loss_cotangent_kernel<T>), dim3(blocks_for(B, 256)), dim3(256), 0, s, B,
+                       p, q, (const T*)Cbar, (const T*)target, (const double*)nd,
+                       (const double*)nt, (const double*)e, (const double*)stats, (T*)gCbar);
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_training_loss(int prec, long long B, double p, double q, const void* Cbar,
+                         const void* target, void* e_out, void* gCbar, double* stats,
+                         double* scratch, hipStream_t stream) {
+  if (prec == DMN_F32)
+    return loss_t<float>(B, p, q, Cbar, target, e_out, gCbar, stats, scratch, stream);
+  return loss_t<double>(B, p, q, Cbar, target, e_out, gCbar, stats, scratch, stream);
+}
+
+int launch_training_update(int prec, int depth, const TrainUpdateArgs& a, hipStream_t stream) {
+  const AmsArgs o{a.lr_min, a.lr_max, a.lr_decay, a.beta1, a.beta2, a.eps, a.penalty,
+                  a.half_period, a.steps_per_epoch};
+  if (prec == DMN_F32)
+    hipLaunchKernelGGL((train_update_kernel<float>), dim3(1), dim3(kUpdateThreads), 0, stream,
+                       depth, (float*)a.v, (float*)a.alpha, (float*)a.beta, (float*)a.w,
+                       (float*)a.n, (float*)a.state, a.step, (const float*)a.gw,
+                       (const float*)a.gn, o, a.stats, a.take_step);
+  else
+    hipLaunchKernelGGL((train_update_kernel<double>), dim3(1), dim3(kUpdateThreads), 0, stream,
+                       depth, (double*)a.v, (double*)a.alpha, (double*)a.beta, (double*)a.w,
+                       (double*)a.n, (double*)a.state, a.step, (const double*)a.gw,
+                       (const double*)a.gn, o, a.stats, a.take_step);
+  return (int)hipGetLastError();
+}
+
+int launch_sample_stiffness(int prec, long long B, const double* u, void* C1, void* C2,
+                            hipStream_t stream) {
+  if (B == 0) return (int)hipSuccess;
+  if (prec == DMN_F32)
+    hipLaunchKernelGGL((sample_stiffness_kernel<float>), dim3(blocks_for(B, 256)), dim3(256), 0,
+                       stream, B, u, (float*)C1, (float*)C2);
+  else
+    hipLaunchKernelGGL((sample_stiffness_kernel<double>), dim3(blocks_for(B, 256)), dim3(256), 0,
+                       stream, B, u, (double*)C1, (double*)C2);
+  return (int)hipGetLastError();
+}
+
+}  // namespace dmn

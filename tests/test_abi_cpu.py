@@ -163,3 +163,50 @@ def test_orientation_validation_codes():
     nba = lib.dmn_update_adjoint_workspace_size(arr_a, 1, L.DMN_F64)
     assert lib.dmn_update_adjoint(arr_a, 1, ctypes.byref(fib), ctypes.byref(mat), L.DMN_F64,
                                   ALIGNED, max(nba, 1 << 20), None) == L.DMN_EUNSUPPORTED
+
+
+def test_training_validation_codes():
+    lib = L.lib()
+    assert lib.dmn_training_loss_workspace_size(-1) == 0
+    need = lib.dmn_training_loss_workspace_size(100)
+    assert need >= 3 * 100 * 8
+    good = L.DmnLossOpts(1.0, 10.0)
+    call = lambda B=100, prec=L.DMN_F64, o=good, C=FAKE, g=FAKE, st=FAKE, ws=ALIGNED, nb=need: \
+        lib.dmn_training_loss(B, prec, C, FAKE, ctypes.byref(o) if o is not None else None,
+                              None, g, st, ws, nb, None)
+    assert call(B=-1) == L.DMN_EINVAL
+    assert call(prec=L.DMN_F32_STATE) == L.DMN_EUNSUPPORTED
+    assert call(o=None) == L.DMN_EINVAL
+    assert call(o=L.DmnLossOpts(0.5, 10.0)) == L.DMN_EINVAL
+    assert call(o=L.DmnLossOpts(1.0, 0.0)) == L.DMN_EINVAL
+    assert call(o=L.DmnLossOpts(float("nan"), 2.0)) == L.DMN_EINVAL
+    assert call(C=None) == L.DMN_EINVAL
+    assert call(g=None) == L.DMN_EINVAL
+    assert call(st=None) == L.DMN_EINVAL
+    assert call(nb=need - 1) == L.DMN_EWORKSPACE
+    assert call(ws=ctypes.c_void_p(ALIGNED.value + 8)) == L.DMN_EWORKSPACE
+
+    params = L.DmnTrainParams(3, *([FAKE.value] * 7))
+    opts = L.DmnAmsgradOpts(1.5e-3, 1.5e-2, 0.999, 50, 1, 0.9, 0.999, 1e-8, 1e3)
+    upd = lambda pr=params, o=opts, prec=L.DMN_F64, gw=FAKE: lib.dmn_training_update(
+        ctypes.byref(pr) if pr is not None else None, prec, gw, FAKE,
+        ctypes.byref(o) if o is not None else None, FAKE, None)
+    assert upd(pr=None) == L.DMN_EINVAL
+    assert upd(pr=L.DmnTrainParams(0, *([FAKE.value] * 7))) == L.DMN_EINVAL
+    assert upd(pr=L.DmnTrainParams(3, None, *([FAKE.value] * 6))) == L.DMN_EINVAL
+    assert upd(pr=L.DmnTrainParams(3, *([FAKE.value] * 6), None)) == L.DMN_EINVAL
+    assert upd(prec=L.DMN_F32_STATE) == L.DMN_EUNSUPPORTED
+    assert upd(gw=None) == L.DMN_EINVAL
+    assert upd(o=None) == L.DMN_EINVAL
+    for field, bad in (("half_period", 0), ("steps_per_epoch", 0), ("beta1", 1.0),
+                       ("beta2", -0.1), ("eps", 0.0), ("penalty", -1.0), ("lr_decay", 0.0),
+                       ("lr_min", float("nan"))):
+        o = L.DmnAmsgradOpts(1.5e-3, 1.5e-2, 0.999, 50, 1, 0.9, 0.999, 1e-8, 1e3)
+        setattr(o, field, bad)
+        assert upd(o=o) == L.DMN_EINVAL, field
+    assert lib.dmn_training_refresh(None, L.DMN_F64, None) == L.DMN_EINVAL
+    assert lib.dmn_training_refresh(ctypes.byref(params), 5, None) == L.DMN_EUNSUPPORTED
+
+    assert lib.dmn_sample_stiffness(-1, L.DMN_F64, FAKE, FAKE, FAKE, None) == L.DMN_EINVAL
+    assert lib.dmn_sample_stiffness(4, L.DMN_F64, None, FAKE, FAKE, None) == L.DMN_EINVAL
+    assert lib.dmn_sample_stiffness(4, 9, FAKE, FAKE, FAKE, None) == L.DMN_EUNSUPPORTED

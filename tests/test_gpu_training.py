@@ -1,0 +1,328 @@
+"""GPU parity of the offline-training calls against the oracle: the
+objective's data term, per-sample errors and cotangent, the optimiser step
+(gradient chain through the Macaulay weights, the normal angles and the
+mixing penalty; AMSGrad; learning-rate modulation), the stiffness sampler,
+and whole training steps (eager and graph-captured) against complex-step
+gradients and a CPU replay of the same steps.
+
+Bars: FP64 within 1e-10 relative (max-norm against the largest reference
+entry) unless stated, FP32 within 1e-4."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synthetic as S
+from oracle import training as T
+from oracle.grad import normals_from_angles
+from oracle.linear import dmn_linear
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(got, ref):
+    scale = np.abs(ref).max()
+    return np.abs(np.asarray(got) - ref).max() / (scale if scale > 0 else 1.0)
+
+
+def tt(x, dtype=torch.float64):
+    return torch.tensor(np.asarray(x), dtype=dtype, device=dev())
+
+
+def loss_case(B, seed):
+    rs = S.streams(seed)
+    Tt = S.random_spd(rs["stiffness"], B)
+    Cb = Tt * (1.0 + 0.2 * rs["noise"].standard_normal(Tt.shape))
+    Cb[0] = Tt[0]                      # a sample without error
+    Cb[1, :3, :3] = Tt[1, :3, :3]      # zero differences on some components
+    return Cb, Tt
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
+@pytest.mark.parametrize("p,q", [(1.0, 10.0), (2.0, 3.0), (1.5, 1.0)])
+def test_training_loss_matches_oracle(dtype, tol, p, q):
+    from paper_2103_08253_amd import dmn_training_loss
+    B = 37
+    say(f"training loss B={B} p={p} q={q} {dtype}")
+    Cb, Tt = loss_case(B, 41)
+    # both sides see the same (rounded) inputs
+    Cb_t, T_t = tt(Cb, dtype), tt(Tt, dtype)
+    Cb64, T64 = Cb_t.double().cpu().numpy(), T_t.double().cpu().numpy()
+    e = torch.empty(B, dtype=dtype, device=dev())
+    g, stats, _ = dmn_training_loss(Cb_t, T_t, p, q, e=e)
+    torch.cuda.synchronize()
+    e_ref = T.sample_errors(Cb64, T64, p)
+    assert rel(e.double().cpu().numpy(), e_ref) < tol
+    st = stats.cpu().numpy()
+    assert abs(st[0] - T.data_term(e_ref, q)) <= tol * T.data_term(e_ref, q)
+    assert abs(st[1] - e_ref.max()) <= tol * e_ref.max()
+    g_ref = T.data_cotangent(Cb64, T64, p, q)
+    assert rel(g.double().cpu().numpy(), g_ref) < tol
+    assert np.all(g.double().cpu().numpy()[0] == 0.0)
+
+
+def test_training_loss_edge_cases():
+    from paper_2103_08253_amd import dmn_training_loss
+    say("training loss edge cases")
+    d = dev()
+    empty = torch.empty((0, 6, 6), dtype=torch.float64, device=d)
+    _, stats, _ = dmn_training_loss(empty, empty)
+    assert stats.cpu().numpy()[:3].tolist() == [0.0, 0.0, 0.0]
+    _, Tt = loss_case(5, 42)
+    T_t = tt(Tt)
+    g, stats, _ = dmn_training_loss(T_t.clone(), T_t)
+    assert stats.cpu().numpy()[0] == 0.0 and torch.all(g == 0)
+    Cb = T_t.clone()
+    Cb[2, 1, 1] = float("nan")
+    g, stats, _ = dmn_training_loss(Cb, T_t)
+    assert np.isnan(stats.cpu().numpy()[0]) and torch.isnan(g).all()
+
+
+def special_points(n, seed):
+    from scipy.stats import qmc
+    u = qmc.Sobol(d=8, scramble=True, seed=seed).random(n)
+    extra = np.array([[0.0] * 8, [1.0] * 8, [0.5, 0.5, 0.5, 0.5, 0.375, 0.0, 0.25, 0.1],
+                      [0.9, 0.1, 0.9, 0.2, 0.875, 1.0, 1.0, 0.9],
+                      [0.3, 0.7, 0.2, 0.6, 0.125, 1e-9, 0.5, 0.5]])
+    return np.concatenate([u, extra])
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_sample_stiffness_matches_oracle(dtype, tol):
+    from paper_2103_08253_amd import dmn_sample_stiffness
+    u = special_points(256, 13)
+    say(f"stiffness sampler B={len(u)} {dtype}")
+    C1, C2 = dmn_sample_stiffness(tt(u), dtype)
+    torch.cuda.synchronize()
+    C1, C2 = C1.double().cpu().numpy(), C2.double().cpu().numpy()
+    for b, x in enumerate(u):
+        r1, r2 = T.sample_stiffness(x)
+        assert rel(C1[b], r1) < tol, b
+        assert rel(C2[b], r2) < tol, b
+
+
+def chain_gradient(v, alpha, beta, gw, gn, lam):
+    """dJ/d(v, alpha, beta) from gw, gn: Macaulay cut-off and penalty by complex
+    steps of the oracle's penalty, angle chain by complex steps of its normals."""
+    h = 1e-30
+    gv = np.zeros_like(v)
+    for i in range(len(v)):
+        vc = v.astype(complex)
+        vc[i] += 1j * h
+        gv[i] = np.imag(np.dot(gw, T.macaulay(vc)) + T.penalty(vc, lam)) / h
+    ga = np.imag(np.sum(gn * normals_from_angles(alpha + 1j * h, beta), axis=1)) / h
+    gb = np.imag(np.sum(gn * normals_from_angles(alpha, beta + 1j * h), axis=1)) / h
+    return gv, ga, gb
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_training_update_matches_oracle(dtype, tol):
+    from paper_2103_08253_amd import AmsgradOpts, TrainParams, dmn_training_update
+    from paper_2103_08253_amd.training import new_stats
+    K = 4
+    NL, L = 2 ** K, 2 ** K - 1
+    NP = NL + 2 * L
+    rng = np.random.default_rng(17)
+    v = rng.uniform(-0.05, 0.15, NL)
+    alpha, beta = rng.uniform(0, 2 * np.pi, L), rng.uniform(0, 2 * np.pi, L)
+    gw, gn = rng.normal(0, 1e-2, NL), rng.normal(0, 1e-2, (L, 3))
+    m1 = rng.normal(0, 1e-3, (NP,))
+    m2 = rng.uniform(0, 1e-5, NP)
+    mx = m2 + rng.uniform(0, 1e-5, NP)
+    t0 = 7
+    opts = AmsgradOpts(lr_min=1e-3, lr_max=2e-2, lr_decay=0.99, half_period=5,
+                       steps_per_epoch=3, penalty=10.0)
+    say(f"training update K={K} {dtype}")
+    # round the inputs once so both sides see the same values
+    rd = lambda x: tt(x, dtype).double().cpu().numpy()
+    v, alpha, beta, gw, gn, m1, m2, mx = map(rd, (v, alpha, beta, gw, gn, m1, m2, mx))
+    P = TrainParams.create(tt(v, dtype), tt(alpha, dtype), tt(beta, dtype))
+    P.state.copy_(tt(np.stack([m1, m2, mx]), dtype))
+    P.step.fill_(t0)
+    stats = new_stats(dev())
+    stats[0] = 0.125
+    dmn_training_update(P, tt(gw, dtype), tt(gn, dtype), opts, stats)
+    torch.cuda.synchronize()
+    gv, ga, gb = chain_gradient(v, alpha, beta, gw, gn, opts.penalty)
+    lr = T.learning_rate(t0 // opts.steps_per_epoch, opts.lr_min, opts.lr_max, opts.half_period,
+                         opts.lr_decay)
+    th, n1, n2, nx = T.amsgrad(np.concatenate([v, alpha, beta]), np.concatenate([gv, ga, gb]),
+                               m1, m2, mx, t0 + 1, lr, opts.beta1, opts.beta2, opts.eps)
+    got = np.concatenate([P.v.double().cpu().numpy(), P.alpha.double().cpu().numpy(),
+                          P.beta.double().cpu().numpy()])
+    assert rel(got - np.concatenate([v, alpha, beta]),
+               th - np.concatenate([v, alpha, beta])) < 50 * tol
+    assert rel(got, th) < tol
+    assert rel(P.state.double().cpu().numpy(), np.stack([n1, n2, nx])) < tol
+    assert int(P.step.item()) == t0 + 1
+    assert rel(P.w.double().cpu().numpy(), T.macaulay(th[:NL])) < tol
+    assert rel(P.n.double().cpu().numpy(), normals_from_angles(th[NL:NL + L], th[NL + L:])) < tol
+    st = stats.cpu().numpy()
+    pen = T.penalty(v, opts.penalty)
+    assert abs(st[4] - pen) <= 1e-12 * max(pen, 1.0)
+    assert abs(st[3] - (0.125 + pen)) <= 1e-12 * (0.125 + pen)
+    assert abs(st[5] - lr) <= 1e-14 * lr
+    assert abs(st[6] - np.sum(T.macaulay(v))) <= 1e-12
+
+
+def training_case(K, B, seed):
+    rs = S.streams(seed)
+    C1 = S.random_spd(rs["stiffness"], B)
+    C2 = S.random_spd(rs["stiffness"], B)
+    truth = S.random_dmn(rs["ground_truth"], K, 0.25)
+    v = rs["init"].uniform(0.0, 1.0, 2 ** K)
+    v = v / v.sum()
+    alpha = rs["init"].uniform(0.0, 2 * np.pi, 2 ** K - 1)
+    beta = rs["init"].uniform(0.0, 2 * np.pi, 2 ** K - 1)
+    return C1, C2, truth, v, alpha, beta
+
+
+def test_training_step_gradient_matches_complex_step():
+    """One eager step with beta1 = beta2 = 0 and eps far above the gradient
+    makes the update -lr g / (|g| + eps), so the parameter change carries the
+    gradient of the whole objective; it must match the oracle's complex-step
+    gradient of J(v, alpha, beta)."""
+    from paper_2103_08253_amd import AmsgradOpts, TrainParams, dmn_homogenize_backward, \
+        dmn_homogenize_linear, dmn_training_loss, dmn_training_update
+    K, B, lam = 3, 16, 10.0
+    say(f"training step gradient K={K} B={B}")
+    C1, C2, truth, v, alpha, beta = training_case(K, B, 51)
+    v[2] = -0.01   # a weight cut off by the Macaulay bracket
+    Tt = dmn_linear(K, truth.w, truth.normals, C1, C2)
+    P = TrainParams.create(tt(v), tt(alpha), tt(beta))
+    C1t, C2t, Tt_t = tt(C1), tt(C2), tt(Tt)
+    Cbar, _ = dmn_homogenize_linear(P.w, P.n, C1t, C2t)
+    gC, stats, _ = dmn_training_loss(Cbar, Tt_t, 1.0, 10.0)
+    gw, gn, _, _, _ = dmn_homogenize_backward(P.w, P.n, C1t, C2t, gC)
+    eps, lr = 1e6, 1e3
+    opts = AmsgradOpts(lr_min=lr, lr_max=lr, lr_decay=1.0, beta1=0.0, beta2=0.0, eps=eps,
+                       penalty=lam)
+    dmn_training_update(P, gw, gn, opts, stats)
+    torch.cuda.synchronize()
+    th0 = np.concatenate([v, alpha, beta])
+    th1 = np.concatenate([P.v.cpu().numpy(), P.alpha.cpu().numpy(), P.beta.cpu().numpy()])
+    d = th0 - th1                      # d = lr g / (|g| + eps), so g = d eps / (lr - |d|)
+    g_gpu = d * eps / (lr - np.abs(d))
+    ref = T.objective_gradient(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
+    g_ref = np.concatenate([ref["gv"], ref["galpha"], ref["gbeta"]])
+    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    assert rel(g_gpu, g_ref) < 1e-8
+    J = T.objective(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
+    assert abs(stats.cpu().numpy()[3] - J) <= 1e-10 * J
+
+
+def test_training_graph_replays_match_eager_steps_and_oracle():
+    """Three graph replays (with eager work and synchronisation between them)
+    equal three eager steps bit for bit, and follow the oracle's replay of the
+    same steps (complex-step gradients, AMSGrad, modulated learning rate)."""
+    from paper_2103_08253_amd import AmsgradOpts, TrainParams, TrainingStepGraph
+    K, B = 3, 16
+    say(f"training graph K={K} B={B}")
+    C1, C2, truth, v, alpha, beta = training_case(K, B, 52)
+    Tt = dmn_linear(K, truth.w, truth.normals, C1, C2)
+    opts = AmsgradOpts(steps_per_epoch=2, half_period=3, penalty=100.0)
+    C1t, C2t, Tt_t = tt(C1), tt(C2), tt(Tt)
+    Pg = TrainParams.create(tt(v), tt(alpha), tt(beta))
+    Pe = TrainParams.create(tt(v), tt(alpha), tt(beta))
+    graph = TrainingStepGraph(Pg, C1t, C2t, Tt_t, opts=opts)
+    eager = TrainingStepGraph.__new__(TrainingStepGraph)
+    eager.__dict__.update(graph.__dict__)
+    eager.params = Pe
+    eager.stats = torch.zeros_like(graph.stats)
+    th = np.concatenate([v, alpha, beta])
+    NL, L = 2 ** K, 2 ** K - 1
+    st = [np.zeros(len(th))] * 3
+    for step in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device=dev()).sum().item()   # eager work between replays
+        eager.step_eager()
+        torch.cuda.synchronize()
+        for a, b in ((Pg.v, Pe.v), (Pg.alpha, Pe.alpha), (Pg.beta, Pe.beta),
+                     (Pg.state, Pe.state), (graph.stats, eager.stats)):
+            assert torch.equal(a, b), step
+        # oracle replay
+        vv, aa, bb = th[:NL], th[NL:NL + L], th[NL + L:]
+        J = T.objective(K, vv, aa, bb, C1, C2, Tt, 1.0, 10.0, opts.penalty)
+        g = T.objective_gradient(K, vv, aa, bb, C1, C2, Tt, 1.0, 10.0, opts.penalty)
+        lr = T.learning_rate(step // opts.steps_per_epoch, opts.lr_min, opts.lr_max,
+                             opts.half_period, opts.lr_decay)
+        th, *st = T.amsgrad(th, np.concatenate([g["gv"], g["galpha"], g["gbeta"]]), *st,
+                            step + 1, lr)
+        assert abs(graph.stats.cpu().numpy()[3] - J) <= 1e-10 * J, step
+        got = np.concatenate([Pg.v.cpu().numpy(), Pg.alpha.cpu().numpy(),
+                              Pg.beta.cpu().numpy()])
+        say(f"   step {step}: J {J:.6e} param rel err {rel(got, th):.2e}")
+        assert rel(got, th) < 1e-10, step
+
+
+def test_training_reduces_the_objective():
+    from paper_2103_08253_amd import (AmsgradOpts, TrainParams, TrainingStepGraph,
+                                      dmn_homogenize_linear)
+    K, B = 4, 64
+    say(f"training run K={K} B={B}, 400 steps")
+    C1, C2, truth, v, alpha, beta = training_case(K, B, 53)
+    C1t, C2t = tt(C1), tt(C2)
+    Tt, _ = dmn_homogenize_linear(tt(truth.w), tt(truth.normals), C1t, C2t)
+    P = TrainParams.create(tt(v), tt(alpha), tt(beta))
+    g = TrainingStepGraph(P, C1t, C2t, Tt, opts=AmsgradOpts(steps_per_epoch=4))
+    hist = []
+    for i in range(400):
+        g.replay()
+        if i % 50 == 0 or i == 399:
+            hist.append(float(g.stats[3].item()))
+    say(f"   objective {hist[0]:.4e} -> {hist[-1]:.4e}")
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < 0.7 * hist[0]
+
+
+def test_training_full_size_step():
+    """Depth 8, B = 4096 (the training workload): per-sample errors and the
+    objective against the oracle, and the update against the oracle's AMSGrad
+    applied to the chained gradient of the GPU's gw, gn."""
+    from paper_2103_08253_amd import (AmsgradOpts, TrainParams, dmn_homogenize_backward,
+                                      dmn_homogenize_linear, dmn_training_loss,
+                                      dmn_training_update)
+    wl = S.config3()
+    K, B = 8, wl.C1.shape[0]
+    say(f"training full size K={K} B={B}")
+    C1t, C2t = tt(wl.C1), tt(wl.C2)
+    Tt, _ = dmn_homogenize_linear(tt(wl.truth.w), tt(wl.truth.normals), C1t, C2t)
+    P = TrainParams.create(tt(wl.v0), tt(wl.alpha0), tt(wl.beta0))
+    Cbar, _ = dmn_homogenize_linear(P.w, P.n, C1t, C2t)
+    e = torch.empty(B, dtype=torch.float64, device=dev())
+    gC, stats, _ = dmn_training_loss(Cbar, Tt, 1.0, 10.0, e=e)
+    gw, gn, _, _, _ = dmn_homogenize_backward(P.w, P.n, C1t, C2t, gC)
+    opts = AmsgradOpts()
+    dmn_training_update(P, gw, gn, opts, stats)
+    torch.cuda.synchronize()
+    # oracle on a sample of 64 samples: the linear map, then the errors
+    pick = np.random.default_rng(7).choice(B, 64, replace=False)
+    Tt_np = Tt.cpu().numpy()
+    ref_C = dmn_linear(K, T.macaulay(wl.v0), normals_from_angles(wl.alpha0, wl.beta0),
+                       wl.C1[pick], wl.C2[pick])
+    e_ref = T.sample_errors(ref_C, Tt_np[pick], 1.0)
+    assert rel(e.cpu().numpy()[pick], e_ref) < 1e-10
+    e_all = e.cpu().numpy()
+    st = stats.cpu().numpy()
+    assert abs(st[0] - T.data_term(e_all, 10.0)) <= 1e-12 * st[0]
+    gv, ga, gb = chain_gradient(wl.v0, wl.alpha0, wl.beta0, gw.cpu().numpy(), gn.cpu().numpy(),
+                                opts.penalty)
+    z = np.zeros(2 ** K + 2 * (2 ** K - 1))
+    th, *_ = T.amsgrad(np.concatenate([wl.v0, wl.alpha0, wl.beta0]),
+                       np.concatenate([gv, ga, gb]), z, z, z, 1, opts.lr_max)
+    got = np.concatenate([P.v.cpu().numpy(), P.alpha.cpu().numpy(), P.beta.cpu().numpy()])
+    assert rel(got, th) < 1e-12

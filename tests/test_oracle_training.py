@@ -218,3 +218,17 @@ def test_sampler_domains_at_cube_corners():
     hi = T.sample_parameters(np.ones(8))
     assert np.allclose(lo, (0.0, -3.0, -3.0, -3.0, 0.0, 0.0, 0.0, 0.0), rtol=0, atol=1e-14)
     assert np.allclose(hi, (1.0, 3.0, 3.0, 3.0, 2 * np.pi, np.pi, np.pi, 2 * np.pi), atol=1e-14)
+
+
+def test_zero_differences_have_zero_derivative():
+    """Reading T2: entries where target and prediction agree contribute no
+    gradient, and neither does a sample without error."""
+    rs = S.streams(34)
+    Tt = S.random_spd(rs["stiffness"], 3)
+    Cb = Tt * (1.0 + 0.1 * rs["noise"].standard_normal(Tt.shape))
+    Cb[0] = Tt[0]
+    Cb[1, 2, 2] = Tt[1, 2, 2]
+    for p, q in ((1.0, 1.0), (1.0, 10.0), (2.0, 1.0)):
+        G = T.data_cotangent(Cb, Tt, p, q)
+        assert np.all(G[0] == 0.0) and G[1, 2, 2] == 0.0
+        assert np.all(G[2] != 0.0)
