@@ -24,6 +24,8 @@ gp         Online evaluation at one Gauss point: Newton on the jumps with the
            effective stress and algorithmic tangent (Sec. 3.2).
 grad       Gradients of the linear map by complex-step differentiation.
 orientation  Fibre-orientation interpolation of the normals (Sec. 2.3).
+compression  Tree compression of zero-weight subtrees (Sec. 3.1) and the
+           linear map of the compressed tree.
 training   Offline-training objective (Sec. 3.1), AMSGrad with the modulated
            learning rate (Sec. 4.5) and the stiffness sampler (Sec. 4.4).
 

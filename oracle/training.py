@@ -8,7 +8,7 @@ sampler.  Test infrastructure like the rest of the oracle.
   lambda (sum <v>_+ - 1)^2 of the mixing constraint.  Exponents p = 1,
   q = 10 and lambda = 1e3 in the paper's training (Sec. 4.5).
 * Gradient: complex-step derivative of the objective through the oracle's
-  Milton-form linear map (complex-safe throughout).
+  Milton-form linear map of the compressed tree (complex-safe throughout).
 * Optimiser (Sec. 4.5): AMSGrad with the learning rate modulated between a
   minimum and a maximum by a cosine of half period M and damped
   geometrically by gamma per epoch.
@@ -39,8 +39,8 @@ Readings (where the paper leaves a choice open):
 """
 import numpy as np
 
+from .compression import dmn_linear_compressed
 from .grad import normals_from_angles
-from .linear import dmn_linear
 from .mandel import FAC, P1, P2, sym_to_mandel
 
 H = 1e-30
@@ -88,8 +88,9 @@ def penalty(v, lam):
 
 
 def objective(K, v, alpha, beta, C1, C2, T, p=1.0, q=10.0, lam=1e3):
-    """J(v, alpha, beta) for fixed lamination normals n(alpha, beta)."""
-    Cbar = dmn_linear(K, macaulay(v), normals_from_angles(alpha, beta), C1, C2)
+    """J(v, alpha, beta) for fixed lamination normals n(alpha, beta); leaves
+    whose weight <v>_+ is zero are removed by tree compression (Sec. 3.1)."""
+    Cbar = dmn_linear_compressed(K, macaulay(v), normals_from_angles(alpha, beta), C1, C2)
     return data_term(sample_errors(Cbar, T, p), q) + penalty(v, lam)
 
 

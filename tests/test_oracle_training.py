@@ -232,3 +232,29 @@ def test_zero_differences_have_zero_derivative():
         G = T.data_cotangent(Cb, Tt, p, q)
         assert np.all(G[0] == 0.0) and G[1, 2, 2] == 0.0
         assert np.all(G[2] != 0.0)
+
+
+def test_objective_with_a_dead_subtree_matches_differences():
+    """Leaves 2 and 3 (a whole sibling pair) cut off by the Macaulay bracket:
+    the objective is that of the compressed tree; its complex-step gradient
+    matches differences in every parameter, and the dead weights and the
+    normal of the dead laminate and of its parent get none."""
+    K = 2
+    C1, C2, truth, _, _, v, alpha, beta = _case(K=K, B=4)
+    Tt = dmn_linear(K, truth.w, truth.normals, C1, C2)
+    v = v.copy()
+    v[2], v[3] = -0.05, -0.02
+    g = T.objective_gradient(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, 10.0)
+    fv = lambda x: T.objective(K, x, alpha, beta, C1, C2, Tt, 1.0, 10.0, 10.0)
+    fa = lambda x: T.objective(K, v, x, beta, C1, C2, Tt, 1.0, 10.0, 10.0)
+    fb = lambda x: T.objective(K, v, alpha, x, C1, C2, Tt, 1.0, 10.0, 10.0)
+    for key, f, x in (("gv", fv, v), ("galpha", fa, alpha), ("gbeta", fb, beta)):
+        for i in range(len(x)):
+            fd = _richardson(f, x, i, 1e-4)
+            assert abs(g[key][i] - fd) <= 1e-7 * max(1.0, abs(fd)), (key, i)
+    # laminate over leaves 2, 3 is dead; the root then has a single child
+    from oracle.tree import lam_pos
+    for k, i in ((2, 2), (1, 1)):
+        p = lam_pos(K, k, i)
+        assert g["galpha"][p] == 0.0 and g["gbeta"][p] == 0.0
+    assert g["gv"][2] == 0.0 and g["gv"][3] == 0.0
