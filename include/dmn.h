@@ -65,7 +65,8 @@ extern "C" {
 #define DMN_STATUS_NONFINITE 2 /* non-finite input or residual */
 #define DMN_STATUS_NOTSPD 3    /* a laminate pivot of the Hessian is not positive definite */
 #define DMN_STATUS_LOCAL 4     /* J2 return mapping did not converge */
-#define DMN_STATUS_BADPARAM 5  /* negative leaf weight or a laminate with zero child weight */
+#define DMN_STATUS_BADPARAM 5  /* negative or non-finite leaf weight, no weight at all, or a
+                                  laminate whose children carry no weight */
 
 #define DMN_MAX_DEPTH 10
 
@@ -78,7 +79,13 @@ extern "C" {
 #define DMN_ORI_QUADRATIC 3 /* M = 6 */
 
 /* A direct DMN: depth K, leaf weights w[2^K] (non-negative, need not sum to
- * one: fractions are weight ratios and averages use w / sum(w)), and either
+ * one: fractions are weight ratios and averages use w / sum(w)).  Leaves of
+ * zero weight are allowed when a sibling subtree keeps weight; a subtree
+ * whose leaves all have zero weight (a dead subtree) is removed from the
+ * tree by the linear map and its backward, which is the paper's tree
+ * compression (Sec. 3.1), and is rejected by the Gauss-point update and the
+ * adjoint (status / error DMN_STATUS_BADPARAM: compress such a DMN before the
+ * online evaluation, as the paper does).  The net also has either
  *   ori_shape = DMN_ORI_NONE: normals n[2^K - 1][3] in paper order (unit
  *     length expected; used as passed); or
  *   ori_shape = DMN_ORI_LINEAR / TRILINEAR / QUADRATIC: normals that depend
@@ -175,8 +182,11 @@ size_t dmn_homogenize_linear_workspace_size(const dmn_net* net, int64_t B, int p
  * symmetric).  prec: DMN_F64 or DMN_F32 (all arrays, including w, n, the
  * orientation coefficients and lam, in that precision).  lam [B][2]: the
  * fibre orientation (l1, l2) of each sample for an orientation-interpolated
- * net (Sec. 2.3, see dmn_net), NULL for fixed normals.  An invalid DMN
- * (negative weight, zero child weight) or a non-SPD laminate pivot sets the
+ * net (Sec. 2.3, see dmn_net), NULL for fixed normals.  Dead subtrees (all
+ * leaf weights zero) are removed from the tree (Sec. 3.1 compression): a
+ * laminate with one dead child returns its other child's stiffness.  An
+ * invalid DMN (a negative or non-finite weight, or no weight at all) or a
+ * non-SPD laminate pivot sets the
  * device error word at the start of the workspace (int32, 0 = fine; read it
  * after the stream has finished) and leaves NaN in the affected outputs. */
 int dmn_homogenize_linear(const dmn_net* net, int64_t B, int prec, const void* C1,
@@ -195,6 +205,12 @@ size_t dmn_homogenize_backward_workspace_size(const dmn_net* net, int64_t B, int
  *                holds d/d ori_p[i] (M values) then d/d ori_q[i], each summed
  *                over the samples with their own orientation lam
  *   gC1, gC2 [B][36]  per-sample d<gCbar, Cbar>/d C1, C2 (symmetric), or NULL
+ * With dead subtrees (see dmn_net) the laminates inside them and those with
+ * a dead child get gn = 0, leaves inside them get nothing from their dead
+ * laminates, and a zero-weight leaf next to a live sibling gets the one-sided
+ * derivative d/dw at w = 0; entries of leaves inside a dead subtree are
+ * finite but are not derivatives (training zeroes them through the Macaulay
+ * bracket, see dmn_training_update).
  * The batch sums use a fixed reduction order (bit-reproducible run to run).
  * The forward is recomputed inside the call.  Same error word as the forward. */
 int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void* C1,

@@ -132,7 +132,8 @@ int dmn_homogenize_linear(const dmn_net* net, int64_t B, int prec, const void* C
   int32_t* err = (int32_t*)ws;
   Table tb = table_at(ws, kAlign);
   const void* nfix = net->ori_shape == DMN_ORI_NONE ? net->n : nullptr;
-  if (dmn::launch_prep_tables(net->w, nfix, net->depth, prec, tb.rows, tb.flag, err, stream))
+  if (dmn::launch_prep_tables(net->w, nfix, net->depth, prec, tb.rows, tb.flag, err, stream,
+                              true))
     return DMN_EHIP;
   if (B == 0) return DMN_OK;
   if (dmn::launch_linear_forward(net->depth, prec, tb.rows, tb.flag, B, C1, C2, Cbar, err,
@@ -174,7 +175,7 @@ int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void*
   double* partials = (double*)((char*)gsum + align_up(L * 4 * sizeof(double)));
   void* gang = (char*)partials + align_up(slots * L * 4 * sizeof(double));
   const void* nfix = net->ori_shape == DMN_ORI_NONE ? net->n : nullptr;
-  if (dmn::launch_prep_tables(net->w, nfix, K, prec, tb.rows, tb.flag, err, stream))
+  if (dmn::launch_prep_tables(net->w, nfix, K, prec, tb.rows, tb.flag, err, stream, true))
     return DMN_EHIP;
   // B == 0 still runs the (empty) reductions so gw, gn are overwritten with zeros
   if (dmn::launch_linear_backward(K, prec, tb.rows, tb.flag, B, C1, C2, gCbar, gw, gn, gC1, gC2,

@@ -64,8 +64,9 @@ struct GpLaunch {
 };
 
 // Host launchers (return hipError_t as int).
+// allow_dead: accept subtrees without weight (linear map and its VJP), see dmn_prep.hip
 int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
-                       int32_t* err, hipStream_t stream);
+                       int32_t* err, hipStream_t stream, bool allow_dead = false);
 int launch_gp_update(int depth, int lanes_per_point, int prec, bool ori, const GpLaunch& args,
                      int n_blocks, hipStream_t stream);
 int launch_zero_ints(int32_t* p, int n, hipStream_t stream);

@@ -9,9 +9,16 @@
 //   rfac = W_L W_R / ((W_L + W_R) sum(w))  (scale of the laminate's block of A^T W sigma)
 //   dc1/dW_L = W_R / W^2, dc1/dW_R = -W_L / W^2
 // followed by the leaf section w / sum(w) [2^K] and 1 / sum(w), and a
-// field-major copy of the first six fields; flags the DMN as invalid when a weight is negative or not finite, or a
-// laminate's children carry no weight.  Subtree sums are formed pairwise in
-// a fixed order, so the table is bit-identical run to run.
+// field-major copy of the first six fields; flags the DMN as invalid when a
+// weight is negative or not finite, or no leaf carries weight.  A laminate
+// whose children carry no weight (a dead subtree) is flagged too, unless the
+// caller accepts dead subtrees (the linear map and its VJP): then its row is
+// c1 = c2 = 1/2, rfac = 0, dc1/dW = 0, so the subtree stays finite while its
+// live parent, whose fraction for it is exactly 0, takes the other child's
+// result unchanged and passes it no cotangent, which is what removing the
+// subtree from the tree (Sec. 3.1, tree compression) computes.  Subtree sums
+// are formed pairwise in a fixed order, so the table is bit-identical run to
+// run.
 #include "dmn_internal.hpp"
 
 namespace dmn {
@@ -21,7 +28,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, const T* __restrict__ n,
                                                    int K, T* __restrict__ tab,
                                                    int32_t* __restrict__ flag,
-                                                   int32_t* __restrict__ err) {
+                                                   int32_t* __restrict__ err, int allow_dead) {
   // node sums of the whole tree in LDS, heap order: node 1 = root, leaves at
   // 2^K ... 2^(K+1)-1; each internal node is the sum of its two children
   __shared__ T W[2 << DMN_MAX_DEPTH];
@@ -43,6 +50,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, cons
     __syncthreads();
   }
   const T wtot = W[1];
+  if (!(wtot > T(0))) mybad = 1;
   for (int pos = threadIdx.x; pos < L; pos += blockDim.x) {
     // level k and 0-based index i0 of the laminate at paper position pos
     int k = K, base = 0;
@@ -53,17 +61,18 @@ __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, cons
     const int h = (1 << (k - 1)) + (pos - base);  // heap index
     const T WL = W[2 * h], WR = W[2 * h + 1];
     const T Wn = WL + WR;
-    if (!(Wn > T(0))) mybad = 1;
+    const bool live = Wn > T(0);
+    if (!live && !allow_dead) mybad = 1;
     T* r = tab + (size_t)pos * kTabStride;
-    const T c1 = WL / Wn;
+    const T c1 = live ? WL / Wn : T(0.5);
     r[0] = c1;
     r[1] = T(1) - c1;
     r[2] = n ? n[(size_t)pos * 3 + 0] : T(0);  // no fixed normals: filled per point
     r[3] = n ? n[(size_t)pos * 3 + 1] : T(0);
     r[4] = n ? n[(size_t)pos * 3 + 2] : T(0);
-    r[5] = WL * WR / (Wn * wtot);
-    r[6] = WR / (Wn * Wn);
-    r[7] = -WL / (Wn * Wn);
+    r[5] = live ? WL * WR / (Wn * wtot) : T(0);
+    r[6] = live ? WR / (Wn * Wn) : T(0);
+    r[7] = live ? -WL / (Wn * Wn) : T(0);
     T* soa = tab + table_soa_offset(K);
 #pragma unroll
     for (int f = 0; f < 6; ++f) soa[(size_t)f * L + pos] = r[f];
@@ -107,13 +116,13 @@ int device_cu_count() {
 }
 
 int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
-                       int32_t* err, hipStream_t stream) {
+                       int32_t* err, hipStream_t stream, bool allow_dead) {
   if (prec == DMN_F32) {
     hipLaunchKernelGGL(prep_kernel<float>, dim3(1), dim3(256), 0, stream, (const float*)w,
-                       (const float*)n, depth, (float*)tab, flag, err);
+                       (const float*)n, depth, (float*)tab, flag, err, allow_dead ? 1 : 0);
   } else {
     hipLaunchKernelGGL(prep_kernel<double>, dim3(1), dim3(256), 0, stream, (const double*)w,
-                       (const double*)n, depth, (double*)tab, flag, err);
+                       (const double*)n, depth, (double*)tab, flag, err, allow_dead ? 1 : 0);
   }
   return (int)hipGetLastError();
 }

@@ -27,72 +27,87 @@ __device__ __forceinline__ double voigt_factor(int k) {
 
 __device__ __forceinline__ double pow_p(double x, double p, bool p1) { return p1 ? x : pow(x, p); }
 
-// Per sample: nd = ||V(target - Cbar)||_p, nt = ||V target||_p, e = nd / nt.
+// The per-sample kernels give each of the 36 entries of a stiffness record its
+// own thread: a workgroup of 252 threads covers 7 consecutive samples, so a
+// wave reads consecutive doubles of the [B][36] arrays.
+constexpr int kEntryThreads = 252;
+constexpr int kSamplesPerGroup = kEntryThreads / 36;
+
+// Per sample: nd = ||V(target - Cbar)||_p, nt = ||V target||_p, e = nd / nt
+// (the 36 terms summed in entry order by the sample's first thread).
 template <typename T>
-__global__ __launch_bounds__(256) void loss_norms_kernel(long long B, double p,
-                                                         const T* __restrict__ Cbar,
-                                                         const T* __restrict__ target,
-                                                         double* __restrict__ nd,
-                                                         double* __restrict__ nt,
-                                                         double* __restrict__ e, T* e_out) {
-  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= B) return;
+__global__ __launch_bounds__(kEntryThreads) void loss_norms_kernel(
+    long long B, double p, const T* __restrict__ Cbar, const T* __restrict__ target,
+    double* __restrict__ nd, double* __restrict__ nt, double* __restrict__ e, T* e_out) {
+  __shared__ double td[kEntryThreads], tt[kEntryThreads];
+  const int j = threadIdx.x;
+  const int ls = j / 36, k = j - 36 * ls;
+  const long long s = (long long)blockIdx.x * kSamplesPerGroup + ls;
   const bool p1 = p == 1.0;
-  const T* c = Cbar + (size_t)s * 36;
-  const T* t = target + (size_t)s * 36;
-  double sd = 0.0, st = 0.0;
-#pragma unroll
-  for (int k = 0; k < 36; ++k) {
+  double a = 0.0, b = 0.0;
+  if (s < B) {
     const double f = voigt_factor(k);
-    const double tv = (double)t[k];
-    sd += pow_p(fabs((tv - (double)c[k]) * f), p, p1);
-    st += pow_p(fabs(tv * f), p, p1);
+    const double tv = (double)target[(size_t)s * 36 + k];
+    a = pow_p(fabs((tv - (double)Cbar[(size_t)s * 36 + k]) * f), p, p1);
+    b = pow_p(fabs(tv * f), p, p1);
   }
-  const double a = p1 ? sd : pow(sd, 1.0 / p);
-  const double b = p1 ? st : pow(st, 1.0 / p);
-  nd[s] = a;
-  nt[s] = b;
-  e[s] = a / b;
-  if (e_out) e_out[s] = (T)(a / b);
+  td[j] = a;
+  tt[j] = b;
+  __syncthreads();
+  if (k == 0 && s < B) {
+    double sd = 0.0, st = 0.0;
+    for (int i = 0; i < 36; ++i) {
+      sd += td[j + i];
+      st += tt[j + i];
+    }
+    const double x = p1 ? sd : pow(sd, 1.0 / p);
+    const double y = p1 ? st : pow(st, 1.0 / p);
+    nd[s] = x;
+    nt[s] = y;
+    e[s] = x / y;
+    if (e_out) e_out[s] = (T)(x / y);
+  }
 }
 
-// One workgroup: M = max e (NaN propagates), S = sum (e / M)^q in a fixed
-// order, data term M S^(1/q) / B.  stats[0..2] = data term, M, S.
+// Running (max M, sum of (x / M)^q) pair; merging rescales the smaller part.
+// NaN anywhere makes both NaN.
+struct MaxPowSum {
+  double m, s;
+};
+__device__ __forceinline__ MaxPowSum mps_merge(MaxPowSum a, MaxPowSum b, double q) {
+  if (a.m != a.m || b.m != b.m) return MaxPowSum{__builtin_nan(""), __builtin_nan("")};
+  const double m = fmax(a.m, b.m);
+  if (!(m > 0.0)) return MaxPowSum{0.0, 0.0};
+  const double sa = a.m > 0.0 ? a.s * pow(a.m / m, q) : 0.0;
+  const double sb = b.m > 0.0 ? b.s * pow(b.m / m, q) : 0.0;
+  return MaxPowSum{m, sa + sb};
+}
+__device__ __forceinline__ MaxPowSum mps_shfl_xor(MaxPowSum v, int o) {
+  return MaxPowSum{__shfl_xor(v.m, o, 64), __shfl_xor(v.s, o, 64)};
+}
+
+// One workgroup: each thread folds a strided slice of e into (M, S), then a
+// fixed butterfly inside each wave and a fixed pass over the wave results.
+// stats[0..2] = M S^(1/q) / B, M, S (0 for an empty or error-free batch).
 __global__ __launch_bounds__(kReduceThreads) void loss_reduce_kernel(long long B, double q,
                                                                      const double* __restrict__ e,
                                                                      double* __restrict__ stats) {
-  __shared__ double red[kReduceThreads];
+  __shared__ double wm[kReduceThreads / 64], wsum[kReduceThreads / 64];
   const int tid = threadIdx.x;
-  double m = 0.0;
-  for (long long s = tid; s < B; s += kReduceThreads) {
-    const double x = e[s];
-    m = (x > m || x != x) ? x : m;
+  MaxPowSum acc{0.0, 0.0};
+  for (long long s = tid; s < B; s += kReduceThreads) acc = mps_merge(acc, MaxPowSum{e[s], 1.0}, q);
+  for (int o = 32; o > 0; o >>= 1) acc = mps_merge(acc, mps_shfl_xor(acc, o), q);
+  if ((tid & 63) == 0) {
+    wm[tid >> 6] = acc.m;
+    wsum[tid >> 6] = acc.s;
   }
-  red[tid] = m;
   __syncthreads();
-  for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
-    if (tid < h) {
-      const double x = red[tid + h], y = red[tid];
-      red[tid] = (x > y || x != x) ? x : y;
-    }
-    __syncthreads();
-  }
-  const double M = red[0];
-  __syncthreads();
-  double acc = 0.0;
-  if (M > 0.0 || M != M)
-    for (long long s = tid; s < B; s += kReduceThreads) acc += pow(e[s] / M, q);
-  red[tid] = acc;
-  __syncthreads();
-  for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
-    if (tid < h) red[tid] += red[tid + h];
-    __syncthreads();
-  }
   if (tid == 0) {
-    const double S = red[0];
-    stats[0] = (M > 0.0 || M != M) ? M * pow(S, 1.0 / q) / (double)B : 0.0;
-    stats[1] = M;
-    stats[2] = S;
+    MaxPowSum r{wm[0], wsum[0]};
+    for (int w = 1; w < kReduceThreads / 64; ++w) r = mps_merge(r, MaxPowSum{wm[w], wsum[w]}, q);
+    stats[0] = (r.m > 0.0 || r.m != r.m) ? r.m * pow(r.s, 1.0 / q) / (double)B : 0.0;
+    stats[1] = r.m;
+    stats[2] = r.s;
   }
 }
 
@@ -100,15 +115,13 @@ __global__ __launch_bounds__(kReduceThreads) void loss_reduce_kernel(long long B
 //         = (1/B) S^(1/q - 1) (e_s / M)^(q - 1) * (-1 / nt_s) d||D||_p/dD * f
 // with D = V(target - Cbar); zero where the batch or the sample has no error.
 template <typename T>
-__global__ __launch_bounds__(256) void loss_cotangent_kernel(long long B, double p, double q,
-                                                             const T* __restrict__ Cbar,
-                                                             const T* __restrict__ target,
-                                                             const double* __restrict__ nd,
-                                                             const double* __restrict__ nt,
-                                                             const double* __restrict__ e,
-                                                             const double* __restrict__ stats,
-                                                             T* __restrict__ gC) {
-  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kEntryThreads) void loss_cotangent_kernel(
+    long long B, double p, double q, const T* __restrict__ Cbar, const T* __restrict__ target,
+    const double* __restrict__ nd, const double* __restrict__ nt, const double* __restrict__ e,
+    const double* __restrict__ stats, T* __restrict__ gC) {
+  const int j = threadIdx.x;
+  const int ls = j / 36, k = j - 36 * ls;
+  const long long s = (long long)blockIdx.x * kSamplesPerGroup + ls;
   if (s >= B) return;
   const double M = stats[1], S = stats[2];
   const double ds = nd[s];
@@ -117,18 +130,12 @@ __global__ __launch_bounds__(256) void loss_cotangent_kernel(long long B, double
     coef = pow(S, 1.0 / q - 1.0) * pow(e[s] / M, q - 1.0) / ((double)B * nt[s]);
   else if (M != M || ds != ds)
     coef = M + ds;  // NaN in, NaN out
-  const bool p1 = p == 1.0;
-  const T* c = Cbar + (size_t)s * 36;
-  const T* t = target + (size_t)s * 36;
-  T* g = gC + (size_t)s * 36;
-#pragma unroll
-  for (int k = 0; k < 36; ++k) {
-    const double f = voigt_factor(k);
-    const double d = ((double)t[k] - (double)c[k]) * f;
-    const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
-    const double dn = p1 ? sg : (ds > 0.0 ? pow(fabs(d) / ds, p - 1.0) * sg : 0.0);
-    g[k] = (T)(-coef * dn * f);
-  }
+  const size_t idx = (size_t)s * 36 + k;
+  const double f = voigt_factor(k);
+  const double d = ((double)target[idx] - (double)Cbar[idx]) * f;
+  const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+  const double dn = p == 1.0 ? sg : (ds > 0.0 ? pow(fabs(d) / ds, p - 1.0) * sg : 0.0);
+  gC[idx] = (T)(-coef * dn * f);
 }
 
 struct AmsArgs {
@@ -142,84 +149,85 @@ __device__ __forceinline__ double modulated_rate(const AmsArgs& o, long long m) 
          (o.lr_min + 0.5 * (o.lr_max - o.lr_min) * (1.0 + cos(kPi * (double)m / o.half_period)));
 }
 
-// One workgroup.  Reads sum <v>_+ (fixed order), then (step != 0) takes one
-// AMSGrad step on (v, alpha, beta) with the gradients
+// One workgroup.  Sums <v>_+ (fixed butterfly per wave, then the waves in
+// order), then each thread owns one weight or both angles of one laminate
+// (each angle's gradient needs the other's old value): with take_step it
+// applies the chain
 //   dJ/dv_i     = (gw_i + 2 lambda (sum <v>_+ - 1)) [v_i > 0]
-//   dJ/dalpha_l = gn_l . dn/dalpha,   dJ/dbeta_l = gn_l . dn/dbeta,
-// and finally writes w = <v>_+ and n(alpha, beta) for the next forward.
+//   dJ/dalpha_l = gn_l . dn/dalpha,   dJ/dbeta_l = gn_l . dn/dbeta
+// and one AMSGrad step, and in any case writes w = <v>_+ and n(alpha, beta)
+// of its (new) parameters for the next forward.
 template <typename T>
 __global__ __launch_bounds__(kUpdateThreads) void train_update_kernel(
     int K, T* __restrict__ v, T* __restrict__ alpha, T* __restrict__ beta, T* __restrict__ w,
     T* __restrict__ n, T* __restrict__ state, long long* __restrict__ step,
     const T* __restrict__ gw, const T* __restrict__ gn, AmsArgs o, double* __restrict__ stats,
     int take_step) {
-  __shared__ double red[kUpdateThreads];
+  __shared__ double wsum[kUpdateThreads / 64];
   const int tid = threadIdx.x;
   const int NL = 1 << K, L = NL - 1, NP = NL + 2 * L;
+  const long long t0 = take_step ? *step : 0;  // every read precedes the barrier below
   double acc = 0.0;
   for (int i = tid; i < NL; i += kUpdateThreads) acc += fmax((double)v[i], 0.0);
-  red[tid] = acc;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((tid & 63) == 0) wsum[tid >> 6] = acc;
   __syncthreads();
-  for (int h = kUpdateThreads / 2; h > 0; h >>= 1) {
-    if (tid < h) red[tid] += red[tid + h];
-    __syncthreads();
-  }
-  const double sw = red[0];
-  if (take_step) {
-    const long long t0 = *step;
-    const double pen_g = 2.0 * o.penalty * (sw - 1.0);
-    const double lr = modulated_rate(o, t0 / o.steps_per_epoch);
-    const double t = (double)(t0 + 1);
-    const double step_size = lr / (1.0 - pow(o.beta1, t));
-    const double bc2 = 1.0 - pow(o.beta2, t);
-    T* m1 = state;
-    T* m2 = state + NP;
-    T* mx = state + 2 * NP;
-    // one AMSGrad update of parameter slot i with gradient g
-    auto amsgrad = [&](int i, double th, double g) {
-      const double a1 = o.beta1 * (double)m1[i] + (1.0 - o.beta1) * g;
-      const double a2 = o.beta2 * (double)m2[i] + (1.0 - o.beta2) * g * g;
-      const double ax = fmax((double)mx[i], a2);
-      m1[i] = (T)a1;
-      m2[i] = (T)a2;
-      mx[i] = (T)ax;
-      return th - step_size * a1 / (sqrt(ax / bc2) + o.eps);
-    };
-    // a thread owns a weight, or both angles of one laminate (each angle's
-    // gradient needs the other's old value)
-    for (int i = tid; i < NL + L; i += kUpdateThreads) {
-      if (i < NL) {
-        const double th = (double)v[i];
-        v[i] = (T)amsgrad(i, th, th > 0.0 ? (double)gw[i] + pen_g : 0.0);
-      } else {
-        const int l = i - NL;
-        const double a = (double)alpha[l], b = (double)beta[l];
-        double sa, ca, sb, cb;
+  double sw = 0.0;
+  for (int q = 0; q < kUpdateThreads / 64; ++q) sw += wsum[q];
+  const double pen_g = 2.0 * o.penalty * (sw - 1.0);
+  const double lr = take_step ? modulated_rate(o, t0 / o.steps_per_epoch) : 0.0;
+  const double tn = (double)(t0 + 1);
+  const double step_size = take_step ? lr / (1.0 - pow(o.beta1, tn)) : 0.0;
+  const double bc2 = take_step ? 1.0 - pow(o.beta2, tn) : 1.0;
+  T* m1 = state;
+  T* m2 = state + NP;
+  T* mx = state + 2 * NP;
+  // one AMSGrad update of parameter slot i with gradient g
+  auto amsgrad = [&](int i, double th, double g) {
+    const double a1 = o.beta1 * (double)m1[i] + (1.0 - o.beta1) * g;
+    const double a2 = o.beta2 * (double)m2[i] + (1.0 - o.beta2) * g * g;
+    const double ax = fmax((double)mx[i], a2);
+    m1[i] = (T)a1;
+    m2[i] = (T)a2;
+    mx[i] = (T)ax;
+    return th - step_size * a1 / (sqrt(ax / bc2) + o.eps);
+  };
+  for (int i = tid; i < NL + L; i += kUpdateThreads) {
+    if (i < NL) {
+      double th = (double)v[i];
+      if (take_step) {
+        th = (double)(T)amsgrad(i, th, th > 0.0 ? (double)gw[i] + pen_g : 0.0);
+        v[i] = (T)th;
+      }
+      w[i] = (T)fmax(th, 0.0);
+    } else {
+      const int l = i - NL;
+      double a = (double)alpha[l], b = (double)beta[l];
+      double sa, ca, sb, cb;
+      sincos(a, &sa, &ca);
+      sincos(b, &sb, &cb);
+      if (take_step) {
+        const double g0 = (double)gn[3 * l], g1 = (double)gn[3 * l + 1];
+        const double g2 = (double)gn[3 * l + 2];
+        a = (double)(T)amsgrad(NL + l, a, g0 * ca * cb + g1 * ca * sb - g2 * sa);
+        b = (double)(T)amsgrad(NL + L + l, b, -g0 * sa * sb + g1 * sa * cb);
+        alpha[l] = (T)a;
+        beta[l] = (T)b;
         sincos(a, &sa, &ca);
         sincos(b, &sb, &cb);
-        const double g0 = (double)gn[3 * l], g1 = (double)gn[3 * l + 1], g2 = (double)gn[3 * l + 2];
-        alpha[l] = (T)amsgrad(NL + l, a, g0 * ca * cb + g1 * ca * sb - g2 * sa);
-        beta[l] = (T)amsgrad(NL + L + l, b, -g0 * sa * sb + g1 * sa * cb);
       }
+      n[3 * l] = (T)(sa * cb);
+      n[3 * l + 1] = (T)(sa * sb);
+      n[3 * l + 2] = (T)ca;
     }
-    if (tid == 0) {
-      const double pen = o.penalty * (sw - 1.0) * (sw - 1.0);
-      stats[3] = stats[0] + pen;
-      stats[4] = pen;
-      stats[5] = lr;
-      stats[6] = sw;
-    }
-    __syncthreads();  // every read of *step and of the old parameters is done
-    if (tid == 0) *step = t0 + 1;
   }
-  for (int i = tid; i < NL; i += kUpdateThreads) w[i] = (T)fmax((double)v[i], 0.0);
-  for (int l = tid; l < L; l += kUpdateThreads) {
-    double sa, ca, sb, cb;
-    sincos((double)alpha[l], &sa, &ca);
-    sincos((double)beta[l], &sb, &cb);
-    n[3 * l] = (T)(sa * cb);
-    n[3 * l + 1] = (T)(sa * sb);
-    n[3 * l + 2] = (T)ca;
+  if (take_step && tid == 0) {
+    const double pen = o.penalty * (sw - 1.0) * (sw - 1.0);
+    stats[3] = stats[0] + pen;
+    stats[4] = pen;
+    stats[5] = lr;
+    stats[6] = sw;
+    *step = t0 + 1;
   }
 }
 
@@ -309,14 +317,16 @@ int loss_t(long long B, double p, double q, const void* Cbar, const void* target
   double* nt = scratch + B;
   double* e = scratch + 2 * B;
   if (B > 0)
-    hipLaunchKernelGGL((loss_norms_kernel<T>), dim3(blocks_for(B, 256)), dim3(256), 0, s, B, p,
-                       (const T*)Cbar, (const T*)target, nd, nt, e, (T*)e_out);
+    hipLaunchKernelGGL((loss_norms_kernel<T>), dim3(blocks_for(B, kSamplesPerGroup)),
+                       dim3(kEntryThreads), 0, s, B, p, (const T*)Cbar, (const T*)target, nd, nt,
+                       e, (T*)e_out);
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, B, q,
                      (const double*)e, stats);
   if (B > 0)
-    hipLaunchKernelGGL((loss_cotangent_kernel<T>), dim3(blocks_for(B, 256)), dim3(256), 0, s, B,
-                       p, q, (const T*)Cbar, (const T*)target, (const double*)nd,
-                       (const double*)nt, (const double*)e, (const double*)stats, (T*)gCbar);
+    hipLaunchKernelGGL((loss_cotangent_kernel<T>), dim3(blocks_for(B, kSamplesPerGroup)),
+                       dim3(kEntryThreads), 0, s, B, p, q, (const T*)Cbar, (const T*)target,
+                       (const double*)nd, (const double*)nt, (const double*)e,
+                       (const double*)stats, (T*)gCbar);
   return (int)hipGetLastError();
 }
 

@@ -326,3 +326,109 @@ def test_training_full_size_step():
                        np.concatenate([gv, ga, gb]), z, z, z, 1, opts.lr_max)
     got = np.concatenate([P.v.cpu().numpy(), P.alpha.cpu().numpy(), P.beta.cpu().numpy()])
     assert rel(got, th) < 1e-12
+
+
+def dead_weights(K, seed):
+    """Leaf weights with zeros: one leaf beside a live sibling, a whole sibling
+    pair, and (K >= 4) a whole depth-2 subtree."""
+    rs = S.streams(seed)
+    net = S.random_dmn(rs["dmn"], K, 0.3)
+    w = net.w.copy()
+    w[1] = 0.0
+    w[4:6] = 0.0
+    if K >= 4:
+        w[8:12] = 0.0
+    return w, net.normals, rs
+
+
+@pytest.mark.parametrize("K,B", [(3, 9), (4, 37), (8, 33)])
+def test_linear_map_compresses_dead_subtrees(K, B):
+    from oracle.compression import dmn_linear_compressed
+    from paper_2103_08253_amd import dmn_homogenize_linear, error_word
+    say(f"linear map with dead subtrees K={K} B={B}")
+    w, nrm, rs = dead_weights(K, 70 + K)
+    C1, C2 = S.random_spd(rs["stiffness"], B), S.random_spd(rs["stiffness"], B)
+    Cb, ws = dmn_homogenize_linear(tt(w), tt(nrm), tt(C1), tt(C2))
+    torch.cuda.synchronize()
+    assert error_word(ws) == 0
+    ref = dmn_linear_compressed(K, w, nrm, C1, C2)
+    assert rel(Cb.cpu().numpy(), ref) < 1e-10
+
+
+def test_linear_backward_with_dead_subtrees():
+    """gn of every laminate and gw of every leaf with weight against complex
+    steps through the oracle's compressed map."""
+    from oracle.compression import dmn_linear_compressed
+    from paper_2103_08253_amd import dmn_homogenize_backward, error_word
+    K, B = 4, 11
+    say(f"linear backward with dead subtrees K={K} B={B}")
+    w, nrm, rs = dead_weights(K, 75)
+    C1, C2 = S.random_spd(rs["stiffness"], B), S.random_spd(rs["stiffness"], B)
+    G = rs["cotangent"].standard_normal((B, 6, 6))
+    gw, gn, _, _, ws = dmn_homogenize_backward(tt(w), tt(nrm), tt(C1), tt(C2), tt(G))
+    torch.cuda.synchronize()
+    assert error_word(ws) == 0
+    h = 1e-30
+    J = lambda ww, nn: np.sum(G * dmn_linear_compressed(K, ww, nn, C1, C2))
+    gn_ref = np.zeros_like(nrm)
+    for p in range(2 ** K - 1):
+        for c in range(3):
+            nc = nrm.astype(complex)
+            nc[p, c] += 1j * h
+            gn_ref[p, c] = np.imag(J(w, nc)) / h
+    # the map depends on n only through its direction: compare tangential parts
+    tang = lambda g: g - np.sum(g * nrm, axis=1, keepdims=True) * nrm
+    assert rel(tang(gn.cpu().numpy()), tang(gn_ref)) < 1e-9
+    gw_got = gw.cpu().numpy()
+    assert np.all(np.isfinite(gw_got))
+    for j in range(2 ** K):
+        if w[j] == 0.0:
+            continue     # removed leaves: no derivative of the compressed map to compare
+        wc = w.astype(complex)
+        wc[j] += 1j * h
+        ref = np.imag(J(wc, nrm)) / h
+        assert abs(gw_got[j] - ref) <= 1e-9 * np.abs(gw_got).max(), j
+
+
+def test_training_step_with_dead_subtree_matches_complex_step():
+    from paper_2103_08253_amd import AmsgradOpts, TrainParams, dmn_homogenize_backward, \
+        dmn_homogenize_linear, dmn_training_loss, dmn_training_update
+    K, B, lam = 3, 16, 10.0
+    say(f"training step with a dead sibling pair K={K} B={B}")
+    C1, C2, truth, v, alpha, beta = training_case(K, B, 54)
+    v[2], v[3] = -0.01, -0.02   # a dead sibling pair
+    v[6] = 0.0                  # a zero leaf beside a live sibling
+    Tt = dmn_linear(K, truth.w, truth.normals, C1, C2)
+    P = TrainParams.create(tt(v), tt(alpha), tt(beta))
+    C1t, C2t, Tt_t = tt(C1), tt(C2), tt(Tt)
+    Cbar, wsf = dmn_homogenize_linear(P.w, P.n, C1t, C2t)
+    gC, stats, _ = dmn_training_loss(Cbar, Tt_t, 1.0, 10.0)
+    gw, gn, _, _, wsb = dmn_homogenize_backward(P.w, P.n, C1t, C2t, gC)
+    eps, lr = 1e6, 1e3
+    opts = AmsgradOpts(lr_min=lr, lr_max=lr, lr_decay=1.0, beta1=0.0, beta2=0.0, eps=eps,
+                       penalty=lam)
+    dmn_training_update(P, gw, gn, opts, stats)
+    torch.cuda.synchronize()
+    from paper_2103_08253_amd import error_word
+    assert error_word(wsf) == 0 and error_word(wsb) == 0
+    th0 = np.concatenate([v, alpha, beta])
+    th1 = np.concatenate([P.v.cpu().numpy(), P.alpha.cpu().numpy(), P.beta.cpu().numpy()])
+    d = th0 - th1
+    g_gpu = d * eps / (lr - np.abs(d))
+    ref = T.objective_gradient(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
+    g_ref = np.concatenate([ref["gv"], ref["galpha"], ref["gbeta"]])
+    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    assert rel(g_gpu, g_ref) < 1e-8
+    J = T.objective(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
+    assert abs(stats.cpu().numpy()[3] - J) <= 1e-10 * J
+
+
+def test_gauss_point_update_rejects_dead_subtrees():
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    say("Gauss-point update with a dead subtree")
+    w, nrm, rs = dead_weights(3, 76)
+    E = tt(1e-3 * rs["direction"].standard_normal((5, 6)))
+    g = PointGroup.allocate(tt(w), tt(nrm), E)
+    dmn_update_gauss_points([g], S.FIBER, S.MATRIX)
+    torch.cuda.synchronize()
+    assert (g.status == 5).all()
