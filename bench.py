@@ -458,9 +458,12 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         j0 = float(gstep.stats[3].item())
         reps = 50
         ms = _event_ms(gstep.replay, reps) / reps
+        hist = {1: j0, 51: float(gstep.stats[3].item())}
+        for _ in range(1950 if nb == 32 else 450):
+            gstep.replay()
+        hist[int(Pt.step.item())] = float(gstep.stats[3].item())
         train[nb] = dict(ms_per_step=ms, samples_per_s=nb / (ms * 1e-3),
-                         objective_first=j0, objective_after=float(gstep.stats[3].item()),
-                         steps_taken=int(Pt.step.item()))
+                         objective_at_step=hist)
     u = torch.rand((B, 8), dtype=torch.float64, device=dev)
     dmn_sample_stiffness(u)
     torch.cuda.synchronize()

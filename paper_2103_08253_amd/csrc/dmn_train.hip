@@ -69,45 +69,42 @@ __global__ __launch_bounds__(kEntryThreads) void loss_norms_kernel(
   }
 }
 
-// Running (max M, sum of (x / M)^q) pair; merging rescales the smaller part.
-// NaN anywhere makes both NaN.
-struct MaxPowSum {
-  double m, s;
-};
-__device__ __forceinline__ MaxPowSum mps_merge(MaxPowSum a, MaxPowSum b, double q) {
-  if (a.m != a.m || b.m != b.m) return MaxPowSum{__builtin_nan(""), __builtin_nan("")};
-  const double m = fmax(a.m, b.m);
-  if (!(m > 0.0)) return MaxPowSum{0.0, 0.0};
-  const double sa = a.m > 0.0 ? a.s * pow(a.m / m, q) : 0.0;
-  const double sb = b.m > 0.0 ? b.s * pow(b.m / m, q) : 0.0;
-  return MaxPowSum{m, sa + sb};
-}
-__device__ __forceinline__ MaxPowSum mps_shfl_xor(MaxPowSum v, int o) {
-  return MaxPowSum{__shfl_xor(v.m, o, 64), __shfl_xor(v.s, o, 64)};
+// NaN-propagating maximum
+__device__ __forceinline__ double nan_max(double a, double b) {
+  return (a != a || b != b) ? __builtin_nan("") : fmax(a, b);
 }
 
-// One workgroup: each thread folds a strided slice of e into (M, S), then a
-// fixed butterfly inside each wave and a fixed pass over the wave results.
-// stats[0..2] = M S^(1/q) / B, M, S (0 for an empty or error-free batch).
+// One workgroup, two passes over e: M = max e (NaN propagates), then
+// S = sum (e / M)^q; each pass folds a strided slice per thread, combines a
+// wave with a fixed butterfly and the waves in order, so the sums do not
+// depend on scheduling.  stats[0..2] = M S^(1/q) / B, M, S (0 for an empty or
+// error-free batch).
 __global__ __launch_bounds__(kReduceThreads) void loss_reduce_kernel(long long B, double q,
                                                                      const double* __restrict__ e,
                                                                      double* __restrict__ stats) {
-  __shared__ double wm[kReduceThreads / 64], wsum[kReduceThreads / 64];
+  constexpr int kWaves = kReduceThreads / 64;
+  __shared__ double wmax[kWaves], wsum[kWaves];
   const int tid = threadIdx.x;
-  MaxPowSum acc{0.0, 0.0};
-  for (long long s = tid; s < B; s += kReduceThreads) acc = mps_merge(acc, MaxPowSum{e[s], 1.0}, q);
-  for (int o = 32; o > 0; o >>= 1) acc = mps_merge(acc, mps_shfl_xor(acc, o), q);
-  if ((tid & 63) == 0) {
-    wm[tid >> 6] = acc.m;
-    wsum[tid >> 6] = acc.s;
-  }
+  double m = 0.0;
+  for (long long s = tid; s < B; s += kReduceThreads) m = nan_max(m, e[s]);
+  for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));
+  if ((tid & 63) == 0) wmax[tid >> 6] = m;
+  __syncthreads();
+  double M = wmax[0];
+  for (int w = 1; w < kWaves; ++w) M = nan_max(M, wmax[w]);
+  const bool any = M > 0.0 || M != M;
+  double acc = 0.0;
+  if (any)
+    for (long long s = tid; s < B; s += kReduceThreads) acc += pow(e[s] / M, q);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((tid & 63) == 0) wsum[tid >> 6] = acc;
   __syncthreads();
   if (tid == 0) {
-    MaxPowSum r{wm[0], wsum[0]};
-    for (int w = 1; w < kReduceThreads / 64; ++w) r = mps_merge(r, MaxPowSum{wm[w], wsum[w]}, q);
-    stats[0] = (r.m > 0.0 || r.m != r.m) ? r.m * pow(r.s, 1.0 / q) / (double)B : 0.0;
-    stats[1] = r.m;
-    stats[2] = r.s;
+    double S = 0.0;
+    for (int w = 0; w < kWaves; ++w) S += wsum[w];
+    stats[0] = any ? M * pow(S, 1.0 / q) / (double)B : 0.0;
+    stats[1] = M;
+    stats[2] = S;
   }
 }
 
