@@ -468,6 +468,22 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
     dmn_sample_stiffness(u)
     torch.cuda.synchronize()
     samp_ms = _event_ms(lambda: dmn_sample_stiffness(u), 5) / 5
+    # batch sweep of the captured linear forward + backward (the training step's
+    # kernels) beyond the 4,096-sample workload
+    from paper_2103_08253_amd import LinearStepGraph
+    sweep = {}
+    for nb in (4096, 16384, 65536, 262144):
+        tws = S.config3(batch=nb)
+        c1s = torch.tensor(tws.C1, device=dev)
+        c2s = torch.tensor(tws.C2, device=dev)
+        gcs = torch.tensor(S.streams(3)["cotangent"].standard_normal((nb, 6, 6)), device=dev)
+        lg = LinearStepGraph(wt, nt, c1s, c2s, gcs)
+        lg.replay()
+        torch.cuda.synchronize()
+        ms = _event_ms(lg.replay, 5) / 5
+        sweep[nb] = dict(ms=ms, samples_per_s=nb / (ms * 1e-3))
+        del lg, c1s, c2s, gcs
+    out["train_fwd_bwd_batch_sweep"] = sweep
     out["training_objective_step_graph"] = dict(
         depth=8, p=1.0, q=10.0, optimiser="AMSGrad, modulated learning rate",
         batch_4096=train[B], batch_32=train[32],

@@ -432,3 +432,58 @@ def test_gauss_point_update_rejects_dead_subtrees():
     dmn_update_gauss_points([g], S.FIBER, S.MATRIX)
     torch.cuda.synchronize()
     assert (g.status == 5).all()
+
+
+@pytest.mark.parametrize("K", [1, 10])
+def test_training_update_extreme_depths(K):
+    """Depth 1 (one laminate) and depth 10 (3,070 parameters, several per
+    thread): the update against the oracle's chain and AMSGrad."""
+    from paper_2103_08253_amd import AmsgradOpts, TrainParams, dmn_training_update
+    from paper_2103_08253_amd.training import new_stats
+    NL, L = 2 ** K, 2 ** K - 1
+    say(f"training update K={K}")
+    rng = np.random.default_rng(90 + K)
+    v = rng.uniform(-0.2, 1.0, NL) / NL
+    alpha, beta = rng.uniform(0, 2 * np.pi, L), rng.uniform(0, 2 * np.pi, L)
+    gw, gn = rng.normal(0, 1e-2, NL), rng.normal(0, 1e-2, (L, 3))
+    P = TrainParams.create(tt(v), tt(alpha), tt(beta))
+    stats = new_stats(dev())
+    opts = AmsgradOpts(penalty=5.0)
+    dmn_training_update(P, tt(gw), tt(gn), opts, stats)
+    torch.cuda.synchronize()
+    gv, ga, gb = chain_gradient(v, alpha, beta, gw, gn, opts.penalty)
+    z = np.zeros(NL + 2 * L)
+    th, *_ = T.amsgrad(np.concatenate([v, alpha, beta]), np.concatenate([gv, ga, gb]), z, z, z,
+                       1, opts.lr_max)
+    got = np.concatenate([P.v.cpu().numpy(), P.alpha.cpu().numpy(), P.beta.cpu().numpy()])
+    assert rel(got, th) < 1e-12
+    assert rel(P.n.cpu().numpy(), normals_from_angles(th[NL:NL + L], th[NL + L:])) < 1e-12
+
+
+def test_training_step_f32_gradient():
+    """FP32 storage and FP32 linear map, FP64 sums: the step's implied gradient
+    against the FP64 oracle within 1e-3."""
+    from paper_2103_08253_amd import AmsgradOpts, TrainParams, TrainingStepGraph
+    K, B, lam = 4, 64, 10.0
+    say(f"training step f32 K={K} B={B}")
+    C1, C2, truth, v, alpha, beta = training_case(K, B, 55)
+    f32 = lambda x: tt(x, torch.float32)
+    r = lambda x: f32(x).double().cpu().numpy()
+    C1, C2, v, alpha, beta = r(C1), r(C2), r(v), r(alpha), r(beta)
+    Tt = r(dmn_linear(K, truth.w, truth.normals, C1, C2))
+    eps, lr = 1e6, 1e5   # steps of 0.1 g, well above the FP32 spacing of the parameters
+    opts = AmsgradOpts(lr_min=lr, lr_max=lr, lr_decay=1.0, beta1=0.0, beta2=0.0, eps=eps,
+                       penalty=lam)
+    P = TrainParams.create(f32(v), f32(alpha), f32(beta))
+    g = TrainingStepGraph(P, f32(C1), f32(C2), f32(Tt), opts=opts)
+    g.replay()
+    torch.cuda.synchronize()
+    th0 = np.concatenate([v, alpha, beta])
+    th1 = np.concatenate([P.v.double().cpu().numpy(), P.alpha.double().cpu().numpy(),
+                          P.beta.double().cpu().numpy()])
+    d = th0 - th1
+    g_gpu = d * eps / (lr - np.abs(d))
+    ref = T.objective_gradient(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
+    g_ref = np.concatenate([ref["gv"], ref["galpha"], ref["gbeta"]])
+    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    assert rel(g_gpu, g_ref) < 1e-3
