@@ -109,6 +109,39 @@ def objective_gradient(K, v, alpha, beta, C1, C2, T, p=1.0, q=10.0, lam=1e3):
     return dict(gv=gv, galpha=ga, gbeta=gb)
 
 
+def objective_oriented(K, v, P, Q, kind, lam, C1, C2, T, p=1.0, q=10.0, penalty_lam=1e3):
+    """J(v, P, Q) with orientation-interpolated normals (Sec. 2.3): sample s
+    sees the normals of its own orientation lam[s] = (l1, l2), from the angle
+    coefficients P, Q [L, M]; the compressed tree as in ``objective``."""
+    from .orientation import interpolated_normals
+    w = macaulay(v)
+    Cbar = np.stack([dmn_linear_compressed(K, w, interpolated_normals(P, Q, l[0], l[1], kind),
+                                           C1[s:s + 1], C2[s:s + 1])[0]
+                     for s, l in enumerate(lam)])
+    return data_term(sample_errors(Cbar, T, p), q) + penalty(v, penalty_lam)
+
+
+def objective_oriented_gradient(K, v, P, Q, kind, lam, C1, C2, T, p=1.0, q=10.0,
+                                penalty_lam=1e3):
+    """Complex-step gradient of ``objective_oriented``: dict(gv, gP, gQ)."""
+    f = lambda vv, PP, QQ: objective_oriented(K, vv, PP, QQ, kind, lam, C1, C2, T, p, q,
+                                              penalty_lam)
+    gv = np.zeros(len(v))
+    for i in range(len(v)):
+        vc = np.asarray(v, dtype=complex).copy()
+        vc[i] += 1j * H
+        gv[i] = np.imag(f(vc, P, Q)) / H
+    gP, gQ = np.zeros(np.shape(P)), np.zeros(np.shape(Q))
+    for idx in np.ndindex(*np.shape(P)):
+        Pc = np.asarray(P, dtype=complex).copy()
+        Pc[idx] += 1j * H
+        gP[idx] = np.imag(f(v, Pc, Q)) / H
+        Qc = np.asarray(Q, dtype=complex).copy()
+        Qc[idx] += 1j * H
+        gQ[idx] = np.imag(f(v, P, Qc)) / H
+    return dict(gv=gv, gP=gP, gQ=gQ)
+
+
 def data_cotangent(Cbar, T, p=1.0, q=10.0):
     """d(data term)/d(Cbar) entry by entry [B, 6, 6], by complex steps."""
     B = len(Cbar)

@@ -325,3 +325,61 @@ def hysteresis_workload(n_points: int = 65536, n_steps: int = 80, amplitude: flo
     case = np.arange(n_points) % 6
     E = (amplitude * hysteresis_factor(n_steps))[:, None, None] * UNIAXIAL_DIRECTIONS[case][None]
     return net, lam, E, case
+
+
+# ---------------------------------------------------------------- training on orientations
+
+TRIANGLE_VERTICES = ((1.0, 0.0), (1.0 / 3.0, 1.0 / 3.0), (0.5, 0.5))
+
+
+def orientation_discretization(level: int) -> np.ndarray:
+    """Sampling points of the fibre-orientation triangle after `level`
+    subdivisions into four self-similar triangles each (Sec. 4.3): the
+    vertices of all sub-triangles plus their centres, [n, 2] as (l1, l2)."""
+    tris = [tuple(np.array(v) for v in TRIANGLE_VERTICES)]
+    for _ in range(level):
+        nxt = []
+        for a, b, c in tris:
+            ab, bc, ca = (a + b) / 2, (b + c) / 2, (c + a) / 2
+            nxt += [(a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)]
+        tris = nxt
+    pts = {}
+    for t in tris:
+        for p in list(t) + [(t[0] + t[1] + t[2]) / 3]:
+            pts[tuple(np.round(p, 12))] = p
+    return np.array(sorted(pts.values(), key=lambda p: (p[0], p[1])))
+
+
+@dataclass
+class OrientedTrainingWorkload:
+    """Training batch over a discrete set of fibre orientations: samples are
+    assigned to the orientations cyclically (Sec. 4.5) and stored grouped by
+    orientation; `offsets[k]:offsets[k+1]` are the samples of orientation k."""
+    C1: np.ndarray
+    C2: np.ndarray
+    lam: np.ndarray          # [G, 2] orientations
+    offsets: np.ndarray      # [G + 1]
+    truth: InterpolatedDmn
+    v0: np.ndarray
+    p0: np.ndarray
+    q0: np.ndarray
+
+
+def oriented_training_workload(batch: int = 4096, depth: int = 8, level: int = 2,
+                               kind: str = "linear") -> OrientedTrainingWorkload:
+    rs = streams(7)
+    C1 = random_spd(rs["stiffness"], batch)
+    C2 = random_spd(rs["stiffness"], batch)
+    lam = orientation_discretization(level)
+    G = len(lam)
+    group = np.arange(batch) % G                      # cyclic assignment
+    order = np.argsort(group, kind="stable")
+    counts = np.bincount(group, minlength=G)
+    offsets = np.concatenate([[0], np.cumsum(counts)])
+    truth = interpolated_dmn(rs["ground_truth"], depth, 0.25, kind)
+    n_leaves, M = 2 ** depth, SHAPE_COUNTS[kind]
+    v0 = rs["init"].uniform(0.0, 1.0, n_leaves)
+    v0 = v0 / v0.sum()
+    p0 = rs["init"].uniform(0.0, 2.0 * np.pi, (n_leaves - 1, M))
+    q0 = rs["init"].uniform(0.0, 2.0 * np.pi, (n_leaves - 1, M))
+    return OrientedTrainingWorkload(C1[order], C2[order], lam, offsets, truth, v0, p0, q0)

@@ -258,3 +258,70 @@ def test_objective_with_a_dead_subtree_matches_differences():
         p = lam_pos(K, k, i)
         assert g["galpha"][p] == 0.0 and g["gbeta"][p] == 0.0
     assert g["gv"][2] == 0.0 and g["gv"][3] == 0.0
+
+
+def test_orientation_discretization_counts_and_hierarchy():
+    """Four, ten and 31 sampling points after 0, 1, 2 subdivisions (Sec. 4.3),
+    each level containing the previous one, all inside the triangle."""
+    from oracle.orientation import in_triangle
+    prev = None
+    for level, n in ((0, 4), (1, 10), (2, 31)):
+        pts = S.orientation_discretization(level)
+        assert len(pts) == n
+        assert all(in_triangle(l1, l2, 1e-12) for l1, l2 in pts)
+        if prev is not None:
+            for p in prev:
+                assert np.min(np.abs(pts - p).sum(axis=1)) < 1e-12
+        prev = pts
+
+
+def _oriented_case(K=2, B=4, kind="trilinear", seed=81):
+    rs = S.streams(seed)
+    C1 = S.random_spd(rs["stiffness"], B)
+    C2 = S.random_spd(rs["stiffness"], B)
+    truth = S.interpolated_dmn(rs["ground_truth"], K, 0.3, kind)
+    lam = S.orientation_discretization(1)[[0, 4, 7, 9][:B]]
+    v = rs["init"].uniform(0.2, 1.0, 2 ** K)
+    v = 1.1 * v / v.sum()
+    M = S.SHAPE_COUNTS[kind]
+    P = rs["init"].uniform(0.0, 2 * np.pi, (2 ** K - 1, M))
+    Q = rs["init"].uniform(0.0, 2 * np.pi, (2 ** K - 1, M))
+    from oracle.orientation import oriented_linear
+    Tt = oriented_linear(K, truth.w, truth.p, truth.q, kind, lam, C1, C2)
+    return C1, C2, lam, v, P, Q, Tt
+
+
+def test_oriented_objective_reduces_to_fixed_normals():
+    """Equal coefficients across the shape functions give every orientation
+    the same angles (partition of unity): the oriented objective and its
+    coefficient gradients reduce to the fixed-normal ones (summed over j)."""
+    K, kind = 2, "quadratic"
+    C1, C2, lam, v, P, Q, Tt = _oriented_case(K=K, kind=kind)
+    M = S.SHAPE_COUNTS[kind]
+    a, b = P[:, 0], Q[:, 0]
+    Pc, Qc = np.repeat(a[:, None], M, 1), np.repeat(b[:, None], M, 1)
+    J1 = T.objective_oriented(K, v, Pc, Qc, kind, lam, C1, C2, Tt, 1.0, 10.0, 10.0)
+    J0 = T.objective(K, v, a, b, C1, C2, Tt, 1.0, 10.0, 10.0)
+    assert abs(J1 - J0) <= 1e-12 * abs(J0)
+    g1 = T.objective_oriented_gradient(K, v, Pc, Qc, kind, lam, C1, C2, Tt, 1.0, 10.0, 10.0)
+    g0 = T.objective_gradient(K, v, a, b, C1, C2, Tt, 1.0, 10.0, 10.0)
+    assert np.allclose(g1["gv"], g0["gv"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(g1["gP"].sum(axis=1), g0["galpha"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(g1["gQ"].sum(axis=1), g0["gbeta"], rtol=1e-10, atol=1e-12)
+
+
+def test_oriented_objective_gradient_matches_differences():
+    K, kind = 2, "linear"
+    C1, C2, lam, v, P, Q, Tt = _oriented_case(K=K, kind=kind, seed=82)
+    g = T.objective_oriented_gradient(K, v, P, Q, kind, lam, C1, C2, Tt, 1.0, 10.0, 10.0)
+    f = lambda vv, PP, QQ: T.objective_oriented(K, vv, PP, QQ, kind, lam, C1, C2, Tt, 1.0,
+                                                10.0, 10.0)
+    for i in range(len(v)):
+        fd = _richardson(lambda x: f(x, P, Q), v, i, 1e-4)
+        assert abs(g["gv"][i] - fd) <= 1e-7 * max(1.0, abs(fd)), i
+    for idx in np.ndindex(*P.shape):
+        flat = np.ravel_multi_index(idx, P.shape)
+        fdp = _richardson(lambda x: f(v, x.reshape(P.shape), Q), P.ravel(), flat, 1e-4)
+        fdq = _richardson(lambda x: f(v, P, x.reshape(Q.shape)), Q.ravel(), flat, 1e-4)
+        assert abs(g["gP"][idx] - fdp) <= 1e-7 * max(1.0, abs(fdp)), idx
+        assert abs(g["gQ"][idx] - fdq) <= 1e-7 * max(1.0, abs(fdq)), idx
