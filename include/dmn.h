@@ -410,6 +410,59 @@ int dmn_training_update(const dmn_train_params* params, int prec, const void* gw
  * the first forward). */
 int dmn_training_refresh(const dmn_train_params* params, int prec, hipStream_t stream);
 
+/* Training over a discrete set of G fibre orientations (Sec. 2.3, the
+ * paper's identification of an orientation-interpolated DMN, Sec. 4.5):
+ * samples of orientation k see the normals n_k, so a step evaluates the
+ * fixed-normal dmn_homogenize_linear / dmn_homogenize_backward once per
+ * orientation group with n_k from dmn_orientation_group_normals, takes the
+ * objective over the whole batch with dmn_training_loss, chains the groups'
+ * gw, gn to the angle coefficients with dmn_orientation_group_chain and
+ * updates (v, p, q) with dmn_training_update_oriented. */
+
+/* n [G][L][3]: for orientation lam[k] = (l1, l2) (lam [G][2]) and angle
+ * coefficients p, q [L][M] (M from ori_shape, see dmn_net), laminate l gets
+ * alpha = p_l . s(lam_k), beta = q_l . s(lam_k) and
+ * n = (sin alpha cos beta, sin alpha sin beta, cos alpha).  prec DMN_F64 or
+ * DMN_F32 for every array. */
+int dmn_orientation_group_normals(int32_t depth, int32_t ori_shape, int32_t G, int prec,
+                                  const void* p, const void* q, const void* lam, void* n,
+                                  hipStream_t stream);
+
+/* From the groups' VJPs gw_groups [G][2^K] and gn_groups [G][L][3] (of
+ * dmn_homogenize_backward at n_k): gw [2^K] = sum_k gw_groups[k] and
+ * gpq [L][2][M]: row l holds d/dp_l (M values) then d/dq_l, through
+ * n_k(p, q) and the shape functions at lam_k.  Sums over k in order. */
+int dmn_orientation_group_chain(int32_t depth, int32_t ori_shape, int32_t G, int prec,
+                                const void* p, const void* q, const void* lam,
+                                const void* gw_groups, const void* gn_groups, void* gw,
+                                void* gpq, hipStream_t stream);
+
+/* Trainable parameters of an orientation-interpolated DMN: unconstrained
+ * weights v [2^K] (w = <v>_+), angle coefficients p, q [L][M]. */
+typedef struct dmn_train_params_oriented {
+  int32_t depth;
+  int32_t ori_shape; /* DMN_ORI_LINEAR, _TRILINEAR or _QUADRATIC */
+  void* v;           /* [2^K], updated in place */
+  void* p;           /* [L][M], updated in place */
+  void* q;           /* [L][M], updated in place */
+  void* w;           /* [2^K] out: <v>_+ of the current v */
+  void* state;       /* [3][2^K + 2 L M]: first moments, second moments, their
+                        running maxima, for the slots v, p, q in that order;
+                        zero before the first update */
+  int64_t* step;     /* device counter of updates taken */
+} dmn_train_params_oriented;
+
+/* One optimiser step as dmn_training_update, with the coefficient gradients
+ * gpq [L][2][M] of dmn_orientation_group_chain in place of the angle chain;
+ * writes stats[3..6] and refreshes w. */
+int dmn_training_update_oriented(const dmn_train_params_oriented* params, int prec,
+                                 const void* gw, const void* gpq, const dmn_amsgrad_opts* opts,
+                                 double* stats, hipStream_t stream);
+
+/* w = <v>_+ of params without a step. */
+int dmn_training_refresh_oriented(const dmn_train_params_oriented* params, int prec,
+                                  hipStream_t stream);
+
 /* Stiffness sampler of Sec. 4.4: for each of B points u [B][8] (FP64) of
  * the unit cube, the eight parameters (a, e1, e2, e3, beta, theta, psi, phi)
  * are a = u0, e_i = -3 + 6 u_i, beta = 2 pi u4, theta in [0, pi] with

@@ -13,6 +13,7 @@ from .api import (AdjointGroup, Orientation, PointGroup, dmn_homogenize_backward
                   error_word, workspace)
 from ._lib import DmnError, STATUS  # noqa: F401
 from .graph import LinearStepGraph, LoadStepGraph  # noqa: F401
-from .training import (AmsgradOpts, TrainParams, TrainingStepGraph,  # noqa: F401
-                       dmn_sample_stiffness, dmn_training_loss, dmn_training_refresh,
-                       dmn_training_update)
+from .training import (AmsgradOpts, OrientedTrainingStepGraph, OrientedTrainParams,  # noqa: F401
+                       TrainingStepGraph, TrainParams, dmn_orientation_group_chain,
+                       dmn_orientation_group_normals, dmn_sample_stiffness, dmn_training_loss,
+                       dmn_training_refresh, dmn_training_update, dmn_training_update_oriented)

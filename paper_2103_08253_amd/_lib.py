@@ -75,6 +75,12 @@ class DmnTrainParams(ctypes.Structure):
                 ("state", ctypes.c_void_p), ("step", ctypes.c_void_p)]
 
 
+class DmnTrainParamsOriented(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("ori_shape", ctypes.c_int32), ("v", ctypes.c_void_p),
+                ("p", ctypes.c_void_p), ("q", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("state", ctypes.c_void_p), ("step", ctypes.c_void_p)]
+
+
 DMN_TRAIN_STATS = 8
 
 # exported functions and their signatures
@@ -90,6 +96,23 @@ _SIGS = {
                                            ctypes.c_void_p]),
     "dmn_training_refresh": (ctypes.c_int, [ctypes.POINTER(DmnTrainParams), ctypes.c_int,
                                             ctypes.c_void_p]),
+    "dmn_orientation_group_normals": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32,
+                                                     ctypes.c_int32, ctypes.c_int,
+                                                     ctypes.c_void_p, ctypes.c_void_p,
+                                                     ctypes.c_void_p, ctypes.c_void_p,
+                                                     ctypes.c_void_p]),
+    "dmn_orientation_group_chain": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "dmn_training_update_oriented": (ctypes.c_int, [ctypes.POINTER(DmnTrainParamsOriented),
+                                                    ctypes.c_int, ctypes.c_void_p,
+                                                    ctypes.c_void_p,
+                                                    ctypes.POINTER(DmnAmsgradOpts),
+                                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "dmn_training_refresh_oriented": (ctypes.c_int, [ctypes.POINTER(DmnTrainParamsOriented),
+                                                     ctypes.c_int, ctypes.c_void_p]),
     "dmn_sample_stiffness": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "dmn_version": (ctypes.c_char_p, []),

@@ -106,11 +106,13 @@ def dmn_homogenize_linear(w, n, C1, C2, Cbar=None, ws=None, ori=None):
     return Cbar, ws
 
 
-def dmn_homogenize_backward(w, n, C1, C2, gCbar, want_input_grads=False, ws=None, ori=None):
+def dmn_homogenize_backward(w, n, C1, C2, gCbar, want_input_grads=False, ws=None, ori=None,
+                            gw=None, gn=None):
     """(gw, gn, gC1, gC2) of sum_b <gCbar[b], Cbar[b]>; gC1/gC2 None unless requested.
 
     With ``ori`` gn is [L, 2, M]: the cotangents of the angle coefficients p
-    (first) and q of every laminate, summed over the samples."""
+    (first) and q of every laminate, summed over the samples.  ``gw``, ``gn``
+    may be given as output tensors (e.g. rows of a per-group stack)."""
     dtype = C1.dtype
     B = C1.shape[0]
     net, K, lam = _linear_net(w, n, ori, dtype, B)
@@ -118,9 +120,13 @@ def dmn_homogenize_backward(w, n, C1, C2, gCbar, want_input_grads=False, ws=None
         _need(t, nm, dtype)
         if t.numel() != 36 * B:
             raise ValueError(f"{nm} must be [B, 6, 6]")
-    gw = torch.empty(2 ** K, dtype=dtype, device=C1.device)
     gn_shape = (2 ** K - 1, 3) if ori is None else (2 ** K - 1, 2, L.ORI_COUNT[ori.kind])
-    gn = torch.empty(gn_shape, dtype=dtype, device=C1.device)
+    if gw is None:
+        gw = torch.empty(2 ** K, dtype=dtype, device=C1.device)
+    if gn is None:
+        gn = torch.empty(gn_shape, dtype=dtype, device=C1.device)
+    _need(gw, "gw", dtype, (2 ** K,))
+    _need(gn, "gn", dtype, gn_shape)
     gC1 = gC2 = None
     if want_input_grads:
         gC1 = torch.empty((B, 6, 6), dtype=dtype, device=C1.device)

@@ -495,6 +495,93 @@ int dmn_training_refresh(const dmn_train_params* params, int prec, hipStream_t s
   return dmn::launch_training_update(prec, params->depth, a, stream) ? DMN_EHIP : DMN_OK;
 }
 
+int dmn_orientation_group_normals(int32_t depth, int32_t ori_shape, int32_t G, int prec,
+                                  const void* p, const void* q, const void* lam, void* n,
+                                  hipStream_t stream) {
+  const int m = ori_count(ori_shape);
+  if (!depth_ok(depth) || m <= 0 || G < 0) return DMN_EINVAL;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!p || !q || (G > 0 && (!lam || !n))) return DMN_EINVAL;
+  return dmn::launch_group_normals(prec, depth, m, G, p, q, lam, n, stream) ? DMN_EHIP : DMN_OK;
+}
+
+int dmn_orientation_group_chain(int32_t depth, int32_t ori_shape, int32_t G, int prec,
+                                const void* p, const void* q, const void* lam,
+                                const void* gw_groups, const void* gn_groups, void* gw,
+                                void* gpq, hipStream_t stream) {
+  const int m = ori_count(ori_shape);
+  if (!depth_ok(depth) || m <= 0 || G < 0) return DMN_EINVAL;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!p || !q || !gw || !gpq || (G > 0 && (!lam || !gw_groups || !gn_groups)))
+    return DMN_EINVAL;
+  return dmn::launch_group_chain(prec, depth, m, G, p, q, lam, gw_groups, gn_groups, gw, gpq,
+                                 stream)
+             ? DMN_EHIP
+             : DMN_OK;
+}
+
+static int oriented_params_check(const dmn_train_params_oriented* t) {
+  if (!t || !depth_ok(t->depth) || ori_count(t->ori_shape) <= 0) return DMN_EINVAL;
+  if (!t->v || !t->p || !t->q || !t->w || !t->state || !t->step) return DMN_EINVAL;
+  return DMN_OK;
+}
+
+static dmn::TrainUpdateArgs oriented_args(const dmn_train_params_oriented* t) {
+  dmn::TrainUpdateArgs a = {};
+  a.v = t->v;
+  a.alpha = t->p;
+  a.beta = t->q;
+  a.w = t->w;
+  a.state = t->state;
+  a.step = (long long*)t->step;
+  a.half_period = 1;
+  a.steps_per_epoch = 1;
+  return a;
+}
+
+int dmn_training_update_oriented(const dmn_train_params_oriented* params, int prec,
+                                 const void* gw, const void* gpq, const dmn_amsgrad_opts* opts,
+                                 double* stats, hipStream_t stream) {
+  if (const int rc = oriented_params_check(params)) return rc;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!gw || !gpq || !opts || !stats) return DMN_EINVAL;
+  const dmn_amsgrad_opts& o = *opts;
+  if (!(o.lr_min >= 0.0) || !(o.lr_max >= 0.0) || !(o.lr_decay > 0.0) || o.half_period < 1 ||
+      o.steps_per_epoch < 1 || !(o.beta1 >= 0.0 && o.beta1 < 1.0) ||
+      !(o.beta2 >= 0.0 && o.beta2 < 1.0) || !(o.eps > 0.0) || !(o.penalty >= 0.0))
+    return DMN_EINVAL;
+  dmn::TrainUpdateArgs a = oriented_args(params);
+  a.gw = gw;
+  a.gn = gpq;
+  a.stats = stats;
+  a.lr_min = o.lr_min;
+  a.lr_max = o.lr_max;
+  a.lr_decay = o.lr_decay;
+  a.beta1 = o.beta1;
+  a.beta2 = o.beta2;
+  a.eps = o.eps;
+  a.penalty = o.penalty;
+  a.half_period = o.half_period;
+  a.steps_per_epoch = o.steps_per_epoch;
+  a.take_step = 1;
+  return dmn::launch_training_update_coeff(prec, params->depth, ori_count(params->ori_shape), a,
+                                           stream)
+             ? DMN_EHIP
+             : DMN_OK;
+}
+
+int dmn_training_refresh_oriented(const dmn_train_params_oriented* params, int prec,
+                                  hipStream_t stream) {
+  if (const int rc = oriented_params_check(params)) return rc;
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  dmn::TrainUpdateArgs a = oriented_args(params);
+  a.take_step = 0;
+  return dmn::launch_training_update_coeff(prec, params->depth, ori_count(params->ori_shape), a,
+                                           stream)
+             ? DMN_EHIP
+             : DMN_OK;
+}
+
 int dmn_sample_stiffness(int64_t B, int prec, const double* u, void* C1, void* C2,
                          hipStream_t stream) {
   if (B < 0) return DMN_EINVAL;

@@ -623,19 +623,22 @@ __device__ __forceinline__ void laminate_param_grad(const Normal<double>& nv, do
 // 1-3, 2-3).
 template <typename T>
 __device__ __forceinline__ void orientation_shape(T l1, T l2, int m, T s[6]) {
+  // Branch-free: every entry is written (zeros past m) and the callers read
+  // s with compile-time indices, so the array lives in registers.  (With a
+  // branch per family and a runtime-length loop over s, the uniform-branch
+  // lowering merged the three families' last stores into one scratch store
+  // whose offset register was left undefined on the quadratic path.)
   const T f1 = l1 - l2;
   const T f2 = T(3) - T(3) * l1 - T(3) * l2;
   const T f3 = T(2) * l1 + T(4) * l2 - T(2);
-  if (m == 3) {
-    s[0] = f1; s[1] = f2; s[2] = f3;
-  } else if (m == 4) {
-    const T b = f1 * f2 * f3;
-    s[0] = f1 - T(9) * b; s[1] = f2 - T(9) * b; s[2] = f3 - T(9) * b; s[3] = T(27) * b;
-  } else {
-    s[0] = f1 * (T(2) * f1 - T(1)); s[1] = f2 * (T(2) * f2 - T(1));
-    s[2] = f3 * (T(2) * f3 - T(1));
-    s[3] = T(4) * f1 * f2; s[4] = T(4) * f1 * f3; s[5] = T(4) * f2 * f3;
-  }
+  const T b = f1 * f2 * f3;
+  const bool quad = m == 6, tri = m == 4;
+  s[0] = quad ? f1 * (T(2) * f1 - T(1)) : (tri ? f1 - T(9) * b : f1);
+  s[1] = quad ? f2 * (T(2) * f2 - T(1)) : (tri ? f2 - T(9) * b : f2);
+  s[2] = quad ? f3 * (T(2) * f3 - T(1)) : (tri ? f3 - T(9) * b : f3);
+  s[3] = quad ? T(4) * f1 * f2 : (tri ? T(27) * b : T(0));
+  s[4] = quad ? T(4) * f1 * f3 : T(0);
+  s[5] = quad ? T(4) * f2 * f3 : T(0);
 }
 
 __device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
@@ -655,11 +658,12 @@ __device__ __forceinline__ void orientation_normals(const T* __restrict__ p,
 #pragma unroll 1
   for (int pos = t; pos < L; pos += lanes) {
     T a = T(0), b = T(0);
-#pragma unroll 1
-    for (int j = 0; j < m; ++j) {
-      a += p[(size_t)pos * m + j] * s[j];
-      b += q[(size_t)pos * m + j] * s[j];
-    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j < m) {
+        a += p[(size_t)pos * m + j] * s[j];
+        b += q[(size_t)pos * m + j] * s[j];
+      }
     T sa, ca, sb, cb;
     sin_cos(a, &sa, &ca);
     sin_cos(b, &sb, &cb);

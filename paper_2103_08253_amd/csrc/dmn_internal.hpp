@@ -145,6 +145,16 @@ struct TrainUpdateArgs {
 int launch_training_update(int prec, int depth, const TrainUpdateArgs& args, hipStream_t stream);
 int launch_sample_stiffness(int prec, long long B, const double* u, void* C1, void* C2,
                             hipStream_t stream);
+// Orientation groups: normals [G][L][3] of each group, chain of per-group
+// cotangents to gw and the coefficient cotangents [L][2][m], and the update of
+// (v, p, q) (p, q passed in TrainUpdateArgs::alpha / beta, their gradients in gn).
+int launch_group_normals(int prec, int depth, int m, int G, const void* p, const void* q,
+                         const void* lam, void* n, hipStream_t stream);
+int launch_group_chain(int prec, int depth, int m, int G, const void* p, const void* q,
+                       const void* lam, const void* gw_g, const void* gn_g, void* gw, void* gpq,
+                       hipStream_t stream);
+int launch_training_update_coeff(int prec, int depth, int m, const TrainUpdateArgs& args,
+                                 hipStream_t stream);
 int launch_adjoint(int depth, const AdjointLaunch& args, hipStream_t stream);
 
 }  // namespace dmn

@@ -228,6 +228,161 @@ __global__ __launch_bounds__(kUpdateThreads) void train_update_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Training over a discrete set of fibre orientations (Sec. 2.3, Sec. 4.5):
+// the samples of orientation k all see the normals n_k, so a step runs the
+// fixed-normal linear map and its VJP once per orientation group; these
+// kernels give the groups their normals and chain their cotangents back to
+// the angle coefficients p, q [L][m].
+
+// n[k][l] = n(p_l . s(lam_k), q_l . s(lam_k)), one thread per (k, l).
+template <typename T>
+__global__ __launch_bounds__(256) void group_normals_kernel(int G, int L, int m,
+                                                            const T* __restrict__ p,
+                                                            const T* __restrict__ q,
+                                                            const T* __restrict__ lam,
+                                                            T* __restrict__ n) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)G * L) return;
+  const int k = (int)(idx / L), l = (int)(idx - (long long)k * L);
+  double sh[6];
+  orientation_shape<double>((double)lam[2 * k], (double)lam[2 * k + 1], m, sh);
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    if (j < m) {
+      a += (double)p[(size_t)l * m + j] * sh[j];
+      b += (double)q[(size_t)l * m + j] * sh[j];
+    }
+  double sa, ca, sb, cb;
+  sincos(a, &sa, &ca);
+  sincos(b, &sb, &cb);
+  T* o = n + (size_t)idx * 3;
+  o[0] = (T)(sa * cb);
+  o[1] = (T)(sa * sb);
+  o[2] = (T)ca;
+}
+
+// gw = sum_k gw_g[k] and, per laminate l,
+//   gpq[l][0][j] = sum_k (gn_g[k][l] . dn/dalpha) s_j(lam_k),
+//   gpq[l][1][j] = sum_k (gn_g[k][l] . dn/dbeta)  s_j(lam_k),
+// summed over k in order; one thread per leaf or laminate.
+template <typename T>
+__global__ __launch_bounds__(256) void group_chain_kernel(
+    int G, int NL, int L, int m, const T* __restrict__ p, const T* __restrict__ q,
+    const T* __restrict__ lam, const T* __restrict__ gw_g, const T* __restrict__ gn_g,
+    T* __restrict__ gw, T* __restrict__ gpq) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < NL) {
+    double acc = 0.0;
+    for (int k = 0; k < G; ++k) acc += (double)gw_g[(size_t)k * NL + idx];
+    gw[idx] = (T)acc;
+    return;
+  }
+  const int l = idx - NL;
+  if (l >= L) return;
+  double gp[6] = {0, 0, 0, 0, 0, 0}, gq[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < G; ++k) {
+    double sh[6];
+    orientation_shape<double>((double)lam[2 * k], (double)lam[2 * k + 1], m, sh);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j < m) {
+        a += (double)p[(size_t)l * m + j] * sh[j];
+        b += (double)q[(size_t)l * m + j] * sh[j];
+      }
+    double sa, ca, sb, cb;
+    sincos(a, &sa, &ca);
+    sincos(b, &sb, &cb);
+    const T* g = gn_g + ((size_t)k * L + l) * 3;
+    const double g0 = (double)g[0], g1 = (double)g[1], g2 = (double)g[2];
+    const double ga = g0 * ca * cb + g1 * ca * sb - g2 * sa;
+    const double gb = -g0 * sa * sb + g1 * sa * cb;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      gp[j] += ga * sh[j];
+      gq[j] += gb * sh[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    if (j < m) {
+      gpq[((size_t)l * 2) * m + j] = (T)gp[j];
+      gpq[((size_t)l * 2 + 1) * m + j] = (T)gq[j];
+    }
+}
+
+// One workgroup: AMSGrad on the slots v [NL], p [L m], q [L m] with
+//   dJ/dv_i = (gw_i + 2 lambda (sum <v>_+ - 1)) [v_i > 0],
+//   dJ/dp, dJ/dq from gpq [L][2][m];
+// then (or, without take_step, only) w = <v>_+.
+template <typename T>
+__global__ __launch_bounds__(kUpdateThreads) void train_update_coeff_kernel(
+    int K, int m, T* __restrict__ v, T* __restrict__ p, T* __restrict__ q, T* __restrict__ w,
+    T* __restrict__ state, long long* __restrict__ step, const T* __restrict__ gw,
+    const T* __restrict__ gpq, AmsArgs o, double* __restrict__ stats, int take_step) {
+  __shared__ double wsum[kUpdateThreads / 64];
+  const int tid = threadIdx.x;
+  const int NL = 1 << K, L = NL - 1, LM = L * m, NP = NL + 2 * LM;
+  const long long t0 = take_step ? *step : 0;  // every read precedes the barrier below
+  double acc = 0.0;
+  for (int i = tid; i < NL; i += kUpdateThreads) acc += fmax((double)v[i], 0.0);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+  __syncthreads();
+  double sw = 0.0;
+  for (int r = 0; r < kUpdateThreads / 64; ++r) sw += wsum[r];
+  if (!take_step) {
+    for (int i = tid; i < NL; i += kUpdateThreads) w[i] = (T)fmax((double)v[i], 0.0);
+    return;
+  }
+  const double pen_g = 2.0 * o.penalty * (sw - 1.0);
+  const double lr = modulated_rate(o, t0 / o.steps_per_epoch);
+  const double tn = (double)(t0 + 1);
+  const double step_size = lr / (1.0 - pow(o.beta1, tn));
+  const double bc2 = 1.0 - pow(o.beta2, tn);
+  T* m1 = state;
+  T* m2 = state + NP;
+  T* mx = state + 2 * NP;
+  for (int i = tid; i < NP; i += kUpdateThreads) {
+    double th, g;
+    if (i < NL) {
+      th = (double)v[i];
+      g = th > 0.0 ? (double)gw[i] + pen_g : 0.0;
+    } else {
+      const int r = i < NL + LM ? i - NL : i - NL - LM;  // l m + j
+      const int l = r / m, j = r - l * m;
+      const bool isq = i >= NL + LM;
+      th = isq ? (double)q[r] : (double)p[r];
+      g = (double)gpq[((size_t)l * 2 + (isq ? 1 : 0)) * m + j];
+    }
+    const double a1 = o.beta1 * (double)m1[i] + (1.0 - o.beta1) * g;
+    const double a2 = o.beta2 * (double)m2[i] + (1.0 - o.beta2) * g * g;
+    const double ax = fmax((double)mx[i], a2);
+    m1[i] = (T)a1;
+    m2[i] = (T)a2;
+    mx[i] = (T)ax;
+    const T nt = (T)(th - step_size * a1 / (sqrt(ax / bc2) + o.eps));
+    if (i < NL) {
+      v[i] = nt;
+      w[i] = (T)fmax((double)nt, 0.0);
+    } else if (i < NL + LM) {
+      p[i - NL] = nt;
+    } else {
+      q[i - NL - LM] = nt;
+    }
+  }
+  if (tid == 0) {
+    const double pen = o.penalty * (sw - 1.0) * (sw - 1.0);
+    stats[3] = stats[0] + pen;
+    stats[4] = pen;
+    stats[5] = lr;
+    stats[6] = sw;
+    *step = t0 + 1;
+  }
+}
+
 // theta in [0, pi] with theta - sin(theta) = pi u: Newton from the small-angle
 // estimate (6 pi u)^(1/3), which lies left of the root; the function is
 // convex and increasing, so after the first step the iterates decrease
@@ -349,6 +504,55 @@ int launch_training_update(int prec, int depth, const TrainUpdateArgs& a, hipStr
     hipLaunchKernelGGL((train_update_kernel<double>), dim3(1), dim3(kUpdateThreads), 0, stream,
                        depth, (double*)a.v, (double*)a.alpha, (double*)a.beta, (double*)a.w,
                        (double*)a.n, (double*)a.state, a.step, (const double*)a.gw,
+                       (const double*)a.gn, o, a.stats, a.take_step);
+  return (int)hipGetLastError();
+}
+
+int launch_group_normals(int prec, int depth, int m, int G, const void* p, const void* q,
+                         const void* lam, void* n, hipStream_t stream) {
+  const int L = (1 << depth) - 1;
+  const long long total = (long long)G * L;
+  if (total == 0) return (int)hipSuccess;
+  const unsigned nb = blocks_for(total, 256);
+  if (prec == DMN_F32)
+    hipLaunchKernelGGL((group_normals_kernel<float>), dim3(nb), dim3(256), 0, stream, G, L, m,
+                       (const float*)p, (const float*)q, (const float*)lam, (float*)n);
+  else
+    hipLaunchKernelGGL((group_normals_kernel<double>), dim3(nb), dim3(256), 0, stream, G, L, m,
+                       (const double*)p, (const double*)q, (const double*)lam, (double*)n);
+  return (int)hipGetLastError();
+}
+
+int launch_group_chain(int prec, int depth, int m, int G, const void* p, const void* q,
+                       const void* lam, const void* gw_g, const void* gn_g, void* gw, void* gpq,
+                       hipStream_t stream) {
+  const int NL = 1 << depth, L = NL - 1;
+  const unsigned nb = blocks_for(NL + L, 256);
+  if (prec == DMN_F32)
+    hipLaunchKernelGGL((group_chain_kernel<float>), dim3(nb), dim3(256), 0, stream, G, NL, L, m,
+                       (const float*)p, (const float*)q, (const float*)lam, (const float*)gw_g,
+                       (const float*)gn_g, (float*)gw, (float*)gpq);
+  else
+    hipLaunchKernelGGL((group_chain_kernel<double>), dim3(nb), dim3(256), 0, stream, G, NL, L, m,
+                       (const double*)p, (const double*)q, (const double*)lam,
+                       (const double*)gw_g, (const double*)gn_g, (double*)gw, (double*)gpq);
+  return (int)hipGetLastError();
+}
+
+int launch_training_update_coeff(int prec, int depth, int m, const TrainUpdateArgs& a,
+                                 hipStream_t stream) {
+  const AmsArgs o{a.lr_min, a.lr_max, a.lr_decay, a.beta1, a.beta2, a.eps, a.penalty,
+                  a.half_period, a.steps_per_epoch};
+  // alpha / beta carry the coefficient arrays p / q, gn the coefficient gradients
+  if (prec == DMN_F32)
+    hipLaunchKernelGGL((train_update_coeff_kernel<float>), dim3(1), dim3(kUpdateThreads), 0,
+                       stream, depth, m, (float*)a.v, (float*)a.alpha, (float*)a.beta,
+                       (float*)a.w, (float*)a.state, a.step, (const float*)a.gw,
+                       (const float*)a.gn, o, a.stats, a.take_step);
+  else
+    hipLaunchKernelGGL((train_update_coeff_kernel<double>), dim3(1), dim3(kUpdateThreads), 0,
+                       stream, depth, m, (double*)a.v, (double*)a.alpha, (double*)a.beta,
+                       (double*)a.w, (double*)a.state, a.step, (const double*)a.gw,
                        (const double*)a.gn, o, a.stats, a.take_step);
   return (int)hipGetLastError();
 }

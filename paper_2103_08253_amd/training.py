@@ -213,3 +213,172 @@ class TrainingStepGraph:
     def step_eager(self):
         """The same step without the graph (for comparisons)."""
         self._enqueue()
+
+
+# ---------------------------------------------------------------- orientation groups
+
+@dataclass
+class OrientedTrainParams:
+    """Device tensors of an orientation-interpolated DMN's trainable parameters
+    (weights v, angle coefficients p, q [L, M]) and optimiser state."""
+    kind: str
+    v: torch.Tensor
+    p: torch.Tensor
+    q: torch.Tensor
+    w: torch.Tensor
+    state: torch.Tensor
+    step: torch.Tensor
+
+    @classmethod
+    def create(cls, kind, v, p, q):
+        if kind not in L.ORI_COUNT:
+            raise ValueError(f"unknown shape functions {kind!r}")
+        dev, dt = v.device, v.dtype
+        NL = v.numel()
+        LM = p.numel()
+        prm = cls(kind, v.detach().clone().contiguous(), p.detach().clone().contiguous(),
+                  q.detach().clone().contiguous(), torch.empty(NL, dtype=dt, device=dev),
+                  torch.zeros((3, NL + 2 * LM), dtype=dt, device=dev),
+                  torch.zeros(1, dtype=torch.int64, device=dev))
+        rc = L.lib().dmn_training_refresh_oriented(ctypes.byref(prm.to_c()), _PREC[dt], _stream())
+        L.check(rc, "dmn_training_refresh_oriented")
+        return prm
+
+    @property
+    def depth(self):
+        return int(round(torch.log2(torch.tensor(float(self.v.numel()))).item()))
+
+    @property
+    def m(self):
+        return L.ORI_COUNT[self.kind]
+
+    def to_c(self):
+        K, dt = self.depth, self.v.dtype
+        if 2 ** K != self.v.numel() or not 1 <= K <= 10:
+            raise ValueError("v must hold 2^K weights with 1 <= K <= 10")
+        Lm, M = 2 ** K - 1, self.m
+        _need(self.v, "v", dt, (2 ** K,))
+        _need(self.p, "p", dt, (Lm, M))
+        _need(self.q, "q", dt, (Lm, M))
+        _need(self.w, "w", dt, (2 ** K,))
+        _need(self.state, "state", dt, (3, 2 ** K + 2 * Lm * M))
+        _need(self.step, "step", torch.int64, (1,))
+        return L.DmnTrainParamsOriented(K, L.DMN_ORI[self.kind], self.v.data_ptr(),
+                                        self.p.data_ptr(), self.q.data_ptr(), self.w.data_ptr(),
+                                        self.state.data_ptr(), self.step.data_ptr())
+
+
+def dmn_orientation_group_normals(params: OrientedTrainParams, lam, n=None):
+    """Normals [G, L, 3] of the orientations lam [G, 2]."""
+    dt, K = params.v.dtype, params.depth
+    G = lam.shape[0]
+    _need(lam, "lam", dt, (G, 2))
+    if n is None:
+        n = torch.empty((G, 2 ** K - 1, 3), dtype=dt, device=lam.device)
+    _need(n, "n", dt, (G, 2 ** K - 1, 3))
+    rc = L.lib().dmn_orientation_group_normals(K, L.DMN_ORI[params.kind], G, _PREC[dt],
+                                               _ptr(params.p), _ptr(params.q), _ptr(lam),
+                                               _ptr(n), _stream())
+    L.check(rc, "dmn_orientation_group_normals")
+    return n
+
+
+def dmn_orientation_group_chain(params: OrientedTrainParams, lam, gw_groups, gn_groups,
+                                gw=None, gpq=None):
+    """(gw [2^K], gpq [L, 2, M]) from the groups' VJPs [G, 2^K], [G, L, 3]."""
+    dt, K, M = params.v.dtype, params.depth, params.m
+    G = lam.shape[0]
+    _need(gw_groups, "gw_groups", dt, (G, 2 ** K))
+    _need(gn_groups, "gn_groups", dt, (G, 2 ** K - 1, 3))
+    if gw is None:
+        gw = torch.empty(2 ** K, dtype=dt, device=lam.device)
+    if gpq is None:
+        gpq = torch.empty((2 ** K - 1, 2, M), dtype=dt, device=lam.device)
+    rc = L.lib().dmn_orientation_group_chain(K, L.DMN_ORI[params.kind], G, _PREC[dt],
+                                             _ptr(params.p), _ptr(params.q), _ptr(lam),
+                                             _ptr(gw_groups), _ptr(gn_groups), _ptr(gw),
+                                             _ptr(gpq), _stream())
+    L.check(rc, "dmn_orientation_group_chain")
+    return gw, gpq
+
+
+def dmn_training_update_oriented(params: OrientedTrainParams, gw, gpq,
+                                 opts: Optional[AmsgradOpts] = None, stats=None):
+    dt, K = params.v.dtype, params.depth
+    _need(gw, "gw", dt, (2 ** K,))
+    _need(gpq, "gpq", dt, (2 ** K - 1, 2, params.m))
+    if stats is None:
+        stats = new_stats(params.v.device)
+    o = (opts or AmsgradOpts()).to_c()
+    rc = L.lib().dmn_training_update_oriented(ctypes.byref(params.to_c()), _PREC[dt], _ptr(gw),
+                                              _ptr(gpq), ctypes.byref(o), _ptr(stats), _stream())
+    L.check(rc, "dmn_training_update_oriented")
+    return stats
+
+
+class OrientedTrainingStepGraph:
+    """One training step of an orientation-interpolated DMN over a batch
+    grouped by orientation (samples offsets[k]:offsets[k+1] have orientation
+    lam[k]) as a HIP graph: group normals, the fixed-normal linear map per
+    group, the objective over the whole batch, the VJP per group, the chain
+    to (p, q) and the AMSGrad update."""
+
+    def __init__(self, params: OrientedTrainParams, C1, C2, target, lam, offsets,
+                 p: float = 1.0, q: float = 10.0, opts: Optional[AmsgradOpts] = None):
+        self.params, self.C1, self.C2, self.target, self.lam = params, C1, C2, target, lam
+        self.offsets = [int(x) for x in offsets]
+        self.p, self.q, self.opts = p, q, opts or AmsgradOpts()
+        dev, dt = C1.device, C1.dtype
+        B, G, K = C1.shape[0], lam.shape[0], params.depth
+        if len(self.offsets) != G + 1 or self.offsets[0] != 0 or self.offsets[-1] != B:
+            raise ValueError("offsets must split the batch into one range per orientation")
+        self.Cbar = torch.empty((B, 6, 6), dtype=dt, device=dev)
+        self.gCbar = torch.empty((B, 6, 6), dtype=dt, device=dev)
+        self.stats = new_stats(dev)
+        self.n_groups = torch.empty((G, 2 ** K - 1, 3), dtype=dt, device=dev)
+        self.gw_groups = torch.empty((G, 2 ** K), dtype=dt, device=dev)
+        self.gn_groups = torch.empty((G, 2 ** K - 1, 3), dtype=dt, device=dev)
+        self.gw = torch.empty(2 ** K, dtype=dt, device=dev)
+        self.gpq = torch.empty((2 ** K - 1, 2, params.m), dtype=dt, device=dev)
+        self.ws_fwd, self.ws_bwd = [None] * G, [None] * G
+        self._enqueue(sizing=True)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        stream = torch.cuda.Stream(device=dev)
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(self.graph, stream=stream):
+            self._enqueue()
+        torch.cuda.current_stream().wait_stream(stream)
+
+    def _enqueue(self, sizing=False):
+        P, o = self.params, self.offsets
+        dmn_orientation_group_normals(P, self.lam, n=self.n_groups)
+        for k in range(len(o) - 1):
+            a, b = o[k], o[k + 1]
+            _, self.ws_fwd[k] = dmn_homogenize_linear(P.w, self.n_groups[k], self.C1[a:b],
+                                                      self.C2[a:b], Cbar=self.Cbar[a:b],
+                                                      ws=self.ws_fwd[k])
+        _, _, ws = dmn_training_loss(self.Cbar, self.target, self.p, self.q, gCbar=self.gCbar,
+                                     stats=self.stats, ws=None if sizing else self.ws_loss)
+        self.ws_loss = ws
+        for k in range(len(o) - 1):
+            a, b = o[k], o[k + 1]
+            self.ws_bwd[k] = dmn_homogenize_backward(
+                P.w, self.n_groups[k], self.C1[a:b], self.C2[a:b], self.gCbar[a:b],
+                ws=self.ws_bwd[k], gw=self.gw_groups[k], gn=self.gn_groups[k])[-1]
+        dmn_orientation_group_chain(P, self.lam, self.gw_groups, self.gn_groups, gw=self.gw,
+                                    gpq=self.gpq)
+        if not sizing:
+            dmn_training_update_oriented(P, self.gw, self.gpq, self.opts, self.stats)
+
+    def replay(self):
+        """Enqueue one training step on the current stream."""
+        self.graph.replay()
+
+    def step_eager(self):
+        self._enqueue()
+
+    def error_words(self):
+        """Device error words of every group's linear map and VJP (synchronises)."""
+        from .api import error_word
+        return [error_word(w) for w in self.ws_fwd + self.ws_bwd]

@@ -487,3 +487,130 @@ def test_training_step_f32_gradient():
     g_ref = np.concatenate([ref["gv"], ref["galpha"], ref["gbeta"]])
     say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
     assert rel(g_gpu, g_ref) < 1e-3
+
+
+# ---------------------------------------------------------------- orientation groups
+
+@pytest.mark.parametrize("kind", ["linear", "trilinear", "quadratic"])
+def test_orientation_group_normals_and_chain(kind):
+    from oracle.orientation import interpolated_normals
+    from paper_2103_08253_amd import (OrientedTrainParams, dmn_orientation_group_chain,
+                                      dmn_orientation_group_normals)
+    K = 3
+    say(f"orientation groups K={K} {kind}")
+    rs = S.streams(91)
+    net = S.interpolated_dmn(rs["dmn"], K, 0.3, kind)
+    lam = S.orientation_discretization(1)
+    G, L = len(lam), 2 ** K - 1
+    P = OrientedTrainParams.create(kind, tt(net.w), tt(net.p), tt(net.q))
+    n = dmn_orientation_group_normals(P, tt(lam))
+    torch.cuda.synchronize()
+    ref = np.stack([interpolated_normals(net.p, net.q, l1, l2, kind) for l1, l2 in lam])
+    assert rel(n.cpu().numpy(), ref) < 1e-13
+    gw_g = rs["cotangent"].standard_normal((G, 2 ** K))
+    gn_g = rs["cotangent"].standard_normal((G, L, 3))
+    gw, gpq = dmn_orientation_group_chain(P, tt(lam), tt(gw_g), tt(gn_g))
+    torch.cuda.synchronize()
+    assert rel(gw.cpu().numpy(), gw_g.sum(axis=0)) < 1e-15
+    # complex steps of sum_k <gn_k, n_k(p, q)> through the oracle's normals
+    h = 1e-30
+    Jc = lambda pp, qq: sum(np.sum(gn_g[k] * interpolated_normals(pp, qq, l1, l2, kind))
+                            for k, (l1, l2) in enumerate(lam))
+    gp_ref, gq_ref = np.zeros_like(net.p), np.zeros_like(net.q)
+    for idx in np.ndindex(*net.p.shape):
+        pc = net.p.astype(complex)
+        pc[idx] += 1j * h
+        gp_ref[idx] = np.imag(Jc(pc, net.q)) / h
+        qc = net.q.astype(complex)
+        qc[idx] += 1j * h
+        gq_ref[idx] = np.imag(Jc(net.p, qc)) / h
+    got = gpq.cpu().numpy()
+    assert rel(got[:, 0, :], gp_ref) < 1e-12
+    assert rel(got[:, 1, :], gq_ref) < 1e-12
+
+
+def oriented_case(K, B, kind, seed, level=0):
+    from oracle.orientation import oriented_linear
+    rs = S.streams(seed)
+    lam_g = S.orientation_discretization(level)
+    G = len(lam_g)
+    group = np.arange(B) % G
+    order = np.argsort(group, kind="stable")
+    offsets = np.concatenate([[0], np.cumsum(np.bincount(group, minlength=G))])
+    C1 = S.random_spd(rs["stiffness"], B)[order]
+    C2 = S.random_spd(rs["stiffness"], B)[order]
+    lam_s = lam_g[group[order]]
+    truth = S.interpolated_dmn(rs["ground_truth"], K, 0.25, kind)
+    Tt = oriented_linear(K, truth.w, truth.p, truth.q, kind, lam_s, C1, C2)
+    M = S.SHAPE_COUNTS[kind]
+    v = rs["init"].uniform(0.0, 1.0, 2 ** K)
+    v = v / v.sum()
+    p = rs["init"].uniform(0.0, 2 * np.pi, (2 ** K - 1, M))
+    q = rs["init"].uniform(0.0, 2 * np.pi, (2 ** K - 1, M))
+    return C1, C2, Tt, lam_g, lam_s, offsets, v, p, q
+
+
+@pytest.mark.parametrize("dead", [False, True])
+def test_oriented_training_step_gradient_matches_complex_step(dead):
+    from paper_2103_08253_amd import AmsgradOpts, OrientedTrainingStepGraph, OrientedTrainParams
+    K, B, kind, lam_pen = 3, 16, "trilinear", 10.0
+    say(f"oriented training step K={K} B={B} {kind} dead={dead}")
+    C1, C2, Tt, lam_g, lam_s, offsets, v, p, q = oriented_case(K, B, kind, 92)
+    if dead:
+        v[2], v[3] = -0.01, -0.02
+    eps, lr = 1e6, 1e3
+    opts = AmsgradOpts(lr_min=lr, lr_max=lr, lr_decay=1.0, beta1=0.0, beta2=0.0, eps=eps,
+                       penalty=lam_pen)
+    P = OrientedTrainParams.create(kind, tt(v), tt(p), tt(q))
+    g = OrientedTrainingStepGraph(P, tt(C1), tt(C2), tt(Tt), tt(lam_g), offsets, opts=opts)
+    g.step_eager()
+    torch.cuda.synchronize()
+    assert all(e == 0 for e in g.error_words())
+    th0 = np.concatenate([v, p.ravel(), q.ravel()])
+    th1 = np.concatenate([P.v.cpu().numpy(), P.p.cpu().numpy().ravel(),
+                          P.q.cpu().numpy().ravel()])
+    d = th0 - th1
+    g_gpu = d * eps / (lr - np.abs(d))
+    ref = T.objective_oriented_gradient(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
+    g_ref = np.concatenate([ref["gv"], ref["gP"].ravel(), ref["gQ"].ravel()])
+    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    assert rel(g_gpu, g_ref) < 1e-8
+    J = T.objective_oriented(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
+    assert abs(g.stats.cpu().numpy()[3] - J) <= 1e-10 * J
+
+
+def test_oriented_training_graph_matches_eager_and_oracle():
+    from paper_2103_08253_amd import AmsgradOpts, OrientedTrainingStepGraph, OrientedTrainParams
+    K, B, kind = 3, 20, "linear"
+    say(f"oriented training graph K={K} B={B} {kind}")
+    C1, C2, Tt, lam_g, lam_s, offsets, v, p, q = oriented_case(K, B, kind, 93, level=1)
+    opts = AmsgradOpts(steps_per_epoch=2, half_period=3, penalty=100.0)
+    Pg = OrientedTrainParams.create(kind, tt(v), tt(p), tt(q))
+    Pe = OrientedTrainParams.create(kind, tt(v), tt(p), tt(q))
+    args = (tt(C1), tt(C2), tt(Tt), tt(lam_g), offsets)
+    graph = OrientedTrainingStepGraph(Pg, *args, opts=opts)
+    eager = OrientedTrainingStepGraph(Pe, *args, opts=opts)
+    th = np.concatenate([v, p.ravel(), q.ravel()])
+    NL, LM = 2 ** K, p.size
+    st = [np.zeros(len(th))] * 3
+    for step in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        eager.step_eager()
+        torch.cuda.synchronize()
+        for a, b in ((Pg.v, Pe.v), (Pg.p, Pe.p), (Pg.q, Pe.q), (Pg.state, Pe.state),
+                     (graph.stats, eager.stats)):
+            assert torch.equal(a, b), step
+        vv, pp, qq = th[:NL], th[NL:NL + LM].reshape(p.shape), th[NL + LM:].reshape(q.shape)
+        J = T.objective_oriented(K, vv, pp, qq, kind, lam_s, C1, C2, Tt, 1.0, 10.0, opts.penalty)
+        g = T.objective_oriented_gradient(K, vv, pp, qq, kind, lam_s, C1, C2, Tt, 1.0, 10.0,
+                                          opts.penalty)
+        lr = T.learning_rate(step // opts.steps_per_epoch, opts.lr_min, opts.lr_max,
+                             opts.half_period, opts.lr_decay)
+        th, *st = T.amsgrad(th, np.concatenate([g["gv"], g["gP"].ravel(), g["gQ"].ravel()]),
+                            *st, step + 1, lr)
+        assert abs(graph.stats.cpu().numpy()[3] - J) <= 1e-10 * J, step
+        got = np.concatenate([Pg.v.cpu().numpy(), Pg.p.cpu().numpy().ravel(),
+                              Pg.q.cpu().numpy().ravel()])
+        say(f"   step {step}: J {J:.6e} param rel err {rel(got, th):.2e}")
+        assert rel(got, th) < 1e-10, step
