@@ -484,6 +484,49 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         sweep[nb] = dict(ms=ms, samples_per_s=nb / (ms * 1e-3))
         del lg, c1s, c2s, gcs
     out["train_fwd_bwd_batch_sweep"] = sweep
+    # training over the paper's 31 fibre orientations (linear shape functions):
+    # the batch grouped by orientation, one fixed-normal map and VJP per group
+    from paper_2103_08253_amd import (OrientedTrainingStepGraph, OrientedTrainParams,
+                                      dmn_orientation_group_normals)
+    ow = S.oriented_training_workload(batch=B)
+    lam_t = torch.tensor(ow.lam, device=dev)
+    truth_o = OrientedTrainParams.create(ow.truth.kind, torch.tensor(ow.truth.w, device=dev),
+                                         torch.tensor(ow.truth.p, device=dev),
+                                         torch.tensor(ow.truth.q, device=dev))
+    n_truth = dmn_orientation_group_normals(truth_o, lam_t)
+    C1o = torch.tensor(ow.C1, device=dev)
+    C2o = torch.tensor(ow.C2, device=dev)
+    tgt_o = torch.empty_like(C1o)
+    for k in range(len(ow.lam)):
+        a_, b_ = int(ow.offsets[k]), int(ow.offsets[k + 1])
+        dmn_homogenize_linear(truth_o.w, n_truth[k], C1o[a_:b_], C2o[a_:b_], Cbar=tgt_o[a_:b_])
+    train_o = {}
+    for nb in (B, 32):
+        G = len(ow.lam)
+        per = [nb // G + (1 if k < nb % G else 0) for k in range(G)]   # spread over groups
+        idx = np.concatenate([ow.offsets[k] + np.arange(per[k]) for k in range(G)])
+        grp = np.searchsorted(ow.offsets, idx, side="right") - 1
+        offs = np.concatenate([[0], np.cumsum(np.bincount(grp, minlength=G))])
+        sel = torch.tensor(idx, device=dev)
+        Po = OrientedTrainParams.create(ow.truth.kind, torch.tensor(ow.v0, device=dev),
+                                        torch.tensor(ow.p0, device=dev),
+                                        torch.tensor(ow.q0, device=dev))
+        go = OrientedTrainingStepGraph(Po, C1o[sel].contiguous(), C2o[sel].contiguous(),
+                                       tgt_o[sel].contiguous(), lam_t, offs,
+                                       opts=AmsgradOpts(steps_per_epoch=10))
+        go.replay()
+        torch.cuda.synchronize()
+        j0 = float(go.stats[3].item())
+        ms = _event_ms(go.replay, 20) / 20
+        hist = {1: j0, 21: float(go.stats[3].item())}
+        for _ in range(480):
+            go.replay()
+        hist[int(Po.step.item())] = float(go.stats[3].item())
+        train_o[nb] = dict(ms_per_step=ms, samples_per_s=nb / (ms * 1e-3),
+                           objective_at_step=hist)
+    out["training_oriented_step_graph"] = dict(
+        depth=8, orientations=len(ow.lam), shape_functions=ow.truth.kind,
+        batch_4096=train_o[B], batch_32=train_o[32])
     out["training_objective_step_graph"] = dict(
         depth=8, p=1.0, q=10.0, optimiser="AMSGrad, modulated learning rate",
         batch_4096=train[B], batch_32=train[32],

@@ -324,8 +324,12 @@ class OrientedTrainingStepGraph:
     to (p, q) and the AMSGrad update."""
 
     def __init__(self, params: OrientedTrainParams, C1, C2, target, lam, offsets,
-                 p: float = 1.0, q: float = 10.0, opts: Optional[AmsgradOpts] = None):
+                 p: float = 1.0, q: float = 10.0, opts: Optional[AmsgradOpts] = None,
+                 streams: int = 4):
         self.params, self.C1, self.C2, self.target, self.lam = params, C1, C2, target, lam
+        # the groups' maps and VJPs are independent: spread them over a few
+        # streams (default priority) that fork from and join the main stream
+        self.side = [torch.cuda.Stream(device=C1.device) for _ in range(max(0, streams - 1))]
         self.offsets = [int(x) for x in offsets]
         self.p, self.q, self.opts = p, q, opts or AmsgradOpts()
         dev, dt = C1.device, C1.dtype
@@ -350,22 +354,39 @@ class OrientedTrainingStepGraph:
             self._enqueue()
         torch.cuda.current_stream().wait_stream(stream)
 
+    def _fan_out(self, fn):
+        """Run fn(k) for every group, group k on stream k mod (1 + side streams)."""
+        main = torch.cuda.current_stream()
+        lanes = [main] + self.side
+        for st in self.side:
+            st.wait_stream(main)
+        for k in range(len(self.offsets) - 1):
+            with torch.cuda.stream(lanes[k % len(lanes)]):
+                fn(k)
+        for st in self.side:
+            main.wait_stream(st)
+
     def _enqueue(self, sizing=False):
         P, o = self.params, self.offsets
         dmn_orientation_group_normals(P, self.lam, n=self.n_groups)
-        for k in range(len(o) - 1):
+
+        def fwd(k):
             a, b = o[k], o[k + 1]
             _, self.ws_fwd[k] = dmn_homogenize_linear(P.w, self.n_groups[k], self.C1[a:b],
                                                       self.C2[a:b], Cbar=self.Cbar[a:b],
                                                       ws=self.ws_fwd[k])
-        _, _, ws = dmn_training_loss(self.Cbar, self.target, self.p, self.q, gCbar=self.gCbar,
-                                     stats=self.stats, ws=None if sizing else self.ws_loss)
-        self.ws_loss = ws
-        for k in range(len(o) - 1):
+
+        def bwd(k):
             a, b = o[k], o[k + 1]
             self.ws_bwd[k] = dmn_homogenize_backward(
                 P.w, self.n_groups[k], self.C1[a:b], self.C2[a:b], self.gCbar[a:b],
                 ws=self.ws_bwd[k], gw=self.gw_groups[k], gn=self.gn_groups[k])[-1]
+
+        self._fan_out(fwd)
+        _, _, ws = dmn_training_loss(self.Cbar, self.target, self.p, self.q, gCbar=self.gCbar,
+                                     stats=self.stats, ws=None if sizing else self.ws_loss)
+        self.ws_loss = ws
+        self._fan_out(bwd)
         dmn_orientation_group_chain(P, self.lam, self.gw_groups, self.gn_groups, gw=self.gw,
                                     gpq=self.gpq)
         if not sizing:
