@@ -17,7 +17,7 @@ def case(K, B=3, seed=61):
 
 
 def rel(a, b):
-    return np.abs(a - b).max() / np.abs(b).max()
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
 def test_positive_weights_keep_the_full_tree():
@@ -67,3 +67,70 @@ def test_single_live_leaf_returns_its_phase():
         ref = C1 if j % 2 == 0 else C2
         assert np.array_equal(dmn_linear_compressed(K, w, net.normals, C1, C2), ref)
     assert compressed_tree(K, np.zeros(2 ** K)) is None
+
+
+# ---------------------------------------------------------------- online evaluation
+
+def gp_case(K, seed, T=4, mag=0.05):
+    rs = S.streams(seed)
+    net = S.random_dmn(rs["dmn"], K, 0.3)
+    E = S.ramp_with_noise(rs, 1, T, mag, 1e-3)[:, 0, :]
+    return net, E
+
+
+def test_compressed_gp_without_dead_leaves_is_the_full_model():
+    from oracle.compression import CompressedDmnModel, compressed_path
+    from oracle.gp import DmnModel, run_path
+    K = 3
+    net, E = gp_case(K, 101)
+    full = run_path(DmnModel(K, net.w, net.normals, S.FIBER, S.MATRIX), E)
+    comp = compressed_path(CompressedDmnModel(K, net.w, net.normals, S.FIBER, S.MATRIX), E)
+    for f, c in zip(full, comp):
+        assert f["status"] == c["status"] == 0 and f["iters"] == c["iters"]
+        assert rel(c["sigma"], f["sigma"]) < 1e-12 and rel(c["C"], f["C"]) < 1e-11
+        assert rel(c["a"], f["a"]) < 1e-10 and rel(c["z"], f["z"]) < 1e-10
+
+
+def test_compressed_gp_is_the_zero_weight_limit():
+    """The dense model with weights eps on the removed leaves approaches the
+    compressed model as eps -> 0 (stress, tangent, live internal variables)."""
+    from oracle.compression import CompressedDmnModel, compressed_path
+    from oracle.gp import DmnModel, run_path
+    K = 3
+    net, E = gp_case(K, 102, T=3)
+    dead = [2, 3, 5]          # a dead sibling pair and a zero leaf beside a live one
+    w0 = net.w.copy()
+    w0[dead] = 0.0
+    model = CompressedDmnModel(K, w0, net.normals, S.FIBER, S.MATRIX)
+    comp = compressed_path(model, E)
+    live_m = [m for m in range(2 ** (K - 1)) if 2 * m + 1 in model.live_leaves]
+    errs = []
+    for eps in (1e-5, 1e-7, 1e-9):
+        we = w0.copy()
+        we[dead] = eps
+        full = run_path(DmnModel(K, we, net.normals, S.FIBER, S.MATRIX), E)
+        e = 0.0
+        for f, c in zip(full, comp):
+            assert f["status"] == c["status"] == 0
+            e = max(e, rel(f["sigma"], c["sigma"]), rel(f["C"], c["C"]),
+                    rel(f["z"][live_m], c["z"][live_m]))
+        errs.append(e)
+    # first-order convergence in eps (a dilute inclusion perturbs at O(eps))
+    assert errs[2] < 1e-4 and errs[1] < 0.05 * errs[0] and errs[2] < 0.05 * errs[1], errs
+
+
+def test_compressed_gp_dead_half_is_the_live_laminate():
+    from oracle.compression import CompressedDmnModel, compressed_path
+    from oracle.gp import DmnModel, run_path
+    K = 2
+    net, E = gp_case(K, 103, T=3)
+    w = net.w.copy()
+    w[2:] = 0.0
+    p = lam_pos(K, 2, 1)
+    ref = run_path(DmnModel(1, w[:2], net.normals[p:p + 1], S.FIBER, S.MATRIX), E)
+    comp = compressed_path(CompressedDmnModel(K, w, net.normals, S.FIBER, S.MATRIX), E)
+    for f, c in zip(ref, comp):
+        assert f["status"] == c["status"] == 0 and f["iters"] == c["iters"]
+        assert rel(c["sigma"], f["sigma"]) < 1e-13 and rel(c["C"], f["C"]) < 1e-12
+        assert rel(c["z"][:1], f["z"]) < 1e-12
+        assert rel(c["a"][3 * p:3 * p + 3], f["a"]) < 1e-12
