@@ -65,8 +65,7 @@ extern "C" {
 #define DMN_STATUS_NONFINITE 2 /* non-finite input or residual */
 #define DMN_STATUS_NOTSPD 3    /* a laminate pivot of the Hessian is not positive definite */
 #define DMN_STATUS_LOCAL 4     /* J2 return mapping did not converge */
-#define DMN_STATUS_BADPARAM 5  /* negative or non-finite leaf weight, no weight at all, or a
-                                  laminate whose children carry no weight */
+#define DMN_STATUS_BADPARAM 5  /* negative or non-finite leaf weight, or no weight at all */
 
 #define DMN_MAX_DEPTH 10
 
@@ -80,12 +79,14 @@ extern "C" {
 
 /* A direct DMN: depth K, leaf weights w[2^K] (non-negative, need not sum to
  * one: fractions are weight ratios and averages use w / sum(w)).  Leaves of
- * zero weight are allowed when a sibling subtree keeps weight; a subtree
- * whose leaves all have zero weight (a dead subtree) is removed from the
- * tree by the linear map and its backward, which is the paper's tree
- * compression (Sec. 3.1), and is rejected by the Gauss-point update and the
- * adjoint (status / error DMN_STATUS_BADPARAM: compress such a DMN before the
- * online evaluation, as the paper does).  The net also has either
+ * zero weight are allowed, also whole subtrees without weight (dead
+ * subtrees, which training produces): the linear map, its backward and the
+ * Gauss-point update remove them from the tree, which is the paper's tree
+ * compression (Sec. 3.1) computed in place (a laminate with a dead child
+ * passes its other child through unchanged; dead leaves still run their leaf
+ * law, their internal variables and the jumps of removed laminates carry no
+ * meaning).  The adjoint rejects dead subtrees (DMN_STATUS_BADPARAM error
+ * bit).  The net also has either
  *   ori_shape = DMN_ORI_NONE: normals n[2^K - 1][3] in paper order (unit
  *     length expected; used as passed); or
  *   ori_shape = DMN_ORI_LINEAR / TRILINEAR / QUADRATIC: normals that depend

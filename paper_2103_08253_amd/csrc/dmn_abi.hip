@@ -239,8 +239,9 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
     tabs[i] = table_at(ws, off);
     off += table_bytes(groups[i].net.depth, DMN_F64);
     const void* nfix = groups[i].net.ori_shape == DMN_ORI_NONE ? groups[i].net.n : nullptr;
+    // dead subtrees are removed (tree compression), as in the linear map
     if (dmn::launch_prep_tables(groups[i].net.w, nfix, groups[i].net.depth, DMN_F64,
-                                tabs[i].rows, tabs[i].flag, nullptr, stream))
+                                tabs[i].rows, tabs[i].flag, nullptr, stream, true))
       return DMN_EHIP;
   }
 

@@ -423,15 +423,41 @@ def test_training_step_with_dead_subtree_matches_complex_step():
     assert abs(stats.cpu().numpy()[3] - J) <= 1e-10 * J
 
 
-def test_gauss_point_update_rejects_dead_subtrees():
+@pytest.mark.parametrize("K,P,T", [(3, 24, 4), (8, 16, 3)])
+def test_gauss_point_update_compresses_dead_subtrees(K, P, T):
+    """The Gauss-point update of a DMN with dead subtrees against the oracle's
+    compressed tree: stress, tangent, iteration counts every step; internal
+    variables of live leaves and jumps of live laminates at the end."""
+    from oracle.compression import CompressedDmnModel, compressed_path
     from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
-    say("Gauss-point update with a dead subtree")
-    w, nrm, rs = dead_weights(3, 76)
-    E = tt(1e-3 * rs["direction"].standard_normal((5, 6)))
-    g = PointGroup.allocate(tt(w), tt(nrm), E)
-    dmn_update_gauss_points([g], S.FIBER, S.MATRIX)
-    torch.cuda.synchronize()
-    assert (g.status == 5).all()
+    say(f"Gauss-point update with dead subtrees K={K} P={P} T={T}")
+    w, nrm, rs = dead_weights(K, 77 + K)
+    E = S.ramp_with_noise(rs, P, T, 0.03, 1e-3)
+    g = PointGroup.allocate(tt(w), tt(nrm), tt(E[0]))
+    model = CompressedDmnModel(K, w, nrm, S.FIBER, S.MATRIX)
+    refs = [compressed_path(model, E[:, p, :]) for p in range(P)]
+    keep = [p for p in range(P) if min(x["margin"] for x in refs[p]) >= 1e-9]
+    assert len(keep) >= P // 2
+    M = 2 ** (K - 1)
+    live_m = [m for m in range(M) if 2 * m + 1 in model.live_leaves]
+    live_a = np.concatenate([[3 * q, 3 * q + 1, 3 * q + 2] for q in model.pos])
+    ws = None
+    for t in range(T):
+        g.E.copy_(tt(E[t]))
+        ws = dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws)
+        torch.cuda.synchronize()
+        sig, tan = g.sigma.cpu().numpy(), g.tangent.cpu().numpy().reshape(P, 6, 6)
+        st, it = g.status.cpu().numpy(), g.iters.cpu().numpy()
+        for p in keep:
+            r = refs[p][t]
+            assert st[p] == r["status"] == 0 and it[p] == r["iters"], (t, p)
+            assert rel(sig[p], r["sigma"]) < 1e-10 and rel(tan[p], r["C"]) < 1e-10, (t, p)
+        g.advance()
+    z = g.z_in.cpu().numpy().reshape(P, M, 7)
+    a = g.a_in.cpu().numpy().reshape(P, -1)
+    for p in keep:
+        assert rel(z[p][live_m], refs[p][-1]["z"][live_m]) < 1e-9
+        assert rel(a[p][live_a], refs[p][-1]["a"][live_a]) < 1e-9
 
 
 @pytest.mark.parametrize("K", [1, 10])
