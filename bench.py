@@ -120,9 +120,9 @@ def main():
                     help="skip the mixed-batch graph and the one-launch-per-point forms")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single "
-              "MI355X (points are independent; see the sharding notes of the design).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the hot path on a single "
+              "MI355X; Gauss points are independent, and sharding them over several GPUs "
+              "is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

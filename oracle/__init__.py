@@ -29,6 +29,6 @@ compression  Tree compression of zero-weight subtrees (Sec. 3.1) and the
 training   Offline-training objective (Sec. 3.1), AMSGrad with the modulated
            learning rate (Sec. 4.5) and the stiffness sampler (Sec. 4.4).
 
-Readings of points the paper leaves open are listed in each function's
-docstring and in the design notes of the repository.
+Readings of points the paper leaves open are stated in each function's
+docstring.
 """
