@@ -210,3 +210,36 @@ def test_training_validation_codes():
     assert lib.dmn_sample_stiffness(-1, L.DMN_F64, FAKE, FAKE, FAKE, None) == L.DMN_EINVAL
     assert lib.dmn_sample_stiffness(4, L.DMN_F64, None, FAKE, FAKE, None) == L.DMN_EINVAL
     assert lib.dmn_sample_stiffness(4, 9, FAKE, FAKE, FAKE, None) == L.DMN_EUNSUPPORTED
+
+
+def test_orientation_group_validation_codes():
+    lib = L.lib()
+    lin = L.DMN_ORI["linear"]
+    gn = lambda depth=3, shape=lin, G=4, prec=L.DMN_F64, p=FAKE, lam=FAKE: \
+        lib.dmn_orientation_group_normals(depth, shape, G, prec, p, FAKE, lam, FAKE, None)
+    assert gn(depth=0) == L.DMN_EINVAL
+    assert gn(shape=L.DMN_ORI["none"]) == L.DMN_EINVAL
+    assert gn(shape=9) == L.DMN_EINVAL
+    assert gn(G=-1) == L.DMN_EINVAL
+    assert gn(prec=L.DMN_F32_STATE) == L.DMN_EUNSUPPORTED
+    assert gn(p=None) == L.DMN_EINVAL
+    assert gn(lam=None) == L.DMN_EINVAL
+    ch = lambda G=4, gw=FAKE, gpq=FAKE: lib.dmn_orientation_group_chain(
+        3, lin, G, L.DMN_F64, FAKE, FAKE, FAKE, FAKE, FAKE, gw, gpq, None)
+    assert ch(gw=None) == L.DMN_EINVAL
+    assert ch(gpq=None) == L.DMN_EINVAL
+    assert ch(G=-2) == L.DMN_EINVAL
+    opts = L.DmnAmsgradOpts(1.5e-3, 1.5e-2, 0.999, 50, 1, 0.9, 0.999, 1e-8, 1e3)
+    good = L.DmnTrainParamsOriented(3, lin, *([FAKE.value] * 6))
+    up = lambda pr=good, o=opts, prec=L.DMN_F64: lib.dmn_training_update_oriented(
+        ctypes.byref(pr) if pr is not None else None, prec, FAKE, FAKE,
+        ctypes.byref(o) if o is not None else None, FAKE, None)
+    assert up(pr=None) == L.DMN_EINVAL
+    assert up(pr=L.DmnTrainParamsOriented(3, 0, *([FAKE.value] * 6))) == L.DMN_EINVAL
+    assert up(pr=L.DmnTrainParamsOriented(11, lin, *([FAKE.value] * 6))) == L.DMN_EINVAL
+    assert up(pr=L.DmnTrainParamsOriented(3, lin, None, *([FAKE.value] * 5))) == L.DMN_EINVAL
+    assert up(o=None) == L.DMN_EINVAL
+    assert up(prec=4) == L.DMN_EUNSUPPORTED
+    bad = L.DmnAmsgradOpts(1.5e-3, 1.5e-2, 0.999, 0, 1, 0.9, 0.999, 1e-8, 1e3)
+    assert up(o=bad) == L.DMN_EINVAL
+    assert lib.dmn_training_refresh_oriented(None, L.DMN_F64, None) == L.DMN_EINVAL
