@@ -55,7 +55,8 @@ extern "C" {
 
 /* precision of storage and arithmetic */
 #define DMN_F64 0       /* FP64 storage, FP64 arithmetic */
-#define DMN_F32 1       /* FP32 storage, FP32 arithmetic (linear map only) */
+#define DMN_F32 1       /* FP32 storage, FP32 arithmetic (linear map, its backward and
+                           the training calls, which keep their sums in FP64) */
 #define DMN_F32_STATE 2 /* FP32 storage of per-point arrays, FP64 arithmetic (reserved:
                            currently rejected with DMN_EUNSUPPORTED) */
 
@@ -101,8 +102,10 @@ extern "C" {
  *     triangle extrapolate the polynomials.  Supported by
  *     dmn_update_gauss_points (per-point orientation).  The linear map and
  *     its backward accept the per-sample form below but currently return
- *     DMN_EUNSUPPORTED (switched off); dmn_update_adjoint returns
- *     DMN_EUNSUPPORTED.
+ *     DMN_EUNSUPPORTED (switched off); training over a discrete set of
+ *     orientations runs the fixed-normal calls per orientation group
+ *     instead (dmn_orientation_group_normals and the calls after it).
+ *     dmn_update_adjoint returns DMN_EUNSUPPORTED.
  * All arrays are device memory in the precision of the call. */
 typedef struct dmn_net {
   int32_t depth;
