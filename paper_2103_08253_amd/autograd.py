@@ -6,8 +6,11 @@
   adjoint swept over checkpointed segments as its backward (gradients w.r.t.
   the leaf weights and normals).
 
-Normals are taken as passed; build them from spherical angles with
-`normals_from_angles` to train the angles (torch differentiates that map).
+Normals are taken as passed.  `normals_from_angles` is a convenience for
+callers who compose the map with their own torch code (torch then
+differentiates the angle map); the library's training step
+(`training.TrainingStepGraph`) does not use it: there the angle chain and the
+optimiser run in the update kernel.
 """
 import torch
 
