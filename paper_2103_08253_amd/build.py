@@ -3,8 +3,8 @@
     python -m paper_2103_08253_amd.build [--jobs N] [--verbose]
 
 Each csrc/*.hip file is compiled to an object with hipcc, then linked into
-paper_2103_08253_amd/libdmn.so.  Packed FP32 instructions are disabled for
-all device code.
+paper_2103_08253_amd/libdmn.so; the host programs in examples/ are linked
+against it.  Packed FP32 instructions are disabled for all device code.
 """
 import argparse
 import os
@@ -61,7 +61,29 @@ def build(jobs=None, verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    _build_examples(verbose)
     return LIB
+
+
+EXAMPLES = os.path.join(PKG, "examples")
+
+
+def _build_examples(verbose):
+    """Host programs that use libdmn through its C ABI only (linked in-tree)."""
+    for f in sorted(os.listdir(EXAMPLES)):
+        if not f.endswith(".cpp"):
+            continue
+        exe = os.path.join(EXAMPLES, f[:-4])
+        cmd = [HIPCC, "-O2", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE,
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               os.path.join(EXAMPLES, f), "-o", exe + ".tmp", "-L", PKG, "-ldmn",
+               "-Wl,-rpath,$ORIGIN/.."]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {f}:\n{r.stdout}\n{r.stderr}")
+        os.replace(exe + ".tmp", exe)
 
 
 def main(argv=None):
