@@ -640,3 +640,30 @@ def test_oriented_training_graph_matches_eager_and_oracle():
                               Pg.q.cpu().numpy().ravel()])
         say(f"   step {step}: J {J:.6e} param rel err {rel(got, th):.2e}")
         assert rel(got, th) < 1e-10, step
+
+
+def test_oriented_training_step_with_empty_groups():
+    """Ten orientations and six samples: four groups are empty (their map and
+    VJP run with no samples and contribute nothing)."""
+    from paper_2103_08253_amd import AmsgradOpts, OrientedTrainingStepGraph, OrientedTrainParams
+    K, B, kind, lam_pen = 3, 6, "linear", 10.0
+    say(f"oriented training step with empty groups K={K} B={B}")
+    C1, C2, Tt, lam_g, lam_s, offsets, v, p, q = oriented_case(K, B, kind, 94, level=1)
+    assert (np.diff(offsets) == 0).sum() == 4
+    eps, lr = 1e6, 1e3
+    opts = AmsgradOpts(lr_min=lr, lr_max=lr, lr_decay=1.0, beta1=0.0, beta2=0.0, eps=eps,
+                       penalty=lam_pen)
+    P = OrientedTrainParams.create(kind, tt(v), tt(p), tt(q))
+    g = OrientedTrainingStepGraph(P, tt(C1), tt(C2), tt(Tt), tt(lam_g), offsets, opts=opts)
+    g.replay()
+    torch.cuda.synchronize()
+    assert all(e == 0 for e in g.error_words())
+    th0 = np.concatenate([v, p.ravel(), q.ravel()])
+    th1 = np.concatenate([P.v.cpu().numpy(), P.p.cpu().numpy().ravel(),
+                          P.q.cpu().numpy().ravel()])
+    d = th0 - th1
+    g_gpu = d * eps / (lr - np.abs(d))
+    ref = T.objective_oriented_gradient(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
+    g_ref = np.concatenate([ref["gv"], ref["gP"].ravel(), ref["gQ"].ravel()])
+    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    assert rel(g_gpu, g_ref) < 1e-8
