@@ -1,7 +1,8 @@
-// Offline training of a DMN with fixed normals: the objective's data term and
-// its cotangent (Sec. 3.1), the parameter update (Macaulay weights, normal
-// angles, mixing penalty of Sec. 3.1; AMSGrad with the modulated learning
-// rate of Sec. 4.5) and the stiffness sampler of Sec. 4.4.
+// Offline training of a DMN: the objective's data term and its cotangent
+// (Sec. 3.1), the parameter update (Macaulay weights, normal angles, mixing
+// penalty of Sec. 3.1; AMSGrad with the modulated learning rate of Sec. 4.5),
+// the per-group normals and cotangent chain for training over a discrete set
+// of fibre orientations (Sec. 2.3), and the stiffness sampler of Sec. 4.4.
 //
 // All of it is bandwidth- or latency-bound work next to the linear map and its
 // VJP: per-sample kernels read and write whole 36-entry stiffness records,
