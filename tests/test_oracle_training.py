@@ -325,3 +325,42 @@ def test_oriented_objective_gradient_matches_differences():
         fdq = _richardson(lambda x: f(v, P, x.reshape(Q.shape)), Q.ravel(), flat, 1e-4)
         assert abs(g["gP"][idx] - fdp) <= 1e-7 * max(1.0, abs(fdp)), idx
         assert abs(g["gQ"][idx] - fdq) <= 1e-7 * max(1.0, abs(fdq)), idx
+
+
+def _training_setup():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "training_setup.txt")
+    disc, const = [], {}
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        f = line.split()
+        if f[0] == "discretization":
+            disc.append(tuple(int(x) for x in f[1:]))
+        else:
+            const[f[0]] = float(f[1])
+    return disc, const
+
+
+def test_sample_table_of_the_paper():
+    """The table of sample counts: 4, 10, 31 sampling points; cyclic
+    assignment of the samples gives the printed samples per microstructure;
+    the 90 / 10 split gives the printed set sizes."""
+    disc, _ = _training_setup()
+    for level, points, total, per, train, val in disc:
+        lam = S.orientation_discretization(level)
+        assert len(lam) == points
+        counts = np.bincount(np.arange(total) % points, minlength=points)
+        assert np.all(counts == per)
+        assert round(0.9 * total) == train and total - train == val
+
+
+def test_optimiser_defaults_are_the_papers():
+    from paper_2103_08253_amd.training import AmsgradOpts
+    _, c = _training_setup()
+    o = AmsgradOpts()
+    assert (o.lr_max, o.lr_min, o.lr_decay, o.half_period, o.penalty) == \
+        (c["lr_max"], c["lr_min"], c["lr_decay"], int(c["half_period"]), c["penalty"])
+    assert T.learning_rate(0) == c["lr_max"]
+    assert abs(T.learning_rate(int(c["half_period"])) -
+               c["lr_decay"] ** c["half_period"] * c["lr_min"]) < 1e-18
