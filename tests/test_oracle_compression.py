@@ -134,3 +134,28 @@ def test_compressed_gp_dead_half_is_the_live_laminate():
         assert rel(c["sigma"], f["sigma"]) < 1e-13 and rel(c["C"], f["C"]) < 1e-12
         assert rel(c["z"][:1], f["z"]) < 1e-12
         assert rel(c["a"][3 * p:3 * p + 3], f["a"]) < 1e-12
+
+
+def test_compressed_path_derivative_matches_differences():
+    """Complex-step derivative of the compressed path (a dead sibling pair)
+    along a direction over the live weights and all angles, against central
+    differences of the same functional."""
+    from oracle.adjoint import TIGHT, path_directional_derivative, path_functional
+    from oracle.grad import normals_from_angles
+    K = 2
+    net, E = gp_case(K, 104, T=3)
+    w = net.w.copy()
+    w[2:] = 0.0
+    alpha, beta = S.normals_to_angles(net.normals)
+    rs = S.streams(105)
+    g = S.unit_directions(rs["cotangent"], 1)
+    E3 = E[:, None, :]
+    vw = np.array([0.3, -0.7, 0.0, 0.0])
+    va, vb = rs["noise"].standard_normal(3), rs["noise"].standard_normal(3)
+    d = path_directional_derivative(K, w, alpha, beta, S.FIBER, S.MATRIX, E3, g, vw, va, vb,
+                                    compressed=True)
+    f = lambda h: path_functional(K, w + h * vw, normals_from_angles(alpha + h * va, beta + h * vb),
+                                  S.FIBER, S.MATRIX, E3, g, TIGHT, compressed=True)
+    h = 1e-6
+    fd = (f(h) - f(-h)) / (2 * h)
+    assert abs(d - fd) <= 1e-6 * max(abs(d), 1.0)
