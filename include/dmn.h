@@ -81,13 +81,14 @@ extern "C" {
 /* A direct DMN: depth K, leaf weights w[2^K] (non-negative, need not sum to
  * one: fractions are weight ratios and averages use w / sum(w)).  Leaves of
  * zero weight are allowed, also whole subtrees without weight (dead
- * subtrees, which training produces): the linear map, its backward and the
- * Gauss-point update remove them from the tree, which is the paper's tree
+ * subtrees, which training produces): the linear map, its backward, the
+ * Gauss-point update and its adjoint remove them from the tree, which is the
+ * paper's tree
  * compression (Sec. 3.1) computed in place (a laminate with a dead child
  * passes its other child through unchanged; dead leaves still run their leaf
  * law, their internal variables and the jumps of removed laminates carry no
- * meaning).  The adjoint rejects dead subtrees (DMN_STATUS_BADPARAM error
- * bit).  The net also has either
+ * meaning; the adjoint's cotangents of removed leaves' weights are finite but
+ * not derivatives).  The net also has either
  *   ori_shape = DMN_ORI_NONE: normals n[2^K - 1][3] in paper order (unit
  *     length expected; used as passed); or
  *   ori_shape = DMN_ORI_LINEAR / TRILINEAR / QUADRATIC: normals that depend

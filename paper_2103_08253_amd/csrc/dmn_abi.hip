@@ -361,8 +361,9 @@ int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
     double* gsum = (double*)((char*)ws + off + table_bytes(K, DMN_F64));
     double* partials = (double*)((char*)gsum + align_up(rows * sizeof(double)));
     off += adjoint_group_bytes(g);
+    // dead subtrees are removed (tree compression), as in the forward update
     if (dmn::launch_prep_tables(g.net.w, g.net.n, K, DMN_F64, tb.rows, tb.flag,
-                                i == 0 ? err : nullptr, stream))
+                                i == 0 ? err : nullptr, stream, true))
       return DMN_EHIP;
     if (g.P == 0) continue;
     dmn::AdjointLaunch a;

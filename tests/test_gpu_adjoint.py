@@ -215,3 +215,30 @@ def test_autograd_wrappers():
     _, gw, gn = gpu_gradient(net, E, g, ck=2, tol=1e-10)
     assert np.allclose(w2.grad.cpu().numpy(), gw, rtol=1e-12, atol=1e-14)
     assert np.allclose(n2.grad.cpu().numpy(), gn, rtol=1e-12, atol=1e-14)
+
+
+def test_adjoint_with_dead_subtrees_matches_compressed_path():
+    """A dead sibling pair and a zero leaf: the swept adjoint's gradient along
+    directions over the live weights and all angles against the complex-step
+    derivative of the oracle's compressed path."""
+    say("case: path adjoint with dead subtrees, depth 3")
+    K = 3
+    net, E, g = case(K, 430, 3, 4)
+    w = net.w.copy()
+    w[2:4] = 0.0
+    w[6] = 0.0
+    net.w = w
+    _, gw, gn = gpu_gradient(net, E, g, ck=2)
+    assert np.all(np.isfinite(gw)) and np.all(np.isfinite(gn))
+    alpha, beta = S.normals_to_angles(net.normals)
+    ga, gb = angle_grads(gn, alpha, beta)
+    rs = S.streams(431)
+    for trial in range(3):
+        vw = rs["noise"].standard_normal(2 ** K) * (w > 0)
+        va = rs["noise"].standard_normal(2 ** K - 1)
+        vb = rs["noise"].standard_normal(2 ** K - 1)
+        got = gw @ vw + ga @ va + gb @ vb
+        ref = path_directional_derivative(K, w, alpha, beta, S.FIBER, S.MATRIX, E, g, vw, va,
+                                          vb, compressed=True)
+        say(f"   direction {trial}: gpu {got:.12e} oracle {ref:.12e}")
+        assert abs(got - ref) <= 1e-9 * max(abs(ref), 1e-3)
