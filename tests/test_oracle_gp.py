@@ -157,3 +157,33 @@ def test_status_codes():
     # zero strain from the virgin state: zero residual, converged without a step
     out = G.gp_update(m, np.zeros(6), z, a)
     assert out["status"] == 0 and out["iters"] == 0
+
+
+def test_rotational_covariance_of_the_nonlinear_update():
+    """Isotropic phases: rotating the macro strain path and every normal by R
+    rotates the stress, the tangent and the plastic strains, and leaves the
+    accumulated plastic strains, the iteration counts and the jump lengths
+    unchanged."""
+    from oracle.mandel import rotation_mandel
+    rng = np.random.default_rng(19)
+    K = 3
+    net = S.random_dmn(rng, K, 0.3)
+    R, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(R) < 0:
+        R[:, 0] *= -1
+    Q = rotation_mandel(R)
+    d = rng.standard_normal(6)
+    E_path = np.outer(np.linspace(0.25, 1.0, 4), 0.04 * d / np.linalg.norm(d))
+    base = G.run_path(G.DmnModel(K, net.w, net.normals, S.FIBER, S.MATRIX), E_path)
+    rot = G.run_path(G.DmnModel(K, net.w, net.normals @ R.T, S.FIBER, S.MATRIX),
+                     E_path @ Q.T)
+    assert any(np.abs(o["z"][:, 6]).max() > 0 for o in base)   # the path yields
+    for b, r in zip(base, rot):
+        assert b["status"] == r["status"] == 0 and b["iters"] == r["iters"]
+        assert np.abs(r["sigma"] - Q @ b["sigma"]).max() <= 1e-10 * np.abs(b["sigma"]).max()
+        assert np.abs(r["C"] - Q @ b["C"] @ Q.T).max() <= 1e-10 * np.abs(b["C"]).max()
+        assert np.allclose(r["z"][:, :6], b["z"][:, :6] @ Q.T, atol=1e-12)
+        assert np.allclose(r["z"][:, 6], b["z"][:, 6], atol=1e-14)
+        ja = np.linalg.norm(b["a"].reshape(-1, 3), axis=1)
+        jr = np.linalg.norm(r["a"].reshape(-1, 3), axis=1)
+        assert np.allclose(ja, jr, rtol=1e-9, atol=1e-14)
