@@ -485,8 +485,10 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         del lg, c1s, c2s, gcs
     out["train_fwd_bwd_batch_sweep"] = sweep
     # training over the paper's 31 fibre orientations (linear shape functions):
-    # the batch grouped by orientation, one fixed-normal map and VJP per group
+    # the batch grouped by orientation, the fixed-normal maps and VJPs of all
+    # groups in one grouped call each (beside: one call per group on 4 streams)
     from paper_2103_08253_amd import (OrientedTrainingStepGraph, OrientedTrainParams,
+                                      dmn_homogenize_linear_groups,
                                       dmn_orientation_group_normals)
     ow = S.oriented_training_workload(batch=B)
     lam_t = torch.tensor(ow.lam, device=dev)
@@ -496,10 +498,7 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
     n_truth = dmn_orientation_group_normals(truth_o, lam_t)
     C1o = torch.tensor(ow.C1, device=dev)
     C2o = torch.tensor(ow.C2, device=dev)
-    tgt_o = torch.empty_like(C1o)
-    for k in range(len(ow.lam)):
-        a_, b_ = int(ow.offsets[k]), int(ow.offsets[k + 1])
-        dmn_homogenize_linear(truth_o.w, n_truth[k], C1o[a_:b_], C2o[a_:b_], Cbar=tgt_o[a_:b_])
+    tgt_o, _ = dmn_homogenize_linear_groups(truth_o.w, n_truth, ow.offsets, C1o, C2o)
     train_o = {}
     for nb in (B, 32):
         G = len(ow.lam)
@@ -522,8 +521,18 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         for _ in range(480):
             go.replay()
         hist[int(Po.step.item())] = float(go.stats[3].item())
+        Pp = OrientedTrainParams.create(ow.truth.kind, torch.tensor(ow.v0, device=dev),
+                                        torch.tensor(ow.p0, device=dev),
+                                        torch.tensor(ow.q0, device=dev))
+        gp = OrientedTrainingStepGraph(Pp, C1o[sel].contiguous(), C2o[sel].contiguous(),
+                                       tgt_o[sel].contiguous(), lam_t, offs,
+                                       opts=AmsgradOpts(steps_per_epoch=10), grouped=False)
+        gp.replay()
+        torch.cuda.synchronize()
+        ms_pg = _event_ms(gp.replay, 20) / 20
+        del gp
         train_o[nb] = dict(ms_per_step=ms, samples_per_s=nb / (ms * 1e-3),
-                           objective_at_step=hist)
+                           per_group_calls_ms_per_step=ms_pg, objective_at_step=hist)
     out["training_oriented_step_graph"] = dict(
         depth=8, orientations=len(ow.lam), shape_functions=ow.truth.kind,
         batch_4096=train_o[B], batch_32=train_o[32])

@@ -418,11 +418,51 @@ int dmn_training_refresh(const dmn_train_params* params, int prec, hipStream_t s
 /* Training over a discrete set of G fibre orientations (Sec. 2.3, the
  * paper's identification of an orientation-interpolated DMN, Sec. 4.5):
  * samples of orientation k see the normals n_k, so a step evaluates the
- * fixed-normal dmn_homogenize_linear / dmn_homogenize_backward once per
- * orientation group with n_k from dmn_orientation_group_normals, takes the
+ * fixed-normal linear map and its VJP for every orientation group with n_k
+ * from dmn_orientation_group_normals (all groups at once with
+ * dmn_homogenize_linear_groups / dmn_homogenize_backward_groups, or one
+ * dmn_homogenize_linear / dmn_homogenize_backward call per group), takes the
  * objective over the whole batch with dmn_training_loss, chains the groups'
  * gw, gn to the angle coefficients with dmn_orientation_group_chain and
  * updates (v, p, q) with dmn_training_update_oriented. */
+
+/* Workspace bytes for dmn_homogenize_linear_groups (0 for an invalid depth,
+ * G or prec). */
+size_t dmn_homogenize_linear_groups_workspace_size(int32_t depth, int32_t G, int prec);
+
+/* The linear map (Sec. 3.1) of G DMNs of one depth that share the leaf
+ * weights w [2^K] and differ in their normals n_groups [G][L][3] (paper
+ * order; one DMN per orientation of a discrete set, Sec. 2.3), over one batch
+ * whose samples offsets[k] .. offsets[k+1]-1 belong to group k.  offsets:
+ * host array of G+1 int64 with offsets[0] = 0, non-decreasing (empty groups
+ * allowed), offsets[G] = B, read during the call.  C1, C2, Cbar [B][36] as
+ * for dmn_homogenize_linear, whose results (also for dead subtrees) the call
+ * reproduces group by group: it prepares the G tables in one launch and
+ * evaluates up to 64 groups per forward launch.  Invalid offsets or G < 1
+ * return DMN_EINVAL.  Same device error word as dmn_homogenize_linear (set
+ * when any group fails). */
+int dmn_homogenize_linear_groups(int32_t depth, int32_t G, const int64_t* offsets, int prec,
+                                 const void* w, const void* n_groups, const void* C1,
+                                 const void* C2, void* Cbar, void* ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/* Workspace bytes for dmn_homogenize_backward_groups (0 for an invalid depth,
+ * G, offsets or prec). */
+size_t dmn_homogenize_backward_groups_workspace_size(int32_t depth, int32_t G,
+                                                     const int64_t* offsets, int prec);
+
+/* VJP of dmn_homogenize_linear_groups: given gCbar [B][36], writes
+ * (overwrites) gw_groups [G][2^K] and gn_groups [G][L][3], group k's rows
+ * being what dmn_homogenize_backward returns for the samples of group k at
+ * normals n_groups[k] (zero for an empty group), bit-identical to it (the
+ * same waves per group and the same fixed reduction order).  No phase
+ * stiffness cotangents.  The forward is recomputed inside the call.  Same
+ * error word as the forward. */
+int dmn_homogenize_backward_groups(int32_t depth, int32_t G, const int64_t* offsets, int prec,
+                                   const void* w, const void* n_groups, const void* C1,
+                                   const void* C2, const void* gCbar, void* gw_groups,
+                                   void* gn_groups, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
 
 /* n [G][L][3]: for orientation lam[k] = (l1, l2) (lam [G][2]) and angle
  * coefficients p, q [L][M] (M from ori_shape, see dmn_net), laminate l gets

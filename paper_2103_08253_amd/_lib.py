@@ -129,6 +129,25 @@ _SIGS = {
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_size_t, ctypes.c_void_p]),
+    "dmn_homogenize_linear_groups_workspace_size": (ctypes.c_size_t, [ctypes.c_int32,
+                                                                      ctypes.c_int32,
+                                                                      ctypes.c_int]),
+    "dmn_homogenize_linear_groups": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                                    ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_size_t, ctypes.c_void_p]),
+    "dmn_homogenize_backward_groups_workspace_size": (ctypes.c_size_t, [
+        ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    "dmn_homogenize_backward_groups": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32,
+                                                      ctypes.POINTER(ctypes.c_int64),
+                                                      ctypes.c_int, ctypes.c_void_p,
+                                                      ctypes.c_void_p, ctypes.c_void_p,
+                                                      ctypes.c_void_p, ctypes.c_void_p,
+                                                      ctypes.c_void_p, ctypes.c_void_p,
+                                                      ctypes.c_void_p, ctypes.c_size_t,
+                                                      ctypes.c_void_p]),
     "dmn_update_gauss_points_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(DmnPointGroup),
                                                                  ctypes.c_int32, ctypes.c_int]),
     "dmn_update_gauss_points": (ctypes.c_int, [ctypes.POINTER(DmnPointGroup), ctypes.c_int32,

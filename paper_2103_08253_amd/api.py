@@ -143,6 +143,74 @@ def dmn_homogenize_backward(w, n, C1, C2, gCbar, want_input_grads=False, ws=None
     return gw, gn, gC1, gC2, ws
 
 
+def _group_offsets(offsets, G: int, B: int):
+    """Host int64 array of the G + 1 sample offsets of a grouped call."""
+    off = [int(x) for x in offsets]
+    if len(off) != G + 1 or off[0] != 0 or off[-1] != B or any(
+            b < a for a, b in zip(off, off[1:])):
+        raise ValueError("offsets must split the batch into one range per group")
+    return (ctypes.c_int64 * (G + 1))(*off)
+
+
+def _groups_args(w, n_groups, offsets, C1, tensors):
+    dtype = C1.dtype
+    if dtype not in _PREC:
+        raise TypeError("float64 or float32 expected")
+    K = int(round(torch.log2(torch.tensor(float(w.numel()))).item()))
+    if 2 ** K != w.numel() or not 1 <= K <= 10:
+        raise ValueError("w must hold 2^K leaf weights with 1 <= K <= 10")
+    if n_groups.dim() != 3 or n_groups.shape[1:] != (2 ** K - 1, 3) or n_groups.shape[0] < 1:
+        raise ValueError("n_groups must be [G, 2^K - 1, 3]")
+    G, B = n_groups.shape[0], C1.shape[0]
+    _need(w, "w", dtype, (2 ** K,))
+    _need(n_groups, "n_groups", dtype)
+    for t, nm in tensors:
+        _need(t, nm, dtype)
+        if t.numel() != 36 * B:
+            raise ValueError(f"{nm} must be [B, 6, 6]")
+    return K, G, B, _group_offsets(offsets, G, B), _PREC[dtype]
+
+
+def dmn_homogenize_linear_groups(w, n_groups, offsets, C1, C2, Cbar=None, ws=None):
+    """Linear map of G DMNs sharing w with normals n_groups [G, L, 3]; samples
+    offsets[k]:offsets[k+1] of the batch belong to group k."""
+    if Cbar is None:
+        Cbar = torch.empty((C1.shape[0], 6, 6), dtype=C1.dtype, device=C1.device)
+    K, G, B, off, prec = _groups_args(w, n_groups, offsets, C1,
+                                      ((C1, "C1"), (C2, "C2"), (Cbar, "Cbar")))
+    lib = L.lib()
+    nbytes = lib.dmn_homogenize_linear_groups_workspace_size(K, G, prec)
+    if ws is None or ws.numel() < nbytes:
+        ws = workspace(nbytes, C1.device)
+    rc = lib.dmn_homogenize_linear_groups(K, G, off, prec, _ptr(w), _ptr(n_groups), _ptr(C1),
+                                          _ptr(C2), _ptr(Cbar), _ptr(ws), ws.numel(), _stream())
+    L.check(rc, "dmn_homogenize_linear_groups")
+    return Cbar, ws
+
+
+def dmn_homogenize_backward_groups(w, n_groups, offsets, C1, C2, gCbar, gw_groups=None,
+                                   gn_groups=None, ws=None):
+    """(gw_groups [G, 2^K], gn_groups [G, L, 3], ws): group k's rows are the
+    VJP of its samples at normals n_groups[k]."""
+    K, G, B, off, prec = _groups_args(w, n_groups, offsets, C1,
+                                      ((C1, "C1"), (C2, "C2"), (gCbar, "gCbar")))
+    if gw_groups is None:
+        gw_groups = torch.empty((G, 2 ** K), dtype=C1.dtype, device=C1.device)
+    if gn_groups is None:
+        gn_groups = torch.empty((G, 2 ** K - 1, 3), dtype=C1.dtype, device=C1.device)
+    _need(gw_groups, "gw_groups", C1.dtype, (G, 2 ** K))
+    _need(gn_groups, "gn_groups", C1.dtype, (G, 2 ** K - 1, 3))
+    lib = L.lib()
+    nbytes = lib.dmn_homogenize_backward_groups_workspace_size(K, G, off, prec)
+    if ws is None or ws.numel() < nbytes:
+        ws = workspace(nbytes, C1.device)
+    rc = lib.dmn_homogenize_backward_groups(K, G, off, prec, _ptr(w), _ptr(n_groups), _ptr(C1),
+                                            _ptr(C2), _ptr(gCbar), _ptr(gw_groups),
+                                            _ptr(gn_groups), _ptr(ws), ws.numel(), _stream())
+    L.check(rc, "dmn_homogenize_backward_groups")
+    return gw_groups, gn_groups, ws
+
+
 @dataclass
 class Orientation:
     """Normals interpolated over the fibre orientation triangle: shape-function

@@ -6,7 +6,7 @@
 #include <atomic>
 #include <vector>
 
-#include "dmn_internal.hpp"
+#include "dmn_groups.hpp"
 
 namespace {
 
@@ -180,6 +180,80 @@ int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void*
   // B == 0 still runs the (empty) reductions so gw, gn are overwritten with zeros
   if (dmn::launch_linear_backward(K, prec, tb.rows, tb.flag, B, C1, C2, gCbar, gw, gn, gC1, gC2,
                                   partials, gsum, err, lin_ori(net, lam, gang), stream))
+    return DMN_EHIP;
+  return DMN_OK;
+}
+
+// sample offsets of a grouped linear call: G >= 1, offsets[0] = 0, non-decreasing
+static bool group_offsets_ok(int32_t G, const int64_t* off) {
+  if (G < 1 || !off || off[0] != 0) return false;
+  for (int32_t k = 0; k < G; ++k)
+    if (off[k + 1] < off[k]) return false;
+  return true;
+}
+
+size_t dmn_homogenize_linear_groups_workspace_size(int32_t depth, int32_t G, int prec) {
+  if (!depth_ok(depth) || G < 1 || (prec != DMN_F64 && prec != DMN_F32)) return 0;
+  return kAlign + (size_t)G * table_bytes(depth, prec);
+}
+
+int dmn_homogenize_linear_groups(int32_t depth, int32_t G, const int64_t* offsets, int prec,
+                                 const void* w, const void* n_groups, const void* C1,
+                                 const void* C2, void* Cbar, void* ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!depth_ok(depth) || !group_offsets_ok(G, offsets) || !w || !n_groups) return DMN_EINVAL;
+  const int64_t B = offsets[G];
+  if (B > 0 && (!C1 || !C2 || !Cbar)) return DMN_EINVAL;
+  const size_t need = dmn_homogenize_linear_groups_workspace_size(depth, G, prec);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
+  int32_t* err = (int32_t*)ws;
+  Table tb = table_at(ws, kAlign);
+  const long long tbytes = (long long)table_bytes(depth, prec);
+  if (dmn::launch_prep_tables_groups(w, n_groups, depth, prec, G, tb.rows, tb.flag, tbytes, err,
+                                     stream))
+    return DMN_EHIP;
+  if (B == 0) return DMN_OK;
+  if (dmn::launch_linear_forward_groups(depth, prec, tb.rows, tb.flag, tbytes, G, offsets, C1, C2,
+                                        Cbar, err, stream))
+    return DMN_EHIP;
+  return DMN_OK;
+}
+
+size_t dmn_homogenize_backward_groups_workspace_size(int32_t depth, int32_t G,
+                                                     const int64_t* offsets, int prec) {
+  if (!depth_ok(depth) || !group_offsets_ok(G, offsets) || (prec != DMN_F64 && prec != DMN_F32))
+    return 0;
+  const size_t L = ((size_t)1 << depth) - 1;
+  const size_t slots = (size_t)dmn::linear_backward_group_slots(depth, G, offsets);
+  return kAlign + (size_t)G * table_bytes(depth, prec) +
+         align_up((size_t)G * L * 4 * sizeof(double)) + align_up(slots * L * 4 * sizeof(double));
+}
+
+int dmn_homogenize_backward_groups(int32_t depth, int32_t G, const int64_t* offsets, int prec,
+                                   const void* w, const void* n_groups, const void* C1,
+                                   const void* C2, const void* gCbar, void* gw_groups,
+                                   void* gn_groups, void* ws, size_t ws_bytes,
+                                   hipStream_t stream) {
+  if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
+  if (!depth_ok(depth) || !group_offsets_ok(G, offsets) || !w || !n_groups) return DMN_EINVAL;
+  if (!gw_groups || !gn_groups) return DMN_EINVAL;
+  const int64_t B = offsets[G];
+  if (B > 0 && (!C1 || !C2 || !gCbar)) return DMN_EINVAL;
+  const size_t need = dmn_homogenize_backward_groups_workspace_size(depth, G, offsets, prec);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
+  const size_t L = ((size_t)1 << depth) - 1;
+  int32_t* err = (int32_t*)ws;
+  Table tb = table_at(ws, kAlign);
+  const long long tbytes = (long long)table_bytes(depth, prec);
+  double* gsum = (double*)((char*)ws + kAlign + (size_t)G * (size_t)tbytes);
+  double* partials = (double*)((char*)gsum + align_up((size_t)G * L * 4 * sizeof(double)));
+  if (dmn::launch_prep_tables_groups(w, n_groups, depth, prec, G, tb.rows, tb.flag, tbytes, err,
+                                     stream))
+    return DMN_EHIP;
+  // B == 0 still runs the (empty) reductions so every group's gradients are zeroed
+  if (dmn::launch_linear_backward_groups(depth, prec, tb.rows, tb.flag, tbytes, G, offsets, C1, C2,
+                                         gCbar, gw_groups, gn_groups, partials, gsum, err, stream))
     return DMN_EHIP;
   return DMN_OK;
 }

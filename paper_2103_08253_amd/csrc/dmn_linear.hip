@@ -13,7 +13,11 @@
 // reads) rather than in every lane's registers.  Parameter
 // cotangents are accumulated per lane over the samples a wave processes and
 // reduced over waves in a fixed order (bit-reproducible).
-#include "dmn_internal.hpp"
+//
+// A launch may carry several DMNs of one depth (sample groups, one table
+// each): workgroup ranges map to groups, each group's samples and partial
+// sums are contiguous, and the plain calls are the one-group case.
+#include "dmn_groups.hpp"
 
 namespace dmn {
 namespace {
@@ -38,6 +42,16 @@ __device__ __forceinline__ int lpos(int t) {
   constexpr int m = ilog2l(H);
   constexpr int k = K - D + 1 + m;
   return (1 << K) - (1 << k) + t * (1 << m) + (H - (1 << m));
+}
+
+// group of this workgroup (a scan over at most kMaxLinGroups entries; a
+// group without workgroups is never selected)
+__device__ __forceinline__ int lin_group(const LinGroups& grp) {
+  int g = 0;
+#pragma unroll 1
+  for (int q = 1; q < grp.ng; ++q)
+    if ((int)blockIdx.x >= grp.block0[q]) g = q;
+  return g;
 }
 
 template <int K, int D>
@@ -141,21 +155,26 @@ __device__ __forceinline__ T shfl_upv(T v, int o, int w) {
 }
 
 template <typename T, int K, int D, bool ORI>
-__global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ tab,
-                                                        const int32_t* __restrict__ flag,
-                                                        long long B, const T* __restrict__ C1,
+__global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ tab0,
+                                                        const int32_t* __restrict__ flag0,
+                                                        const T* __restrict__ C1,
                                                         const T* __restrict__ C2,
                                                         T* __restrict__ Cbar,
                                                         int32_t* __restrict__ err,
-                                                        const LinOri<T> ori) {
+                                                        const LinOri<T> ori,
+                                                        const LinGroups grp) {
   using C = LCfg<K, D>;
   __shared__ T leafC[C::PPW][2][21];
   __shared__ T nl[ORI ? C::PPW * 3 * C::L : 1];
   const int lane = threadIdx.x;
   const int slot = lane / C::LP, t = lane % C::LP;
-  const long long braw = (long long)blockIdx.x * C::PPW + slot;
-  const bool in_range = braw < B;
-  const long long b = in_range ? braw : B - 1;
+  const int g = lin_group(grp);
+  const T* tab = (const T*)((const char*)tab0 + g * grp.tab_stride);
+  const int32_t* flag = (const int32_t*)((const char*)flag0 + g * grp.tab_stride);
+  const long long s0 = grp.off[g], Bg = grp.off[g + 1] - s0;
+  const long long braw = (long long)(blockIdx.x - grp.block0[g]) * C::PPW + slot;
+  const bool in_range = braw < Bg;
+  const long long b = s0 + (in_range ? braw : Bg - 1);
   if (t == 0) {
     load_sym(C1 + (size_t)b * 36, leafC[slot][0]);
     load_sym(C2 + (size_t)b * 36, leafC[slot][1]);
@@ -258,10 +277,10 @@ __device__ __forceinline__ void lin_back(const R& rows, const LinOri<T>& ori, lo
 
 template <typename T, int K, int D, bool IG, bool ORI>
 __global__ __launch_bounds__(64) void linear_bwd_kernel(
-    const T* __restrict__ tab, const int32_t* __restrict__ flag, long long B,
+    const T* __restrict__ tab0, const int32_t* __restrict__ flag0, long long B,
     const T* __restrict__ C1, const T* __restrict__ C2, const T* __restrict__ gCbar,
     T* __restrict__ gC1, T* __restrict__ gC2, double* __restrict__ partials,
-    int32_t* __restrict__ err, const LinOri<T> ori) {
+    int32_t* __restrict__ err, const LinOri<T> ori, const LinGroups grp) {
   using C = LCfg<K, D>;
   static_assert(C::NLAM >= 1, "lane subtree needs a laminate");
   __shared__ T nodeC[21][C::PPW * C::NODES];
@@ -278,11 +297,18 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[h][c] = 0.0;
   int fail = 0;
+  // this workgroup's group: its table, samples s0 .. s0+Bg-1 and workgroups
+  const int g = lin_group(grp);
+  const T* tab = (const T*)((const char*)tab0 + g * grp.tab_stride);
+  const int32_t* flag = (const int32_t*)((const char*)flag0 + g * grp.tab_stride);
+  const long long s0 = grp.off[g], Bg = grp.off[g + 1] - s0;
+  const int gb = (int)blockIdx.x - grp.block0[g];
+  const int gblocks = grp.block0[g + 1] - grp.block0[g];
   __syncthreads();
-  for (long long sg = blockIdx.x; sg * C::PPW < B; sg += gridDim.x) {
+  for (long long sg = gb; sg * C::PPW < Bg; sg += gblocks) {
     const long long braw = sg * C::PPW + slot;
-    const bool live = braw < B;
-    const long long b = live ? braw : B - 1;
+    const bool live = braw < Bg;
+    const long long b = s0 + (live ? braw : Bg - 1);
     if (t == 0) {
       load_sym(C1 + (size_t)b * 36, leafC[slot][0]);
       load_sym(C2 + (size_t)b * 36, leafC[slot][1]);
@@ -384,12 +410,14 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
     }
     __syncthreads();  // nodeC, leafC and nl are rewritten by the next sample group
   }
-  // partial sums of this wave slot, stored [pos * 4 + c][slot]
-  const size_t pslot = (size_t)blockIdx.x * C::PPW + slot;
-  const size_t nslots = (size_t)gridDim.x * C::PPW;
+  // partial sums of this wave slot, stored [pos * 4 + c][slot] in the
+  // group's region (its slots follow those of the groups before it)
+  const size_t pslot = (size_t)gb * C::PPW + slot;
+  const size_t nslots = (size_t)gblocks * C::PPW;
+  double* gpart = partials + (size_t)grp.block0[g] * C::PPW * (4 * C::L);
   auto put = [&](int pos, const double* v) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) partials[((size_t)pos * 4 + c) * nslots + pslot] = v[c];
+    for (int c = 0; c < 4; ++c) gpart[((size_t)pos * 4 + c) * nslots + pslot] = v[c];
   };
   [&] {
     if constexpr (C::NLAM >= 1) {
@@ -419,14 +447,18 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
 }
 
 // Sum the partials over wave slots in a fixed order: one workgroup per
-// (laminate, component) row; each thread sums a strided subset, then a
-// fixed-shape tree in LDS.  gsum[pos * 4 + c].
+// (group, laminate, component) row; each thread sums a strided subset of the
+// group's slots, then a fixed-shape tree in LDS.  gsum[g][pos * 4 + c].
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials,
-                                                              long long nslots, int L4,
-                                                              double* __restrict__ gsum) {
+                                                              int ppw, int L4,
+                                                              double* __restrict__ gsum,
+                                                              const LinGroups grp) {
   __shared__ double part[256];
-  const int i = blockIdx.x;
-  const double* row = partials + (size_t)i * nslots;
+  const int g = blockIdx.x / L4;
+  const int r = blockIdx.x % L4;
+  const long long nslots = (long long)(grp.block0[g + 1] - grp.block0[g]) * ppw;
+  const double* row =
+      partials + (size_t)grp.block0[g] * ppw * L4 + (size_t)r * nslots;
   double s = 0.0;
   for (long long q = threadIdx.x; q < nslots; q += blockDim.x) s += row[q];
   part[threadIdx.x] = s;
@@ -435,20 +467,27 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
     if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && i < L4) gsum[i] = part[0];
+  if (threadIdx.x == 0) gsum[(size_t)g * L4 + r] = part[0];
 }
 
 // Leaf-weight and normal gradients from the per-laminate sums: a leaf
 // collects dc1/dW_L (left subtree) or dc1/dW_R (right subtree) times the
-// laminate's c1-cotangent over its root path.
+// laminate's c1-cotangent over its root path.  Group g = blockIdx.y: sums
+// gsum + g 4L, table tab_stride bytes apart, outputs gw + g 2^K, gn + g 3L.
 template <typename T>
-__global__ __launch_bounds__(256) void finish_grads_kernel(const double* __restrict__ gsum,
-                                                           const T* __restrict__ tab, int K,
-                                                           T* __restrict__ gw,
-                                                           T* __restrict__ gn, int write_gn) {
+__global__ __launch_bounds__(256) void finish_grads_kernel(const double* __restrict__ gsum0,
+                                                           const T* __restrict__ tab0,
+                                                           long long tab_stride, int K,
+                                                           T* __restrict__ gw0,
+                                                           T* __restrict__ gn0, int write_gn) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nleaf = 1 << K;
   const int L = nleaf - 1;
+  const long long g = blockIdx.y;
+  const double* gsum = gsum0 + g * 4 * L;
+  const T* tab = (const T*)((const char*)tab0 + g * tab_stride);
+  T* gw = gw0 + g * nleaf;
+  T* gn = gn0 + g * 3 * L;
   if (i < nleaf) {
     double s = 0.0;
     for (int k = K; k >= 1; --k) {
@@ -517,28 +556,82 @@ static int lin_default_D(int depth) {
   return d < 1 ? 1 : d;
 }
 
+static int lin_ppw(int depth) { return 64 >> (depth - lin_default_D(depth)); }
+
+// persistent waves of the backward for a group of B samples (at least one, so
+// that an empty group still writes zero gradients)
+static long long bwd_waves(int depth, long long B) {
+  const int ppw = lin_ppw(depth);
+  long long waves = (B + ppw - 1) / ppw;
+  if (waves > kMaxBwdWaves) waves = kMaxBwdWaves;
+  if (waves < 1) waves = 1;
+  return waves;
+}
+
+long long linear_backward_partials(int depth, long long B) {
+  return bwd_waves(depth, B) * lin_ppw(depth);
+}
+
+long long linear_backward_group_slots(int depth, int G, const int64_t* off) {
+  long long slots = 0;
+  for (int g = 0; g < G; ++g) slots += bwd_waves(depth, off[g + 1] - off[g]) * lin_ppw(depth);
+  return slots;
+}
+
+// Group table of the chunk of groups g0 .. g0+ng-1; blocks(B) gives the
+// workgroups of a group of B samples.  Returns the workgroups of the launch,
+// or -1 when they exceed the grid.
+template <class F>
+static long long chunk_groups(LinGroups& gr, const int64_t* off, int g0, int ng,
+                              long long tab_stride, F blocks) {
+  gr = LinGroups{};
+  gr.ng = ng;
+  gr.tab_stride = tab_stride;
+  long long total = 0;
+  for (int q = 0; q < ng; ++q) {
+    gr.off[q] = off[g0 + q];
+    gr.block0[q] = (int)total;
+    total += blocks(off[g0 + q + 1] - off[g0 + q]);
+    if (total > 0x7fffffffLL) return -1;
+  }
+  gr.off[ng] = off[g0 + ng];
+  gr.block0[ng] = (int)total;
+  return total;
+}
+
 template <typename T, int K>
-static int fwd_k(const void* tab, const int32_t* flag, long long B, const void* C1, const void* C2,
-                 void* Cbar, int32_t* err, const LinOriArgs& o, hipStream_t s) {
+static int fwd_k(const void* tab, const int32_t* flag, long long tab_stride, int G,
+                 const int64_t* off, const void* C1, const void* C2, void* Cbar, int32_t* err,
+                 const LinOriArgs& o, hipStream_t s) {
   constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
   using C = LCfg<K, D>;
-  const long long nb = (B + C::PPW - 1) / C::PPW;
   const LinOri<T> ori{(const T*)o.p, (const T*)o.q, (const T*)o.lam, (T*)o.gang, o.m};
   // per-sample orientation (ORI = true) is not launched: switched off after
   // an unexplained device fault on its first GPU run
   if (o.m > 0) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL((linear_fwd_kernel<T, K, D, false>), dim3((unsigned)nb), dim3(64), 0, s,
-                     (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (T*)Cbar, err, ori);
+  for (int g0 = 0; g0 < G; g0 += kMaxLinGroups) {
+    const int ng = G - g0 < kMaxLinGroups ? G - g0 : kMaxLinGroups;
+    LinGroups gr;
+    const long long nb = chunk_groups(gr, off, g0, ng, tab_stride,
+                                      [](long long B) { return (B + C::PPW - 1) / C::PPW; });
+    if (nb < 0) return (int)hipErrorInvalidValue;
+    if (nb == 0) continue;
+    hipLaunchKernelGGL((linear_fwd_kernel<T, K, D, false>), dim3((unsigned)nb), dim3(64), 0, s,
+                       (const T*)((const char*)tab + g0 * tab_stride),
+                       (const int32_t*)((const char*)flag + g0 * tab_stride), (const T*)C1,
+                       (const T*)C2, (T*)Cbar, err, ori, gr);
+  }
   return (int)hipGetLastError();
 }
 
 template <typename T>
-static int fwd_t(int depth, const void* tab, const int32_t* flag, long long B, const void* C1,
-                 const void* C2, void* Cbar, int32_t* err, const LinOriArgs& o, hipStream_t s) {
+static int fwd_t(int depth, const void* tab, const int32_t* flag, long long tab_stride, int G,
+                 const int64_t* off, const void* C1, const void* C2, void* Cbar, int32_t* err,
+                 const LinOriArgs& o, hipStream_t s) {
   switch (depth) {
 #define DMN_FWD_CASE(KK) \
   case KK:               \
-    return fwd_k<T, KK>(tab, flag, B, C1, C2, Cbar, err, o, s);
+    return fwd_k<T, KK>(tab, flag, tab_stride, G, off, C1, C2, Cbar, err, o, s);
     DMN_FWD_CASE(1)
     DMN_FWD_CASE(2)
     DMN_FWD_CASE(3)
@@ -558,68 +651,81 @@ static int fwd_t(int depth, const void* tab, const int32_t* flag, long long B, c
 int launch_linear_forward(int depth, int prec, const void* tab, const int32_t* flag, long long B,
                           const void* C1, const void* C2, void* Cbar, int32_t* err,
                           const LinOriArgs& ori, hipStream_t stream) {
-  if (prec == DMN_F32) return fwd_t<float>(depth, tab, flag, B, C1, C2, Cbar, err, ori, stream);
-  return fwd_t<double>(depth, tab, flag, B, C1, C2, Cbar, err, ori, stream);
+  const int64_t off[2] = {0, B};
+  if (prec == DMN_F32)
+    return fwd_t<float>(depth, tab, flag, 0, 1, off, C1, C2, Cbar, err, ori, stream);
+  return fwd_t<double>(depth, tab, flag, 0, 1, off, C1, C2, Cbar, err, ori, stream);
 }
 
-long long linear_backward_partials(int depth, long long B) {
-  const int D = lin_default_D(depth);
-  const int LP = 1 << (depth - D);
-  const int PPW = 64 / LP;
-  long long waves = (B + PPW - 1) / PPW;
-  if (waves > kMaxBwdWaves) waves = kMaxBwdWaves;
-  if (waves < 1) waves = 1;
-  return waves * PPW;
+int launch_linear_forward_groups(int depth, int prec, const void* tab, const int32_t* flag,
+                                 long long tab_stride, int G, const int64_t* off,
+                                 const void* C1, const void* C2, void* Cbar, int32_t* err,
+                                 hipStream_t stream) {
+  const LinOriArgs none;
+  if (prec == DMN_F32)
+    return fwd_t<float>(depth, tab, flag, tab_stride, G, off, C1, C2, Cbar, err, none, stream);
+  return fwd_t<double>(depth, tab, flag, tab_stride, G, off, C1, C2, Cbar, err, none, stream);
 }
 
-template <typename T, int K, bool IG, bool ORI>
+template <typename T, int K, bool IG>
 static void bwd_launch(long long waves, const void* tab, const int32_t* flag, long long B,
                        const void* C1, const void* C2, const void* gCbar, void* gC1, void* gC2,
-                       double* partials, int32_t* err, const LinOri<T>& ori, hipStream_t s) {
+                       double* partials, int32_t* err, const LinOri<T>& ori, const LinGroups& gr,
+                       hipStream_t s) {
   constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
-  hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, IG, ORI>), dim3((unsigned)waves), dim3(64), 0, s,
-                     (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar,
-                     (T*)gC1, (T*)gC2, partials, err, ori);
+  hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, IG, false>), dim3((unsigned)waves), dim3(64), 0,
+                     s, (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar,
+                     (T*)gC1, (T*)gC2, partials, err, ori, gr);
 }
 
 template <typename T, int K>
-static int bwd_k(const void* tab, const int32_t* flag, long long B, const void* C1, const void* C2,
-                 const void* gCbar, void* gw, void* gn, void* gC1, void* gC2, double* partials,
-                 double* gsum, int32_t* err, const LinOriArgs& o, hipStream_t s) {
+static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int G,
+                 const int64_t* off, const void* C1, const void* C2, const void* gCbar,
+                 void* gw, void* gn, void* gC1, void* gC2, double* partials, double* gsum,
+                 int32_t* err, const LinOriArgs& o, hipStream_t s) {
   constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
   using C = LCfg<K, D>;
-  const long long nslots = linear_backward_partials(K, B);
-  const long long waves = nslots / C::PPW;
   const LinOri<T> ori{(const T*)o.p, (const T*)o.q, (const T*)o.lam, (T*)o.gang, o.m};
-  const bool ig = gC1 != nullptr, oriented = o.m > 0;
-  if (oriented) return (int)hipErrorInvalidValue;  // switched off, see the forward launcher
-  if (ig)
-    bwd_launch<T, K, true, false>(waves, tab, flag, B, C1, C2, gCbar, gC1, gC2, partials, err, ori,
-                                  s);
-  else
-    bwd_launch<T, K, false, false>(waves, tab, flag, B, C1, C2, gCbar, gC1, gC2, partials, err,
-                                   ori, s);
+  if (o.m > 0) return (int)hipErrorInvalidValue;  // switched off, see the forward launcher
+  const bool ig = gC1 != nullptr;
   const int L4 = C::L * 4;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(L4), dim3(256), 0, s,
-                     (const double*)partials, nslots, L4, gsum);
   const int nleaf = 1 << K;
-  hipLaunchKernelGGL((finish_grads_kernel<T>), dim3((nleaf + 255) / 256), dim3(256), 0, s,
-                     (const double*)gsum, (const T*)tab, K, (T*)gw, (T*)gn, oriented ? 0 : 1);
-  if (oriented)
-    hipLaunchKernelGGL((reduce_orientation_kernel<T>), dim3(C::L), dim3(256), 0, s,
-                       (const T*)o.gang, (const T*)o.lam, B, o.m, (T*)gn);
+  double* part = partials;
+  for (int g0 = 0; g0 < G; g0 += kMaxLinGroups) {
+    const int ng = G - g0 < kMaxLinGroups ? G - g0 : kMaxLinGroups;
+    LinGroups gr;
+    const long long waves =
+        chunk_groups(gr, off, g0, ng, tab_stride, [](long long B) { return bwd_waves(K, B); });
+    if (waves < 0 || (long long)ng * L4 > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    const void* tabc = (const char*)tab + g0 * tab_stride;
+    const int32_t* flagc = (const int32_t*)((const char*)flag + g0 * tab_stride);
+    if (ig)
+      bwd_launch<T, K, true>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part, err, ori,
+                             gr, s);
+    else
+      bwd_launch<T, K, false>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part, err,
+                              ori, gr, s);
+    double* gs = gsum + (size_t)g0 * L4;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(ng * L4)), dim3(256), 0, s,
+                       (const double*)part, C::PPW, L4, gs, gr);
+    hipLaunchKernelGGL((finish_grads_kernel<T>), dim3((nleaf + 255) / 256, (unsigned)ng), dim3(256),
+                       0, s, (const double*)gs, (const T*)tabc, tab_stride, K,
+                       (T*)gw + (size_t)g0 * nleaf, (T*)gn + (size_t)g0 * 3 * C::L, 1);
+    part += (size_t)waves * C::PPW * L4;
+  }
   return (int)hipGetLastError();
 }
 
 template <typename T>
-static int bwd_t(int depth, const void* tab, const int32_t* flag, long long B, const void* C1,
-                 const void* C2, const void* gCbar, void* gw, void* gn, void* gC1, void* gC2,
-                 double* partials, double* gsum, int32_t* err, const LinOriArgs& o,
-                 hipStream_t s) {
+static int bwd_t(int depth, const void* tab, const int32_t* flag, long long tab_stride, int G,
+                 const int64_t* off, const void* C1, const void* C2, const void* gCbar,
+                 void* gw, void* gn, void* gC1, void* gC2, double* partials, double* gsum,
+                 int32_t* err, const LinOriArgs& o, hipStream_t s) {
   switch (depth) {
-#define DMN_BWD_CASE(KK) \
-  case KK:               \
-    return bwd_k<T, KK>(tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum, err, o, s);
+#define DMN_BWD_CASE(KK)                                                                       \
+  case KK:                                                                                     \
+    return bwd_k<T, KK>(tab, flag, tab_stride, G, off, C1, C2, gCbar, gw, gn, gC1, gC2, partials, \
+                        gsum, err, o, s);
     DMN_BWD_CASE(1)
     DMN_BWD_CASE(2)
     DMN_BWD_CASE(3)
@@ -641,11 +747,25 @@ int launch_linear_backward(int depth, int prec, const void* tab, const int32_t* 
                            void* gw, void* gn, void* gC1, void* gC2, double* partials,
                            double* gsum, int32_t* err, const LinOriArgs& ori,
                            hipStream_t stream) {
+  const int64_t off[2] = {0, B};
   if (prec == DMN_F32)
-    return bwd_t<float>(depth, tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum,
-                        err, ori, stream);
-  return bwd_t<double>(depth, tab, flag, B, C1, C2, gCbar, gw, gn, gC1, gC2, partials, gsum, err,
-                       ori, stream);
+    return bwd_t<float>(depth, tab, flag, 0, 1, off, C1, C2, gCbar, gw, gn, gC1, gC2, partials,
+                        gsum, err, ori, stream);
+  return bwd_t<double>(depth, tab, flag, 0, 1, off, C1, C2, gCbar, gw, gn, gC1, gC2, partials,
+                       gsum, err, ori, stream);
+}
+
+int launch_linear_backward_groups(int depth, int prec, const void* tab, const int32_t* flag,
+                                  long long tab_stride, int G, const int64_t* off,
+                                  const void* C1, const void* C2, const void* gCbar, void* gw,
+                                  void* gn, double* partials, double* gsum, int32_t* err,
+                                  hipStream_t stream) {
+  const LinOriArgs none;
+  if (prec == DMN_F32)
+    return bwd_t<float>(depth, tab, flag, tab_stride, G, off, C1, C2, gCbar, gw, gn, nullptr,
+                        nullptr, partials, gsum, err, none, stream);
+  return bwd_t<double>(depth, tab, flag, tab_stride, G, off, C1, C2, gCbar, gw, gn, nullptr,
+                       nullptr, partials, gsum, err, none, stream);
 }
 
 }  // namespace dmn

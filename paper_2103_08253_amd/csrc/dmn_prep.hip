@@ -2,7 +2,9 @@
 // and volume fractions; Sec. 3.2 weight matrix W).
 //
 // From the leaf weights w[2^K] and the normals n[2^K-1][3] (paper order) one
-// workgroup builds the laminate table used by every kernel:
+// workgroup builds the laminate table used by every kernel (workgroup g of a
+// grouped launch: normals n + g L 3, table and flag tab_stride bytes after
+// the first):
 //   c1 = W_L / (W_L + W_R), c2 = 1 - c1   (W_X: summed leaf weights of a child)
 //   n                                      (copied as passed; zero if n is null,
 //                                           for normals interpolated per point)
@@ -19,15 +21,16 @@
 // subtree from the tree (Sec. 3.1, tree compression) computes.  Subtree sums
 // are formed pairwise in a fixed order, so the table is bit-identical run to
 // run.
-#include "dmn_internal.hpp"
+#include "dmn_groups.hpp"
 
 namespace dmn {
 namespace {
 
 template <typename T>
 __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, const T* __restrict__ n,
-                                                   int K, T* __restrict__ tab,
-                                                   int32_t* __restrict__ flag,
+                                                   int K, T* __restrict__ tab0,
+                                                   int32_t* __restrict__ flag0,
+                                                   long long tab_stride,
                                                    int32_t* __restrict__ err, int allow_dead) {
   // node sums of the whole tree in LDS, heap order: node 1 = root, leaves at
   // 2^K ... 2^(K+1)-1; each internal node is the sum of its two children
@@ -35,6 +38,10 @@ __global__ __launch_bounds__(256) void prep_kernel(const T* __restrict__ w, cons
   __shared__ int bad;
   const int nleaf = 1 << K;
   const int L = nleaf - 1;
+  const long long g = blockIdx.x;
+  T* tab = (T*)((char*)tab0 + g * tab_stride);
+  int32_t* flag = (int32_t*)((char*)flag0 + g * tab_stride);
+  if (n) n += g * L * 3;
   if (threadIdx.x == 0) bad = 0;
   int mybad = 0;
   for (int j = threadIdx.x; j < nleaf; j += blockDim.x) {
@@ -115,16 +122,31 @@ int device_cu_count() {
   return cached[dev];
 }
 
-int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
-                       int32_t* err, hipStream_t stream, bool allow_dead) {
+static int launch_prep(const void* w, const void* n, int depth, int prec, int G, void* tab,
+                       int32_t* flag, long long tab_stride, int32_t* err, hipStream_t stream,
+                       bool allow_dead) {
+  if (G < 1) return (int)hipSuccess;
   if (prec == DMN_F32) {
-    hipLaunchKernelGGL(prep_kernel<float>, dim3(1), dim3(256), 0, stream, (const float*)w,
-                       (const float*)n, depth, (float*)tab, flag, err, allow_dead ? 1 : 0);
+    hipLaunchKernelGGL(prep_kernel<float>, dim3((unsigned)G), dim3(256), 0, stream,
+                       (const float*)w, (const float*)n, depth, (float*)tab, flag, tab_stride,
+                       err, allow_dead ? 1 : 0);
   } else {
-    hipLaunchKernelGGL(prep_kernel<double>, dim3(1), dim3(256), 0, stream, (const double*)w,
-                       (const double*)n, depth, (double*)tab, flag, err, allow_dead ? 1 : 0);
+    hipLaunchKernelGGL(prep_kernel<double>, dim3((unsigned)G), dim3(256), 0, stream,
+                       (const double*)w, (const double*)n, depth, (double*)tab, flag, tab_stride,
+                       err, allow_dead ? 1 : 0);
   }
   return (int)hipGetLastError();
+}
+
+int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* tab, int32_t* flag,
+                       int32_t* err, hipStream_t stream, bool allow_dead) {
+  return launch_prep(w, n, depth, prec, 1, tab, flag, 0, err, stream, allow_dead);
+}
+
+int launch_prep_tables_groups(const void* w, const void* n, int depth, int prec, int G, void* tab,
+                              int32_t* flag, long long tab_stride, int32_t* err,
+                              hipStream_t stream) {
+  return launch_prep(w, n, depth, prec, G, tab, flag, tab_stride, err, stream, true);
 }
 
 }  // namespace dmn

@@ -13,8 +13,9 @@ from typing import Optional
 import torch
 
 from . import _lib as L
-from .api import (_PREC, _need, _ptr, _stream, dmn_homogenize_backward, dmn_homogenize_linear,
-                  workspace)
+from .api import (_PREC, _need, _ptr, _stream, dmn_homogenize_backward,
+                  dmn_homogenize_backward_groups, dmn_homogenize_linear,
+                  dmn_homogenize_linear_groups, workspace)
 
 STATS_NAMES = ("data", "max_error", "scaled_sum", "objective", "penalty", "lr", "weight_sum")
 
@@ -319,17 +320,23 @@ def dmn_training_update_oriented(params: OrientedTrainParams, gw, gpq,
 class OrientedTrainingStepGraph:
     """One training step of an orientation-interpolated DMN over a batch
     grouped by orientation (samples offsets[k]:offsets[k+1] have orientation
-    lam[k]) as a HIP graph: group normals, the fixed-normal linear map per
-    group, the objective over the whole batch, the VJP per group, the chain
-    to (p, q) and the AMSGrad update."""
+    lam[k]) as a HIP graph: group normals, the fixed-normal linear map of
+    every group, the objective over the whole batch, the VJP of every group,
+    the chain to (p, q) and the AMSGrad update.
+
+    ``grouped``: all groups in one call each for the map and its VJP
+    (dmn_homogenize_linear_groups / dmn_homogenize_backward_groups);
+    otherwise one call per group, spread over ``streams`` streams."""
 
     def __init__(self, params: OrientedTrainParams, C1, C2, target, lam, offsets,
                  p: float = 1.0, q: float = 10.0, opts: Optional[AmsgradOpts] = None,
-                 streams: int = 4):
+                 streams: int = 4, grouped: bool = True):
         self.params, self.C1, self.C2, self.target, self.lam = params, C1, C2, target, lam
-        # the groups' maps and VJPs are independent: spread them over a few
-        # streams (default priority) that fork from and join the main stream
-        self.side = [torch.cuda.Stream(device=C1.device) for _ in range(max(0, streams - 1))]
+        self.grouped = grouped
+        # per-group calls are independent: spread them over a few streams
+        # (default priority) that fork from and join the main stream
+        self.side = [] if grouped else [torch.cuda.Stream(device=C1.device)
+                                        for _ in range(max(0, streams - 1))]
         self.offsets = [int(x) for x in offsets]
         self.p, self.q, self.opts = p, q, opts or AmsgradOpts()
         dev, dt = C1.device, C1.dtype
@@ -345,6 +352,7 @@ class OrientedTrainingStepGraph:
         self.gw = torch.empty(2 ** K, dtype=dt, device=dev)
         self.gpq = torch.empty((2 ** K - 1, 2, params.m), dtype=dt, device=dev)
         self.ws_fwd, self.ws_bwd = [None] * G, [None] * G
+        self.ws_gfwd = self.ws_gbwd = None
         self._enqueue(sizing=True)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
@@ -382,11 +390,21 @@ class OrientedTrainingStepGraph:
                 P.w, self.n_groups[k], self.C1[a:b], self.C2[a:b], self.gCbar[a:b],
                 ws=self.ws_bwd[k], gw=self.gw_groups[k], gn=self.gn_groups[k])[-1]
 
-        self._fan_out(fwd)
+        if self.grouped:
+            _, self.ws_gfwd = dmn_homogenize_linear_groups(P.w, self.n_groups, o, self.C1,
+                                                           self.C2, Cbar=self.Cbar,
+                                                           ws=self.ws_gfwd)
+        else:
+            self._fan_out(fwd)
         _, _, ws = dmn_training_loss(self.Cbar, self.target, self.p, self.q, gCbar=self.gCbar,
                                      stats=self.stats, ws=None if sizing else self.ws_loss)
         self.ws_loss = ws
-        self._fan_out(bwd)
+        if self.grouped:
+            self.ws_gbwd = dmn_homogenize_backward_groups(
+                P.w, self.n_groups, o, self.C1, self.C2, self.gCbar, gw_groups=self.gw_groups,
+                gn_groups=self.gn_groups, ws=self.ws_gbwd)[-1]
+        else:
+            self._fan_out(bwd)
         dmn_orientation_group_chain(P, self.lam, self.gw_groups, self.gn_groups, gw=self.gw,
                                     gpq=self.gpq)
         if not sizing:
@@ -400,6 +418,8 @@ class OrientedTrainingStepGraph:
         self._enqueue()
 
     def error_words(self):
-        """Device error words of every group's linear map and VJP (synchronises)."""
+        """Device error words of the linear maps and VJPs (synchronises)."""
         from .api import error_word
+        if self.grouped:
+            return [error_word(self.ws_gfwd), error_word(self.ws_gbwd)]
         return [error_word(w) for w in self.ws_fwd + self.ws_bwd]

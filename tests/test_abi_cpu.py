@@ -243,3 +243,48 @@ def test_orientation_group_validation_codes():
     bad = L.DmnAmsgradOpts(1.5e-3, 1.5e-2, 0.999, 0, 1, 0.9, 0.999, 1e-8, 1e3)
     assert up(o=bad) == L.DMN_EINVAL
     assert lib.dmn_training_refresh_oriented(None, L.DMN_F64, None) == L.DMN_EINVAL
+
+
+def test_grouped_linear_validation_codes():
+    lib = L.lib()
+    off = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    good = off(0, 2, 2, 5)
+    one = lib.dmn_homogenize_linear_groups_workspace_size(3, 1, L.DMN_F64)
+    assert one > 0
+    assert lib.dmn_homogenize_linear_groups_workspace_size(3, 3, L.DMN_F64) == 3 * one - 2 * 256
+    assert lib.dmn_homogenize_linear_groups_workspace_size(0, 3, L.DMN_F64) == 0
+    assert lib.dmn_homogenize_linear_groups_workspace_size(3, 0, L.DMN_F64) == 0
+    assert lib.dmn_homogenize_linear_groups_workspace_size(3, 3, L.DMN_F32_STATE) == 0
+    fw = lambda depth=3, G=3, o=good, prec=L.DMN_F64, w=FAKE, n=FAKE, c=FAKE, ws=None, nb=0: \
+        lib.dmn_homogenize_linear_groups(depth, G, o, prec, w, n, c, c, c, ws, nb, None)
+    assert fw(depth=0) == L.DMN_EINVAL
+    assert fw(depth=11) == L.DMN_EINVAL
+    assert fw(G=0) == L.DMN_EINVAL
+    assert fw(o=None) == L.DMN_EINVAL
+    assert fw(o=off(0, 3, 2, 5)) == L.DMN_EINVAL      # decreasing
+    assert fw(o=off(1, 2, 3, 5)) == L.DMN_EINVAL      # does not start at 0
+    assert fw(prec=L.DMN_F32_STATE) == L.DMN_EUNSUPPORTED
+    assert fw(w=None) == L.DMN_EINVAL
+    assert fw(n=None) == L.DMN_EINVAL
+    assert fw(c=None) == L.DMN_EINVAL
+    assert fw(o=off(0, 0, 0, 0), c=None) == L.DMN_EWORKSPACE   # empty batch needs no arrays
+    assert fw() == L.DMN_EWORKSPACE
+    assert fw(ws=ctypes.c_void_p(ALIGNED.value + 8), nb=1 << 20) == L.DMN_EWORKSPACE
+    bsize = lambda o=good, G=3, depth=8: lib.dmn_homogenize_backward_groups_workspace_size(
+        depth, G, o, L.DMN_F64)
+    assert bsize() > lib.dmn_homogenize_linear_groups_workspace_size(8, 3, L.DMN_F64)
+    assert bsize(o=off(0, 3, 2, 5)) == 0
+    assert bsize(o=None) == 0
+    assert bsize(G=0) == 0
+    # more samples in a group need more partial slots, an empty group one wave
+    assert bsize(o=off(0, 2, 2, 500)) > bsize()
+    assert bsize(o=off(0, 0, 0, 0)) > 0
+    bw = lambda G=3, o=good, gw=FAKE, gn=FAKE, c=FAKE, ws=None: \
+        lib.dmn_homogenize_backward_groups(3, G, o, L.DMN_F64, FAKE, FAKE, c, c, c, gw, gn, ws,
+                                           0, None)
+    assert bw(gw=None) == L.DMN_EINVAL
+    assert bw(gn=None) == L.DMN_EINVAL
+    assert bw(c=None) == L.DMN_EINVAL
+    assert bw(G=0) == L.DMN_EINVAL
+    assert bw(o=off(0, 3, 2, 5)) == L.DMN_EINVAL
+    assert bw() == L.DMN_EWORKSPACE

@@ -667,3 +667,79 @@ def test_oriented_training_step_with_empty_groups():
     g_ref = np.concatenate([ref["gv"], ref["gP"].ravel(), ref["gQ"].ravel()])
     say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
     assert rel(g_gpu, g_ref) < 1e-8
+
+
+def grouped_case(K, G, per, seed):
+    """G DMNs sharing w (with a dead leaf pair when K > 1), random normals per
+    group, group sizes in 0..per with every fifth group empty."""
+    rs = S.streams(seed)
+    sizes = rs["init"].integers(0, per + 1, G)
+    sizes[2::5] = 0
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    B = int(offsets[-1])
+    w = S.random_dmn(rs["ground_truth"], K, 0.3).w
+    if K > 1:
+        w[2:4] = 0.0
+    n_groups = S.unit_normals(rs["ground_truth"], G * (2 ** K - 1)).reshape(G, 2 ** K - 1, 3)
+    C1 = S.random_spd(rs["stiffness"], B)
+    C2 = S.random_spd(rs["stiffness"], B)
+    gC = rs["noise"].standard_normal((B, 6, 6))
+    return w, n_groups, offsets, C1, C2, gC
+
+
+@pytest.mark.parametrize("K,G,per,dtype", [(3, 70, 9, torch.float64), (8, 31, 20, torch.float64),
+                                           (5, 10, 40, torch.float32), (1, 3, 50, torch.float64)])
+def test_grouped_linear_matches_per_group_calls_and_oracle(K, G, per, dtype):
+    """The grouped map and VJP equal one plain call per group bit for bit (same
+    tables, waves and reduction order), with empty groups, a dead subtree and
+    more groups than one launch takes; Cbar also against the oracle's
+    compressed-tree map."""
+    from oracle.compression import dmn_linear_compressed
+    from paper_2103_08253_amd import (dmn_homogenize_backward, dmn_homogenize_backward_groups,
+                                      dmn_homogenize_linear, dmn_homogenize_linear_groups,
+                                      error_word)
+    w, n_groups, offsets, C1, C2, gC = grouped_case(K, G, per, 95 + K)
+    say(f"grouped linear K={K} G={G} B={offsets[-1]} {dtype}")
+    wt, nt = tt(w, dtype), tt(n_groups, dtype)
+    C1t, C2t, gCt = tt(C1, dtype), tt(C2, dtype), tt(gC, dtype)
+    Cbar, wsf = dmn_homogenize_linear_groups(wt, nt, offsets, C1t, C2t)
+    gw, gn, wsb = dmn_homogenize_backward_groups(wt, nt, offsets, C1t, C2t, gCt)
+    torch.cuda.synchronize()
+    assert error_word(wsf) == 0 and error_word(wsb) == 0
+    tol = 1e-10 if dtype == torch.float64 else 1e-4
+    for k in range(G):
+        a, b = int(offsets[k]), int(offsets[k + 1])
+        ref_C, _ = dmn_homogenize_linear(wt, nt[k].contiguous(), C1t[a:b], C2t[a:b])
+        ref_w, ref_n, _, _, _ = dmn_homogenize_backward(wt, nt[k].contiguous(), C1t[a:b],
+                                                        C2t[a:b], gCt[a:b])
+        assert torch.equal(Cbar[a:b], ref_C), k
+        assert torch.equal(gw[k], ref_w) and torch.equal(gn[k], ref_n), k
+        if b == a:
+            assert not gw[k].any() and not gn[k].any(), k
+        elif k % 7 == 0:
+            ref = np.stack([dmn_linear_compressed(K, w, n_groups[k], C1[i], C2[i])
+                            for i in range(a, b)])
+            assert rel(Cbar[a:b].cpu().numpy(), ref) < tol, k
+
+
+def test_oriented_training_grouped_equals_per_group_calls():
+    """The oriented step with grouped calls and with one call per group on
+    four streams gives bit-identical parameters, state and statistics."""
+    from paper_2103_08253_amd import AmsgradOpts, OrientedTrainingStepGraph, OrientedTrainParams
+    K, B, kind = 4, 40, "quadratic"
+    say(f"oriented training grouped vs per-group K={K} B={B} {kind}")
+    C1, C2, Tt, lam_g, lam_s, offsets, v, p, q = oriented_case(K, B, kind, 96, level=1)
+    opts = AmsgradOpts(steps_per_epoch=2, half_period=3, penalty=100.0)
+    Pa = OrientedTrainParams.create(kind, tt(v), tt(p), tt(q))
+    Pb = OrientedTrainParams.create(kind, tt(v), tt(p), tt(q))
+    args = (tt(C1), tt(C2), tt(Tt), tt(lam_g), offsets)
+    ga = OrientedTrainingStepGraph(Pa, *args, opts=opts)
+    gb = OrientedTrainingStepGraph(Pb, *args, opts=opts, grouped=False)
+    for step in range(3):
+        ga.replay()
+        gb.replay()
+        torch.cuda.synchronize()
+        for a, b in ((Pa.v, Pb.v), (Pa.p, Pb.p), (Pa.q, Pb.q), (Pa.state, Pb.state),
+                     (ga.stats, gb.stats)):
+            assert torch.equal(a, b), step
+    assert all(e == 0 for e in ga.error_words() + gb.error_words())
