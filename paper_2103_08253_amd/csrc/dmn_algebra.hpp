@@ -143,29 +143,37 @@ __device__ __forceinline__ bool laminate_linear(const T CL[21], const T CR[21], 
 // output C as a full symmetric matrix stored packed (so <Gm, dC> sums all 36
 // entries).  Returns the cotangents of CL and CR (same convention), of c1
 // (with c2 = 1 - c1), and of the normal components.
-//   T = U K^-1 U^T,  Gt = -c1 c2 Gm,  V = U K^-1
-//   G_U = 2 Gt V,  G_K = -V^T Gt V,  G_S = N G_K N^T,  G_dC = sym(G_U N^T)
+//   T = U K^-1 U^T,  Gt = -c1 c2 Gm,  V = U K^-1,  P = Gm V
+//   G_U = 2 Gt V = -2 c1 c2 P,  G_K = -V^T Gt V = c1 c2 V^T P,
+//   G_S = N G_K N^T,  G_dC = sym(G_U N^T)
 //   G_CL = c1 Gm + c2 G_S - G_dC,  G_CR = c2 Gm + c1 G_S + G_dC
-//   G_c1 = <Gm, CL - CR> - (1 - 2 c1) <Gm, T> + <G_S, CR - CL>
-//   G_N  = 2 S N G_K + dC G_U,  G_n_d = <G_N, dN/dn_d>
+//   G_c1 = <Gm, CL - CR> - (1 - 2 c1) <Gm, T> + <G_S, CR - CL>,
+//          <Gm, T> = sum U o P
+//   G_N  = 2 S N G_K + dC G_U,  G_n_d = <G_N, dN/dn_d> (nine entries of G_N)
+// Written to keep few values live: S and dC are formed one row at a time,
+// G_S and G_dC one entry at a time straight into G_CL and G_CR.
 template <typename T>
 __device__ __forceinline__ void laminate_linear_vjp(const T CL[21], const T CR[21],
                                                     const Normal<T>& nv, T c1, T c2,
                                                     const T Gm[21], T GL[21], T GR[21], T& gc1,
                                                     T gn[3]) {
-  T S[21], dC[21];
-#pragma unroll
-  for (int k = 0; k < 21; ++k) {
-    S[k] = c2 * CL[k] + c1 * CR[k];
-    dC[k] = CR[k] - CL[k];
-  }
   T SN[6][3], U[6][3];
-  sym_times_N(S, nv, SN);
-  sym_times_N(dC, nv, U);
-  T col[6], kc[3];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    T srow[6], drow[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int k = sidx(r, c);
+      srow[c] = c2 * CL[k] + c1 * CR[k];
+      drow[c] = CR[k] - CL[k];
+    }
+    nv.applyT(srow, SN[r]);
+    nv.applyT(drow, U[r]);
+  }
   T Km[3][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    T col[6], kc[3];
 #pragma unroll
     for (int r = 0; r < 6; ++r) col[r] = SN[r][c];
     nv.applyT(col, kc);
@@ -183,9 +191,9 @@ __device__ __forceinline__ void laminate_linear_vjp(const T CL[21], const T CR[2
     V[r][1] = U[r][0] * m01 + U[r][1] * m11 + U[r][2] * m12;
     V[r][2] = U[r][0] * m02 + U[r][1] * m12 + U[r][2] * m22;
   }
-  const T cc = c1 * c2;
-  // X = Gt V = -cc Gm V ; G_U = 2 X
-  T X[6][3];
+  // P = Gm V and <Gm, T> = sum U o P
+  T P[6][3];
+  T a2 = T(0);
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -193,9 +201,10 @@ __device__ __forceinline__ void laminate_linear_vjp(const T CL[21], const T CR[2
       T acc = T(0);
 #pragma unroll
       for (int j = 0; j < 6; ++j) acc += Gm[sidx(i, j)] * V[j][a];
-      X[i][a] = -cc * acc;
+      P[i][a] = acc;
+      a2 += U[i][a] * acc;
     }
-  // G_K = -V^T X (symmetric 3x3)
+  const T cc = c1 * c2;
   T GK[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -203,71 +212,57 @@ __device__ __forceinline__ void laminate_linear_vjp(const T CL[21], const T CR[2
     for (int b = a; b < 3; ++b) {
       T acc = T(0);
 #pragma unroll
-      for (int i = 0; i < 6; ++i) acc += V[i][a] * X[i][b];
-      GK[a][b] = -acc;
-      GK[b][a] = -acc;
+      for (int i = 0; i < 6; ++i) acc += V[i][a] * P[i][b];
+      GK[a][b] = cc * acc;
+      GK[b][a] = cc * acc;
     }
-  // N G_K (6x3), then G_S = (N G_K) N^T, row i = N (N G_K)[i][:]
+  // G_U, in place of P
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) P[i][a] *= T(-2) * cc;
+  // the nine entries of G_N = 2 SN G_K + dC G_U that dN/dn touches
+  auto gN = [&](int i, int a) {
+    T acc = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc += T(2) * SN[i][b] * GK[b][a];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc += (CR[sidx(i, j)] - CL[sidx(i, j)]) * P[j][a];
+    return acc;
+  };
+  const T r = T(kRsqrt2);
+  gn[0] = gN(0, 0) + r * (gN(4, 2) + gN(5, 1));
+  gn[1] = gN(1, 1) + r * (gN(3, 2) + gN(5, 0));
+  gn[2] = gN(2, 2) + r * (gN(3, 1) + gN(4, 0));
+  // N G_K (6x3)
   T NGK[6][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     T x[3] = {GK[0][c], GK[1][c], GK[2][c]}, y[6];
     nv.apply(x, y);
 #pragma unroll
-    for (int r = 0; r < 6; ++r) NGK[r][c] = y[r];
+    for (int q = 0; q < 6; ++q) NGK[q][c] = y[q];
   }
-  T GS[21];
+  // entry (i, j), i <= j: G_S = (N NGK_i)_j, G_dC = ((N G_U_i)_j + (N G_U_j)_i) / 2
+  T a1 = T(0);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    T y[6];
-    nv.apply(NGK[i], y);
-#pragma unroll
-    for (int j = i; j < 6; ++j) GS[sidx(i, j)] = y[j];
-  }
-  // Y = G_U N^T, row i = N G_U[i][:] ; G_dC = sym(Y)
-  T Y[6][6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    T gu[3] = {T(2) * X[i][0], T(2) * X[i][1], T(2) * X[i][2]};
-    nv.apply(gu, Y[i]);
-  }
-  T Tm[21];
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = i; j < 6; ++j)
-      Tm[sidx(i, j)] = V[i][0] * U[j][0] + V[i][1] * U[j][1] + V[i][2] * U[j][2];
-  T a1 = T(0), a2 = T(0);
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
+    T ys[6], yu[6];
+    nv.apply(NGK[i], ys);
+    nv.apply(P[i], yu);
 #pragma unroll
     for (int j = i; j < 6; ++j) {
       const int k = sidx(i, j);
-      const T wgt = i == j ? T(1) : T(2);
-      const T gdc = T(0.5) * (Y[i][j] + Y[j][i]);
-      GL[k] = c1 * Gm[k] + c2 * GS[k] - gdc;
-      GR[k] = c2 * Gm[k] + c1 * GS[k] + gdc;
-      a1 += wgt * (Gm[k] - GS[k]) * dC[k];
-      a2 += wgt * Gm[k] * Tm[k];
+      T yt[6];
+      nv.apply(P[j], yt);
+      const T gdc = T(0.5) * (yu[j] + yt[i]);
+      const T gs = ys[j];
+      GL[k] = c1 * Gm[k] + c2 * gs - gdc;
+      GR[k] = c2 * Gm[k] + c1 * gs + gdc;
+      a1 += (i == j ? T(1) : T(2)) * (Gm[k] - gs) * (CR[k] - CL[k]);
     }
+  }
   gc1 = -a1 - (T(1) - T(2) * c1) * a2;
-  // G_N = 2 SN G_K + dC G_U
-  T GN[6][3];
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      T acc = T(0);
-#pragma unroll
-      for (int b = 0; b < 3; ++b) acc += T(2) * SN[i][b] * GK[b][a];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) acc += dC[sidx(i, j)] * T(2) * X[j][a];
-      GN[i][a] = acc;
-    }
-  const T r = T(kRsqrt2);
-  gn[0] = GN[0][0] + r * (GN[4][2] + GN[5][1]);
-  gn[1] = GN[1][1] + r * (GN[3][2] + GN[5][0]);
-  gn[2] = GN[2][2] + r * (GN[3][1] + GN[4][0]);
 }
 
 // Newton laminate step, in place: on entry (C, tau, sb) hold the left
