@@ -743,3 +743,35 @@ def test_oriented_training_grouped_equals_per_group_calls():
                      (ga.stats, gb.stats)):
             assert torch.equal(a, b), step
     assert all(e == 0 for e in ga.error_words() + gb.error_words())
+
+
+def test_oriented_training_step_f32_gradient():
+    """FP32 storage through the grouped linear calls, the group normals and
+    chain and the coefficient update (quadratic shape functions): the step's
+    implied gradient against the FP64 oracle on the same rounded inputs within
+    1e-3."""
+    from paper_2103_08253_amd import AmsgradOpts, OrientedTrainingStepGraph, OrientedTrainParams
+    K, B, kind, lam_pen = 3, 24, "quadratic", 10.0
+    say(f"oriented training step f32 K={K} B={B} {kind}")
+    C1, C2, Tt, lam_g, lam_s, offsets, v, p, q = oriented_case(K, B, kind, 97, level=1)
+    f32 = lambda x: tt(x, torch.float32)
+    r = lambda x: f32(x).double().cpu().numpy()
+    C1, C2, Tt, lam_g, v, p, q = r(C1), r(C2), r(Tt), r(lam_g), r(v), r(p), r(q)
+    lam_s = np.repeat(lam_g, np.diff(offsets), axis=0)
+    eps, lr = 1e6, 1e5   # steps of 0.1 g, well above the FP32 spacing of the parameters
+    opts = AmsgradOpts(lr_min=lr, lr_max=lr, lr_decay=1.0, beta1=0.0, beta2=0.0, eps=eps,
+                       penalty=lam_pen)
+    P = OrientedTrainParams.create(kind, f32(v), f32(p), f32(q))
+    g = OrientedTrainingStepGraph(P, f32(C1), f32(C2), f32(Tt), f32(lam_g), offsets, opts=opts)
+    g.replay()
+    torch.cuda.synchronize()
+    assert all(e == 0 for e in g.error_words())
+    th0 = np.concatenate([v, p.ravel(), q.ravel()])
+    th1 = np.concatenate([P.v.double().cpu().numpy(), P.p.double().cpu().numpy().ravel(),
+                          P.q.double().cpu().numpy().ravel()])
+    d = th0 - th1
+    g_gpu = d * eps / (lr - np.abs(d))
+    ref = T.objective_oriented_gradient(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
+    g_ref = np.concatenate([ref["gv"], ref["gP"].ravel(), ref["gQ"].ravel()])
+    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    assert rel(g_gpu, g_ref) < 1e-3
