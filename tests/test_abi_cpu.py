@@ -288,3 +288,28 @@ def test_grouped_linear_validation_codes():
     assert bw(G=0) == L.DMN_EINVAL
     assert bw(o=off(0, 3, 2, 5)) == L.DMN_EINVAL
     assert bw() == L.DMN_EWORKSPACE
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback: without the built library every call raises."""
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libdmn.so"))
+    with pytest.raises(L.DmnError, match="no fallback"):
+        L.lib()
+
+
+def test_wrappers_refuse_host_tensors():
+    """The bindings only marshal device tensors; host tensors are rejected
+    before any library call (no CPU path)."""
+    torch = pytest.importorskip("torch")
+    from paper_2103_08253_amd import (dmn_homogenize_backward_groups, dmn_homogenize_linear,
+                                      dmn_homogenize_linear_groups)
+    w = torch.ones(8, dtype=torch.float64)
+    n = torch.zeros(7, 3, dtype=torch.float64)
+    C = torch.eye(6, dtype=torch.float64).expand(2, 6, 6).contiguous()
+    with pytest.raises(TypeError, match="GPU tensor"):
+        dmn_homogenize_linear(w, n, C, C)
+    with pytest.raises(TypeError, match="GPU tensor"):
+        dmn_homogenize_linear_groups(w, n[None], [0, 2], C, C)
+    with pytest.raises(TypeError, match="GPU tensor"):
+        dmn_homogenize_backward_groups(w, n[None], [0, 2], C, C, C)
