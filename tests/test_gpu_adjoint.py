@@ -170,6 +170,8 @@ def test_adjoint_production_size_checkpointed():
                                        wl.E[:, two, :], wl.g_sigma[two], vw, va, vb)
     say(f"  2 points: adjoint {got2:.12e} oracle {ref2:.12e}")
     assert abs(got2 - ref2) <= 1e-8 * abs(ref2)
+    # the path depends on w only through w / sum(w): w . gw vanishes
+    assert abs(net.w @ gw2) <= 1e-9 * np.abs(net.w * gw2).sum()
     # 32 points against GPU central differences, kinked points excluded
     E_t = torch.tensor(wl.E, device=d)
     h = 1e-6
@@ -190,6 +192,7 @@ def test_adjoint_production_size_checkpointed():
     got = gwk @ vw + gak @ va + gbk @ vb
     say(f"  {len(keep)} points: adjoint {got:.10e} FD {fd:.10e}")
     assert abs(got - fd) <= 1e-5 * abs(fd)
+    assert abs(net.w @ gwk) <= 1e-9 * np.abs(net.w * gwk).sum()
 
 
 def test_autograd_wrappers():

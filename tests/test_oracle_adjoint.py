@@ -3,7 +3,10 @@
 * it matches central finite differences (h = 1e-6) on a plastic depth-2 path
   whose leaves stay away from the yield surface under the perturbation;
 * on an elastic path it equals the derivative of the linear DMN map (a
-  different code path: Milton's formula) contracted with the macro strain.
+  different code path: Milton's formula) contracted with the macro strain;
+* the outputs depend on the weights only through w / sum(w) (Sec. 3.2), so on
+  a plastic path the derivative along v_w = w vanishes (a dropped
+  normalisation anywhere in the path breaks this).
 """
 import numpy as np
 
@@ -54,3 +57,19 @@ def test_elastic_path_equals_linear_map_derivative():
     cs = path_directional_derivative(K, net.w, alpha, beta, S.FIBER, S.MATRIX, E, g, vw, va, vb)
     ref = lin["gw"] @ vw + lin["galpha"] @ va + lin["gbeta"] @ vb
     assert abs(cs - ref) <= 1e-9 * max(abs(ref), 1e-12), (cs, ref)
+
+
+def test_path_derivative_vanishes_along_weight_scaling():
+    K = 3
+    net, alpha, beta, E, g = setup(K, 302, n_points=2, steps=4, mag=0.02)
+    model = DmnModel(K, net.w, net.normals, S.FIBER, S.MATRIX)
+    plastic = any(o["z"][:, 6].max() > 0 for p in range(2) for o in run_path(model, E[:, p, :], TIGHT))
+    assert plastic
+    za, zb = np.zeros(7), np.zeros(7)
+    along = path_directional_derivative(K, net.w, alpha, beta, S.FIBER, S.MATRIX, E, g, net.w,
+                                        za, zb)
+    rng = np.random.default_rng(3)
+    scale = abs(path_directional_derivative(K, net.w, alpha, beta, S.FIBER, S.MATRIX, E, g,
+                                            rng.standard_normal(8), za, zb))
+    assert scale > 1e-3
+    assert abs(along) <= 1e-12 * scale, (along, scale)
