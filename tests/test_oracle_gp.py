@@ -9,7 +9,10 @@
   condition written out by hand;
 * equal normals collapse a nonlinear depth-4 DMN to a single laminate;
 * identical elastic phases leave the jumps at zero;
-* the status codes of the failure modes.
+* the status codes of the failure modes;
+* rotating the load path and the normals rotates the outputs (isotropic phases);
+* exchanging the two subtrees of the root leaves the outputs unchanged and
+  negates the root jump.
 """
 import numpy as np
 import pytest
@@ -187,3 +190,42 @@ def test_rotational_covariance_of_the_nonlinear_update():
         ja = np.linalg.norm(b["a"].reshape(-1, 3), axis=1)
         jr = np.linalg.norm(r["a"].reshape(-1, 3), axis=1)
         assert np.allclose(ja, jr, rtol=1e-9, atol=1e-14)
+
+
+def test_swapping_the_root_subtrees():
+    """The laminate law is symmetric in its two children: exchanging the two
+    subtrees of the root (their weights, normals and states) leaves stress,
+    tangent and iteration counts unchanged, negates the root jump (the left
+    child moves by -c2 N a, the right one by +c1 N a, Sec. 3.2) and permutes
+    the other jumps and the internal variables.  A wrong fraction or sign in
+    the localisation breaks the symmetry."""
+    from oracle.tree import lam_pos, laminates
+    rng = np.random.default_rng(20)
+    K = 3
+    net = S.random_dmn(rng, K, 0.3)
+    half = 2 ** (K - 1)
+    # laminate (k, i) below the root maps to (k, i -/+ 2^(k-2)) in the other subtree
+    perm = np.arange(2 ** K - 1)
+    for (k, i) in laminates(K):
+        if k > 1:
+            shift = 2 ** (k - 2)
+            perm[lam_pos(K, k, i)] = lam_pos(K, k, i + shift if i <= shift else i - shift)
+    w_sw = np.concatenate([net.w[half:], net.w[:half]])
+    n_sw = net.normals[perm]
+    d = rng.standard_normal(6)
+    E_path = np.outer(np.linspace(0.25, 1.0, 4), 0.04 * d / np.linalg.norm(d))
+    base = G.run_path(G.DmnModel(K, net.w, net.normals, S.FIBER, S.MATRIX), E_path)
+    sw = G.run_path(G.DmnModel(K, w_sw, n_sw, S.FIBER, S.MATRIX), E_path)
+    assert any(np.abs(o["z"][:, 6]).max() > 0 for o in base)   # the path yields
+    root = lam_pos(K, 1, 1)
+    mhalf = half // 2
+    for b, s in zip(base, sw):
+        assert b["status"] == s["status"] == 0 and b["iters"] == s["iters"]
+        assert np.abs(s["sigma"] - b["sigma"]).max() <= 1e-10 * np.abs(b["sigma"]).max()
+        assert np.abs(s["C"] - b["C"]).max() <= 1e-10 * np.abs(b["C"]).max()
+        zb = np.concatenate([b["z"][mhalf:], b["z"][:mhalf]])
+        assert np.allclose(s["z"], zb, rtol=1e-9, atol=1e-14)
+        ab, as_ = b["a"].reshape(-1, 3), s["a"].reshape(-1, 3)
+        assert np.allclose(as_[root], -ab[root], rtol=1e-9, atol=1e-14)
+        others = [p for p in range(2 ** K - 1) if p != root]
+        assert np.allclose(as_[perm[others]], ab[others], rtol=1e-9, atol=1e-14)
