@@ -14,7 +14,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .mandel import projector_P
-from .tree import fractions, gradient_operator, lam_pos, n_laminates
+from .tree import fractions, gradient_operator, lam_pos
 
 
 def milton_alpha(CL, CR):

@@ -11,7 +11,7 @@ A graph replays the device pointers it was captured with: inputs are read
 from, and outputs written to, the same tensors on every replay, so a caller
 refills the input tensors in place (``copy_``) between replays.
 """
-from typing import List, Optional, Sequence
+from typing import List, Sequence
 
 import torch
 
@@ -21,7 +21,6 @@ from .api import (PointGroup, dmn_homogenize_backward, dmn_homogenize_linear,
 
 
 def _gp_workspace(groups: Sequence[PointGroup]):
-    import ctypes
     arr = (L.DmnPointGroup * len(groups))(*[g.to_c() for g in groups])
     nbytes = L.lib().dmn_update_gauss_points_workspace_size(arr, len(groups), groups[0].prec)
     if nbytes == 0:

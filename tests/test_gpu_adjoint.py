@@ -17,7 +17,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import synthetic as S
-from oracle.adjoint import TIGHT, path_directional_derivative
+from oracle.adjoint import path_directional_derivative
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-13

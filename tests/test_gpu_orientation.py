@@ -2,7 +2,6 @@
 (every point its own fibre orientation (l1, l2); Sec. 2.3) against the FP64
 oracle, which builds each point's normals with oracle.orientation and runs
 its dense Newton update.  Same bars as the fixed-normal parity tests."""
-import sys
 
 import numpy as np
 import pytest

@@ -15,7 +15,6 @@
   negates the root jump.
 """
 import numpy as np
-import pytest
 import scipy.optimize as so
 
 import synthetic as S

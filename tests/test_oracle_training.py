@@ -12,9 +12,8 @@ import pytest
 
 import synthetic as S
 from oracle import training as T
-from oracle.grad import normals_from_angles
 from oracle.linear import dmn_linear
-from oracle.mandel import P1, P2, iso_stiffness, sym_to_mandel
+from oracle.mandel import P1, iso_stiffness, sym_to_mandel
 
 
 def lame(K, G):

@@ -10,7 +10,6 @@ import os
 import re
 
 import numpy as np
-import pytest
 
 from oracle import mandel as M
 from oracle import tree as T
