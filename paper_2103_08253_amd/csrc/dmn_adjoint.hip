@@ -53,7 +53,6 @@ struct AdjointLeaf {
   const double* gbar;      // [6]
   const double* zeta;      // this point's zeta^{n+1} or null
   const double* leafw;     // normalised leaf weights of the DMN
-  double (*sig)[6];        // [NLEAF][6] out: leaf stresses
   template <int K, int D, int Q>
   __device__ __forceinline__ void operator()(const Ctx<K, D>& cx, std::integral_constant<int, Q>,
                                              const double (&e)[6], double (&Cn)[21],
@@ -87,10 +86,9 @@ struct AdjointLeaf {
       double gb[6], gz[7];
 #pragma unroll
       for (int k = 0; k < 6; ++k) gb[k] = gbar[k];
-      j2_vjp(cx.mat, e, epn, z[6], gb, ze, zp, tn, gz);  // tn = e_j / w~_j
+      double sv[6];
+      j2_vjp(cx.mat, e, epn, z[6], gb, ze, zp, tn, gz, sv);  // tn = e_j / w~_j
     }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) sig[Q][k] = sn[k];
   }
 };
 
@@ -204,31 +202,30 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
       }
     }
     // leaf strains at the converged jumps; tree solve with the adjoint prestress
-    double eps[C::NLEAF][6], sig[C::NLEAF][6], de[C::NLEAF][6];
+    double eps[C::NLEAF][6], de[C::NLEAF][6];
     localize(cx, st, up, E, 0.0, eps);
-    AdjointLeaf<C::NLEAF> leaf{gbar, zeta, leafw, sig};
+    AdjointLeaf<C::NLEAF> leaf{gbar, zeta, leafw};
     EvalOut ev;
     evaluate_full(cx, st, up, eps, ev, leaf);
     lfail_any |= ev.lfail;
     spd_any |= ev.spdfail;
     direction(cx, st, up, true, de);  // da = -lam, de = -(A lam)
-    // leaf adjoints
+    // leaf adjoints; the strains are localised again and the stresses
+    // recomputed rather than held through the tree solve (registers)
+    localize(cx, st, up, E, 0.0, eps);
     double mu[C::NLEAF][6], ws[C::NLEAF][6], rho[C::NLEAF];
     double srho = 0.0;
 #pragma unroll
     for (int q = 0; q < C::NLEAF; ++q) {
       const double wj = leafw[cx.t * C::NLEAF + q];
-      double gmd[6], psi[6];
-      rho[q] = 0.0;
+      double gmd[6], psi[6], sig[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         gmd[k] = gbar[k] + de[q][k];
         psi[k] = wj * gmd[k];
-        rho[q] += sig[q][k] * gmd[k];
-        ws[q][k] = wj * sig[q][k];
       }
-      srho += wj * rho[q];
       if (q % 2 == 0) {
+        iso_stress(cx.fib, eps[q], sig);
         iso_stress(cx.fib, psi, mu[q]);
       } else {
         const int mloc = cx.t * (C::NLEAF / 2) + q / 2;
@@ -240,13 +237,20 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
           ze[k] = zeta ? zeta[(size_t)mloc * 7 + k] : 0.0;
         }
         if (zeta) zp = zeta[(size_t)mloc * 7 + 6];
-        j2_vjp(cx.mat, eps[q], epn, z[6], psi, ze, zp, mu[q], gz);
+        j2_vjp(cx.mat, eps[q], epn, z[6], psi, ze, zp, mu[q], gz, sig);
         if (live) {
           double* out = args.g_z_prev + (size_t)pt * C::M * 7 + (size_t)mloc * 7;
 #pragma unroll
           for (int k = 0; k < 7; ++k) out[k] = gz[k];
         }
       }
+      rho[q] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        rho[q] += sig[k] * gmd[k];
+        ws[q][k] = wj * sig[k];
+      }
+      srho += wj * rho[q];
     }
     // subtree sums and laminate parameter cotangents
     double Sm[6], Ss[6];

@@ -496,7 +496,7 @@ __device__ __forceinline__ bool j2_return(const J2Law& m, const double eps[6], c
 // cotangents psi of the stress and zeta = (zeta_e, zeta_p) of the new internal
 // variables (plastic strain, p), returns the cotangents of the strain (geps)
 // and of the old internal variables (gz = (gz_e, gz_p)).  The forward state is
-// recomputed.  With e = eps - ep_n, q = |s_tr|, nh = s_tr / q, dg the plastic
+// recomputed, and the stress at eps comes out as j2_return gives it (sig).  With e = eps - ep_n, q = |s_tr|, nh = s_tr / q, dg the plastic
 // multiplier, kappa = 1 / (2G + 2/3 H'(p)), beta = 2G / q, c = sqrt(2/3):
 //   ge  = K (1.psi) 1 + 2G dev(psi)                         (elastic part)
 //       + 2G kappa gbar nh + beta (dev(nu) - nh (nh.nu))    (plastic only)
@@ -504,11 +504,12 @@ __device__ __forceinline__ bool j2_return(const J2Law& m, const double eps[6], c
 //   geps = ge,  gz_e = zeta_e - ge,  gz_p = zeta_p - c H' kappa gbar (plastic)
 __device__ __forceinline__ void j2_vjp(const J2Law& m, const double eps[6], const double epn[6],
                                        double pn, const double psi[6], const double ze[6],
-                                       double zp, double geps[6], double gz[7]) {
+                                       double zp, double geps[6], double gz[7], double sig[6]) {
   double e[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) e[s] = eps[s] - epn[s];
-  const double tr3 = (e[0] + e[1] + e[2]) * (1.0 / 3.0);
+  const double tr = e[0] + e[1] + e[2];
+  const double tr3 = tr * (1.0 / 3.0);
   double str[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) str[s] = 2.0 * m.G * (s < 3 ? e[s] - tr3 : e[s]);
@@ -524,6 +525,7 @@ __device__ __forceinline__ void j2_vjp(const J2Law& m, const double eps[6], cons
   for (int s = 0; s < 6; ++s)
     ge[s] = (s < 3 ? m.K * ipsi + 2.0 * m.G * (psi[s] - ipsi / 3.0) : 2.0 * m.G * psi[s]);
   double gpn = zp;
+  double theta = 1.0;
   if (f > 0.0) {
     const double xtol = kLocalTol * q / (2.0 * m.G);
     double x = 0.0;
@@ -538,6 +540,7 @@ __device__ __forceinline__ void j2_vjp(const J2Law& m, const double eps[6], cons
     }
     const double pp = pn + kSqrt23 * x;
     const double Hp = m.k_inf + m.dsigma * m.b * exp(-m.b * pp);
+    theta = 1.0 - 2.0 * m.G * x / q;
     const double kappa = 1.0 / (2.0 * m.G + (2.0 / 3.0) * Hp);
     const double beta = 2.0 * m.G / q;
     double nh[6];
@@ -570,6 +573,9 @@ __device__ __forceinline__ void j2_vjp(const J2Law& m, const double eps[6], cons
     gz[s] = ze[s] - ge[s];
   }
   gz[6] = gpn;
+  const double Ktr = m.K * tr;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) sig[s] = (s < 3 ? Ktr : 0.0) + theta * str[s];
 }
 
 // Parameter cotangents of one laminate in the path adjoint: with subtree sums
