@@ -572,6 +572,30 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         updates_per_s=Pm * wl.n_steps / (ms * 1e-3), last_step_all_converged=ok,
         tuning={int(k): [v["lanes_per_point"], v["waves_per_cu"]]
                 for k, v in mixed_tuned.items()})
+    del graph, groups, E_steps
+
+    # what the two roofs give on this device, for context beside the published
+    # peaks: an FP64 matrix product through the vendor BLAS (matrix cores) and
+    # a device-to-device copy
+    n = 8192
+    a = torch.randn(n, n, dtype=torch.float64, device=dev)
+    b = torch.randn(n, n, dtype=torch.float64, device=dev)
+    c = torch.empty_like(a)
+    torch.matmul(a, b, out=c)
+    torch.cuda.synchronize()
+    ms_mm = _event_ms(lambda: torch.matmul(a, b, out=c), 5) / 5
+    del a, b, c
+    nbytes = 1 << 30
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    ms_cp = _event_ms(lambda: y.copy_(x), 10) / 10
+    del x, y
+    out["measured_peaks"] = dict(
+        fp64_dgemm_n8192_tflops=2.0 * n ** 3 / (ms_mm * 1e-3) / 1e12,
+        hbm_copy_1GiB_GBps=2.0 * nbytes / (ms_cp * 1e-3) / 1e9,
+        published=dict(fp64_tflops=78.6, hbm_GBps=8000.0))
     return out
 
 
