@@ -464,6 +464,19 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         hist[int(Pt.step.item())] = float(gstep.stats[3].item())
         train[nb] = dict(ms_per_step=ms, samples_per_s=nb / (ms * 1e-3),
                          objective_at_step=hist)
+        # the same step in FP32 storage and arithmetic for the linear map and
+        # its VJP (FP64 sums), the precision of the paper's PyTorch training
+        f32 = lambda t: t.to(torch.float32)
+        P32 = TrainParams.create(torch.tensor(tw.v0, device=dev, dtype=torch.float32),
+                                 torch.tensor(tw.alpha0, device=dev, dtype=torch.float32),
+                                 torch.tensor(tw.beta0, device=dev, dtype=torch.float32))
+        g32 = TrainingStepGraph(P32, f32(C1[:nb]).contiguous(), f32(C2[:nb]).contiguous(),
+                                f32(tgt[:nb]).contiguous(), opts=AmsgradOpts(steps_per_epoch=10))
+        g32.replay()
+        torch.cuda.synchronize()
+        ms32 = _event_ms(g32.replay, reps) / reps
+        train[nb]["fp32"] = dict(ms_per_step=ms32, samples_per_s=nb / (ms32 * 1e-3))
+        del g32, P32
     u = torch.rand((B, 8), dtype=torch.float64, device=dev)
     dmn_sample_stiffness(u)
     torch.cuda.synchronize()
@@ -482,7 +495,13 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         torch.cuda.synchronize()
         ms = _event_ms(lg.replay, 5) / 5
         sweep[nb] = dict(ms=ms, samples_per_s=nb / (ms * 1e-3))
-        del lg, c1s, c2s, gcs
+        del lg
+        lg32 = LinearStepGraph(wt.float(), nt.float(), c1s.float(), c2s.float(), gcs.float())
+        lg32.replay()
+        torch.cuda.synchronize()
+        ms32 = _event_ms(lg32.replay, 5) / 5
+        sweep[nb]["fp32"] = dict(ms=ms32, samples_per_s=nb / (ms32 * 1e-3))
+        del lg32, c1s, c2s, gcs
     out["train_fwd_bwd_batch_sweep"] = sweep
     # training over the paper's 31 fibre orientations (linear shape functions):
     # the batch grouped by orientation, the fixed-normal maps and VJPs of all
