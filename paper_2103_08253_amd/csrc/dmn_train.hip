@@ -264,26 +264,30 @@ __global__ __launch_bounds__(256) void group_normals_kernel(int G, int L, int m,
   o[2] = (T)ca;
 }
 
-// gw = sum_k gw_g[k] and, per laminate l,
+// gw = sum_k gw_g[k] (workgroups 0 .. gw_blocks-1, one thread per leaf, k in
+// order) and, per laminate l (one 64-lane workgroup each),
 //   gpq[l][0][j] = sum_k (gn_g[k][l] . dn/dalpha) s_j(lam_k),
-//   gpq[l][1][j] = sum_k (gn_g[k][l] . dn/dbeta)  s_j(lam_k),
-// summed over k in order; one thread per leaf or laminate.
+//   gpq[l][1][j] = sum_k (gn_g[k][l] . dn/dbeta)  s_j(lam_k):
+// lane t takes the orientations k = t, t + 64, ... in order, then a fixed
+// butterfly sums the lanes (the same order every run).
 template <typename T>
-__global__ __launch_bounds__(256) void group_chain_kernel(
-    int G, int NL, int L, int m, const T* __restrict__ p, const T* __restrict__ q,
-    const T* __restrict__ lam, const T* __restrict__ gw_g, const T* __restrict__ gn_g,
-    T* __restrict__ gw, T* __restrict__ gpq) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < NL) {
-    double acc = 0.0;
-    for (int k = 0; k < G; ++k) acc += (double)gw_g[(size_t)k * NL + idx];
-    gw[idx] = (T)acc;
+__global__ __launch_bounds__(64) void group_chain_kernel(
+    int G, int NL, int L, int m, int gw_blocks, const T* __restrict__ p,
+    const T* __restrict__ q, const T* __restrict__ lam, const T* __restrict__ gw_g,
+    const T* __restrict__ gn_g, T* __restrict__ gw, T* __restrict__ gpq) {
+  const int lane = threadIdx.x;
+  if ((int)blockIdx.x < gw_blocks) {
+    const int i = blockIdx.x * 64 + lane;
+    if (i < NL) {
+      double acc = 0.0;
+      for (int k = 0; k < G; ++k) acc += (double)gw_g[(size_t)k * NL + i];
+      gw[i] = (T)acc;
+    }
     return;
   }
-  const int l = idx - NL;
-  if (l >= L) return;
+  const int l = (int)blockIdx.x - gw_blocks;  // < L: the grid has gw_blocks + L workgroups
   double gp[6] = {0, 0, 0, 0, 0, 0}, gq[6] = {0, 0, 0, 0, 0, 0};
-  for (int k = 0; k < G; ++k) {
+  for (int k = lane; k < G; k += 64) {
     double sh[6];
     orientation_shape<double>((double)lam[2 * k], (double)lam[2 * k + 1], m, sh);
     double a = 0.0, b = 0.0;
@@ -307,11 +311,20 @@ __global__ __launch_bounds__(256) void group_chain_kernel(
     }
   }
 #pragma unroll
-  for (int j = 0; j < 6; ++j)
-    if (j < m) {
-      gpq[((size_t)l * 2) * m + j] = (T)gp[j];
-      gpq[((size_t)l * 2 + 1) * m + j] = (T)gq[j];
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      gp[j] += __shfl_xor(gp[j], o, 64);
+      gq[j] += __shfl_xor(gq[j], o, 64);
     }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j < m) {
+        gpq[((size_t)l * 2) * m + j] = (T)gp[j];
+        gpq[((size_t)l * 2 + 1) * m + j] = (T)gq[j];
+      }
+  }
 }
 
 // One workgroup: AMSGrad on the slots v [NL], p [L m], q [L m] with
@@ -528,14 +541,15 @@ int launch_group_chain(int prec, int depth, int m, int G, const void* p, const v
                        const void* lam, const void* gw_g, const void* gn_g, void* gw, void* gpq,
                        hipStream_t stream) {
   const int NL = 1 << depth, L = NL - 1;
-  const unsigned nb = blocks_for(NL + L, 256);
+  const int gw_blocks = (int)blocks_for(NL, 64);
+  const unsigned nb = (unsigned)(gw_blocks + L);
   if (prec == DMN_F32)
-    hipLaunchKernelGGL((group_chain_kernel<float>), dim3(nb), dim3(256), 0, stream, G, NL, L, m,
-                       (const float*)p, (const float*)q, (const float*)lam, (const float*)gw_g,
-                       (const float*)gn_g, (float*)gw, (float*)gpq);
+    hipLaunchKernelGGL((group_chain_kernel<float>), dim3(nb), dim3(64), 0, stream, G, NL, L, m,
+                       gw_blocks, (const float*)p, (const float*)q, (const float*)lam,
+                       (const float*)gw_g, (const float*)gn_g, (float*)gw, (float*)gpq);
   else
-    hipLaunchKernelGGL((group_chain_kernel<double>), dim3(nb), dim3(256), 0, stream, G, NL, L, m,
-                       (const double*)p, (const double*)q, (const double*)lam,
+    hipLaunchKernelGGL((group_chain_kernel<double>), dim3(nb), dim3(64), 0, stream, G, NL, L, m,
+                       gw_blocks, (const double*)p, (const double*)q, (const double*)lam,
                        (const double*)gw_g, (const double*)gn_g, (double*)gw, (double*)gpq);
   return (int)hipGetLastError();
 }
