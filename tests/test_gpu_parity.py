@@ -125,6 +125,51 @@ def test_gp_depth8_production_size_sampled():
     say(f"  plastic matrix-leaf fraction at the last step: {plastic:.3f}")
 
 
+def test_gp_mixed_batch_full_size_sampled(tmp_path):
+    """The mixed-depth batch at its full size (131,072 points over 16 DMNs of
+    depths 5-9, 20 steps) in the launch configuration the bench times: tuned
+    per depth, all 16 groups in one call per step.  The oracle follows two
+    sampled points of every DMN along their whole path; every point of the
+    batch converges at every step."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    from paper_2103_08253_amd import autotune as A
+    say("case: gp mixed batch, 131072 points over 16 DMNs x 20 steps, 2 sampled per DMN")
+    d = dev()
+    wl = S.config2()
+    rs = S.streams(2)["picks"]
+    idx = [np.nonzero(wl.dmn_id == m)[0] for m in range(len(wl.nets))]
+    picks = [rs.choice(sel, 2, replace=False) for sel in idx]
+    groups = [PointGroup.allocate(torch.tensor(net.w, device=d),
+                                  torch.tensor(net.normals, device=d),
+                                  torch.tensor(wl.E[0, sel], device=d))
+              for net, sel in zip(wl.nets, idx)]
+    try:
+        A.tune_gauss_points(groups, S.FIBER, S.MATRIX, cache_path=str(tmp_path / "tune.json"))
+        for g in groups:
+            g.z_in.zero_()
+            g.a_in.zero_()
+        outs = [[] for _ in groups]
+        ws = None
+        for step in range(wl.n_steps):
+            for g, sel in zip(groups, idx):
+                g.E.copy_(torch.tensor(wl.E[step, sel], device=d))
+            ws = dmn_update_gauss_points(groups, S.FIBER, S.MATRIX, ws=ws)
+            torch.cuda.synchronize()
+            for m, (g, sel, pk) in enumerate(zip(groups, idx, picks)):
+                assert bool((g.status == 0).all().item()), (m, step)
+                rows = torch.tensor(np.searchsorted(sel, pk), device=d)
+                outs[m].append(dict(sigma=g.sigma[rows].cpu().numpy(),
+                                    C=g.tangent[rows].cpu().numpy(),
+                                    z=g.z_out[rows].cpu().numpy(), a=g.a_out[rows].cpu().numpy(),
+                                    iters=g.iters[rows].cpu().numpy(),
+                                    status=g.status[rows].cpu().numpy()))
+                g.advance()
+    finally:
+        A.reset_tuning()
+    for m, net in enumerate(wl.nets):
+        compare_paths(net, wl.E[:, picks[m], :], range(2), outs[m])
+
+
 def test_gp_depth9_small():
     say("case: gp depth 9, 5 points x 4 steps")
     rs = S.streams(109)
