@@ -51,7 +51,8 @@ extern "C" {
 #define DMN_EINVAL (-1)       /* null pointer, depth outside [1,10], bad sizes or options */
 #define DMN_EWORKSPACE (-2)   /* workspace missing or smaller than the size query */
 #define DMN_EHIP (-3)         /* a HIP launch failed */
-#define DMN_EUNSUPPORTED (-4) /* precision / option combination not implemented */
+#define DMN_EUNSUPPORTED (-4) /* precision / option combination not implemented, or a
+                                 depth not run on the device (see DMN_MAX_DEPTH) */
 
 /* precision of storage and arithmetic */
 #define DMN_F64 0       /* FP64 storage, FP64 arithmetic */
@@ -68,7 +69,14 @@ extern "C" {
 #define DMN_STATUS_LOCAL 4     /* J2 return mapping did not converge */
 #define DMN_STATUS_BADPARAM 5  /* negative or non-finite leaf weight, or no weight at all */
 
+/* Depths 1..DMN_MAX_DEPTH pass argument validation.  The Gauss-point update,
+ * its adjoint and the linear map with its VJP (plain and grouped) run up to
+ * DMN_MAX_RUN_DEPTH and return DMN_EUNSUPPORTED at depth 10: their depth-10
+ * kernels hold 5 to 18 KB of register spills per lane and have not been run
+ * on the device.  The training update, refresh and orientation-group calls
+ * take every depth up to DMN_MAX_DEPTH. */
 #define DMN_MAX_DEPTH 10
+#define DMN_MAX_RUN_DEPTH 9
 
 /* Fibre-orientation interpolation of the normals (Sec. 2.3): shape-function
  * family of the orientation-interpolation table and its number M of

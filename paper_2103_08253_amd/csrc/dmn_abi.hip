@@ -22,6 +22,8 @@ inline size_t table_bytes(int depth, int prec) {
 }
 
 inline bool depth_ok(int32_t d) { return d >= 1 && d <= DMN_MAX_DEPTH; }
+// depths whose Gauss-point, adjoint and linear kernels have run on the device
+inline bool depth_runs(int32_t d) { return d <= DMN_MAX_RUN_DEPTH; }
 
 // shape functions of an orientation interpolation, 0 for fixed normals, -1 invalid
 inline int ori_count(int32_t shape) {
@@ -127,6 +129,7 @@ int dmn_homogenize_linear(const dmn_net* net, int64_t B, int prec, const void* C
   if (prec != DMN_F64 && prec != DMN_F32) return DMN_EUNSUPPORTED;
   if (const int rc = linear_net_check(net, B, lam)) return rc;
   if (B > 0 && (!C1 || !C2 || !Cbar)) return DMN_EINVAL;
+  if (!depth_runs(net->depth)) return DMN_EUNSUPPORTED;
   const size_t need = dmn_homogenize_linear_workspace_size(net, B, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   int32_t* err = (int32_t*)ws;
@@ -164,6 +167,7 @@ int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void*
   if (!gw || !gn) return DMN_EINVAL;
   if (B > 0 && (!C1 || !C2 || !gCbar)) return DMN_EINVAL;
   if ((gC1 == nullptr) != (gC2 == nullptr)) return DMN_EINVAL;
+  if (!depth_runs(net->depth)) return DMN_EUNSUPPORTED;
   const size_t need = dmn_homogenize_backward_workspace_size(net, B, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   const int K = net->depth;
@@ -205,6 +209,7 @@ int dmn_homogenize_linear_groups(int32_t depth, int32_t G, const int64_t* offset
   if (!depth_ok(depth) || !group_offsets_ok(G, offsets) || !w || !n_groups) return DMN_EINVAL;
   const int64_t B = offsets[G];
   if (B > 0 && (!C1 || !C2 || !Cbar)) return DMN_EINVAL;
+  if (!depth_runs(depth)) return DMN_EUNSUPPORTED;
   const size_t need = dmn_homogenize_linear_groups_workspace_size(depth, G, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   int32_t* err = (int32_t*)ws;
@@ -240,6 +245,7 @@ int dmn_homogenize_backward_groups(int32_t depth, int32_t G, const int64_t* offs
   if (!gw_groups || !gn_groups) return DMN_EINVAL;
   const int64_t B = offsets[G];
   if (B > 0 && (!C1 || !C2 || !gCbar)) return DMN_EINVAL;
+  if (!depth_runs(depth)) return DMN_EUNSUPPORTED;
   const size_t need = dmn_homogenize_backward_groups_workspace_size(depth, G, offsets, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   const size_t L = ((size_t)1 << depth) - 1;
@@ -290,6 +296,7 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                     !g.tangent || !g.iters || !g.status))
       return DMN_EINVAL;
     if (g.P > 0 && (g.z_in == g.z_out || g.a_in == g.a_out)) return DMN_EINVAL;
+    if (!depth_runs(g.net.depth)) return DMN_EUNSUPPORTED;
   }
   // one snapshot of the tuning table per call
   GpTune tune[DMN_MAX_DEPTH + 1];
@@ -422,6 +429,7 @@ int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
     if (const int rc = fixed_net_check(&g.net)) return rc;
     if (g.P > 0 && (!g.E || !g.z_in || !g.a_conv || !g.g_z_prev)) return DMN_EINVAL;
     if (g.P > 0 && g.g_z_next != nullptr && g.g_z_next == g.g_z_prev) return DMN_EINVAL;
+    if (!depth_runs(g.net.depth)) return DMN_EUNSUPPORTED;
   }
   const size_t need = dmn_update_adjoint_workspace_size(groups, n_groups, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
