@@ -69,14 +69,18 @@ extern "C" {
 #define DMN_STATUS_LOCAL 4     /* J2 return mapping did not converge */
 #define DMN_STATUS_BADPARAM 5  /* negative or non-finite leaf weight, or no weight at all */
 
-/* Depths 1..DMN_MAX_DEPTH pass argument validation.  The Gauss-point update,
- * its adjoint and the linear map with its VJP (plain and grouped) run up to
- * DMN_MAX_RUN_DEPTH and return DMN_EUNSUPPORTED at depth 10: their depth-10
- * kernels hold 5 to 18 KB of register spills per lane and have not been run
- * on the device.  The training update, refresh and orientation-group calls
- * take every depth up to DMN_MAX_DEPTH. */
+/* Depths 1..DMN_MAX_DEPTH pass argument validation.  Deeper than the depths
+ * below, a call returns DMN_EUNSUPPORTED: its kernels compile but hold
+ * several KB of register spills per lane and have not been run on the device.
+ *   DMN_MAX_RUN_DEPTH:      dmn_update_gauss_points, dmn_homogenize_linear,
+ *                           dmn_homogenize_linear_groups
+ *   DMN_MAX_RUN_DEPTH_VJP:  dmn_homogenize_backward,
+ *                           dmn_homogenize_backward_groups, dmn_update_adjoint
+ * The training update, refresh and orientation-group calls take every depth
+ * up to DMN_MAX_DEPTH. */
 #define DMN_MAX_DEPTH 10
 #define DMN_MAX_RUN_DEPTH 9
+#define DMN_MAX_RUN_DEPTH_VJP 8
 
 /* Fibre-orientation interpolation of the normals (Sec. 2.3): shape-function
  * family of the orientation-interpolation table and its number M of

@@ -22,8 +22,10 @@ inline size_t table_bytes(int depth, int prec) {
 }
 
 inline bool depth_ok(int32_t d) { return d >= 1 && d <= DMN_MAX_DEPTH; }
-// depths whose Gauss-point, adjoint and linear kernels have run on the device
+// depths whose kernels have run on the device: the Gauss-point update and the
+// linear map, and the vector-Jacobian products (linear backward, adjoint)
 inline bool depth_runs(int32_t d) { return d <= DMN_MAX_RUN_DEPTH; }
+inline bool depth_runs_vjp(int32_t d) { return d <= DMN_MAX_RUN_DEPTH_VJP; }
 
 // shape functions of an orientation interpolation, 0 for fixed normals, -1 invalid
 inline int ori_count(int32_t shape) {
@@ -167,7 +169,7 @@ int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void*
   if (!gw || !gn) return DMN_EINVAL;
   if (B > 0 && (!C1 || !C2 || !gCbar)) return DMN_EINVAL;
   if ((gC1 == nullptr) != (gC2 == nullptr)) return DMN_EINVAL;
-  if (!depth_runs(net->depth)) return DMN_EUNSUPPORTED;
+  if (!depth_runs_vjp(net->depth)) return DMN_EUNSUPPORTED;
   const size_t need = dmn_homogenize_backward_workspace_size(net, B, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   const int K = net->depth;
@@ -245,7 +247,7 @@ int dmn_homogenize_backward_groups(int32_t depth, int32_t G, const int64_t* offs
   if (!gw_groups || !gn_groups) return DMN_EINVAL;
   const int64_t B = offsets[G];
   if (B > 0 && (!C1 || !C2 || !gCbar)) return DMN_EINVAL;
-  if (!depth_runs(depth)) return DMN_EUNSUPPORTED;
+  if (!depth_runs_vjp(depth)) return DMN_EUNSUPPORTED;
   const size_t need = dmn_homogenize_backward_groups_workspace_size(depth, G, offsets, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   const size_t L = ((size_t)1 << depth) - 1;
@@ -429,7 +431,7 @@ int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
     if (const int rc = fixed_net_check(&g.net)) return rc;
     if (g.P > 0 && (!g.E || !g.z_in || !g.a_conv || !g.g_z_prev)) return DMN_EINVAL;
     if (g.P > 0 && g.g_z_next != nullptr && g.g_z_next == g.g_z_prev) return DMN_EINVAL;
-    if (!depth_runs(g.net.depth)) return DMN_EUNSUPPORTED;
+    if (!depth_runs_vjp(g.net.depth)) return DMN_EUNSUPPORTED;
   }
   const size_t need = dmn_update_adjoint_workspace_size(groups, n_groups, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;

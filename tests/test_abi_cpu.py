@@ -315,37 +315,39 @@ def test_wrappers_refuse_host_tensors():
         dmn_homogenize_backward_groups(w, n[None], [0, 2], C, C, C)
 
 
-def test_depth10_kernels_are_switched_off():
-    """Depth 10 passes argument validation, but the Gauss-point update, its
-    adjoint and the linear map and VJP (plain and grouped) return
-    DMN_EUNSUPPORTED: their depth-10 kernels have not run on the device.
-    Depth 9 goes on to the workspace check."""
+def test_unrun_depths_are_switched_off():
+    """Depths up to 10 pass argument validation, but calls whose kernels have
+    not run on the device at that depth return DMN_EUNSUPPORTED: the
+    Gauss-point update and the linear map above depth 9, the linear VJP and
+    the adjoint above depth 8.  Below, the call goes on to the workspace
+    check."""
     lib = L.lib()
     fib = L.DmnElastic(72000.0, 0.22)
     mat = L.DmnJ2(2800.0, 0.35, 50.0, 200.0, 30.0, 60.0)
     opts = L.DmnNewtonOpts(1e-10, 25, 10, 1e-4)
     big = 1 << 34
-    for depth, code in ((10, L.DMN_EUNSUPPORTED), (9, None)):
+    off = (ctypes.c_int64 * 2)(0, 4)
+    expect = lambda depth, top: L.DMN_EUNSUPPORTED if depth > top else L.DMN_EWORKSPACE
+    for depth in (8, 9, 10):
         arr = (L.DmnPointGroup * 1)(group(depth))
         rc = lib.dmn_update_gauss_points(arr, 1, ctypes.byref(fib), ctypes.byref(mat), L.DMN_F64,
                                          ctypes.byref(opts), None, 0, None)
-        assert rc == (code or L.DMN_EWORKSPACE), (depth, rc)
+        assert rc == expect(depth, 9), (depth, rc)
+        rc = lib.dmn_homogenize_linear(ctypes.byref(net(depth)), 4, L.DMN_F64, FAKE, FAKE, None,
+                                       FAKE, None, big, None)
+        assert rc == expect(depth, 9), (depth, rc)
+        rc = lib.dmn_homogenize_linear_groups(depth, 1, off, L.DMN_F64, FAKE, FAKE, FAKE, FAKE,
+                                              FAKE, None, big, None)
+        assert rc == expect(depth, 9), (depth, rc)
         ag = L.DmnAdjointGroup(net(depth), 4, FAKE.value, FAKE.value, FAKE.value, FAKE.value,
                                None, ALIGNED.value, FAKE.value, FAKE.value)
         arr_a = (L.DmnAdjointGroup * 1)(ag)
         rc = lib.dmn_update_adjoint(arr_a, 1, ctypes.byref(fib), ctypes.byref(mat), L.DMN_F64,
                                     None, 0, None)
-        assert rc == (code or L.DMN_EWORKSPACE), (depth, rc)
-        rc = lib.dmn_homogenize_linear(ctypes.byref(net(depth)), 4, L.DMN_F64, FAKE, FAKE, None,
-                                       FAKE, None, big, None)
-        assert rc == (code or L.DMN_EWORKSPACE), (depth, rc)
+        assert rc == expect(depth, 8), (depth, rc)
         rc = lib.dmn_homogenize_backward(ctypes.byref(net(depth)), 4, L.DMN_F64, FAKE, FAKE, None,
                                          FAKE, FAKE, FAKE, None, None, None, big, None)
-        assert rc == (code or L.DMN_EWORKSPACE), (depth, rc)
-        off = (ctypes.c_int64 * 2)(0, 4)
-        rc = lib.dmn_homogenize_linear_groups(depth, 1, off, L.DMN_F64, FAKE, FAKE, FAKE, FAKE,
-                                              FAKE, None, big, None)
-        assert rc == (code or L.DMN_EWORKSPACE), (depth, rc)
+        assert rc == expect(depth, 8), (depth, rc)
         rc = lib.dmn_homogenize_backward_groups(depth, 1, off, L.DMN_F64, FAKE, FAKE, FAKE, FAKE,
                                                 FAKE, FAKE, FAKE, None, big, None)
-        assert rc == (code or L.DMN_EWORKSPACE), (depth, rc)
+        assert rc == expect(depth, 8), (depth, rc)

@@ -101,6 +101,26 @@ def test_adjoint_depth8_random_directions():
         assert abs(got - ref) <= 1e-8 * abs(ref)
 
 
+@pytest.mark.parametrize("K", [4, 5, 6, 7])
+def test_adjoint_random_directions_mid_depths(K):
+    """Depths 4-7 (one lane-subtree laminate per lane, several points per wave
+    below depth 7): the swept gradient along random directions against the
+    oracle's complex-step path derivative."""
+    say(f"case: path adjoint depth {K}, 3 points x 5 steps, 2 random directions")
+    net, E, g = case(K, 420 + K, 3, 5)
+    _, gw, gn = gpu_gradient(net, E, g, ck=2)
+    alpha, beta = S.normals_to_angles(net.normals)
+    ga, gb = angle_grads(gn, alpha, beta)
+    rng = np.random.default_rng(7 + K)
+    nl, L = 2 ** K, 2 ** K - 1
+    for _ in range(2):
+        vw, va, vb = rng.standard_normal(nl), rng.standard_normal(L), rng.standard_normal(L)
+        got = gw @ vw + ga @ va + gb @ vb
+        ref = path_directional_derivative(K, net.w, alpha, beta, S.FIBER, S.MATRIX, E, g, vw, va, vb)
+        say(f"  directional derivative gpu {got:.12e} oracle {ref:.12e}")
+        assert abs(got - ref) <= 1e-8 * abs(ref)
+
+
 def test_adjoint_elastic_path_equals_linear_backward():
     """Elastic path: J = sum_p g_p . C_lin E_p, so the path adjoint must equal the
     linear map's backward with cotangent sum_p g_p E_p^T."""
