@@ -75,7 +75,9 @@ extern "C" {
  *   DMN_MAX_RUN_DEPTH:      dmn_update_gauss_points, dmn_homogenize_linear,
  *                           dmn_homogenize_linear_groups
  *   DMN_MAX_RUN_DEPTH_VJP:  dmn_homogenize_backward,
- *                           dmn_homogenize_backward_groups, dmn_update_adjoint
+ *                           dmn_homogenize_backward_groups, dmn_update_adjoint,
+ *                           and orientation-interpolated groups of
+ *                           dmn_update_gauss_points
  * The training update, refresh and orientation-group calls take every depth
  * up to DMN_MAX_DEPTH. */
 #define DMN_MAX_DEPTH 10

@@ -298,7 +298,8 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                     !g.tangent || !g.iters || !g.status))
       return DMN_EINVAL;
     if (g.P > 0 && (g.z_in == g.z_out || g.a_in == g.a_out)) return DMN_EINVAL;
-    if (!depth_runs(g.net.depth)) return DMN_EUNSUPPORTED;
+    if (!depth_runs(g.net.depth) || (m > 0 && !depth_runs_vjp(g.net.depth)))
+      return DMN_EUNSUPPORTED;
   }
   // one snapshot of the tuning table per call
   GpTune tune[DMN_MAX_DEPTH + 1];

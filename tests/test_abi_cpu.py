@@ -138,6 +138,13 @@ def test_orientation_validation_codes():
     assert call(ori_group(L.DMN_ORI["trilinear"], q=None)) == L.DMN_EINVAL
     assert call(ori_group(L.DMN_ORI["quadratic"], lam=None)) == L.DMN_EINVAL
     assert call(ori_group(L.DMN_ORI["none"])) == L.DMN_EINVAL  # fixed normals need n
+    # interpolated normals run up to depth 8 (depth 9's kernel has not run)
+    deep = ori_group(L.DMN_ORI["linear"])
+    deep[0].net.depth = 9
+    assert call(deep) == L.DMN_EUNSUPPORTED
+    deep[0].net.depth = 8
+    assert lib.dmn_update_gauss_points(deep, 1, ctypes.byref(fib), ctypes.byref(mat), L.DMN_F64,
+                                       ctypes.byref(opts), None, 0, None) == L.DMN_EWORKSPACE
     # linear calls: per-sample orientation needs lam; the backward needs space for
     # the per-sample angle cotangents
     onet = L.DmnNet(3, FAKE.value, None, L.DMN_ORI["linear"], FAKE.value, FAKE.value)

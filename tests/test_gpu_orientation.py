@@ -68,7 +68,8 @@ def compare(net, lam, E_path, points, gpu, rows=None):
         f"worst rel {worst:.2e}")
 
 
-@pytest.mark.parametrize("K,kind", [(2, "linear"), (3, "trilinear"), (5, "quadratic"),
+@pytest.mark.parametrize("K,kind", [(1, "quadratic"), (2, "linear"), (3, "trilinear"),
+                                    (4, "linear"), (5, "quadratic"), (6, "trilinear"),
                                     (7, "linear"), (8, "quadratic")])
 def test_orientation_ragged(K, kind):
     say(f"case: orientation-interpolated normals, depth {K}, {kind}, 37 points x 4 steps")
