@@ -446,9 +446,39 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
   if (lane == 0 && (fail || *flag)) atomicOr(err, (*flag ? 1 : 0) | (fail ? 2 : 0));
 }
 
-// Sum the partials over wave slots in a fixed order: one workgroup per
-// (group, laminate, component) row; each thread sums a strided subset of the
-// group's slots, then a fixed-shape tree in LDS.  gsum[g][pos * 4 + c].
+// Sum the partials over wave slots in a fixed order, gsum[g][pos * 4 + c].  A
+// group with at most kSeqSlots slots has one thread per row summing them in
+// slot order (reduce_partials_seq_kernel); a larger one has one workgroup per
+// row, each thread summing a strided subset, then a fixed-shape tree in LDS
+// (reduce_partials_kernel).  The choice depends on the group's slot count
+// only, so a group's sums are the same in a grouped and in a plain call.
+constexpr long long kSeqSlots = 64;
+
+__global__ __launch_bounds__(256) void reduce_partials_seq_kernel(
+    const double* __restrict__ partials, int ppw, int L4, int rows, double* __restrict__ gsum,
+    const LinGroups grp) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows) return;
+  const int g = i / L4;
+  const int r = i % L4;
+  const long long nslots = (long long)(grp.block0[g + 1] - grp.block0[g]) * ppw;
+  if (nslots > kSeqSlots) return;  // a row of reduce_partials_kernel
+  const double* row =
+      partials + (size_t)grp.block0[g] * ppw * L4 + (size_t)r * nslots;
+  // loads issued eight at a time, added in slot order
+  double s = 0.0;
+  long long q = 0;
+  for (; q + 8 <= nslots; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = row[q + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; q < nslots; ++q) s += row[q];
+  gsum[(size_t)g * L4 + r] = s;
+}
+
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials,
                                                               int ppw, int L4,
                                                               double* __restrict__ gsum,
@@ -457,6 +487,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
   const int g = blockIdx.x / L4;
   const int r = blockIdx.x % L4;
   const long long nslots = (long long)(grp.block0[g + 1] - grp.block0[g]) * ppw;
+  if (nslots <= kSeqSlots) return;  // a row of reduce_partials_seq_kernel (whole workgroup)
   const double* row =
       partials + (size_t)grp.block0[g] * ppw * L4 + (size_t)r * nslots;
   double s = 0.0;
@@ -706,8 +737,17 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
       bwd_launch<T, K, false>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part, err,
                               ori, gr, s);
     double* gs = gsum + (size_t)g0 * L4;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(ng * L4)), dim3(256), 0, s,
-                       (const double*)part, C::PPW, L4, gs, gr);
+    bool any_seq = false, any_tree = false;
+    for (int q = 0; q < ng; ++q) {
+      const long long nslots = (long long)(gr.block0[q + 1] - gr.block0[q]) * C::PPW;
+      (nslots <= kSeqSlots ? any_seq : any_tree) = true;
+    }
+    if (any_seq)
+      hipLaunchKernelGGL(reduce_partials_seq_kernel, dim3((unsigned)((ng * L4 + 255) / 256)),
+                         dim3(256), 0, s, (const double*)part, C::PPW, L4, ng * L4, gs, gr);
+    if (any_tree)
+      hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(ng * L4)), dim3(256), 0, s,
+                         (const double*)part, C::PPW, L4, gs, gr);
     hipLaunchKernelGGL((finish_grads_kernel<T>), dim3((nleaf + 255) / 256, (unsigned)ng), dim3(256),
                        0, s, (const double*)gs, (const T*)tabc, tab_stride, K,
                        (T*)gw + (size_t)g0 * nleaf, (T*)gn + (size_t)g0 * 3 * C::L, 1);
