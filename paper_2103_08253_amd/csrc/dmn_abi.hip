@@ -95,8 +95,9 @@ extern "C" {
 const char* dmn_version(void) { return "libdmn 0.1 gfx950"; }
 
 // a net for the linear calls.  Orientation-interpolated normals are switched
-// off here: the first GPU run of the per-sample orientation kernels ended in
-// a device fault whose cause is not yet found.
+// off here: the first GPU runs of the per-sample orientation kernels failed
+// through a miscompile of the shape-function helper (since rewritten), and
+// the path has not been run on the device again.
 static int linear_net_check(const dmn_net* net, int64_t B, const void* lam) {
   if (!net || !depth_ok(net->depth) || B < 0 || !net->w) return DMN_EINVAL;
   const int m = ori_count(net->ori_shape);

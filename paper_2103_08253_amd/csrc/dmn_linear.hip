@@ -638,7 +638,8 @@ static int fwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
   using C = LCfg<K, D>;
   const LinOri<T> ori{(const T*)o.p, (const T*)o.q, (const T*)o.lam, (T*)o.gang, o.m};
   // per-sample orientation (ORI = true) is not launched: switched off after
-  // an unexplained device fault on its first GPU run
+  // its first GPU runs failed (a miscompiled shape-function helper, since
+  // rewritten) and not run on the device since
   if (o.m > 0) return (int)hipErrorInvalidValue;
   for (int g0 = 0; g0 < G; g0 += kMaxLinGroups) {
     const int ng = G - g0 < kMaxLinGroups ? G - g0 : kMaxLinGroups;
