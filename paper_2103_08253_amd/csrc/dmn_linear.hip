@@ -236,7 +236,8 @@ __device__ __forceinline__ void lin_back(const R& rows, const LinOri<T>& ori, lo
                                          long long b, int t, bool live,
                                          const T* C1, const T* C2,
                                          const T (&nodes)[LCfg<K, D>::NLAM][21],
-                                         const T (&Gm)[21], double (&acc)[LCfg<K, D>::NLAM][4],
+                                         const T (&Gm)[21],
+                                         double (&acc)[LCfg<K, D>::NLAM][4][64],
                                          T (&g1)[IG ? 21 : 1], T (&g2)[IG ? 21 : 1]) {
   using C = LCfg<K, D>;
   if constexpr (H >= C::NLEAF) {
@@ -263,10 +264,11 @@ __device__ __forceinline__ void lin_back(const R& rows, const LinOri<T>& ori, lo
     T GL[21], GR[21], gc1, gn[3];
     laminate_linear_vjp(CL, CR, row.nv, row.c1, row.c2, Gm, GL, GR, gc1, gn);
     if (live) {
-      acc[H - 1][0] += (double)gc1;
-      acc[H - 1][1] += (double)gn[0];
-      acc[H - 1][2] += (double)gn[1];
-      acc[H - 1][3] += (double)gn[2];
+      const int ln = threadIdx.x;
+      acc[H - 1][0][ln] += (double)gc1;
+      acc[H - 1][1][ln] += (double)gn[0];
+      acc[H - 1][2][ln] += (double)gn[1];
+      acc[H - 1][3][ln] += (double)gn[2];
       if constexpr (ORI) put_angles<T, C::L>(ori, B, b, pos, rows.nrm, gn);
     }
     lin_back<T, K, D, 2 * H, IG, ORI>(rows, ori, B, b, t, live, C1, C2, nodes, GL, acc, g1, g2);
@@ -291,11 +293,13 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
   const int slot = lane / C::LP, t = lane % C::LP;
   for (int u = lane; u < C::PPW * (C::NUP > 0 ? C::NUP : 1); u += 64)
     for (int c = 0; c < 4; ++c) accU[c][u] = 0.0;
-  double acc[C::NLAM][4];
+  // per-lane sums of the lane-subtree laminates' cotangents, in LDS (each lane
+  // its own column) rather than held in registers through the whole loop
+  __shared__ double acc[C::NLAM][4][64];
 #pragma unroll
   for (int h = 0; h < C::NLAM; ++h)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[h][c] = 0.0;
+    for (int c = 0; c < 4; ++c) acc[h][c][lane] = 0.0;
   int fail = 0;
   // this workgroup's group: its table, samples s0 .. s0+Bg-1 and workgroups
   const int g = lin_group(grp);
@@ -427,7 +431,9 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
         const int m = ilog2l(h);
         const int k = K - D + 1 + m;
         const int pos = (1 << K) - (1 << k) + t * (1 << m) + (h - (1 << m));
-        put(pos, acc[h - 1]);
+        const double v[4] = {acc[h - 1][0][lane], acc[h - 1][1][lane], acc[h - 1][2][lane],
+                             acc[h - 1][3][lane]};
+        put(pos, v);
       }
     }
   }();
