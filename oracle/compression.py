@@ -11,6 +11,7 @@ laminates that remain, with volume fractions from the remaining weights.
 import numpy as np
 import scipy.sparse as sp
 
+from .j2 import LOCAL_MAXIT
 from .linear import laminate_milton
 from .tree import lam_pos
 
@@ -122,7 +123,7 @@ class CompressedDmnModel:
         out[self.pos] = np.asarray(a_red).reshape(-1, 3)
         return out.ravel()
 
-    def evaluate(self, E, z_n, a):
+    def evaluate(self, E, z_n, a, local_max_iter=LOCAL_MAXIT):
         from .j2 import j2_update
         n = len(self.live_leaves)
         eps = E[None, :] + (self.A @ a).reshape(n, 6)
@@ -137,7 +138,7 @@ class CompressedDmnModel:
                 D[r] = self.Cf
             else:
                 m = j // 2
-                out = j2_update(self.mat, eps[r], z_n[m, :6], z_n[m, 6])
+                out = j2_update(self.mat, eps[r], z_n[m, :6], z_n[m, 6], local_max_iter)
                 sig[r], D[r] = out["sigma"], out["D"]
                 z[m, :6], z[m, 6] = out["ep"], out["p"]
                 margin = min(margin, abs(out["margin"]))

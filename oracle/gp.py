@@ -32,7 +32,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from .j2 import J2Material, j2_update
+from .j2 import LOCAL_MAXIT, J2Material, j2_update
 from .mandel import iso_from_E_nu
 from .tree import gradient_operator, lam_leaves, laminates
 
@@ -49,6 +49,8 @@ class NewtonOptions:
     # imaginary part of an iterate is the derivative at the previous iterate, so
     # one more step makes it the derivative at the converged jumps)
     polish: int = 0
+    # cap of the scalar Newton iterations of the J2 return at each matrix leaf
+    local_max_iter: int = LOCAL_MAXIT
 
 
 class DmnModel:
@@ -76,7 +78,7 @@ class DmnModel:
         self.mat = J2Material(**matrix)
         self.B = np.tile(np.eye(6), (self.nL, 1))
 
-    def evaluate(self, E, z_n, a):
+    def evaluate(self, E, z_n, a, local_max_iter=LOCAL_MAXIT):
         """Leaf strains, stresses, tangents and the residual at jumps a."""
         eps = E[None, :] + (self.A @ a).reshape(self.nL, 6)
         dt = np.result_type(self.dtype, eps, z_n)
@@ -91,7 +93,7 @@ class DmnModel:
                 D[j] = self.Cf
             else:
                 m = j // 2
-                out = j2_update(self.mat, eps[j], z_n[m, :6], z_n[m, 6])
+                out = j2_update(self.mat, eps[j], z_n[m, :6], z_n[m, 6], local_max_iter)
                 sig[j], D[j] = out["sigma"], out["D"]
                 z[m, :6], z[m, 6] = out["ep"], out["p"]
                 margin = min(margin, abs(out["margin"]))
@@ -146,7 +148,7 @@ def gp_update(model: DmnModel, E, z_n, a_n, opts: NewtonOptions = NewtonOptions(
         return dict(fail, status=NONFINITE)
     scale = opts.tol * model.L
     a = a_n.copy()
-    ev = model.evaluate(E, z_n, a)
+    ev = model.evaluate(E, z_n, a, opts.local_max_iter)
     margin = ev["margin"]
     iters = 0
     status = OK
@@ -165,7 +167,7 @@ def gp_update(model: DmnModel, E, z_n, a_n, opts: NewtonOptions = NewtonOptions(
             polish -= 1
             H, _ = model.hessian(ev["D"])
             a = a - model.solve(H, ev["r"])
-            ev = model.evaluate(E, z_n, a)
+            ev = model.evaluate(E, z_n, a, opts.local_max_iter)
             continue
         if iters == opts.max_iter:
             status = MAXITER
@@ -178,7 +180,7 @@ def gp_update(model: DmnModel, E, z_n, a_n, opts: NewtonOptions = NewtonOptions(
             break
         s = 1.0
         for bt in range(opts.max_backtrack + 1):
-            trial = model.evaluate(E, z_n, a + s * da)
+            trial = model.evaluate(E, z_n, a + s * da, opts.local_max_iter)
             margin = min(margin, trial["margin"])
             good = _finite(trial) and trial["local_ok"]
             if good and np.linalg.norm(trial["r"]) <= (1.0 - opts.armijo * s) * rn:

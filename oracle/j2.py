@@ -18,7 +18,8 @@ leaf are the traceless plastic strain (Mandel 6-vector) followed by p; a
 trial state exactly on the yield surface (f = 0) counts as elastic; the
 scalar Newton iteration starts at 0 and stops once the update is at most
 1e-14 times q / (2G), the largest plastic multiplier the return admits (at
-most 50 iterations).  A relative test on the iterate itself cannot be met
+most max_iter iterations, 50 unless the caller caps it lower; a return that
+has not met the test by then is reported as not converged).  A relative test on the iterate itself cannot be met
 for small plastic increments: the consistency residual is a difference of
 numbers of size q, so the update stalls at roundoff of q / (2G).
 
@@ -49,7 +50,7 @@ class J2Material:
         return 3.0 * self.K * P1 + 2.0 * self.G * P2
 
 
-def j2_update(mat, eps, ep_n, p_n):
+def j2_update(mat, eps, ep_n, p_n, max_iter=LOCAL_MAXIT):
     """One implicit Euler step of the J2 law at a single leaf.
 
     Returns dict(sigma[6], D[6,6], ep[6], p, plastic, margin, local_iters, ok),
@@ -75,7 +76,7 @@ def j2_update(mat, eps, ep_n, p_n):
     xtol = LOCAL_TOL * np.real(q) / (2.0 * G)
     ok = False
     it = 0
-    for it in range(1, LOCAL_MAXIT + 1):
+    for it in range(1, max_iter + 1):
         p = p_n + SQ23 * x
         g = q - 2.0 * G * x - SQ23 * mat.sigma_y(p)
         dg = -2.0 * G - (2.0 / 3.0) * mat.dsigma_y(p)

@@ -159,6 +159,49 @@ def test_status_codes():
     # zero strain from the virgin state: zero residual, converged without a step
     out = G.gp_update(m, np.zeros(6), z, a)
     assert out["status"] == 0 and out["iters"] == 0
+    # a zero normal makes its laminate's block of the Hessian vanish: not positive definite
+    nz = net.normals.copy()
+    nz[1] = 0.0
+    out = G.gp_update(G.DmnModel(2, net.w, nz, S.FIBER, S.MATRIX), E, z, a)
+    assert out["status"] == G.NOTSPD and out["iters"] == 0 and np.all(out["a"] == a)
+    # the J2 return capped at one scalar iteration cannot meet its test on a plastic leaf
+    out = G.gp_update(m, E, z, a, G.NewtonOptions(local_max_iter=1))
+    assert out["status"] == G.LOCALFAIL and np.all(out["z"] == z)
+    assert G.gp_update(m, E, z, a, G.NewtonOptions(local_max_iter=50))["status"] == 0
+    # an elastic step never enters the scalar iteration
+    out = G.gp_update(m, 1e-5 * E, z, a, G.NewtonOptions(local_max_iter=1))
+    assert out["status"] == 0
+
+
+def test_backtracking_rule():
+    """With a strict sufficient-decrease factor (armijo close to 1) the full
+    Newton step is rejected and halved (reading R5); the converged answer is
+    the same as without backtracking, only the iteration count changes.  With
+    max_backtrack = 1 a half step is accepted whatever its residual."""
+    rng = np.random.default_rng(41)
+    net = S.random_dmn(rng, 3, 0.25)
+    m = model_for(net)
+    E = 0.02 * S.unit_directions(rng, 1)[0]
+    z, a = np.zeros((4, 7)), np.zeros(21)
+    trials = []
+    orig = m.evaluate
+
+    def counting(*args):
+        ev = orig(*args)
+        trials.append(np.linalg.norm(ev["r"]))
+        return ev
+
+    m.evaluate = counting
+    ref = G.gp_update(m, E, z, a)
+    n_ref = len(trials)
+    assert n_ref == ref["iters"] + 1  # no backtracking with the default rule
+    for opts in (G.NewtonOptions(armijo=0.99), G.NewtonOptions(armijo=0.9999, max_backtrack=1)):
+        trials.clear()
+        out = G.gp_update(m, E, z, a, opts)
+        assert out["status"] == 0
+        assert len(trials) > out["iters"] + 1          # some trials were rejected
+        assert np.allclose(out["sigma"], ref["sigma"], rtol=1e-9, atol=1e-9)
+        assert np.allclose(out["C"], ref["C"], rtol=1e-7, atol=1e-6)
 
 
 def test_rotational_covariance_of_the_nonlinear_update():
