@@ -115,12 +115,12 @@ extern "C" {
  *     (sin alpha cos beta, sin alpha sin beta, cos alpha).  ori_p, ori_q are
  *     [2^K - 1][M] in paper order; n is not read.  Points outside the
  *     triangle extrapolate the polynomials.  Supported by
- *     dmn_update_gauss_points (per-point orientation).  The linear map and
- *     its backward accept the per-sample form below but currently return
- *     DMN_EUNSUPPORTED (switched off); training over a discrete set of
- *     orientations runs the fixed-normal calls per orientation group
- *     instead (dmn_orientation_group_normals and the calls after it).
- *     dmn_update_adjoint returns DMN_EUNSUPPORTED.
+ *     dmn_update_gauss_points (per-point orientation) and, up to depth 8,
+ *     by the linear map and its backward (per-sample orientation, see
+ *     there; deeper nets return DMN_EUNSUPPORTED); training over a discrete
+ *     set of orientations can also run the fixed-normal calls per
+ *     orientation group (dmn_orientation_group_normals and the calls after
+ *     it).  dmn_update_adjoint returns DMN_EUNSUPPORTED.
  * All arrays are device memory in the precision of the call. */
 typedef struct dmn_net {
   int32_t depth;
@@ -147,12 +147,21 @@ typedef struct dmn_j2 {
  * |A^T W sigma| <= tol (2^K - 1) |sigma_bar| (Frobenius norms); at most
  * max_iter Newton steps; backtracking halves the step while the trial residual
  * is non-finite or |r(a + s da)| > (1 - armijo s) |r(a)|, at most
- * max_backtrack times (the last trial is then taken as it is). */
+ * max_backtrack times (the last trial is then taken as it is).
+ * local_max_iter caps the scalar Newton iterations of the J2 return at every
+ * matrix leaf (0 selects the default 50); a return that has not converged
+ * within it fails the point with DMN_STATUS_LOCAL.  polish (>= 0) adds that
+ * many full Newton steps once the stop test is met, taken without the
+ * backtracking test and not counted in iters: with 1 the returned jumps
+ * satisfy the Euler-Lagrange equation to roundoff, which a derivative of the
+ * converged path (the path adjoint) assumes; 0 for the plain update. */
 typedef struct dmn_newton_opts {
   double tol;
   int32_t max_iter;
   int32_t max_backtrack;
   double armijo;
+  int32_t local_max_iter;
+  int32_t polish;
 } dmn_newton_opts;
 
 /* One batch of Gauss points that share a DMN.  With M = 2^(K-1) matrix

@@ -34,7 +34,8 @@ class DmnJ2(ctypes.Structure):
 
 class DmnNewtonOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("max_backtrack", ctypes.c_int32), ("armijo", ctypes.c_double)]
+                ("max_backtrack", ctypes.c_int32), ("armijo", ctypes.c_double),
+                ("local_max_iter", ctypes.c_int32), ("polish", ctypes.c_int32)]
 
 
 class DmnPointGroup(ctypes.Structure):

@@ -312,7 +312,8 @@ def _materials(fiber: dict, matrix: dict):
 
 
 def dmn_update_gauss_points(groups: List[PointGroup], fiber: dict, matrix: dict, tol=1e-10,
-                            max_iter=25, max_backtrack=10, armijo=1e-4, ws=None):
+                            max_iter=25, max_backtrack=10, armijo=1e-4, ws=None,
+                            local_max_iter=0, polish=0):
     """One load step at every point of every group (outputs written in place).
 
     All groups hold their per-point arrays in one dtype: float64 (DMN_F64);
@@ -323,7 +324,7 @@ def dmn_update_gauss_points(groups: List[PointGroup], fiber: dict, matrix: dict,
     prec = precs.pop()
     arr = (L.DmnPointGroup * len(groups))(*[g.to_c() for g in groups])
     fib, mat = _materials(fiber, matrix)
-    opts = L.DmnNewtonOpts(tol, max_iter, max_backtrack, armijo)
+    opts = L.DmnNewtonOpts(tol, max_iter, max_backtrack, armijo, local_max_iter, polish)
     lib = L.lib()
     nbytes = lib.dmn_update_gauss_points_workspace_size(arr, len(groups), prec)
     if nbytes == 0:

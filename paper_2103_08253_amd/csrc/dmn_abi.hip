@@ -94,17 +94,15 @@ extern "C" {
 
 const char* dmn_version(void) { return "libdmn 0.1 gfx950"; }
 
-// a net for the linear calls.  Orientation-interpolated normals are switched
-// off here: the first GPU runs of the per-sample orientation kernels failed
-// through a miscompile of the shape-function helper (since rewritten), and
-// the path has not been run on the device again.
+// a net for the linear calls: fixed normals, or normals interpolated per
+// sample from its fibre orientation lam (up to the depth of the VJP kernels)
 static int linear_net_check(const dmn_net* net, int64_t B, const void* lam) {
   if (!net || !depth_ok(net->depth) || B < 0 || !net->w) return DMN_EINVAL;
   const int m = ori_count(net->ori_shape);
   if (m < 0) return DMN_EINVAL;
   if (m == 0) return net->n ? DMN_OK : DMN_EINVAL;
   if (!net->ori_p || !net->ori_q || (B > 0 && !lam)) return DMN_EINVAL;
-  return DMN_EUNSUPPORTED;
+  return depth_runs_vjp(net->depth) ? DMN_OK : DMN_EUNSUPPORTED;
 }
 
 static dmn::LinOriArgs lin_ori(const dmn_net* net, const void* lam, void* gang) {
@@ -286,7 +284,8 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   if (prec != DMN_F64) return DMN_EUNSUPPORTED;  // DMN_F32_STATE is switched off
   if (!phase_ok(fiber) || !j2_ok(matrix) || !opts) return DMN_EINVAL;
   if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->max_backtrack < 0 ||
-      !(opts->armijo >= 0.0 && opts->armijo < 1.0))
+      !(opts->armijo >= 0.0 && opts->armijo < 1.0) || opts->local_max_iter < 0 ||
+      opts->polish < 0)
     return DMN_EINVAL;
   for (int i = 0; i < n_groups; ++i) {
     const dmn_point_group& g = groups[i];
@@ -334,6 +333,7 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   memset(&base, 0, sizeof(base));
   base.max_iter = opts->max_iter;
   base.max_bt = opts->max_backtrack;
+  base.polish = opts->polish;
   base.tol = opts->tol;
   base.armijo = opts->armijo;
   base.fib.K = fiber->E / (3.0 * (1.0 - 2.0 * fiber->nu));
@@ -344,6 +344,7 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   base.mat.k_inf = matrix->k_inf;
   base.mat.dsigma = matrix->dsigma;
   base.mat.b = matrix->b;
+  base.mat.max_it = opts->local_max_iter > 0 ? opts->local_max_iter : dmn::kLocalMaxIt;
 
   // one launch per depth (deepest first) and kind of normals, up to
   // kMaxGroupsPerLaunch groups each
@@ -476,6 +477,7 @@ int dmn_update_adjoint(const dmn_adjoint_group* groups, int32_t n_groups,
     a.mat.k_inf = matrix->k_inf;
     a.mat.dsigma = matrix->dsigma;
     a.mat.b = matrix->b;
+    a.mat.max_it = dmn::kLocalMaxIt;
     if (dmn::launch_adjoint(K, a, stream)) return DMN_EHIP;
   }
   return DMN_OK;

@@ -412,11 +412,12 @@ __device__ __forceinline__ void iso_packed(const IsoElastic& m, double C[21]) {
 
 struct J2Law {
   double K, G, sigma0, k_inf, dsigma, b;
+  int max_it;  // cap of the scalar Newton iterations of the return
 };
 
 constexpr double kSqrt23 = 0.81649658092772603273;  // sqrt(2/3)
 constexpr double kLocalTol = 1e-14;
-constexpr int kLocalMaxIt = 50;
+constexpr int kLocalMaxIt = 50;  // default cap of the scalar Newton iterations
 
 // J2 radial return (implicit Euler) with sigma_Y(p) = s0 + k p + ds (1 - exp(-b p)).
 // Outputs stress, packed consistent tangent and the new internal variables.
@@ -447,7 +448,7 @@ __device__ __forceinline__ bool j2_return(const J2Law& m, const double eps[6], c
   if (f > 0.0) {
     const double xtol = kLocalTol * q / (2.0 * m.G);
     ok = false;
-    for (int it = 0; it < kLocalMaxIt; ++it) {
+    for (int it = 0; it < m.max_it; ++it) {
       const double pp = pn + kSqrt23 * x;
       const double ex = exp(-m.b * pp);
       const double sy = m.sigma0 + m.k_inf * pp + m.dsigma * (1.0 - ex);
@@ -529,7 +530,7 @@ __device__ __forceinline__ void j2_vjp(const J2Law& m, const double eps[6], cons
   if (f > 0.0) {
     const double xtol = kLocalTol * q / (2.0 * m.G);
     double x = 0.0;
-    for (int it = 0; it < kLocalMaxIt; ++it) {
+    for (int it = 0; it < m.max_it; ++it) {
       const double pp = pn + kSqrt23 * x;
       const double ex = exp(-m.b * pp);
       const double sy = m.sigma0 + m.k_inf * pp + m.dsigma * (1.0 - ex);

@@ -201,6 +201,8 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
 
   const double scale = args.tol * (double)C::L;
   int status = 0, iters = 0, bt = 0;
+  int polish = args.polish;  // full steps still to take after the stop test
+  bool polishing = false;    // the current trial is such a step
   bool done = !in_range;
   bool first = true;
   double s = 0.0, rn = 0.0;
@@ -221,7 +223,7 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
       } else {
         const double rt = sqrt(ev.rr);
         const bool good = isfinite(rt) && isfinite(ev.sn2) && !ev.lfail;
-        if ((good && rt <= (1.0 - args.armijo * s) * rn) || bt >= args.max_bt) {
+        if (polishing || (good && rt <= (1.0 - args.armijo * s) * rn) || bt >= args.max_bt) {
 #pragma unroll
           for (int h = 0; h < C::NLAM; ++h)
 #pragma unroll
@@ -234,7 +236,8 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
               for (int k = 0; k < 3; ++k) up.a[k][u] += s * up.da[k][u];
             }
           }
-          ++iters;
+          if (!polishing) ++iters;
+          polishing = false;
           accepted = true;
         } else {
           s *= 0.5;
@@ -247,8 +250,15 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
         int fin = -1;
         if (ev.lfail) fin = DMN_STATUS_LOCAL;
         else if (!isfinite(rn) || !isfinite(sn)) fin = DMN_STATUS_NONFINITE;
-        else if (rn == 0.0 || rn <= scale * sn) fin = ev.spdfail ? DMN_STATUS_NOTSPD : 0;
-        else if (iters >= args.max_iter) fin = DMN_STATUS_MAXITER;
+        else if (rn == 0.0 || rn <= scale * sn) {
+          if (ev.spdfail) fin = DMN_STATUS_NOTSPD;
+          else if (polish > 0) {
+            --polish;
+            polishing = true;  // one more full step, then the test again
+          } else {
+            fin = 0;
+          }
+        } else if (iters >= args.max_iter) fin = DMN_STATUS_MAXITER;
         else if (ev.spdfail) fin = DMN_STATUS_NOTSPD;
         if (fin >= 0) {
           status = fin;

@@ -56,7 +56,7 @@ struct GpLaunch {
   int ng;
   int max_iter;
   int max_bt;
-  int pad;
+  int polish;  // full Newton steps after the stop test is met (not counted, no backtracking)
   double tol;
   double armijo;
   IsoElastic fib;

@@ -585,6 +585,8 @@ __global__ __launch_bounds__(256) void reduce_orientation_kernel(const T* __rest
 }
 
 constexpr int kMaxBwdWaves = 2048;
+// deepest DMN whose linear map and VJP are compiled with per-sample orientation
+constexpr int kMaxOriLinearDepth = 8;
 
 }  // namespace
 
@@ -643,10 +645,8 @@ static int fwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
   constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
   using C = LCfg<K, D>;
   const LinOri<T> ori{(const T*)o.p, (const T*)o.q, (const T*)o.lam, (T*)o.gang, o.m};
-  // per-sample orientation (ORI = true) is not launched: switched off after
-  // its first GPU runs failed (a miscompiled shape-function helper, since
-  // rewritten) and not run on the device since
-  if (o.m > 0) return (int)hipErrorInvalidValue;
+  // per-sample orientation: plain (one-group) calls only
+  if (o.m > 0 && G != 1) return (int)hipErrorInvalidValue;
   for (int g0 = 0; g0 < G; g0 += kMaxLinGroups) {
     const int ng = G - g0 < kMaxLinGroups ? G - g0 : kMaxLinGroups;
     LinGroups gr;
@@ -654,10 +654,18 @@ static int fwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
                                       [](long long B) { return (B + C::PPW - 1) / C::PPW; });
     if (nb < 0) return (int)hipErrorInvalidValue;
     if (nb == 0) continue;
-    hipLaunchKernelGGL((linear_fwd_kernel<T, K, D, false>), dim3((unsigned)nb), dim3(64), 0, s,
-                       (const T*)((const char*)tab + g0 * tab_stride),
-                       (const int32_t*)((const char*)flag + g0 * tab_stride), (const T*)C1,
-                       (const T*)C2, (T*)Cbar, err, ori, gr);
+    const T* tabc = (const T*)((const char*)tab + g0 * tab_stride);
+    const int32_t* flagc = (const int32_t*)((const char*)flag + g0 * tab_stride);
+    if (o.m > 0) {
+      // per-sample orientation is compiled up to the depth of the VJP kernels
+      if constexpr (K <= kMaxOriLinearDepth)
+        hipLaunchKernelGGL((linear_fwd_kernel<T, K, D, true>), dim3((unsigned)nb), dim3(64), 0,
+                           s, tabc, flagc, (const T*)C1, (const T*)C2, (T*)Cbar, err, ori, gr);
+      else
+        return (int)hipErrorInvalidValue;
+    } else
+      hipLaunchKernelGGL((linear_fwd_kernel<T, K, D, false>), dim3((unsigned)nb), dim3(64), 0, s,
+                         tabc, flagc, (const T*)C1, (const T*)C2, (T*)Cbar, err, ori, gr);
   }
   return (int)hipGetLastError();
 }
@@ -705,15 +713,19 @@ int launch_linear_forward_groups(int depth, int prec, const void* tab, const int
   return fwd_t<double>(depth, tab, flag, tab_stride, G, off, C1, C2, Cbar, err, none, stream);
 }
 
-template <typename T, int K, bool IG>
+template <typename T, int K, bool IG, bool ORI>
 static void bwd_launch(long long waves, const void* tab, const int32_t* flag, long long B,
                        const void* C1, const void* C2, const void* gCbar, void* gC1, void* gC2,
                        double* partials, int32_t* err, const LinOri<T>& ori, const LinGroups& gr,
                        hipStream_t s) {
   constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
-  hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, IG, false>), dim3((unsigned)waves), dim3(64), 0,
-                     s, (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar,
-                     (T*)gC1, (T*)gC2, partials, err, ori, gr);
+  if constexpr (ORI && K > kMaxOriLinearDepth) {
+    return;  // not compiled; rejected by the caller
+  } else {
+    hipLaunchKernelGGL((linear_bwd_kernel<T, K, D, IG, ORI>), dim3((unsigned)waves), dim3(64), 0,
+                       s, (const T*)tab, flag, B, (const T*)C1, (const T*)C2, (const T*)gCbar,
+                       (T*)gC1, (T*)gC2, partials, err, ori, gr);
+  }
 }
 
 template <typename T, int K>
@@ -724,7 +736,8 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
   constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
   using C = LCfg<K, D>;
   const LinOri<T> ori{(const T*)o.p, (const T*)o.q, (const T*)o.lam, (T*)o.gang, o.m};
-  if (o.m > 0) return (int)hipErrorInvalidValue;  // switched off, see the forward launcher
+  const bool oriented = o.m > 0;
+  if (oriented && (G != 1 || K > kMaxOriLinearDepth)) return (int)hipErrorInvalidValue;
   const bool ig = gC1 != nullptr;
   const int L4 = C::L * 4;
   const int nleaf = 1 << K;
@@ -737,12 +750,18 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
     if (waves < 0 || (long long)ng * L4 > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     const void* tabc = (const char*)tab + g0 * tab_stride;
     const int32_t* flagc = (const int32_t*)((const char*)flag + g0 * tab_stride);
-    if (ig)
-      bwd_launch<T, K, true>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part, err, ori,
-                             gr, s);
+    if (ig && oriented)
+      bwd_launch<T, K, true, true>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part, err,
+                                   ori, gr, s);
+    else if (ig)
+      bwd_launch<T, K, true, false>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part,
+                                    err, ori, gr, s);
+    else if (oriented)
+      bwd_launch<T, K, false, true>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part,
+                                    err, ori, gr, s);
     else
-      bwd_launch<T, K, false>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part, err,
-                              ori, gr, s);
+      bwd_launch<T, K, false, false>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part,
+                                     err, ori, gr, s);
     double* gs = gsum + (size_t)g0 * L4;
     bool any_seq = false, any_tree = false;
     for (int q = 0; q < ng; ++q) {
@@ -757,7 +776,12 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
                          (const double*)part, C::PPW, L4, gs, gr);
     hipLaunchKernelGGL((finish_grads_kernel<T>), dim3((nleaf + 255) / 256, (unsigned)ng), dim3(256),
                        0, s, (const double*)gs, (const T*)tabc, tab_stride, K,
-                       (T*)gw + (size_t)g0 * nleaf, (T*)gn + (size_t)g0 * 3 * C::L, 1);
+                       (T*)gw + (size_t)g0 * nleaf, (T*)gn + (size_t)g0 * 3 * C::L,
+                       oriented ? 0 : 1);
+    // per-sample orientation: gn is the angle-coefficient cotangent [L][2][m]
+    if (oriented)
+      hipLaunchKernelGGL((reduce_orientation_kernel<T>), dim3(C::L), dim3(256), 0, s,
+                         (const T*)o.gang, (const T*)o.lam, off[G], o.m, (T*)gn);
     part += (size_t)waves * C::PPW * L4;
   }
   return (int)hipGetLastError();

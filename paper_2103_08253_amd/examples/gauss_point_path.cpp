@@ -87,7 +87,7 @@ int main(int argc, char** argv) {
   g.status = status;
   const dmn_elastic fibre{fib[0], fib[1]};
   const dmn_j2 matrix{mat[0], mat[1], mat[2], mat[3], mat[4], mat[5]};
-  const dmn_newton_opts opts{tol, 25, 10, 1e-4};
+  const dmn_newton_opts opts{tol, 25, 10, 1e-4, 0, 0};
 
   g.z_in = z0;
   g.z_out = z1;

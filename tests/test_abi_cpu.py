@@ -102,6 +102,8 @@ def test_gauss_point_validation_codes():
     assert call(o=L.DmnNewtonOpts(0.0, 25, 10, 1e-4)) == L.DMN_EINVAL
     assert call(o=L.DmnNewtonOpts(1e-10, -1, 10, 1e-4)) == L.DMN_EINVAL
     assert call(o=L.DmnNewtonOpts(1e-10, 25, 10, 1.0)) == L.DMN_EINVAL
+    assert call(o=L.DmnNewtonOpts(1e-10, 25, 10, 1e-4, -1)) == L.DMN_EINVAL
+    assert call(o=L.DmnNewtonOpts(1e-10, 25, 10, 1e-4, 0, -1)) == L.DMN_EINVAL
     assert call(nb=need - 1) == L.DMN_EWORKSPACE
     alias = (L.DmnPointGroup * 1)(group(2, z_out=FAKE.value))
     assert call(a=alias, n=1) == L.DMN_EINVAL
@@ -153,14 +155,22 @@ def test_orientation_validation_codes():
     assert nb == lib.dmn_homogenize_linear_workspace_size(ctypes.byref(fnet), 4, L.DMN_F64)
     assert lib.dmn_homogenize_linear(ctypes.byref(onet), 4, L.DMN_F64, FAKE, FAKE, None, FAKE,
                                      ALIGNED, nb, None) == L.DMN_EINVAL
-    # per-sample orientation in the linear calls is switched off
+    # per-sample orientation in the linear calls: valid up to depth 8 (the call
+    # goes on to the workspace check), deeper nets are not compiled for it
     assert lib.dmn_homogenize_linear(ctypes.byref(onet), 4, L.DMN_F64, FAKE, FAKE, FAKE, FAKE,
-                                     ALIGNED, nb, None) == L.DMN_EUNSUPPORTED
+                                     ALIGNED, nb - 1, None) == L.DMN_EWORKSPACE
     nbo = lib.dmn_homogenize_backward_workspace_size(ctypes.byref(onet), 4096, L.DMN_F64)
     nbf = lib.dmn_homogenize_backward_workspace_size(ctypes.byref(fnet), 4096, L.DMN_F64)
     assert nbo - nbf >= 7 * 2 * 4096 * 8
     assert lib.dmn_homogenize_backward(ctypes.byref(onet), 4096, L.DMN_F64, FAKE, FAKE, FAKE,
-                                       FAKE, FAKE, FAKE, None, None, ALIGNED, nbo,
+                                       FAKE, FAKE, FAKE, None, None, ALIGNED, nbo - 1,
+                                       None) == L.DMN_EWORKSPACE
+    onet9 = L.DmnNet(9, FAKE.value, None, L.DMN_ORI["linear"], FAKE.value, FAKE.value)
+    nb9 = lib.dmn_homogenize_backward_workspace_size(ctypes.byref(onet9), 4, L.DMN_F64)
+    assert lib.dmn_homogenize_linear(ctypes.byref(onet9), 4, L.DMN_F64, FAKE, FAKE, FAKE, FAKE,
+                                     ALIGNED, nb9, None) == L.DMN_EUNSUPPORTED
+    assert lib.dmn_homogenize_backward(ctypes.byref(onet9), 4, L.DMN_F64, FAKE, FAKE, FAKE,
+                                       FAKE, FAKE, FAKE, None, None, ALIGNED, nb9,
                                        None) == L.DMN_EUNSUPPORTED
     bad = L.DmnNet(3, FAKE.value, None, 9, FAKE.value, FAKE.value)
     assert lib.dmn_homogenize_linear_workspace_size(ctypes.byref(bad), 4, L.DMN_F64) == 0

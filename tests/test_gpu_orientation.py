@@ -150,10 +150,6 @@ def to_dev(net, lam, dtype, d):
     return torch.tensor(net.w, device=d, dtype=dtype), ori
 
 
-@pytest.mark.skip(reason="per-sample orientation in the linear map is switched off: its first "
-                  "GPU runs gave a wrong error word and then a device fault, later traced to a "
-                  "miscompiled shape-function helper (since rewritten); the path has not been "
-                  "run on the device again")
 @pytest.mark.parametrize("K,B,kind,dtype,tol", [(3, 37, "trilinear", torch.float64, 1e-10),
                                                 (8, 33, "quadratic", torch.float64, 1e-10),
                                                 (5, 40, "linear", torch.float32, 1e-4)])
@@ -175,10 +171,6 @@ def test_oriented_linear_forward(K, B, kind, dtype, tol):
     assert err <= tol
 
 
-@pytest.mark.skip(reason="per-sample orientation in the linear map is switched off: its first "
-                  "GPU runs gave a wrong error word and then a device fault, later traced to a "
-                  "miscompiled shape-function helper (since rewritten); the path has not been "
-                  "run on the device again")
 @pytest.mark.parametrize("K,B,kind,dtype,tol", [(3, 9, "linear", torch.float64, 1e-9),
                                                 (5, 17, "quadratic", torch.float64, 1e-9),
                                                 (8, 4, "trilinear", torch.float64, 1e-9),

@@ -456,6 +456,35 @@ def test_linear_backward_f64_vs_complex_step(K, B, subset):
         assert abs(gpu_val - cs) <= 1e-9 * max(abs(cs), 1e-12), (which, gpu_val, cs)
 
 
+def test_linear_backward_tree_reduction_vs_complex_step():
+    """Depth 8, B = 256: 256 partial-sum slots per parameter row, more than the
+    64 that one thread sums in slot order, so the batch sum runs through the
+    workgroup tree reduction.  12 weights and 8 laminates' angle gradients
+    against the oracle's complex-step derivatives at 1e-10."""
+    from paper_2103_08253_amd import dmn_homogenize_backward
+    K, B = 8, 256
+    say(f"case: linear backward f64 depth {K} batch {B} (tree reduction of the batch sum)")
+    d = dev()
+    tw = S.config3(batch=B, depth=K)
+    net = tw.truth
+    alpha, beta = S.normals_to_angles(net.normals)
+    G = S.streams(4)["cotangent"].standard_normal((B, 6, 6))
+    gw, gn, _, _, _ = dmn_homogenize_backward(
+        torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d),
+        torch.tensor(tw.C1, device=d), torch.tensor(tw.C2, device=d), torch.tensor(G, device=d))
+    gw, gn = gw.cpu().numpy(), gn.cpu().numpy()
+    ga, gb = chain_angles(gn, alpha, beta)
+    rng = np.random.default_rng(17)
+    w_idx = rng.choice(2 ** K, 12, replace=False)
+    a_idx = np.concatenate([[0, 127, 254], rng.choice(np.arange(1, 254), 5, replace=False)])
+    ref = linear_gradients(K, net.w, alpha, beta, tw.C1, tw.C2, G, w_idx, a_idx)
+    ew = np.abs(gw[w_idx] - ref["gw"][w_idx]).max() / np.abs(ref["gw"][w_idx]).max()
+    ra = np.concatenate([ref["galpha"][a_idx], ref["gbeta"][a_idx]])
+    ea = np.abs(np.concatenate([ga[a_idx], gb[a_idx]]) - ra).max() / np.abs(ra).max()
+    say(f"  rel err gw {ew:.2e}, angles {ea:.2e} (element-wise over the selected entries)")
+    assert ew <= RTOL and ea <= RTOL
+
+
 def test_linear_backward_finite_differences_and_f32():
     from paper_2103_08253_amd import dmn_homogenize_backward, dmn_homogenize_linear
     say("case: linear backward depth 8 batch 4096: FD h=1e-6 and FP32")

@@ -326,6 +326,22 @@ def test_training_full_size_step():
                        np.concatenate([gv, ga, gb]), z, z, z, 1, opts.lr_max)
     got = np.concatenate([P.v.cpu().numpy(), P.alpha.cpu().numpy(), P.beta.cpu().numpy()])
     assert rel(got, th) < 1e-12
+    # the batch gradient itself (2048 partial slots per row, tree reduction)
+    # against the oracle's complex-step derivative of sum_s <gCbar_s, Cbar_s>
+    # for one weight and the two angles of one laminate
+    from oracle.grad import linear_gradients
+    ref = linear_gradients(K, T.macaulay(wl.v0), wl.alpha0, wl.beta0, wl.C1, wl.C2,
+                           gC.cpu().numpy(), [37], [101])
+    gn_np = gn.cpu().numpy()
+    da = np.stack([np.cos(wl.alpha0) * np.cos(wl.beta0), np.cos(wl.alpha0) * np.sin(wl.beta0),
+                   -np.sin(wl.alpha0)], -1)
+    db = np.stack([-np.sin(wl.alpha0) * np.sin(wl.beta0), np.sin(wl.alpha0) * np.cos(wl.beta0),
+                   np.zeros_like(wl.alpha0)], -1)
+    got3 = (gw.cpu().numpy()[37], gn_np[101] @ da[101], gn_np[101] @ db[101])
+    ref3 = (ref["gw"][37], ref["galpha"][101], ref["gbeta"][101])
+    for g_v, r_v in zip(got3, ref3):
+        say(f"  gpu {g_v:.15e} oracle {r_v:.15e}")
+        assert abs(g_v - r_v) <= 1e-10 * abs(r_v)
 
 
 def dead_weights(K, seed):
