@@ -266,6 +266,29 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                             const dmn_newton_opts* opts, void* ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/* Size of the per-device array that dmn_update_gauss_points_noalloc uses as
+ * its workspace (1 MiB: up to 16 groups of depth 9, 32 of depth 8). */
+#define DMN_NOALLOC_SCRATCH_BYTES ((size_t)1 << 20)
+
+/* dmn_update_gauss_points for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation and results, with the workspace taken
+ * from a static device array of DMN_NOALLOC_SCRATCH_BYTES instead of an
+ * argument.  The caller still passes every input and output array.  Calls
+ * no hipMalloc, hipFree or other allocating routine; the array's device
+ * address is looked up once per device, on the first call with that device
+ * current, and the array is held until the process ends.  Returns
+ * DMN_EWORKSPACE when the call needs more than DMN_NOALLOC_SCRATCH_BYTES
+ * (dmn_update_gauss_points_workspace_size), DMN_EHIP when the address
+ * lookup fails, otherwise the codes of dmn_update_gauss_points.  Every call
+ * on one device shares that device's array (it keeps the last call's tables;
+ * the work counters are cleared by a kernel at the start of each call), so
+ * calls that overlap on one device, on different streams or from different
+ * threads, race: the caller orders them. */
+int dmn_update_gauss_points_noalloc(const dmn_point_group* groups, int32_t n_groups,
+                                    const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
+                                    const dmn_newton_opts* opts, hipStream_t stream);
+
 /* Launch tuning of dmn_update_gauss_points for one DMN depth.  The kernels
  * split a point's laminate tree across lanes_per_point lanes of a 64-lane
  * wavefront (each lane owns a subtree of depth K - log2(lanes_per_point), the

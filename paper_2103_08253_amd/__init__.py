@@ -11,7 +11,7 @@ runs in the HIP kernels of libdmn.so; this package only marshals arguments
 from .api import (AdjointGroup, Orientation, PointGroup, dmn_homogenize_backward,  # noqa: F401
                   dmn_homogenize_backward_groups, dmn_homogenize_linear,
                   dmn_homogenize_linear_groups, dmn_update_adjoint, dmn_update_gauss_points,
-                  error_word, workspace)
+                  dmn_update_gauss_points_noalloc, error_word, workspace)
 from ._lib import DmnError, STATUS  # noqa: F401
 from .graph import LinearStepGraph, LoadStepGraph  # noqa: F401
 from .training import (AmsgradOpts, OrientedTrainingStepGraph, OrientedTrainParams,  # noqa: F401

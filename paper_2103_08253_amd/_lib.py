@@ -155,6 +155,11 @@ _SIGS = {
                                                ctypes.POINTER(DmnElastic), ctypes.POINTER(DmnJ2),
                                                ctypes.c_int, ctypes.POINTER(DmnNewtonOpts),
                                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dmn_update_gauss_points_noalloc": (ctypes.c_int, [ctypes.POINTER(DmnPointGroup),
+                                                       ctypes.c_int32, ctypes.POINTER(DmnElastic),
+                                                       ctypes.POINTER(DmnJ2), ctypes.c_int,
+                                                       ctypes.POINTER(DmnNewtonOpts),
+                                                       ctypes.c_void_p]),
     "dmn_gp_set_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(DmnGpTuning)]),
     "dmn_gp_get_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(DmnGpTuning)]),
     "dmn_gp_lane_variants": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),

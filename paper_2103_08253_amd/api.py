@@ -338,6 +338,24 @@ def dmn_update_gauss_points(groups: List[PointGroup], fiber: dict, matrix: dict,
     return ws
 
 
+def dmn_update_gauss_points_noalloc(groups: List[PointGroup], fiber: dict, matrix: dict,
+                                    tol=1e-10, max_iter=25, max_backtrack=10, armijo=1e-4,
+                                    local_max_iter=0, polish=0):
+    """dmn_update_gauss_points without a workspace argument: the library's
+    static per-device array serves as workspace (include/dmn.h); no device
+    memory is allocated by the call."""
+    precs = {g.prec for g in groups}
+    if len(precs) != 1:
+        raise TypeError("all groups of one call must use the same per-point dtype")
+    arr = (L.DmnPointGroup * len(groups))(*[g.to_c() for g in groups])
+    fib, mat = _materials(fiber, matrix)
+    opts = L.DmnNewtonOpts(tol, max_iter, max_backtrack, armijo, local_max_iter, polish)
+    rc = L.lib().dmn_update_gauss_points_noalloc(arr, len(groups), ctypes.byref(fib),
+                                                  ctypes.byref(mat), precs.pop(),
+                                                  ctypes.byref(opts), _stream())
+    L.check(rc, "dmn_update_gauss_points_noalloc")
+
+
 @dataclass
 class AdjointGroup:
     """Device arrays of one batch of points for dmn_update_adjoint (include/dmn.h)."""

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "dmn_groups.hpp"
@@ -276,10 +277,12 @@ size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int
   return total;
 }
 
-int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
-                            const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
-                            const dmn_newton_opts* opts, void* ws, size_t ws_bytes,
-                            hipStream_t stream) {
+}  // extern "C"
+
+// Argument validation of the Gauss-point update (host data only).
+static int gp_check(const dmn_point_group* groups, int32_t n_groups, const dmn_elastic* fiber,
+                    const dmn_j2* matrix, int prec, const dmn_newton_opts* opts,
+                    GpTune (&tune)[DMN_MAX_DEPTH + 1]) {
   if (!groups || n_groups < 1 || n_groups > 64) return DMN_EINVAL;
   if (prec != DMN_F64) return DMN_EUNSUPPORTED;  // DMN_F32_STATE is switched off
   if (!phase_ok(fiber) || !j2_ok(matrix) || !opts) return DMN_EINVAL;
@@ -302,7 +305,6 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
       return DMN_EUNSUPPORTED;
   }
   // one snapshot of the tuning table per call
-  GpTune tune[DMN_MAX_DEPTH + 1];
   for (int k = 1; k <= DMN_MAX_DEPTH; ++k) tune[k] = gp_tuning(k);
   for (int i = 0; i < n_groups; ++i) {
     const dmn_point_group& g = groups[i];
@@ -311,13 +313,21 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                           : tune[g.net.depth].lanes;
     if ((g.P + 63) / 64 * lanes > (int64_t)0x7fffffff) return DMN_EINVAL;
   }
-  const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
-  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
+  return DMN_OK;
+}
 
-  // work counters (at most one launch per group), then tables, one per group
+// Launches of the Gauss-point update on a validated call, with the workspace
+// ws (at least dmn_update_gauss_points_workspace_size bytes, 256-byte
+// aligned).  Allocates nothing, on the device or the host.
+static int gp_launch(const dmn_point_group* groups, int32_t n_groups, const dmn_elastic* fiber,
+                     const dmn_j2* matrix, int prec, const dmn_newton_opts* opts,
+                     const GpTune (&tune)[DMN_MAX_DEPTH + 1], void* ws, hipStream_t stream) {
+  // work counters (at most one launch per group), then tables, one per group;
+  // the counters are cleared by a fill kernel (graph-capturable, and a
+  // workspace that keeps an earlier call's contents starts from zero)
   int32_t* counters = (int32_t*)((char*)ws + kAlign);
   if (dmn::launch_zero_ints(counters, n_groups, stream)) return DMN_EHIP;
-  std::vector<Table> tabs(n_groups);
+  Table tabs[64];
   size_t off = 2 * kAlign;
   for (int i = 0; i < n_groups; ++i) {
     tabs[i] = table_at(ws, off);
@@ -348,19 +358,27 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
 
   // one launch per depth (deepest first) and kind of normals, up to
   // kMaxGroupsPerLaunch groups each
-  std::vector<int> order;
-  for (int i = 0; i < n_groups; ++i)
-    if (groups[i].P > 0) order.push_back(i);
   auto is_ori = [&](int i) { return groups[i].net.ori_shape != DMN_ORI_NONE; };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+  auto before = [&](int a, int b) {
     if (groups[a].net.depth != groups[b].net.depth)
       return groups[a].net.depth > groups[b].net.depth;
     return (int)is_ori(a) < (int)is_ori(b);
-  });
-  size_t pos = 0;
+  };
+  int order[64];
+  int n_order = 0;
+  for (int i = 0; i < n_groups; ++i) {
+    if (groups[i].P <= 0) continue;
+    int j = n_order++;  // stable insertion
+    while (j > 0 && before(i, order[j - 1])) {
+      order[j] = order[j - 1];
+      --j;
+    }
+    order[j] = i;
+  }
+  int pos = 0;
   int launch = 0;
   const long long cus = dmn::device_cu_count();
-  while (pos < order.size()) {
+  while (pos < n_order) {
     const int K = groups[order[pos]].net.depth;
     const bool ori = is_ori(order[pos]);
     const int lp = ori ? dmn::gp_default_lanes_per_point(K) : tune[K].lanes;
@@ -369,7 +387,7 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
     dmn::GpLaunch args = base;
     args.ng = 0;
     long long blocks = 0;
-    while (pos < order.size() && groups[order[pos]].net.depth == K &&
+    while (pos < n_order && groups[order[pos]].net.depth == K &&
            is_ori(order[pos]) == ori && args.ng < dmn::kMaxGroupsPerLaunch) {
       const int i = order[pos];
       const dmn_point_group& g = groups[i];
@@ -401,6 +419,55 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
     if (dmn::launch_gp_update(K, lp, prec, ori, args, (int)waves, stream)) return DMN_EHIP;
   }
   return DMN_OK;
+}
+
+// Workspace of dmn_update_gauss_points_noalloc: one array per device, held
+// until the process ends.  Its name is a host-side stand-in: host code uses
+// only the device address taken from hipGetSymbolAddress, per device.
+constexpr size_t kNoallocScratchBytes = DMN_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[64];
+
+// Device address of this device's scratch array (taken once per device, with
+// that device current), or null when the runtime call fails.
+static void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+      return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+extern "C" {
+
+int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
+                            const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
+                            const dmn_newton_opts* opts, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  GpTune tune[DMN_MAX_DEPTH + 1];
+  if (const int rc = gp_check(groups, n_groups, fiber, matrix, prec, opts, tune)) return rc;
+  const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
+  return gp_launch(groups, n_groups, fiber, matrix, prec, opts, tune, ws, stream);
+}
+
+int dmn_update_gauss_points_noalloc(const dmn_point_group* groups, int32_t n_groups,
+                                    const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
+                                    const dmn_newton_opts* opts, hipStream_t stream) {
+  GpTune tune[DMN_MAX_DEPTH + 1];
+  if (const int rc = gp_check(groups, n_groups, fiber, matrix, prec, opts, tune)) return rc;
+  const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
+  if (need > kNoallocScratchBytes) return DMN_EWORKSPACE;
+  void* ws = scratch_address();
+  if (ws == nullptr) return DMN_EHIP;
+  return gp_launch(groups, n_groups, fiber, matrix, prec, opts, tune, ws, stream);
 }
 
 static size_t adjoint_group_bytes(const dmn_adjoint_group& g) {

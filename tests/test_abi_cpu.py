@@ -115,6 +115,28 @@ def test_gauss_point_validation_codes():
     assert call(a=nul, n=1) == L.DMN_EINVAL
 
 
+def test_noalloc_gauss_point_validation_and_size_limit():
+    """The no-allocation entry point validates like dmn_update_gauss_points and
+    rejects a call whose workspace would exceed its static array before any
+    device call (17 groups of depth 9 need more than 1 MiB)."""
+    lib = L.lib()
+    fib = L.DmnElastic(72000.0, 0.22)
+    mat = L.DmnJ2(2800.0, 0.35, 50.0, 200.0, 30.0, 60.0)
+    opts = L.DmnNewtonOpts(1e-10, 25, 10, 1e-4)
+    call = lambda arr, n, o=opts: lib.dmn_update_gauss_points_noalloc(
+        arr, n, ctypes.byref(fib), ctypes.byref(mat), L.DMN_F64, ctypes.byref(o), None)
+    big = (L.DmnPointGroup * 17)(*[group(9) for _ in range(17)])
+    assert lib.dmn_update_gauss_points_workspace_size(big, 17, L.DMN_F64) > (1 << 20)
+    assert call(big, 17) == L.DMN_EWORKSPACE
+    fits = (L.DmnPointGroup * 16)(*[group(9) for _ in range(16)])
+    assert lib.dmn_update_gauss_points_workspace_size(fits, 16, L.DMN_F64) <= (1 << 20)
+    assert call(big, 0) == L.DMN_EINVAL
+    assert call(big, 17, L.DmnNewtonOpts(0.0, 25, 10, 1e-4)) == L.DMN_EINVAL
+    assert lib.dmn_update_gauss_points_noalloc(big, 1, ctypes.byref(fib), ctypes.byref(mat),
+                                               L.DMN_F32_STATE, ctypes.byref(opts),
+                                               None) == L.DMN_EUNSUPPORTED
+
+
 def test_orientation_validation_codes():
     lib = L.lib()
     fib = L.DmnElastic(72000.0, 0.22)
