@@ -58,8 +58,8 @@ extern "C" {
 #define DMN_F64 0       /* FP64 storage, FP64 arithmetic */
 #define DMN_F32 1       /* FP32 storage, FP32 arithmetic (linear map, its backward and
                            the training calls, which keep their sums in FP64) */
-#define DMN_F32_STATE 2 /* FP32 storage of per-point arrays, FP64 arithmetic (reserved:
-                           currently rejected with DMN_EUNSUPPORTED) */
+#define DMN_F32_STATE 2 /* FP32 storage of per-point arrays, FP64 arithmetic
+                           (dmn_update_gauss_points) */
 
 /* per-point status written by dmn_update_gauss_points */
 #define DMN_STATUS_OK 0        /* converged */
@@ -256,8 +256,12 @@ size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int
  * a_in, with the J2 return mapping at matrix leaves and linear elasticity at
  * fibre leaves; return the effective stress, the algorithmic tangent, the
  * updated internal variables and the converged jumps.  Groups may have
- * different depths and normal interpolations.  prec: DMN_F64 (DMN_F32_STATE
- * returns DMN_EUNSUPPORTED).  At most 64 groups per call.  Groups with
+ * different depths and normal interpolations.  prec: DMN_F64, or
+ * DMN_F32_STATE for per-point arrays (E, z, a, sigma, tangent) stored in
+ * FP32: the call widens the inputs into FP64 copies in the workspace, runs
+ * the FP64 update on them and rounds the results to nearest into the FP32
+ * outputs (the DMN parameters, orientations and options stay FP64).  At most
+ * 64 groups per call.  Groups with
  * orientation-interpolated normals use the default lane split of their depth
  * whatever the tuning table says.  A non-finite (l1, l2) gives
  * DMN_STATUS_NONFINITE. */
@@ -280,7 +284,8 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
  * current, and the array is held until the process ends.  Returns
  * DMN_EWORKSPACE when the call needs more than DMN_NOALLOC_SCRATCH_BYTES
  * (dmn_update_gauss_points_workspace_size), DMN_EHIP when the address
- * lookup fails, otherwise the codes of dmn_update_gauss_points.  Every call
+ * lookup fails, DMN_EUNSUPPORTED for DMN_F32_STATE (its FP64 copies of the
+ * per-point arrays do not fit), otherwise the codes of dmn_update_gauss_points.  Every call
  * on one device shares that device's array (it keeps the last call's tables;
  * the work counters are cleared by a kernel at the start of each call), so
  * calls that overlap on one device, on different streams or from different

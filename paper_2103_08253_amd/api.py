@@ -246,7 +246,7 @@ class PointGroup:
         """Outputs (and zero initial state if not given) for the points of E [P, 6].
 
         The per-point arrays take E's dtype (float64; float32 maps to
-        DMN_F32_STATE, which the library currently rejects); w and n are float64."""
+        DMN_F32_STATE: FP32 state, FP64 arithmetic); w and n are float64."""
         K = int(round(torch.log2(torch.tensor(float(w.numel()))).item()))
         P = E.shape[0]
         dev, dt = E.device, E.dtype
@@ -317,7 +317,8 @@ def dmn_update_gauss_points(groups: List[PointGroup], fiber: dict, matrix: dict,
     """One load step at every point of every group (outputs written in place).
 
     All groups hold their per-point arrays in one dtype: float64 (DMN_F64);
-    float32 maps to DMN_F32_STATE, which the library currently rejects."""
+    float32 maps to DMN_F32_STATE (FP32 storage of the per-point arrays, FP64
+    arithmetic on FP64 copies in the workspace)."""
     precs = {g.prec for g in groups}
     if len(precs) != 1:
         raise TypeError("all groups of one call must use the same per-point dtype")

@@ -266,14 +266,27 @@ int dmn_homogenize_backward_groups(int32_t depth, int32_t G, const int64_t* offs
   return DMN_OK;
 }
 
+// FP64 copies of one group's per-point arrays for DMN_F32_STATE, in the order
+// E, z_in, z_out, a_in, a_out, sigma, tangent (each 256-byte aligned)
+static size_t staging_bytes(const dmn_point_group& g) {
+  if (g.P <= 0) return 0;
+  const size_t P = (size_t)g.P, M = (size_t)1 << (g.net.depth - 1);
+  const size_t L = ((size_t)1 << g.net.depth) - 1;
+  return 2 * align_up(P * 6 * 8) + 2 * align_up(P * 7 * M * 8) + 2 * align_up(P * 3 * L * 8) +
+         align_up(P * 36 * 8);
+}
+
 size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int32_t n_groups,
                                               int prec) {
-  if (!groups || n_groups < 1 || n_groups > 64 || prec != DMN_F64) return 0;
+  if (!groups || n_groups < 1 || n_groups > 64 || (prec != DMN_F64 && prec != DMN_F32_STATE))
+    return 0;
   size_t total = kAlign + kAlign;  // header, then one work counter per launch
   for (int i = 0; i < n_groups; ++i) {
     if (!depth_ok(groups[i].net.depth)) return 0;
     total += table_bytes(groups[i].net.depth, DMN_F64);  // DMN parameters are FP64
   }
+  if (prec == DMN_F32_STATE)
+    for (int i = 0; i < n_groups; ++i) total += staging_bytes(groups[i]);
   return total;
 }
 
@@ -284,7 +297,7 @@ static int gp_check(const dmn_point_group* groups, int32_t n_groups, const dmn_e
                     const dmn_j2* matrix, int prec, const dmn_newton_opts* opts,
                     GpTune (&tune)[DMN_MAX_DEPTH + 1]) {
   if (!groups || n_groups < 1 || n_groups > 64) return DMN_EINVAL;
-  if (prec != DMN_F64) return DMN_EUNSUPPORTED;  // DMN_F32_STATE is switched off
+  if (prec != DMN_F64 && prec != DMN_F32_STATE) return DMN_EUNSUPPORTED;
   if (!phase_ok(fiber) || !j2_ok(matrix) || !opts) return DMN_EINVAL;
   if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->max_backtrack < 0 ||
       !(opts->armijo >= 0.0 && opts->armijo < 1.0) || opts->local_max_iter < 0 ||
@@ -455,7 +468,54 @@ int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
   if (const int rc = gp_check(groups, n_groups, fiber, matrix, prec, opts, tune)) return rc;
   const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
-  return gp_launch(groups, n_groups, fiber, matrix, prec, opts, tune, ws, stream);
+  if (prec == DMN_F64) return gp_launch(groups, n_groups, fiber, matrix, prec, opts, tune, ws,
+                                        stream);
+  // FP32 state: widen the inputs into FP64 copies in the workspace, run the
+  // FP64 update on them, round the results back into the caller's arrays
+  dmn_point_group staged[64];
+  char* p = (char*)ws + dmn_update_gauss_points_workspace_size(groups, n_groups, DMN_F64);
+  for (int i = 0; i < n_groups; ++i) {
+    const dmn_point_group& g = groups[i];
+    staged[i] = g;
+    if (g.P <= 0) continue;
+    const long long P = g.P, M = 1LL << (g.net.depth - 1), L = (1LL << g.net.depth) - 1;
+    auto take = [&](long long n) {
+      double* q = (double*)p;
+      p += align_up((size_t)n * 8);
+      return q;
+    };
+    double* E = take(P * 6);
+    double* zi = take(P * 7 * M);
+    double* zo = take(P * 7 * M);
+    double* ai = take(P * 3 * L);
+    double* ao = take(P * 3 * L);
+    double* sg = take(P * 6);
+    double* tg = take(P * 36);
+    if (dmn::launch_widen((const float*)g.E, E, P * 6, stream) ||
+        dmn::launch_widen((const float*)g.z_in, zi, P * 7 * M, stream) ||
+        dmn::launch_widen((const float*)g.a_in, ai, P * 3 * L, stream))
+      return DMN_EHIP;
+    staged[i].E = E;
+    staged[i].z_in = zi;
+    staged[i].z_out = zo;
+    staged[i].a_in = ai;
+    staged[i].a_out = ao;
+    staged[i].sigma = sg;
+    staged[i].tangent = tg;
+  }
+  if (const int rc = gp_launch(staged, n_groups, fiber, matrix, DMN_F64, opts, tune, ws, stream))
+    return rc;
+  for (int i = 0; i < n_groups; ++i) {
+    const dmn_point_group& g = groups[i];
+    if (g.P <= 0) continue;
+    const long long P = g.P, M = 1LL << (g.net.depth - 1), L = (1LL << g.net.depth) - 1;
+    if (dmn::launch_narrow((const double*)staged[i].sigma, (float*)g.sigma, P * 6, stream) ||
+        dmn::launch_narrow((const double*)staged[i].tangent, (float*)g.tangent, P * 36, stream) ||
+        dmn::launch_narrow((const double*)staged[i].z_out, (float*)g.z_out, P * 7 * M, stream) ||
+        dmn::launch_narrow((const double*)staged[i].a_out, (float*)g.a_out, P * 3 * L, stream))
+      return DMN_EHIP;
+  }
+  return DMN_OK;
 }
 
 int dmn_update_gauss_points_noalloc(const dmn_point_group* groups, int32_t n_groups,
@@ -463,6 +523,7 @@ int dmn_update_gauss_points_noalloc(const dmn_point_group* groups, int32_t n_gro
                                     const dmn_newton_opts* opts, hipStream_t stream) {
   GpTune tune[DMN_MAX_DEPTH + 1];
   if (const int rc = gp_check(groups, n_groups, fiber, matrix, prec, opts, tune)) return rc;
+  if (prec != DMN_F64) return DMN_EUNSUPPORTED;  // FP32 state needs per-point staging
   const size_t need = dmn_update_gauss_points_workspace_size(groups, n_groups, prec);
   if (need > kNoallocScratchBytes) return DMN_EWORKSPACE;
   void* ws = scratch_address();

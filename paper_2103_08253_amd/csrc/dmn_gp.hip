@@ -318,8 +318,10 @@ int gp_points_per_block(int depth, int lanes_per_point) {
   return 64 / lanes_per_point;
 }
 
-// Only FP64 storage is instantiated: the FP32-storage instantiation is switched
-// off (its first GPU run ended in a device fault whose cause is not yet found).
+// Only FP64 storage is instantiated: the FP32-storage instantiation of this
+// kernel is not compiled (its first GPU run ended in a device fault whose cause
+// was not found); FP32 state runs this kernel on FP64 copies of the per-point
+// arrays instead (see dmn_update_gauss_points).
 // Orientation-interpolated normals are compiled for the default split of
 // each depth only.
 template <int K, int D>

@@ -70,6 +70,9 @@ int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* 
 int launch_gp_update(int depth, int lanes_per_point, int prec, bool ori, const GpLaunch& args,
                      int n_blocks, hipStream_t stream);
 int launch_zero_ints(int32_t* p, int n, hipStream_t stream);
+// element-wise precision conversion of n values (FP32 <-> FP64)
+int launch_widen(const float* src, double* dst, long long n, hipStream_t stream);
+int launch_narrow(const double* src, float* dst, long long n, hipStream_t stream);
 // compute units of the current device (cached per device)
 int device_cu_count();
 int gp_points_per_block(int depth, int lanes_per_point);

@@ -101,7 +101,34 @@ __global__ void zero_ints_kernel(int32_t* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// dst[i] = (To)src[i], grid-stride; rounds to nearest when narrowing
+template <typename From, typename To>
+__global__ __launch_bounds__(256) void convert_kernel(const From* __restrict__ src,
+                                                      To* __restrict__ dst, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = (To)src[i];
+}
+
+template <typename From, typename To>
+int launch_convert_t(const void* src, void* dst, long long n, hipStream_t stream) {
+  if (n <= 0) return 0;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL((convert_kernel<From, To>), dim3((unsigned)blocks), dim3(256), 0, stream,
+                     (const From*)src, (To*)dst, n);
+  return (int)hipGetLastError();
+}
+
 }  // namespace
+
+int launch_widen(const float* src, double* dst, long long n, hipStream_t stream) {
+  return launch_convert_t<float, double>(src, dst, n, stream);
+}
+
+int launch_narrow(const double* src, float* dst, long long n, hipStream_t stream) {
+  return launch_convert_t<double, float>(src, dst, n, stream);
+}
 
 int launch_zero_ints(int32_t* p, int n, hipStream_t stream) {
   hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n);

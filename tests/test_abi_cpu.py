@@ -85,7 +85,10 @@ def test_gauss_point_validation_codes():
     need = lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F64)
     assert need > 0
     assert lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F32) == 0
-    assert lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F32_STATE) == 0
+    # FP32 state: the FP64 workspace plus FP64 copies of every per-point array
+    need32 = lib.dmn_update_gauss_points_workspace_size(arr, 2, L.DMN_F32_STATE)
+    per_point = lambda K: 8 * (6 + 2 * 7 * 2 ** (K - 1) + 2 * 3 * (2 ** K - 1) + 6 + 36)
+    assert need32 >= need + 4 * (per_point(2) + per_point(8))
 
     def call(a=arr, n=2, f=fib, m=mat, o=opts, prec=L.DMN_F64, nb=need):
         return lib.dmn_update_gauss_points(a, n, ctypes.byref(f) if f else None,
@@ -96,7 +99,7 @@ def test_gauss_point_validation_codes():
     assert call(n=65) == L.DMN_EINVAL
     assert call(prec=L.DMN_F32) == L.DMN_EUNSUPPORTED
     assert call(prec=7) == L.DMN_EUNSUPPORTED
-    assert call(prec=L.DMN_F32_STATE) == L.DMN_EUNSUPPORTED
+    assert call(prec=L.DMN_F32_STATE) == L.DMN_EWORKSPACE  # needs the staging space
     assert call(f=None) == L.DMN_EINVAL
     assert call(m=L.DmnJ2(2800.0, 0.5, 50.0, 200.0, 30.0, 60.0)) == L.DMN_EINVAL
     assert call(o=L.DmnNewtonOpts(0.0, 25, 10, 1e-4)) == L.DMN_EINVAL

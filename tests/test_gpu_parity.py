@@ -237,9 +237,6 @@ def gpu_groups_path(nets, E_path, idx, dtype):
     return outs
 
 
-@pytest.mark.skip(reason="DMN_F32_STATE is switched off: its first GPU run ended in a device "
-                  "fault with no cause found yet (a CPU emulation of the kernel under "
-                  "AddressSanitizer shows no out-of-bounds access on this case)")
 def test_gp_f32_state_mixed_groups():
     """FP32-stored state (DMN_F32_STATE) over 16 mixed-depth groups, 6 steps.
 
@@ -291,9 +288,6 @@ def test_gp_f32_state_mixed_groups():
     assert flips <= 8
 
 
-@pytest.mark.skip(reason="DMN_F32_STATE is switched off: its first GPU run ended in a device "
-                  "fault with no cause found yet (a CPU emulation of the kernel under "
-                  "AddressSanitizer shows no out-of-bounds access on this case)")
 def test_gp_f32_state_depth8_production_size_sampled():
     """FP32 state at the production size (depth 8, 65,536 points, 20 steps);
     the FP64 oracle follows 4 sampled points on the FP32-rounded strains."""
