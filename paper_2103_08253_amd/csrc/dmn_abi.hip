@@ -12,6 +12,8 @@
 namespace {
 
 constexpr size_t kAlign = 256;
+// work counters of the Gauss-point launches: up to two per group
+constexpr size_t kCounterBytes = 2 * 64 * sizeof(int32_t);
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 inline size_t elt_size(int prec) { return prec == DMN_F32 ? sizeof(float) : sizeof(double); }
@@ -280,7 +282,7 @@ size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int
                                               int prec) {
   if (!groups || n_groups < 1 || n_groups > 64 || (prec != DMN_F64 && prec != DMN_F32_STATE))
     return 0;
-  size_t total = kAlign + kAlign;  // header, then one work counter per launch
+  size_t total = kAlign + kCounterBytes;  // header, then the launches' work counters
   for (int i = 0; i < n_groups; ++i) {
     if (!depth_ok(groups[i].net.depth)) return 0;
     total += table_bytes(groups[i].net.depth, DMN_F64);  // DMN parameters are FP64
@@ -335,13 +337,14 @@ static int gp_check(const dmn_point_group* groups, int32_t n_groups, const dmn_e
 static int gp_launch(const dmn_point_group* groups, int32_t n_groups, const dmn_elastic* fiber,
                      const dmn_j2* matrix, int prec, const dmn_newton_opts* opts,
                      const GpTune (&tune)[DMN_MAX_DEPTH + 1], void* ws, hipStream_t stream) {
-  // work counters (at most one launch per group), then tables, one per group;
-  // the counters are cleared by a fill kernel (graph-capturable, and a
-  // workspace that keeps an earlier call's contents starts from zero)
+  // work counters (at most one launch, with up to two counters, per group),
+  // then tables, one per group; the counters are cleared by a fill kernel
+  // (graph-capturable, and a workspace that keeps an earlier call's contents
+  // starts from zero)
   int32_t* counters = (int32_t*)((char*)ws + kAlign);
-  if (dmn::launch_zero_ints(counters, n_groups, stream)) return DMN_EHIP;
+  if (dmn::launch_zero_ints(counters, 2 * n_groups, stream)) return DMN_EHIP;
   Table tabs[64];
-  size_t off = 2 * kAlign;
+  size_t off = kAlign + kCounterBytes;
   for (int i = 0; i < n_groups; ++i) {
     tabs[i] = table_at(ws, off);
     off += table_bytes(groups[i].net.depth, DMN_F64);
@@ -369,18 +372,43 @@ static int gp_launch(const dmn_point_group* groups, int32_t n_groups, const dmn_
   base.mat.b = matrix->b;
   base.mat.max_it = opts->local_max_iter > 0 ? opts->local_max_iter : dmn::kLocalMaxIt;
 
-  // one launch per depth (deepest first) and kind of normals, up to
-  // kMaxGroupsPerLaunch groups each
   auto is_ori = [&](int i) { return groups[i].net.ori_shape != DMN_ORI_NONE; };
+  auto lanes_of = [&](int i) {
+    return is_ori(i) ? dmn::gp_default_lanes_per_point(groups[i].net.depth)
+                     : tune[groups[i].net.depth].lanes;
+  };
+  auto fill = [&](dmn::GroupArgs& a, int i, int block0) {
+    const dmn_point_group& g = groups[i];
+    a.E = g.E;
+    a.z_in = g.z_in;
+    a.z_out = g.z_out;
+    a.a_in = g.a_in;
+    a.a_out = g.a_out;
+    a.sigma = g.sigma;
+    a.tangent = g.tangent;
+    a.iters = g.iters;
+    a.status = g.status;
+    a.tab = (const double*)tabs[i].rows;
+    a.flag = tabs[i].flag;
+    a.ori_p = (const double*)g.net.ori_p;
+    a.ori_q = (const double*)g.net.ori_q;
+    a.lam = (const double*)g.lam;
+    a.ori_m = ori_count(g.net.ori_shape);
+    a.depth = g.net.depth;
+    a.P = g.P;
+    a.block0 = block0;
+    a.lanes = lanes_of(i);
+  };
+  // groups with points, deepest first, fixed normals before interpolated ones
   auto before = [&](int a, int b) {
-    if (groups[a].net.depth != groups[b].net.depth)
-      return groups[a].net.depth > groups[b].net.depth;
-    return (int)is_ori(a) < (int)is_ori(b);
+    if ((int)is_ori(a) != (int)is_ori(b)) return (int)is_ori(a) < (int)is_ori(b);
+    return groups[a].net.depth > groups[b].net.depth;
   };
   int order[64];
-  int n_order = 0;
+  int n_order = 0, n_fixed = 0;
   for (int i = 0; i < n_groups; ++i) {
     if (groups[i].P <= 0) continue;
+    n_fixed += is_ori(i) ? 0 : 1;
     int j = n_order++;  // stable insertion
     while (j > 0 && before(i, order[j - 1])) {
       order[j] = order[j - 1];
@@ -388,45 +416,72 @@ static int gp_launch(const dmn_point_group* groups, int32_t n_groups, const dmn_
     }
     order[j] = i;
   }
+  // order[0, n_fixed) are the fixed-normal groups, deepest first
+  const bool fixed_depth9 = n_fixed > 0 && groups[order[0]].net.depth == dmn::kSplitDepth;
+  const bool fixed_depths_differ =
+      n_fixed > 0 && groups[order[0]].net.depth != groups[order[n_fixed - 1]].net.depth;
+
   int pos = 0;
-  int launch = 0;
+  int counter = 0;
   const long long cus = dmn::device_cu_count();
+  // fixed-normal groups of several depths, or of depth 9: mixed launches of
+  // up to kMaxGroupsPerLaunch groups, depth-9 groups first
+  if (n_fixed > 0 && (fixed_depth9 || fixed_depths_differ)) {
+    while (pos < n_fixed && groups[order[pos]].net.depth >= dmn::kMixedLaneDepth) {
+      dmn::GpLaunch args = base;
+      long long items_split = 0, items = 0;
+      int waves_per_cu = 1;
+      while (pos < n_fixed && args.ng < dmn::kMaxGroupsPerLaunch &&
+             groups[order[pos]].net.depth == dmn::kSplitDepth) {
+        const int i = order[pos++];
+        fill(args.g[args.ng++], i, (int)items_split);
+        items_split += groups[i].P;
+        waves_per_cu = std::max(waves_per_cu, tune[groups[i].net.depth].waves_per_cu);
+      }
+      args.ng_split = args.ng;
+      // depths 2-8 run with lane subtrees of depth dmn::kMixedLaneDepth in a
+      // mixed launch whatever the tuning table says (depth 1 runs on its own)
+      while (pos < n_fixed && args.ng < dmn::kMaxGroupsPerLaunch &&
+             groups[order[pos]].net.depth != dmn::kSplitDepth &&
+             groups[order[pos]].net.depth >= dmn::kMixedLaneDepth) {
+        const int i = order[pos++];
+        const int K = groups[i].net.depth;
+        const int lanes = 1 << (K - dmn::kMixedLaneDepth);
+        const int ppb = dmn::gp_points_per_block(K, lanes);
+        fill(args.g[args.ng], i, (int)items);
+        args.g[args.ng++].lanes = lanes;
+        items += (groups[i].P + ppb - 1) / ppb;
+        waves_per_cu = std::max(waves_per_cu, tune[K].waves_per_cu);
+      }
+      if (args.ng == 0) break;  // only depth-1 groups left: the loop below
+      if (items > 0x7fffffff || items_split > 0x7fffffff) return DMN_EINVAL;
+      args.counter = counters + counter++;
+      args.counter_split = counters + counter++;
+      args.total = (int)items;
+      args.total_split = (int)items_split;
+      const long long persistent = std::max(1LL, cus * waves_per_cu / 2);
+      const long long need = std::max(std::max(items_split, (items + 1) / 2), 1LL);
+      if (dmn::launch_gp_mixed(args, (int)std::min(persistent, need), stream)) return DMN_EHIP;
+    }
+  }
+  // the rest: one launch per depth and kind of normals, up to
+  // kMaxGroupsPerLaunch groups each
   while (pos < n_order) {
     const int K = groups[order[pos]].net.depth;
     const bool ori = is_ori(order[pos]);
-    const int lp = ori ? dmn::gp_default_lanes_per_point(K) : tune[K].lanes;
+    const int lp = lanes_of(order[pos]);
     const long long persistent = cus * tune[K].waves_per_cu;
     const int ppb = dmn::gp_points_per_block(K, lp);
     dmn::GpLaunch args = base;
-    args.ng = 0;
     long long blocks = 0;
     while (pos < n_order && groups[order[pos]].net.depth == K &&
            is_ori(order[pos]) == ori && args.ng < dmn::kMaxGroupsPerLaunch) {
-      const int i = order[pos];
-      const dmn_point_group& g = groups[i];
-      dmn::GroupArgs& a = args.g[args.ng++];
-      a.E = g.E;
-      a.z_in = g.z_in;
-      a.z_out = g.z_out;
-      a.a_in = g.a_in;
-      a.a_out = g.a_out;
-      a.sigma = g.sigma;
-      a.tangent = g.tangent;
-      a.iters = g.iters;
-      a.status = g.status;
-      a.tab = (const double*)tabs[i].rows;
-      a.flag = tabs[i].flag;
-      a.ori_p = (const double*)g.net.ori_p;
-      a.ori_q = (const double*)g.net.ori_q;
-      a.lam = (const double*)g.lam;
-      a.ori_m = ori_count(g.net.ori_shape);
-      a.P = g.P;
-      a.block0 = (int)blocks;
-      blocks += (g.P + ppb - 1) / ppb;
-      ++pos;
+      const int i = order[pos++];
+      fill(args.g[args.ng++], i, (int)blocks);
+      blocks += (groups[i].P + ppb - 1) / ppb;
     }
     if (blocks > 0x7fffffff) return DMN_EINVAL;
-    args.counter = counters + launch++;
+    args.counter = counters + counter++;
     args.total = (int)blocks;
     const long long waves = blocks < persistent ? blocks : persistent;
     if (dmn::launch_gp_update(K, lp, prec, ori, args, (int)waves, stream)) return DMN_EHIP;

@@ -110,7 +110,7 @@ __device__ __forceinline__ void sum_node(const Ctx<K, D>& cx, const LaneState<K,
     double SmR[6], SsR[6];
     sum_node<K, D, 2 * H>(cx, st, mu, ws, live, acc, Sm, Ss);
     sum_node<K, D, 2 * H + 1>(cx, st, mu, ws, live, acc, SmR, SsR);
-    const LamRow row = load_row(cx, lane_pos<K, D, H>(cx.t));
+    const LamRow row = load_row(cx, lane_pos<D, H>(cx.g, cx.t));
     double a[3], lam[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
   cx.slot = lane / C::LP;
   cx.t = lane % C::LP;
   cx.base = cx.slot * C::LP;
-  cx.tab = stage_table<K>(tlds, args.tab + table_soa_offset(K));
+  cx.tab = stage_table<K>(tlds, args.tab + table_soa_offset(K), threadIdx.x, 64);
   cx.nrm = cx.tab + 2 * C::L;
   cx.fib = args.fib;
   cx.mat = args.mat;
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
 #pragma unroll 1
     for (int m = 1; m <= C::UPLEV; ++m) {
       if (upper_active(cx.t, m)) {
-        const int pos = upper_pos<K, D>(m, cx.t);
+        const int pos = upper_pos<D>(cx.g, m, cx.t);
         const int u = cx.slot * C::NUPS + (pos - C::UP0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
         SsR[k] = __shfl_down(Ss[k], (unsigned)o, C::LP);
       }
       if (upper_active(cx.t, m)) {
-        const int pos = upper_pos<K, D>(m, cx.t);
+        const int pos = upper_pos<D>(cx.g, m, cx.t);
         const int u = cx.slot * C::NUPS + (pos - C::UP0);
         const LamRow row = load_row(cx, pos);
         double a[3], lam[3], g4[4];
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const AdjArgs args) {
 #pragma unroll 1
   for (int m = 1; m <= C::UPLEV; ++m) {
     if (upper_active(cx.t, m)) {
-      const int pos = upper_pos<K, D>(m, cx.t);
+      const int pos = upper_pos<D>(cx.g, m, cx.t);
       const int u = cx.slot * C::NUPS + (pos - C::UP0);
 #pragma unroll
       for (int c = 0; c < 4; ++c) P[((size_t)pos * 4 + c) * nslots + pslot] = accU[c][u];
@@ -365,6 +365,14 @@ __global__ __launch_bounds__(256) void adjoint_finish_kernel(const double* __res
 
 constexpr int kMaxAdjWaves = 2048;
 
+// lanes per point of the adjoint kernels: one wave holds a point's tree
+// (lane subtrees of depth max(1, K - 6))
+int adjoint_lanes_per_point(int depth) {
+  int d = depth - 6;
+  if (d < 1) d = 1;
+  return 1 << (depth - d);
+}
+
 template <int K, int D>
 int launch_adj(const AdjArgs& a, long long waves, hipStream_t s) {
   hipLaunchKernelGGL((adjoint_kernel<K, D>), dim3((unsigned)waves), dim3(64), 0, s, a);
@@ -374,7 +382,7 @@ int launch_adj(const AdjArgs& a, long long waves, hipStream_t s) {
 }  // namespace
 
 long long adjoint_partial_slots(int depth, long long P) {
-  const int lp = gp_default_lanes_per_point(depth);
+  const int lp = adjoint_lanes_per_point(depth);
   const int ppw = 64 / lp;
   long long waves = (P + ppw - 1) / ppw;
   if (waves > kMaxAdjWaves) waves = kMaxAdjWaves;
@@ -397,7 +405,7 @@ int launch_adjoint(int depth, const AdjointLaunch& L, hipStream_t stream) {
   a.P = L.P;
   a.fib = L.fib;
   a.mat = L.mat;
-  const int lp = gp_default_lanes_per_point(depth);
+  const int lp = adjoint_lanes_per_point(depth);
   const long long slots = adjoint_partial_slots(depth, L.P);
   const long long waves = slots / (64 / lp);
   const int D = depth - tree::ilog2(lp);

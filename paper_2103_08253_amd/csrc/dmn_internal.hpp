@@ -39,21 +39,26 @@ struct GroupArgs {  // tab points at the table start (AoS rows first)
   const double* ori_q;
   const double* lam;    // [P][2] per-point (l1, l2)
   int ori_m;            // number of shape functions (3, 4, 6), 0 without interpolation
-  int ori_pad;
+  int depth;            // DMN depth K
   const double* tab;   // [L][kTabStride]
   const int32_t* flag; // nonzero: invalid DMN parameters
   long long P;
-  int block0;          // first batch index of this group in the launch
-  int pad;
+  int block0;          // first work item of this group in its counter's numbering
+  int lanes;           // lanes per point of the group's variant
 };
 
-constexpr int kMaxGroupsPerLaunch = 12;
+constexpr int kMaxGroupsPerLaunch = 16;
 
 struct GpLaunch {
   GroupArgs g[kMaxGroupsPerLaunch];
   int* counter;  // zeroed before the launch; batches are taken with atomicAdd
   int total;     // batches in this launch
   int ng;
+  // mixed-depth launches: groups [0, ng_split) are depth-9 groups whose points
+  // are split over two waves, taken one point at a time from counter_split
+  int* counter_split;
+  int total_split;
+  int ng_split;
   int max_iter;
   int max_bt;
   int polish;  // full Newton steps after the stop test is met (not counted, no backtracking)
@@ -62,6 +67,7 @@ struct GpLaunch {
   IsoElastic fib;
   J2Law mat;
 };
+static_assert(sizeof(GpLaunch) <= 4096, "kernel arguments are passed by value");
 
 // Host launchers (return hipError_t as int).
 // allow_dead: accept subtrees without weight (linear map and its VJP), see dmn_prep.hip
@@ -69,6 +75,14 @@ int launch_prep_tables(const void* w, const void* n, int depth, int prec, void* 
                        int32_t* err, hipStream_t stream, bool allow_dead = false);
 int launch_gp_update(int depth, int lanes_per_point, int prec, bool ori, const GpLaunch& args,
                      int n_blocks, hipStream_t stream);
+// one launch over groups of several depths (fixed normals, FP64): n_workgroups
+// persistent workgroups of two waves
+int launch_gp_mixed(const GpLaunch& args, int n_workgroups, hipStream_t stream);
+// depth whose points are split over two waves, and its lanes per point
+constexpr int kSplitDepth = 9;
+constexpr int kSplitLanes = 128;
+// lane-subtree depth of every depth in a mixed launch
+constexpr int kMixedLaneDepth = 2;
 int launch_zero_ints(int32_t* p, int n, hipStream_t stream);
 // element-wise precision conversion of n values (FP32 <-> FP64)
 int launch_widen(const float* src, double* dst, long long n, hipStream_t stream);

@@ -23,13 +23,18 @@ def clean_table():
 
 def test_tuning_table_validation():
     lib = L.lib()
-    # every depth has its default variant listed first or among the variants
-    for K in range(1, 11):
+    # every depth that runs has its default variant among the variants
+    for K in range(1, 9):
         lanes, waves = A.get_tuning(K)
         assert lanes in A.lane_variants(K)
         assert waves == 8
         assert all(64 % v == 0 and v <= 2 ** K for v in A.lane_variants(K))
     assert A.lane_variants(8) == [64]
+    # depth 9: one variant, each point split over the 128 lanes of two waves
+    assert A.lane_variants(9) == [128] and A.get_tuning(9) == (128, 8)
+    assert lib.dmn_gp_set_tuning(9, ctypes.byref(L.DmnGpTuning(64, 4))) == L.DMN_EUNSUPPORTED
+    # depth 10 is not compiled for the update (the call returns DMN_EUNSUPPORTED)
+    assert A.lane_variants(10) == []
     assert A.lane_variants(5) == [16, 8]
     assert lib.dmn_gp_lane_variants(0, None, 0) == 0
     assert lib.dmn_gp_lane_variants(11, None, 0) == 0

@@ -213,6 +213,35 @@ def test_gp_mixed_depth_groups_one_call():
         compare_paths(net, Em, range(min(len(sel), 2)), gpu)
 
 
+def test_gp_mixed_launch_all_depths():
+    """One call over groups of depths 1-4, 7 and 9 (ragged point counts): depths
+    2-9 share one launch (depth 9 split over two waves, the others with the
+    depth of each batch at run time), depth 1 runs on its own; every point of
+    every group against the oracle along 3 steps."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    say("case: gp mixed launch, depths 1, 2, 3, 4, 7, 9")
+    d = dev()
+    rs = S.streams(140)
+    depths, counts = (9, 1, 2, 3, 4, 7, 9), (3, 70, 129, 37, 21, 11, 2)
+    nets = [S.random_dmn(rs["dmn"], K, 0.25) for K in depths]
+    paths = [S.ramp_with_noise(rs, P, 3, 0.02, 1e-3) for P in counts]
+    groups = [PointGroup.allocate(torch.tensor(n.w, device=d), torch.tensor(n.normals, device=d),
+                                  torch.tensor(E[0], device=d)) for n, E in zip(nets, paths)]
+    outs = [[] for _ in groups]
+    for step in range(3):
+        for g, E in zip(groups, paths):
+            g.E.copy_(torch.tensor(E[step], device=d))
+        dmn_update_gauss_points(groups, S.FIBER, S.MATRIX)
+        torch.cuda.synchronize()
+        for m, g in enumerate(groups):
+            outs[m].append(dict(sigma=g.sigma.cpu().numpy(), C=g.tangent.cpu().numpy(),
+                                z=g.z_out.cpu().numpy(), a=g.a_out.cpu().numpy(),
+                                iters=g.iters.cpu().numpy(), status=g.status.cpu().numpy()))
+            g.advance()
+    for m, (net, E) in enumerate(zip(nets, paths)):
+        compare_paths(net, E, range(E.shape[1]), outs[m])
+
+
 F32_STATE_RTOL = 1e-4
 
 
