@@ -1,0 +1,49 @@
+"""Parent side of the CPU-build tests: writes a case, runs tests/simt/run_gp.py
+in a child process under the ASan runtime, and reads the outputs back."""
+import os
+import subprocess
+import sys
+import tempfile
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+import build as B  # noqa: E402
+
+
+def material_arrays(fiber, matrix):
+    return (np.array([fiber["E"], fiber["nu"]]),
+            np.array([matrix["E"], matrix["nu"], matrix["sigma0"], matrix["k_inf"],
+                      matrix["dsigma"], matrix["b"]]))
+
+
+def run_gp(groups, fiber, matrix, opts=(1e-10, 25, 10, 1e-4, 0, 0), prec=0, tuning=(),
+           noalloc=False, defines=(B.VARIANTS,), timeout=900):
+    """groups: dicts with depth, w, E [T, P, 6] and either n or ori/p/q/lam.
+    Returns (outputs per group and step, child's stderr)."""
+    lib = B.build(defines)
+    fib, mat = material_arrays(fiber, matrix)
+    case = dict(n_groups=len(groups), opts=np.array(opts, dtype=np.float64), prec=prec,
+                tuning=np.array(tuning, dtype=np.int64).reshape(-1, 3), noalloc=int(noalloc),
+                fiber=fib, matrix=mat)
+    for g, grp in enumerate(groups):
+        for k, v in grp.items():
+            case[f"g{g}_{k}"] = np.asarray(v)
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
+        np.savez(fin, **case)
+        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(),
+                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
+                   OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.join(HERE, "run_gp.py"), lib, fin, fout],
+                           env=env, capture_output=True, text=True, timeout=timeout)
+        if r.returncode != 0:
+            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
+                                 f"{r.stderr[-6000:]}")
+        d = np.load(fout)
+        T = np.asarray(groups[0]["E"]).shape[0]
+        out = [[{k: d[f"g{g}_s{s}_{k}"] for k in ("sigma", "C", "z", "a", "iters", "status")}
+                for s in range(T)] for g in range(len(groups))]
+    return out, r.stderr

@@ -1,0 +1,154 @@
+"""The Gauss-point update of the library's own HIP sources, built for the CPU
+(tests/simt: lanes as host threads, cross-lane operations and barriers
+emulated) under AddressSanitizer and UndefinedBehaviorSanitizer, against the
+FP64 oracle.
+
+Every global, LDS and array index the kernels take is checked on the host
+here: an out-of-bounds access, a shift or overflow with undefined behaviour,
+or a collective that not every lane reaches stops the child process with a
+report.  The cases cover every compiled lane split of depths 1-8, including
+the (8, 3) split that the device build leaves out, orientation-interpolated
+normals, one call over groups of depths 1-9 (the mixed-depth launch, with
+depth-9 points split over two waves), FP32 state, the entry point without a
+workspace, and the failure statuses.  Results must match the oracle to the
+GPU parity bar (FP64 relative 1e-10, equal iterations and status)."""
+import os
+import shutil
+import sys
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "simt"))
+
+import synthetic as S  # noqa: E402
+from oracle.gp import DmnModel, NewtonOptions, run_path  # noqa: E402
+from oracle.orientation import interpolated_normals  # noqa: E402
+
+pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+
+RTOL = 1e-10
+MARGIN = 1e-9
+
+
+def harness():
+    import harness as H
+    return H
+
+
+def rel(got, ref):
+    scale = np.abs(ref).max()
+    return np.abs(got - ref).max() / (scale if scale > 0 else 1.0)
+
+
+def check_group(out, model_of, E, points, f32=False):
+    """Compare the CPU-build outputs of one group with the oracle's path."""
+    worst, checked = 0.0, 0
+    for p in points:
+        ref = run_path(model_of(p), E[:, p, :], NewtonOptions())
+        if min(r["margin"] for r in ref) < MARGIN:
+            continue
+        checked += 1
+        for s, r in enumerate(ref):
+            g = out[s]
+            if f32:
+                worst = max(worst, rel(g["sigma"][p].astype(np.float64), r["sigma"]))
+                continue
+            assert g["status"][p] == r["status"] and g["iters"][p] == r["iters"], (p, s)
+            es, ec = rel(g["sigma"][p], r["sigma"]), rel(g["C"][p], r["C"])
+            ea = rel(g["a"][p].ravel(), r["a"]) if np.abs(r["a"]).max() > 0 else 0.0
+            ez = rel(g["z"][p].ravel(), r["z"].ravel()) if np.abs(r["z"]).max() > 0 else 0.0
+            worst = max(worst, es, ec, ea, ez)
+    assert checked > 0
+    return worst
+
+
+def fixed_group(K, P, T, seed):
+    rs = S.streams(seed)
+    net = S.random_dmn(rs["dmn"], K, 0.25)
+    E = S.ramp_with_noise(rs, P, T, 0.02, 1e-3)
+    model = DmnModel(K, net.w, net.normals, S.FIBER, S.MATRIX)
+    return dict(depth=K, w=net.w, n=net.normals, E=E), (lambda p: model)
+
+
+# every lane split compiled into the CPU build: (depth, lanes per point)
+VARIANTS = [(1, 1), (2, 2), (2, 1), (3, 4), (3, 2), (4, 8), (4, 4), (5, 16), (5, 8),
+            (6, 32), (6, 16), (7, 64), (7, 32), (8, 64), (8, 32)]
+
+
+@pytest.mark.parametrize("K,lanes", VARIANTS)
+def test_simt_gp_every_lane_split(K, lanes):
+    ppw = 64 // lanes
+    P = min(ppw + 3, 40) if ppw > 1 else 2  # a ragged last batch where a wave holds several
+    grp, model = fixed_group(K, P, 2, 500 + K)
+    out, _ = harness().run_gp([grp], S.FIBER, S.MATRIX, tuning=[(K, lanes, 1)])
+    worst = check_group(out[0], model, grp["E"], range(P))
+    assert worst <= RTOL, worst
+
+
+def test_simt_gp_mixed_depths_one_call():
+    """Groups of depths 9, 8, 6, 3, 2 in one call run in the mixed-depth launch
+    (depth 9 split over two waves); depth 1 runs in its own launch."""
+    depths = [9, 8, 6, 3, 2, 1]
+    built = [fixed_group(K, 3, 2, 600 + K) for K in depths]
+    out, _ = harness().run_gp([g for g, _ in built], S.FIBER, S.MATRIX)
+    for i, (g, model) in enumerate(built):
+        worst = check_group(out[i], model, g["E"], range(3))
+        assert worst <= RTOL, (depths[i], worst)
+
+
+@pytest.mark.parametrize("K,kind", [(1, "quadratic"), (3, "trilinear"), (6, "linear")])
+def test_simt_gp_orientation(K, kind):
+    rs = S.streams(300 + K)
+    net = S.interpolated_dmn(rs["dmn"], K, 0.25, kind)
+    P = 9
+    lam = S.triangle_points(rs["assignment"], P)
+    E = S.ramp_with_noise(rs, P, 2, 0.02, 1e-3)
+    code = {"linear": 1, "trilinear": 2, "quadratic": 3}[kind]
+    out, _ = harness().run_gp([dict(depth=K, w=net.w, ori=code, p=net.p, q=net.q, lam=lam,
+                                    E=E)], S.FIBER, S.MATRIX)
+
+    def model(p):
+        nrm = interpolated_normals(net.p, net.q, lam[p, 0], lam[p, 1], net.kind)
+        return DmnModel(K, net.w, nrm, S.FIBER, S.MATRIX)
+    worst = check_group(out[0], model, E, range(P))
+    assert worst <= RTOL, worst
+
+
+def test_simt_gp_fp32_state_and_noalloc():
+    """FP32 state (FP64 arithmetic on widened copies) within 1e-4 of the
+    oracle; the entry point without a workspace gives the workspace call's
+    results bit for bit."""
+    H = harness()
+    built = [fixed_group(K, P, 2, 700 + K) for K, P in ((6, 5), (3, 7))]
+    groups = [g for g, _ in built]
+    g32 = [dict(g, E=g["E"].astype(np.float32)) for g in groups]
+    out32, _ = H.run_gp(g32, S.FIBER, S.MATRIX, prec=2)
+    for i, (g, model) in enumerate(built):
+        assert check_group(out32[i], model, g["E"].astype(np.float32).astype(np.float64),
+                           range(g["E"].shape[1]), f32=True) <= 1e-4
+    ref, _ = H.run_gp(groups, S.FIBER, S.MATRIX)
+    na, _ = H.run_gp(groups, S.FIBER, S.MATRIX, noalloc=True)
+    for i in range(len(groups)):
+        for s in range(2):
+            for k in ref[i][s]:
+                assert np.array_equal(ref[i][s][k], na[i][s][k]), (i, s, k)
+
+
+def test_simt_gp_failure_statuses():
+    """A non-finite strain fails its point alone (status 2, state passed
+    through); invalid DMN parameters (a negative weight) fail every point of
+    their group (status 5) in a call shared with a valid group."""
+    H = harness()
+    g1, _ = fixed_group(4, 6, 1, 801)
+    g1["E"] = g1["E"].copy()
+    g1["E"][0, 2, 3] = np.nan
+    g2, _ = fixed_group(9, 2, 1, 802)
+    g2["w"] = g2["w"].copy()
+    g2["w"][5] = -1.0
+    out, _ = H.run_gp([g1, g2], S.FIBER, S.MATRIX)
+    st1, st2 = out[0][0]["status"], out[1][0]["status"]
+    assert st1[2] == 2 and all(st1[p] == 0 for p in range(6) if p != 2)
+    assert np.all(out[0][0]["z"][2] == 0) and np.all(out[0][0]["a"][2] == 0)
+    assert np.all(st2 == 5)
