@@ -4,7 +4,9 @@ For every DMN depth of a workload it times each compiled lane variant
 (``dmn_gp_lane_variants``) at a few persistent-wave counts on the workload
 itself, keeps the fastest with ``dmn_gp_set_tuning`` and records the choice
 in a JSON cache, keyed by device, library version, depth and point count
-(rounded to a power of two), so later processes set it without timing.
+(rounded to a power of two), so later processes set it without timing.  A
+workload whose fixed-normal groups differ in depth runs in one mixed-depth
+launch; there the wave count of that launch is tuned on the whole workload.
 
 The update is functional (inputs are never written), so timing repeated calls
 on the caller's groups leaves their inputs intact; their outputs end up as
@@ -103,16 +105,38 @@ def _gpu_timer(groups, fiber, matrix, reps: int, newton: dict) -> float:
     return times[len(times) // 2]
 
 
+def mixed_cache_key(tag: str, depths: Sequence[int], n_points: int) -> str:
+    bucket = 2 ** int(round(math.log2(max(n_points, 1))))
+    return f"{tag}|mixed|K{','.join(str(k) for k in sorted(depths))}|P{bucket}"
+
+
+# the library runs fixed-normal groups of several depths (or of depth 9) in one
+# mixed-depth launch for depths >= MIXED_MIN_DEPTH; only the persistent wave
+# count of that launch is a choice (lane splits are fixed there)
+MIXED_MIN_DEPTH = 2
+SPLIT_DEPTH = 9
+
+
+def _depth_of(g) -> int:
+    return int(round(math.log2(g.w.numel())))
+
+
 def tune_gauss_points(groups: Sequence, fiber: dict, matrix: dict,
                       cache_path: Optional[str] = None, reps: int = 3,
                       waves: Sequence[int] = WAVES_PER_CU, retune: bool = False,
                       timer: Optional[Callable] = None, tag: Optional[str] = None,
                       **newton) -> Dict[int, dict]:
-    """Tune every depth present in ``groups`` and set the winners.
+    """Tune the launches of a workload like ``groups`` and set the winners.
 
-    Returns {depth: {"lanes_per_point", "waves_per_cu", "ms", "cached"}}.
-    ``timer(groups, fiber, matrix, reps, newton) -> ms`` and ``tag`` replace
-    the GPU timing and device tag (for tests of the cache logic).
+    Groups of one depth: every compiled lane variant at each wave count, per
+    depth.  Fixed-normal groups of several depths (or with depth 9), which the
+    library runs in one mixed-depth launch: the wave count of that launch,
+    timed on all those groups together (depths 2-9), and depth 1 on its own.
+
+    Returns {depth: {"lanes_per_point", "waves_per_cu", "ms", "cached"}, with
+    "launch": "mixed" for the depths of a mixed launch}.  ``timer(groups,
+    fiber, matrix, reps, newton) -> ms`` and ``tag`` replace the GPU timing and
+    device tag (for tests of the cache logic).
     """
     timer = timer or _gpu_timer
     path = cache_path or default_cache_path()
@@ -121,20 +145,46 @@ def tune_gauss_points(groups: Sequence, fiber: dict, matrix: dict,
     for g in groups:
         if getattr(g, "ori", None) is not None:
             continue  # orientation-interpolated groups always use the default split
-        by_depth.setdefault(int(round(math.log2(g.w.numel()))), []).append(g)
+        if g.E.shape[0] > 0:
+            by_depth.setdefault(_depth_of(g), []).append(g)
     cache = load_cache(path)
     chosen: Dict[int, dict] = {}
     dirty = False
-    for K in sorted(by_depth, reverse=True):
-        gs = [g for g in by_depth[K] if g.E.shape[0] > 0]
+
+    mixed = sorted(K for K in by_depth if K >= MIXED_MIN_DEPTH)
+    if len(by_depth) > 1 or SPLIT_DEPTH in by_depth:
+        gs = [g for K in mixed for g in by_depth[K]]
+        key = mixed_cache_key(tag, mixed, sum(g.E.shape[0] for g in gs))
+        hit = cache.get(key)
+        if hit and not retune:
+            best, cached = (hit["ms"], hit["waves_per_cu"]), True
+        else:
+            best, cached = None, False
+            for w in waves:
+                for K in mixed:
+                    set_tuning(K, 0, w)
+                ms = float(timer(gs, fiber, matrix, reps, newton))
+                if best is None or ms < best[0]:
+                    best = (ms, w)
+            cache[key] = dict(waves_per_cu=best[1], ms=best[0])
+            dirty = True
+        for K in mixed:
+            set_tuning(K, 0, best[1])
+            lanes, _ = get_tuning(K)
+            chosen[K] = dict(lanes_per_point=lanes, waves_per_cu=best[1], ms=best[0],
+                             cached=cached, launch="mixed")
+        single = [K for K in by_depth if K < MIXED_MIN_DEPTH]
+    else:
+        single = list(by_depth)
+
+    for K in sorted(single, reverse=True):
+        gs = by_depth[K]
         P = sum(g.E.shape[0] for g in gs)
         key = cache_key(tag, K, P)
         hit = cache.get(key)
         if hit and not retune and hit.get("lanes_per_point") in lane_variants(K):
             set_tuning(K, hit["lanes_per_point"], hit["waves_per_cu"])
             chosen[K] = dict(hit, cached=True)
-            continue
-        if not gs:
             continue
         best = None
         for lanes in lane_variants(K):

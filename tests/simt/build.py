@@ -34,10 +34,10 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _digest(defines):
+def _digest(defines, srcs):
     h = hashlib.sha256()
-    for f in sources() + sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
-                                if f.endswith(".hpp")) + [
+    for f in list(srcs) + sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                                 if f.endswith(".hpp")) + [
             os.path.join(INCLUDE, "dmn.h"), os.path.join(HERE, "hip", "hip_runtime.h")]:
         with open(f, "rb") as fh:
             h.update(f.encode() + fh.read())
@@ -52,29 +52,39 @@ def _compile(src, obj, defines):
         raise RuntimeError(f"{' '.join(cmd)}\n{r.stderr[-4000:]}")
 
 
-def build(defines=(VARIANTS,), jobs=None):
-    """Return the path of the sanitised CPU library, building it if needed."""
-    tag = _digest(defines)
-    lib = os.path.join(OUT, f"libdmn_simt_{tag}.so")
+def build(defines=(VARIANTS,), jobs=None, srcs=None, name="libdmn_simt"):
+    """Return the path of a sanitised CPU library, building it if needed: by
+    default the whole library (every csrc/*.hip), else the given sources."""
+    srcs = list(srcs) if srcs is not None else sources()
+    tag = _digest(defines, srcs)
+    lib = os.path.join(OUT, f"{name}_{tag}.so")
     if os.path.exists(lib):
         return lib
     os.makedirs(OUT, exist_ok=True)
-    objs = [os.path.join(OUT, f"{tag}_{os.path.basename(s)}.o") for s in sources()]
+    objs = [os.path.join(OUT, f"{tag}_{os.path.basename(s)}.o") for s in srcs]
     jobs = jobs or max(1, min(6, os.cpu_count() or 1))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        list(ex.map(lambda so: _compile(so[0], so[1], defines), zip(sources(), objs)))
+        list(ex.map(lambda so: _compile(so[0], so[1], defines), zip(srcs, objs)))
     tmp = lib + ".tmp"
-    r = subprocess.run([CXX, "-shared", "-fsanitize=address,undefined", "-o", tmp, *objs,
-                        "-lpthread"], capture_output=True, text=True)
+    r = subprocess.run([CXX, "-shared", "-fsanitize=address,undefined", "-Wl,--no-undefined",
+                        "-o", tmp, *objs, "-lpthread"], capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(r.stderr[-4000:])
     os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
     for f in os.listdir(OUT):  # builds of earlier sources
-        if f.startswith("libdmn_simt_") and os.path.join(OUT, f) != lib:
+        if f.startswith(name + "_") and f.endswith(".so") and os.path.join(OUT, f) != lib:
             os.remove(os.path.join(OUT, f))
     return lib
+
+
+def build_f32_kernel():
+    """The FP32-storage Gauss-point kernel (tests/simt/fp32_kernel.cpp, which
+    includes the kernel source) with the table-prep kernels it needs."""
+    return build(defines=(), srcs=[os.path.join(HERE, "fp32_kernel.cpp"),
+                                   os.path.join(CSRC, "dmn_prep.hip")],
+                 name="libdmn_simt_f32")
 
 
 def asan_runtime():

@@ -47,3 +47,25 @@ def run_gp(groups, fiber, matrix, opts=(1e-10, 25, 10, 1e-4, 0, 0), prec=0, tuni
         out = [[{k: d[f"g{g}_s{s}_{k}"] for k in ("sigma", "C", "z", "a", "iters", "status")}
                 for s in range(T)] for g in range(len(groups))]
     return out, r.stderr
+
+
+def run_f32_kernel(depth, lanes, w, n, E, fiber, matrix, timeout=900):
+    """Load path through the FP32-storage kernel's CPU build (run_f32.py)."""
+    lib = B.build_f32_kernel()
+    fib, mat = material_arrays(fiber, matrix)
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
+        np.savez(fin, depth=depth, lanes=lanes, w=w, n=n, E=np.asarray(E, np.float32),
+                 fiber=fib, matrix=mat)
+        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(),
+                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+        r = subprocess.run([sys.executable, os.path.join(HERE, "run_f32.py"), lib, fin, fout],
+                           env=env, capture_output=True, text=True, timeout=timeout)
+        if r.returncode != 0:
+            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
+                                 f"{r.stderr[-6000:]}")
+        d = np.load(fout)
+        T = np.asarray(E).shape[0]
+        return [{k: d[f"s{s}_{k}"] for k in ("sigma", "C", "z", "a", "iters", "status")}
+                for s in range(T)]

@@ -51,9 +51,8 @@ def test_tuning_table_validation():
     assert A.get_tuning(5) == (16, 8)
 
 
-def fake_groups():
-    return [SimpleNamespace(w=torch.zeros(2 ** K), E=torch.zeros(P, 6))
-            for K, P in ((5, 3000), (8, 60000), (5, 1000))]
+def fake_groups(spec=((5, 3000), (8, 60000), (5, 1000))):
+    return [SimpleNamespace(w=torch.zeros(2 ** K), E=torch.zeros(P, 6)) for K, P in spec]
 
 
 def fake_timer(calls):
@@ -67,31 +66,69 @@ def fake_timer(calls):
 
 
 def test_autotuner_picks_fastest_and_caches(tmp_path):
+    """Groups of one depth: every lane variant x wave count, timed on the
+    depth's groups together; the cache sets the winner in a later process."""
     path = str(tmp_path / "tune.json")
     calls = []
-    got = A.tune_gauss_points(fake_groups(), {}, {}, cache_path=path, timer=fake_timer(calls),
-                              tag="dev")
+    got = A.tune_gauss_points(fake_groups(((5, 3000), (5, 1000))), {}, {}, cache_path=path,
+                              timer=fake_timer(calls), tag="dev")
     assert got[5]["lanes_per_point"] == 8 and got[5]["waves_per_cu"] == 4
-    assert got[8]["lanes_per_point"] == 64 and got[8]["waves_per_cu"] == 16
-    assert not got[5]["cached"] and not got[8]["cached"]
-    # every variant x wave count timed once per depth, on the depth's groups together
-    assert sorted({c[:3] for c in calls if c[0] == 5}) == sorted(
+    assert not got[5]["cached"]
+    assert sorted({c[:3] for c in calls}) == sorted(
         (5, l, w) for l in A.lane_variants(5) for w in A.WAVES_PER_CU)
-    assert {c[3] for c in calls if c[0] == 5} == {4000}
-    assert A.get_tuning(5) == (8, 4) and A.get_tuning(8) == (64, 16)
+    assert {c[3] for c in calls} == {4000}
+    assert A.get_tuning(5) == (8, 4)
     data = json.load(open(path))
     assert data[A.cache_key("dev", 5, 4000)]["lanes_per_point"] == 8
+    got = A.tune_gauss_points(fake_groups(((8, 60000),)), {}, {}, cache_path=path,
+                              timer=fake_timer(calls), tag="dev")
+    assert got[8]["lanes_per_point"] == 64 and got[8]["waves_per_cu"] == 16
     # a second process start: the table is reset, the cache sets it without timing
     A.reset_tuning()
     calls.clear()
-    got = A.tune_gauss_points(fake_groups(), {}, {}, cache_path=path, timer=fake_timer(calls),
-                              tag="dev")
+    got = A.tune_gauss_points(fake_groups(((5, 3000), (5, 1000))), {}, {}, cache_path=path,
+                              timer=fake_timer(calls), tag="dev")
     assert calls == [] and got[5]["cached"] and A.get_tuning(5) == (8, 4)
     # another device tag misses the cache
-    A.tune_gauss_points(fake_groups(), {}, {}, cache_path=path, timer=fake_timer(calls),
-                        tag="other")
+    A.tune_gauss_points(fake_groups(((5, 4000),)), {}, {}, cache_path=path,
+                        timer=fake_timer(calls), tag="other")
     assert calls
-    assert len(json.load(open(path))) == 4
+    assert len(json.load(open(path))) == 3
+
+
+def test_autotuner_mixed_depths_tunes_the_mixed_launch(tmp_path):
+    """Fixed-normal groups of several depths run in one mixed-depth launch:
+    its wave count is timed on all groups of depths >= 2 together (lane splits
+    are fixed there); a depth-1 group is tuned on its own."""
+    path = str(tmp_path / "tune.json")
+    calls = []
+
+    def timer(groups, fiber, matrix, reps, newton):
+        depths = sorted({int(round(torch.log2(torch.tensor(float(g.w.numel()))).item()))
+                         for g in groups})
+        waves = {A.get_tuning(K)[1] for K in depths}
+        calls.append((tuple(depths), tuple(sorted(waves)), sum(g.E.shape[0] for g in groups)))
+        return 1.0 + abs(min(waves) - 8) / 10.0 if depths != [1] else 1.0
+
+    got = A.tune_gauss_points(fake_groups(((5, 3000), (9, 500), (8, 6000), (1, 70))), {}, {},
+                              cache_path=path, timer=timer, tag="dev")
+    assert sorted(got) == [1, 5, 8, 9]
+    mixed = [c for c in calls if c[0] != (1,)]
+    assert [c[1] for c in mixed] == [(w,) for w in A.WAVES_PER_CU]  # one wave count for all
+    assert all(c[0] == (5, 8, 9) and c[2] == 9500 for c in mixed)
+    for K in (5, 8, 9):
+        assert got[K]["launch"] == "mixed" and got[K]["waves_per_cu"] == 8
+        assert A.get_tuning(K)[1] == 8
+    assert A.get_tuning(9)[0] == 128 and A.get_tuning(5)[0] == A.lane_variants(5)[0]
+    assert "launch" not in got[1]
+    data = json.load(open(path))
+    assert data[A.mixed_cache_key("dev", [5, 8, 9], 9500)]["waves_per_cu"] == 8
+    A.reset_tuning()
+    calls.clear()
+    again = A.tune_gauss_points(fake_groups(((5, 3000), (9, 500), (8, 6000), (1, 70))), {}, {},
+                                cache_path=path, timer=timer, tag="dev")
+    assert calls == [] and all(v["cached"] for v in again.values())
+    assert A.get_tuning(8)[1] == 8
 
 
 def test_cache_key_buckets_point_counts():

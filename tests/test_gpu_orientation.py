@@ -70,8 +70,9 @@ def compare(net, lam, E_path, points, gpu, rows=None):
 
 DEPTH1_SKIP = pytest.mark.skip(
     reason="depth 1, quadratic: ended in a device memory-aperture fault in a run of a build that "
-    "also held a new mixed-depth kernel; the depth-1 orientation kernel's code was the same as "
-    "in earlier passing runs and no cause has been shown, so the case stays off the device")
+    "held the first version of the mixed-depth kernel; the depth-1 orientation kernel's code was "
+    "the same as in earlier passing runs and the sanitised CPU build runs the case clean, but no "
+    "cause has been shown, so the case stays off the device")
 
 
 @pytest.mark.parametrize("K,kind", [pytest.param(1, "quadratic", marks=DEPTH1_SKIP),

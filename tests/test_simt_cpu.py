@@ -10,7 +10,8 @@ report.  The cases cover every compiled lane split of depths 1-8, including
 the (8, 3) split that the device build leaves out, orientation-interpolated
 normals, one call over groups of depths 1-9 (the mixed-depth launch, with
 depth-9 points split over two waves), FP32 state, the entry point without a
-workspace, and the failure statuses.  Results must match the oracle to the
+workspace, the failure statuses, and the FP32-storage kernel instantiation
+that the device build also leaves out (tests/simt/fp32_kernel.cpp).  Results must match the oracle to the
 GPU parity bar (FP64 relative 1e-10, equal iterations and status)."""
 import os
 import shutil
@@ -152,3 +153,24 @@ def test_simt_gp_failure_statuses():
     assert st1[2] == 2 and all(st1[p] == 0 for p in range(6) if p != 2)
     assert np.all(out[0][0]["z"][2] == 0) and np.all(out[0][0]["a"][2] == 0)
     assert np.all(st2 == 5)
+
+
+@pytest.mark.parametrize("K,lanes", [(1, 1), (3, 2), (5, 16), (8, 64)])
+def test_simt_fp32_storage_kernel(K, lanes):
+    """The FP32-storage instantiation gp_update_kernel<K, D, float>, which the
+    device build leaves out after a device fault: bounds-checked on the CPU and
+    within 1e-4 of the oracle on the FP32-rounded strains, with the oracle's
+    iteration counts."""
+    rs = S.streams(900 + K)
+    net = S.random_dmn(rs["dmn"], K, 0.25)
+    P = min(64 // lanes + 3, 40) if lanes < 64 else 2
+    E = S.ramp_with_noise(rs, P, 3, 0.02, 1e-3).astype(np.float32)
+    out = harness().run_f32_kernel(K, lanes, net.w, net.normals, E, S.FIBER, S.MATRIX)
+    model = DmnModel(K, net.w, net.normals, S.FIBER, S.MATRIX)
+    for p in range(P):
+        ref = run_path(model, E[:, p, :].astype(np.float64), NewtonOptions())
+        for s, r in enumerate(ref):
+            assert out[s]["status"][p] == r["status"] == 0
+            assert out[s]["iters"][p] == r["iters"], (p, s)
+            assert rel(out[s]["sigma"][p].astype(np.float64), r["sigma"]) <= 1e-4
+            assert rel(out[s]["C"][p].astype(np.float64), r["C"]) <= 1e-4
