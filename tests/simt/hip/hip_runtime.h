@@ -92,8 +92,8 @@ class Barrier {
 
 struct Wave {
   Barrier bar;
-  uint64_t slot[64];
-  bool live[64];
+  uint64_t slot[2][64];  // exchange buffers, used alternately
+  unsigned tag[2][64];    // the exchange each entry was written for
 };
 
 struct Block {
@@ -106,6 +106,7 @@ struct Tls {
   Block* block = nullptr;
   Wave* wave = nullptr;
   int lane = 0;
+  unsigned exchanges = 0;  // cross-lane operations this thread has taken part in
 };
 inline Tls& tls() {
   static thread_local Tls t;
@@ -114,16 +115,24 @@ inline Tls& tls() {
 
 inline int lane_id() { return tls().lane; }
 
+// One barrier per exchange: exchange n uses buffer n % 2, and no lane can
+// write that buffer again (exchange n + 2) before every lane has passed the
+// barrier of exchange n + 1, i.e. has read its value of exchange n.  Each
+// entry carries the exchange number it was written for; a lane that has left
+// the kernel writes no more, and reading its entry gives the NaN pattern.
 template <typename T>
 inline T exchange(T v, int src) {
   static_assert(sizeof(T) <= 8, "exchange of a value wider than 64 bits");
-  Wave& w = *tls().wave;
+  Tls& s = tls();
+  Wave& w = *s.wave;
+  const unsigned n = s.exchanges++;
   uint64_t bits = 0;
   memcpy(&bits, &v, sizeof(T));
-  w.slot[tls().lane] = bits;
+  w.slot[n & 1][s.lane] = bits;
+  w.tag[n & 1][s.lane] = n;
   w.bar.wait("wave (shuffle)");
-  uint64_t got = w.live[src & 63] ? w.slot[src & 63] : ~0ull;  // exited lane: NaN pattern
-  w.bar.wait("wave (shuffle)");
+  const int l = src & 63;
+  const uint64_t got = w.tag[n & 1][l] == n ? w.slot[n & 1][l] : ~0ull;
   T r;
   memcpy(&r, &got, sizeof(T));
   return r;
@@ -145,7 +154,7 @@ void launch(void (*kernel)(P...), dim3 grid, dim3 block, A&&... a) {
         for (int w = 0; w < nwaves; ++w) {
           const int n = std::min(64, nthreads - 64 * w);
           b.waves[w].bar.reset(n);
-          for (int l = 0; l < 64; ++l) b.waves[w].live[l] = l < n;
+          for (int l = 0; l < 64; ++l) b.waves[w].tag[0][l] = b.waves[w].tag[1][l] = ~0u;
         }
         std::vector<std::thread> th;
         th.reserve(nthreads);
@@ -161,7 +170,6 @@ void launch(void (*kernel)(P...), dim3 grid, dim3 block, A&&... a) {
             s.lane = t % 64;
             auto local = args;  // kernel arguments are passed by value
             std::apply(kernel, local);
-            s.wave->live[s.lane] = false;
             s.wave->bar.drop();
             b.bar.drop();
           });
@@ -212,13 +220,14 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
   return simt::exchange(v, idx);
 }
 inline int __any(int pred) {
-  simt::Wave& w = *simt::tls().wave;
+  simt::Tls& s = simt::tls();
+  simt::Wave& w = *s.wave;
+  const unsigned n = s.exchanges++;  // an exchange round, as in simt::exchange
+  w.slot[n & 1][s.lane] = pred ? 1 : 0;
+  w.tag[n & 1][s.lane] = n;
+  w.bar.wait("wave (vote)");
   int r = 0;
-  // one exchange round: every lane publishes its predicate, all read all
-  w.slot[simt::lane_id()] = pred ? 1 : 0;
-  w.bar.wait("wave (vote)");
-  for (int l = 0; l < 64; ++l) r |= (w.live[l] && w.slot[l]) ? 1 : 0;
-  w.bar.wait("wave (vote)");
+  for (int l = 0; l < 64; ++l) r |= (w.tag[n & 1][l] == n && w.slot[n & 1][l]) ? 1 : 0;
   return r;
 }
 
