@@ -10,6 +10,7 @@ a hash of the sources and flags.
 import concurrent.futures as cf
 import hashlib
 import os
+import re
 import subprocess
 import sys
 
@@ -21,7 +22,6 @@ OUT = os.path.join(HERE, "_build")
 CXX = os.environ.get("CXX_SIMT", "g++")
 
 FLAGS = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fPIC",
-         "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
          "-I", HERE, "-I", INCLUDE, "-I", CSRC]
 
 # Gauss-point kernel variants of this build: the device build's list plus the
@@ -32,6 +32,12 @@ VARIANTS = ("-DDMN_GP_VARIANTS(X)=X(1, 1) X(2, 1) X(2, 2) X(3, 1) X(3, 2) X(4, 1
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+# ThreadSanitizer instead of ASan/UBSan: a data race between GPU threads (for
+# example LDS written by one lane and read by another with no barrier between)
+SANITIZERS = {"address": ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"],
+              "thread": ["-fsanitize=thread"]}
 
 
 def _digest(defines, srcs):
@@ -52,10 +58,14 @@ def _compile(src, obj, defines):
         raise RuntimeError(f"{' '.join(cmd)}\n{r.stderr[-4000:]}")
 
 
-def build(defines=(VARIANTS,), jobs=None, srcs=None, name="libdmn_simt"):
+def build(defines=(VARIANTS,), jobs=None, srcs=None, name="libdmn_simt", sanitizer="address"):
     """Return the path of a sanitised CPU library, building it if needed: by
     default the whole library (every csrc/*.hip), else the given sources."""
     srcs = list(srcs) if srcs is not None else sources()
+    san = SANITIZERS[sanitizer]
+    defines = tuple(defines) + tuple(san)
+    if sanitizer != "address":
+        name = f"{name}_{sanitizer}"
     tag = _digest(defines, srcs)
     lib = os.path.join(OUT, f"{name}_{tag}.so")
     if os.path.exists(lib):
@@ -66,15 +76,16 @@ def build(defines=(VARIANTS,), jobs=None, srcs=None, name="libdmn_simt"):
     with cf.ThreadPoolExecutor(jobs) as ex:
         list(ex.map(lambda so: _compile(so[0], so[1], defines), zip(srcs, objs)))
     tmp = lib + ".tmp"
-    r = subprocess.run([CXX, "-shared", "-fsanitize=address,undefined", "-Wl,--no-undefined",
+    r = subprocess.run([CXX, "-shared", san[0], "-Wl,--no-undefined",
                         "-o", tmp, *objs, "-lpthread"], capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(r.stderr[-4000:])
     os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
+    stale = re.compile(rf"^{re.escape(name)}_[0-9a-f]{{16}}\.so$")
     for f in os.listdir(OUT):  # builds of earlier sources
-        if f.startswith(name + "_") and f.endswith(".so") and os.path.join(OUT, f) != lib:
+        if stale.match(f) and os.path.join(OUT, f) != lib:
             os.remove(os.path.join(OUT, f))
     return lib
 
@@ -87,10 +98,11 @@ def build_f32_kernel():
                  name="libdmn_simt_f32")
 
 
-def asan_runtime():
-    """Path of the compiler's ASan runtime, preloaded into the Python process
-    that loads the library."""
-    return subprocess.run([CXX, "-print-file-name=libasan.so"], capture_output=True,
+def asan_runtime(sanitizer="address"):
+    """Path of the compiler's sanitizer runtime, preloaded into the Python
+    process that loads the library."""
+    lib = {"address": "libasan.so", "thread": "libtsan.so"}[sanitizer]
+    return subprocess.run([CXX, f"-print-file-name={lib}"], capture_output=True,
                           text=True, check=True).stdout.strip()
 
 

@@ -19,10 +19,10 @@ def material_arrays(fiber, matrix):
 
 
 def run_gp(groups, fiber, matrix, opts=(1e-10, 25, 10, 1e-4, 0, 0), prec=0, tuning=(),
-           noalloc=False, defines=(B.VARIANTS,), timeout=900):
+           noalloc=False, defines=(B.VARIANTS,), timeout=900, sanitizer="address"):
     """groups: dicts with depth, w, E [T, P, 6] and either n or ori/p/q/lam.
     Returns (outputs per group and step, child's stderr)."""
-    lib = B.build(defines)
+    lib = B.build(defines, sanitizer=sanitizer)
     fib, mat = material_arrays(fiber, matrix)
     case = dict(n_groups=len(groups), opts=np.array(opts, dtype=np.float64), prec=prec,
                 tuning=np.array(tuning, dtype=np.int64).reshape(-1, 3), noalloc=int(noalloc),
@@ -33,9 +33,10 @@ def run_gp(groups, fiber, matrix, opts=(1e-10, 25, 10, 1e-4, 0, 0), prec=0, tuni
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
         np.savez(fin, **case)
-        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(),
+        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(sanitizer),
                    ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                    UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
+                   TSAN_OPTIONS="halt_on_error=1:report_signal_unsafe=0",
                    OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
         r = subprocess.run([sys.executable, os.path.join(HERE, "run_gp.py"), lib, fin, fout],
                            env=env, capture_output=True, text=True, timeout=timeout)

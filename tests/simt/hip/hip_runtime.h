@@ -18,6 +18,7 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <tuple>
@@ -61,7 +62,13 @@ class Barrier {
       release();
       return;
     }
+#ifdef __SANITIZE_THREAD__
+    // ThreadSanitizer does not follow the clocked condition wait of wait_for
+    cv_.wait(l, [&] { return gen_ != g; });
+    if (false) {
+#else
     if (!cv_.wait_for(l, std::chrono::seconds(timeout_s()), [&] { return gen_ != g; })) {
+#endif
       fprintf(stderr, "simt: %s barrier not reached by all live threads (%d of %d)\n", what,
               count_, expected_);
       fflush(stderr);
@@ -148,7 +155,8 @@ void launch(void (*kernel)(P...), dim3 grid, dim3 block, A&&... a) {
   for (unsigned bz = 0; bz < grid.z; ++bz)
     for (unsigned by = 0; by < grid.y; ++by)
       for (unsigned bx = 0; bx < grid.x; ++bx) {
-        Block b;
+        auto owner = std::make_unique<Block>();  // fresh storage per workgroup
+        Block& b = *owner;
         b.bar.reset(nthreads);
         b.waves = std::vector<Wave>(nwaves);
         for (int w = 0; w < nwaves; ++w) {
