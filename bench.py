@@ -34,6 +34,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -47,11 +48,22 @@ GP_SOURCES = ["paper_2103_08253_amd/csrc/dmn_gp.hip", "paper_2103_08253_amd/csrc
               "paper_2103_08253_amd/csrc/dmn_internal.hpp"]
 
 
+def code_text(src: str) -> str:
+    """Source without its comments and blank lines: what the compiler builds
+    from (a string literal holding comment markers would be cut too, which
+    only makes the digest change more often)."""
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def source_digest(paths):
+    """Digest of the kernel sources' code (comments do not count), which the
+    recorded HBM traffic must match."""
     h = hashlib.sha256()
     for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

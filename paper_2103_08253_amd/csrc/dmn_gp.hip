@@ -303,7 +303,9 @@ __global__ __launch_bounds__(64) void gp_update_kernel(const GpLaunch args) {
 // A depth-9 point is split over the two waves of a workgroup: wave h owns the
 // depth-8 subtree under child h of the root laminate (the mapping of a depth-8
 // point, lane subtrees of depth 2), and the root laminate joins them through
-// LDS.  No lane holds more than a depth-8 lane's state, so nothing spills.
+// LDS.  No lane holds more than a depth-8 lane's state, so the point needs
+// no more registers than a depth-8 point (the one-wave depth-9 variant spilled
+// 1.6 KB per lane).
 
 // Paper position, in the depth-9 tree, of position pos8 of the depth-8 subtree
 // under child h of the root: level k' of pos8 (the root's child is k' = 1) has

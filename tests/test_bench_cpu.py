@@ -37,10 +37,14 @@ def test_source_digest_follows_every_kernel_source(tmp_path, monkeypatch):
     files = []
     for i in range(2):
         p = tmp_path / f"k{i}.hip"
-        p.write_text(f"// source {i}\n")
+        p.write_text(f"// source {i}\nint k{i}(int a) {{ return a + {i}; }}\n")
         files.append(str(p))
     d0 = bench.source_digest(files)
     assert d0 == bench.source_digest(files)
+    # comments and blank lines do not change the code the counters were taken on
+    with open(files[0], "a") as f:
+        f.write("\n// a remark\n/* a block\n   remark */\n\n")
+    assert bench.source_digest(files) == d0
     with open(files[1], "a") as f:
-        f.write(" ")
+        f.write("int x;\n")
     assert bench.source_digest(files) != d0
