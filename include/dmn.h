@@ -261,9 +261,15 @@ size_t dmn_update_gauss_points_workspace_size(const dmn_point_group* groups, int
  * FP32: the call widens the inputs into FP64 copies in the workspace, runs
  * the FP64 update on them and rounds the results to nearest into the FP32
  * outputs (the DMN parameters, orientations and options stay FP64).  At most
- * 64 groups per call.  Groups with
- * orientation-interpolated normals use the default lane split of their depth
- * whatever the tuning table says.  A non-finite (l1, l2) gives
+ * 64 groups per call.  Launches: fixed-normal groups of depths 2-9 that differ
+ * in depth, or include depth 9, share one persistent launch (up to 16 groups
+ * each; a depth-9 point is split over the two wavefronts of a workgroup, the
+ * other depths take batches with lane subtrees of depth 2 whatever the tuning
+ * table's lane split, its wave count applies); otherwise groups of one depth
+ * share a launch with the tuned lane split.  Groups with
+ * orientation-interpolated normals, and depth-1 groups, run in launches of
+ * their own; orientation-interpolated groups use the default lane split of
+ * their depth whatever the tuning table says.  A non-finite (l1, l2) gives
  * DMN_STATUS_NONFINITE. */
 int dmn_update_gauss_points(const dmn_point_group* groups, int32_t n_groups,
                             const dmn_elastic* fiber, const dmn_j2* matrix, int prec,
@@ -299,8 +305,11 @@ int dmn_update_gauss_points_noalloc(const dmn_point_group* groups, int32_t n_gro
  * wavefront (each lane owns a subtree of depth K - log2(lanes_per_point), the
  * levels above are combined across lanes), so 64 / lanes_per_point points
  * share a wavefront; waves_per_cu persistent wavefronts per compute unit take
- * batches of points from a work counter.  Tuning changes speed only: every
- * variant computes the same per-point result. */
+ * batches of points from a work counter.  Depth 9 has one variant, 128 lanes
+ * (a point over the two wavefronts of a workgroup).  In a launch shared by
+ * several depths (see dmn_update_gauss_points) only waves_per_cu counts, the
+ * largest of the depths present.  Tuning changes speed only: every variant
+ * computes the same per-point result. */
 typedef struct dmn_gp_tuning {
   int32_t lanes_per_point; /* a value listed by dmn_gp_lane_variants; 0 = default */
   int32_t waves_per_cu;    /* 1..64; 0 = default (8) */
