@@ -70,3 +70,24 @@ def run_f32_kernel(depth, lanes, w, n, E, fiber, matrix, timeout=900):
         T = np.asarray(E).shape[0]
         return [{k: d[f"s{s}_{k}"] for k in ("sigma", "C", "z", "a", "iters", "status")}
                 for s in range(T)]
+
+
+def run_linear(depth, w, n, C1, C2, gCbar, input_grads=False, sanitizer="address", timeout=900):
+    """Linear map and backward through the CPU build (run_linear.py)."""
+    lib = B.build(sanitizer=sanitizer)
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
+        np.savez(fin, depth=depth, w=w, n=n, C1=C1, C2=C2, gCbar=gCbar,
+                 input_grads=int(input_grads))
+        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(sanitizer),
+                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
+                   TSAN_OPTIONS="halt_on_error=1:report_signal_unsafe=0",
+                   OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.join(HERE, "run_linear.py"), lib, fin, fout],
+                           env=env, capture_output=True, text=True, timeout=timeout)
+        if r.returncode != 0:
+            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
+                                 f"{r.stderr[-6000:]}")
+        d = np.load(fout)
+        return {k: d[k] for k in d.files}

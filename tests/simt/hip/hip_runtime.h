@@ -147,16 +147,48 @@ inline T exchange(T v, int src) {
 
 inline void wave_barrier() { tls().wave->bar.wait("wave"); }
 
+// The threads of a workgroup are created once per launch and run the
+// workgroups one after another: the launching thread prepares a workgroup's
+// barriers, releases the threads through `start`, and waits at `done` until
+// every thread has returned from the kernel.
 template <typename... P, typename... A>
 void launch(void (*kernel)(P...), dim3 grid, dim3 block, A&&... a) {
   std::tuple<std::decay_t<P>...> args(std::forward<A>(a)...);
   const int nthreads = (int)(block.x * block.y * block.z);
   const int nwaves = (nthreads + 63) / 64;
+  const long long nblocks = (long long)grid.x * grid.y * grid.z;
+  if (nthreads <= 0 || nblocks <= 0) return;
+  Barrier start(nthreads + 1), done(nthreads + 1);
+  std::unique_ptr<Block> cur;
+  dim3 cur_bid;
+  std::vector<std::thread> th;
+  th.reserve(nthreads);
+  for (int t = 0; t < nthreads; ++t) {
+    th.emplace_back([&, t] {
+      Tls& s = tls();
+      s.tid = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+      s.bdim = block;
+      s.gdim = grid;
+      s.lane = t % 64;
+      for (long long i = 0; i < nblocks; ++i) {
+        start.wait("launch (start)");
+        s.bid = cur_bid;
+        s.block = cur.get();
+        s.wave = &cur->waves[t / 64];
+        s.exchanges = 0;
+        auto local = args;  // kernel arguments are passed by value
+        std::apply(kernel, local);
+        s.wave->bar.drop();
+        s.block->bar.drop();
+        done.wait("launch (done)");
+      }
+    });
+  }
   for (unsigned bz = 0; bz < grid.z; ++bz)
     for (unsigned by = 0; by < grid.y; ++by)
       for (unsigned bx = 0; bx < grid.x; ++bx) {
-        auto owner = std::make_unique<Block>();  // fresh storage per workgroup
-        Block& b = *owner;
+        cur = std::make_unique<Block>();  // fresh storage per workgroup
+        Block& b = *cur;
         b.bar.reset(nthreads);
         b.waves = std::vector<Wave>(nwaves);
         for (int w = 0; w < nwaves; ++w) {
@@ -164,26 +196,11 @@ void launch(void (*kernel)(P...), dim3 grid, dim3 block, A&&... a) {
           b.waves[w].bar.reset(n);
           for (int l = 0; l < 64; ++l) b.waves[w].tag[0][l] = b.waves[w].tag[1][l] = ~0u;
         }
-        std::vector<std::thread> th;
-        th.reserve(nthreads);
-        for (int t = 0; t < nthreads; ++t) {
-          th.emplace_back([&, t] {
-            Tls& s = tls();
-            s.tid = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
-            s.bid = dim3(bx, by, bz);
-            s.bdim = block;
-            s.gdim = grid;
-            s.block = &b;
-            s.wave = &b.waves[t / 64];
-            s.lane = t % 64;
-            auto local = args;  // kernel arguments are passed by value
-            std::apply(kernel, local);
-            s.wave->bar.drop();
-            b.bar.drop();
-          });
-        }
-        for (auto& x : th) x.join();
+        cur_bid = dim3(bx, by, bz);
+        start.wait("launch (start)");
+        done.wait("launch (done)");
       }
+  for (auto& x : th) x.join();
 }
 
 }  // namespace simt

@@ -189,3 +189,55 @@ def test_simt_gp_no_race_between_lanes():
     single, model8 = fixed_group(8, 2, 2, 1008)
     out8, _ = harness().run_gp([single], S.FIBER, S.MATRIX, sanitizer="thread")
     assert check_group(out8[0], model8, single["E"], range(2)) <= RTOL
+
+
+def linear_case(K, B, seed):
+    tw = S.config3(batch=B, depth=K)
+    G = S.streams(seed)["cotangent"].standard_normal((B, 6, 6))
+    return tw, G
+
+
+def check_linear(K, tw, G, out, tol):
+    from oracle.grad import linear_gradients
+    from oracle.linear import dmn_linear
+    net = tw.truth
+    B = tw.C1.shape[0]
+    assert list(out["err"]) == [0, 0]
+    ref = dmn_linear(K, net.w, net.normals, tw.C1, tw.C2)
+    assert max(rel(out["Cbar"][b].astype(np.float64), ref[b]) for b in range(B)) <= tol
+    alpha, beta = S.normals_to_angles(net.normals)
+    gn = out["gn"].astype(np.float64)
+    da = np.stack([np.cos(alpha) * np.cos(beta), np.cos(alpha) * np.sin(beta), -np.sin(alpha)], -1)
+    db = np.stack([-np.sin(alpha) * np.sin(beta), np.sin(alpha) * np.cos(beta),
+                   np.zeros_like(alpha)], -1)
+    ga, gb = (gn * da).sum(-1), (gn * db).sum(-1)
+    w_idx = np.arange(0, 2 ** K, max(1, 2 ** K // 8))
+    a_idx = np.arange(0, 2 ** K - 1, max(1, (2 ** K - 1) // 6))
+    r = linear_gradients(K, net.w, alpha, beta, tw.C1, tw.C2, G, w_idx, a_idx)
+    assert rel(out["gw"][w_idx].astype(np.float64), r["gw"][w_idx]) <= tol
+    ref_a = np.concatenate([r["galpha"][a_idx], r["gbeta"][a_idx]])
+    assert rel(np.concatenate([ga[a_idx], gb[a_idx]]), ref_a) <= tol
+
+
+@pytest.mark.parametrize("K,B,dtype", [(3, 37, np.float64), (5, 70, np.float64),
+                                       (8, 4, np.float64), (3, 37, np.float32)])
+def test_simt_linear_map_and_backward(K, B, dtype):
+    """The linear map and its backward (dmn_homogenize_linear / _backward) in
+    the sanitised build against the oracle's map and complex-step gradients:
+    ragged batches, a depth-8 sample per wave, and at depth 5 with 70 samples
+    72 partial-sum slots, so the batch sum runs through the workgroup tree
+    reduction; FP32 storage and arithmetic within 1e-4."""
+    tw, G = linear_case(K, B, 3)
+    f = (lambda x: np.asarray(x, dtype))
+    out = harness().run_linear(K, f(tw.truth.w), f(tw.truth.normals), f(tw.C1), f(tw.C2), f(G),
+                               input_grads=(K == 3))
+    check_linear(K, tw, G, out, 1e-10 if dtype == np.float64 else 1e-4)
+
+
+def test_simt_linear_no_race_between_lanes():
+    """The linear map, its backward and the reductions of the batch sum (the
+    workgroup tree at depth 5 with 72 slots) under ThreadSanitizer."""
+    tw, G = linear_case(5, 70, 4)
+    out = harness().run_linear(5, tw.truth.w, tw.truth.normals, tw.C1, tw.C2, G,
+                               sanitizer="thread")
+    check_linear(5, tw, G, out, 1e-10)
