@@ -91,3 +91,27 @@ def run_linear(depth, w, n, C1, C2, gCbar, input_grads=False, sanitizer="address
                                  f"{r.stderr[-6000:]}")
         d = np.load(fout)
         return {k: d[k] for k in d.files}
+
+
+def run_adjoint(depth, w, n, E, g, fiber, matrix, opts=(1e-13, 50, 10, 1e-4, 0, 1),
+                sanitizer="address", timeout=900):
+    """Path gradient through the CPU build's forward path and step adjoint
+    (run_adjoint.py)."""
+    lib = B.build(sanitizer=sanitizer)
+    fib, mat = material_arrays(fiber, matrix)
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
+        np.savez(fin, depth=depth, w=w, n=n, E=E, g=g, opts=np.array(opts, dtype=np.float64),
+                 fiber=fib, matrix=mat)
+        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(sanitizer),
+                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
+                   TSAN_OPTIONS="halt_on_error=1:report_signal_unsafe=0",
+                   OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.join(HERE, "run_adjoint.py"), lib, fin, fout],
+                           env=env, capture_output=True, text=True, timeout=timeout)
+        if r.returncode != 0:
+            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
+                                 f"{r.stderr[-6000:]}")
+        d = np.load(fout)
+        return {k: d[k] for k in d.files}

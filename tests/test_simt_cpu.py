@@ -241,3 +241,39 @@ def test_simt_linear_no_race_between_lanes():
     out = harness().run_linear(5, tw.truth.w, tw.truth.normals, tw.C1, tw.C2, G,
                                sanitizer="thread")
     check_linear(5, tw, G, out, 1e-10)
+
+
+@pytest.mark.parametrize("K,P,T,every", [(3, 3, 4, True), (5, 4, 3, False)])
+def test_simt_path_adjoint(K, P, T, every):
+    """The path gradient of J = sum_p g_p . sigma_p(final): forward path with
+    the tight tolerance and one polishing step, then dmn_update_adjoint swept
+    backwards over the steps, in the sanitised build, against the oracle's
+    complex-step path derivative along unit directions (every parameter at
+    depth 3; weights and both angles of a few laminates at depth 5)."""
+    from oracle.adjoint import path_directional_derivative
+    rs = S.streams(400 + K)
+    net = S.random_dmn(rs["dmn"], K, 0.25)
+    E = S.ramp_with_noise(rs, P, T, 0.02, 1e-3)
+    g = S.unit_directions(rs["cotangent"], P)
+    out = harness().run_adjoint(K, net.w, net.normals, E, g, S.FIBER, S.MATRIX)
+    assert not np.any(out["err"])
+    alpha, beta = S.normals_to_angles(net.normals)
+    gn = out["gn"]
+    da = np.stack([np.cos(alpha) * np.cos(beta), np.cos(alpha) * np.sin(beta), -np.sin(alpha)], -1)
+    db = np.stack([-np.sin(alpha) * np.sin(beta), np.sin(alpha) * np.cos(beta),
+                   np.zeros_like(alpha)], -1)
+    ga, gb = (gn * da).sum(-1), (gn * db).sum(-1)
+    nl, L = 2 ** K, 2 ** K - 1
+    picks = range(nl + 2 * L) if every else [0, 5, nl - 1, nl, nl + L // 2, nl + L, nl + 2 * L - 1]
+    scale = max(np.abs(out["gw"]).max(), np.abs(ga).max(), np.abs(gb).max())
+    for k in picks:
+        vw, va, vb = np.zeros(nl), np.zeros(L), np.zeros(L)
+        if k < nl:
+            vw[k], got = 1.0, out["gw"][k]
+        elif k < nl + L:
+            va[k - nl], got = 1.0, ga[k - nl]
+        else:
+            vb[k - nl - L], got = 1.0, gb[k - nl - L]
+        ref = path_directional_derivative(K, net.w, alpha, beta, S.FIBER, S.MATRIX, E, g,
+                                          vw, va, vb)
+        assert abs(got - ref) <= RTOL * scale, (k, got, ref)
