@@ -603,12 +603,39 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
     ok = all(bool((gr.status == 0).all().item()) for gr in groups)
     ms = _event_ms(replay, 2) / 2
     Pm = wl.n_points
+    # one load step (the 11th, after the first ten) called for all groups and
+    # for subsets of them, to see what each depth takes of the shared launch
+    for gr in groups:
+        gr.z_in.zero_()
+        gr.a_in.zero_()
+    for step in range(10):
+        for gr, Em in zip(groups, E_steps):
+            gr.E = Em[step]
+        dmn_update_gauss_points(groups, S.FIBER, S.MATRIX)
+        for gr in groups:
+            gr.advance()
+    for gr, Em in zip(groups, E_steps):
+        gr.E = Em[10]
+    depth_of = [n.depth for n in wl.nets]
+
+    def call_ms(sub):
+        ws_sub = dmn_update_gauss_points(sub, S.FIBER, S.MATRIX)
+        return _event_ms(lambda: dmn_update_gauss_points(sub, S.FIBER, S.MATRIX, ws=ws_sub),
+                         5) / 5
+    split = dict(load_step=11, all_groups_ms=call_ms(groups),
+                 depth9_groups_ms=call_ms([gr for gr, k in zip(groups, depth_of) if k == 9]),
+                 depths_5_to_8_groups_ms=call_ms([gr for gr, k in zip(groups, depth_of)
+                                                  if k != 9]))
+    for K in sorted(set(depth_of) - {9}):
+        split[f"depth{K}_groups_alone_ms"] = call_ms(
+            [gr for gr, k in zip(groups, depth_of) if k == K])
     out["mixed_batch_graph"] = dict(
         points=Pm, dmns=len(wl.nets), depths=sorted({n.depth for n in wl.nets}),
         load_steps_per_replay=wl.n_steps, ms_per_load_step=ms / wl.n_steps,
         updates_per_s=Pm * wl.n_steps / (ms * 1e-3), last_step_all_converged=ok,
         tuning={int(k): [v["lanes_per_point"], v["waves_per_cu"]]
-                for k, v in mixed_tuned.items()})
+                for k, v in mixed_tuned.items()},
+        one_call_by_depth=split)
     del graph, groups, E_steps
 
     # what the two roofs give on this device, for context beside the published
