@@ -603,6 +603,40 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
     ok = all(bool((gr.status == 0).all().item()) for gr in groups)
     ms = _event_ms(replay, 2) / 2
     Pm = wl.n_points
+    # FP32 state (per-point arrays stored in FP32, arithmetic in FP64) on the
+    # same path: its last step against the FP64 run's last step just replayed
+    ref64 = [(gr.sigma.clone(), gr.tangent.clone()) for gr in groups]
+    groups32, E32 = [], []
+    for gr, Em in zip(groups, E_steps):
+        E32.append(Em.float().contiguous())
+        groups32.append(PointGroup.allocate(gr.w, gr.n, E32[-1][0].clone()))
+    graph32 = LoadStepGraph(groups32, S.FIBER, S.MATRIX, E32, keep_sigma=False)
+
+    def replay32():
+        for z, a in graph32.start_state:
+            z.zero_()
+            a.zero_()
+        graph32.replay()
+    replay32()
+    torch.cuda.synchronize()
+    ok32 = all(bool((gr.status == 0).all().item()) for gr in groups32)
+    # per point: max-norm difference relative to the point's largest FP64 entry
+    def per_point(a, b):
+        a, b = a.double().reshape(a.shape[0], -1), b.reshape(b.shape[0], -1)
+        return ((a - b).abs().max(1).values / b.abs().max(1).values).cpu().numpy()
+    ds = np.concatenate([per_point(g32.sigma, s64) for g32, (s64, _) in zip(groups32, ref64)])
+    dc = np.concatenate([per_point(g32.tangent, c64) for g32, (_, c64) in zip(groups32, ref64)])
+    ms32 = _event_ms(replay32, 2) / 2
+    fp32_state = dict(
+        ms_per_load_step=ms32 / wl.n_steps, updates_per_s=Pm * wl.n_steps / (ms32 * 1e-3),
+        last_step_all_converged=ok32,
+        rel_diff_vs_fp64_last_step=dict(
+            sigma_max=float(ds.max()), tangent_median=float(np.median(dc)),
+            tangent_p999=float(np.quantile(dc, 0.999)), tangent_max=float(dc.max()),
+            points_tangent_above_1e_4=int((dc > 1e-4).sum()),
+            note="a point whose leaf at the yield surface takes the other branch in FP32 "
+                 "keeps a continuous stress but a tangent of the other branch"))
+    del graph32, groups32, E32, ref64
     # one load step (the 11th, after the first ten) called for all groups and
     # for subsets of them, to see what each depth takes of the shared launch
     for gr in groups:
@@ -635,7 +669,7 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         updates_per_s=Pm * wl.n_steps / (ms * 1e-3), last_step_all_converged=ok,
         tuning={int(k): [v["lanes_per_point"], v["waves_per_cu"]]
                 for k, v in mixed_tuned.items()},
-        one_call_by_depth=split)
+        one_call_by_depth=split, fp32_state=fp32_state)
     del graph, groups, E_steps
 
     # what the two roofs give on this device, for context beside the published
