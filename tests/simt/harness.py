@@ -72,13 +72,16 @@ def run_f32_kernel(depth, lanes, w, n, E, fiber, matrix, timeout=900):
                 for s in range(T)]
 
 
-def run_linear(depth, w, n, C1, C2, gCbar, input_grads=False, sanitizer="address", timeout=900):
-    """Linear map and backward through the CPU build (run_linear.py)."""
+def run_linear(depth, w, n, C1, C2, gCbar, input_grads=False, sanitizer="address", timeout=900,
+               ori=None):
+    """Linear map and backward through the CPU build (run_linear.py); ori =
+    (code, p, q, lam) for per-sample orientations (n is then not used)."""
     lib = B.build(sanitizer=sanitizer)
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
-        np.savez(fin, depth=depth, w=w, n=n, C1=C1, C2=C2, gCbar=gCbar,
-                 input_grads=int(input_grads))
+        extra = {} if ori is None else dict(ori=ori[0], p=ori[1], q=ori[2], lam=ori[3])
+        np.savez(fin, depth=depth, w=w, n=n if n is not None else np.zeros(1), C1=C1, C2=C2,
+                 gCbar=gCbar, input_grads=int(input_grads), **extra)
         env = dict(os.environ, LD_PRELOAD=B.asan_runtime(sanitizer),
                    ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                    UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",

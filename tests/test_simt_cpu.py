@@ -277,3 +277,36 @@ def test_simt_path_adjoint(K, P, T, every):
         ref = path_directional_derivative(K, net.w, alpha, beta, S.FIBER, S.MATRIX, E, g,
                                           vw, va, vb)
         assert abs(got - ref) <= RTOL * scale, (k, got, ref)
+
+
+@pytest.mark.parametrize("K,B,kind,dtype,tol", [(3, 37, "trilinear", np.float64, 1e-10),
+                                                (6, 6, "quadratic", np.float64, 1e-10),
+                                                (5, 17, "linear", np.float32, 2e-3)])
+def test_simt_oriented_linear_map_and_backward(K, B, kind, dtype, tol):
+    """Per-sample orientation in the linear map and its backward (each
+    sample's normals from its own (l1, l2)) in the sanitised build: the map
+    against the oracle, the cotangents of (w, p, q) along random directions
+    against the oracle's complex-step derivative."""
+    from oracle.orientation import oriented_directional_derivative, oriented_linear
+    rs = S.streams(700 + K)
+    net = S.interpolated_dmn(rs["dmn"], K, 0.3, kind)
+    lam = S.triangle_points(rs["assignment"], B)
+    C1, C2 = S.random_spd(rs["stiffness"], B), S.random_spd(rs["stiffness"], B)
+    G = rs["cotangent"].standard_normal((B, 6, 6))
+    code = {"linear": 1, "trilinear": 2, "quadratic": 3}[kind]
+    f = (lambda x: np.asarray(x, dtype))
+    out = harness().run_linear(K, f(net.w), None, f(C1), f(C2), f(G),
+                               ori=(code, f(net.p), f(net.q), f(lam)))
+    assert list(out["err"]) == [0, 0]
+    ref = oriented_linear(K, net.w, net.p, net.q, kind, lam, C1, C2)
+    assert rel(out["Cbar"].astype(np.float64), ref) <= (tol if dtype == np.float32 else 1e-10)
+    gw, gpq = out["gw"].astype(np.float64), out["gn"].astype(np.float64)
+    L, M = net.p.shape
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        vw, vp, vq = (rng.standard_normal(L + 1), rng.standard_normal((L, M)),
+                      rng.standard_normal((L, M)))
+        got = gw @ vw + np.sum(gpq[:, 0, :] * vp) + np.sum(gpq[:, 1, :] * vq)
+        r = oriented_directional_derivative(K, net.w, net.p, net.q, kind, lam, C1, C2, G,
+                                            vw, vp, vq)
+        assert abs(got - r) <= tol * abs(r), (got, r)
