@@ -1,5 +1,6 @@
-"""Parent side of the CPU-build tests: writes a case, runs tests/simt/run_gp.py
-in a child process under the ASan runtime, and reads the outputs back."""
+"""Parent side of the CPU-build tests: writes a case, runs one of the child
+runners in tests/simt/ in a child process under the sanitiser's runtime, and
+reads the outputs back."""
 import os
 import subprocess
 import sys
@@ -18,6 +19,29 @@ def material_arrays(fiber, matrix):
                       matrix["dsigma"], matrix["b"]]))
 
 
+def _child(script, lib, case, sanitizer="address", timeout=900):
+    """Runs tests/simt/<script> LIB IN.npz OUT.npz on the case under the
+    sanitiser's runtime; returns (outputs, the child's stderr)."""
+    with tempfile.TemporaryDirectory() as td:
+        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
+        np.savez(fin, **case)
+        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(sanitizer),
+                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
+                   TSAN_OPTIONS="halt_on_error=1:report_signal_unsafe=0",
+                   OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.join(HERE, script), lib, fin, fout],
+                           env=env, capture_output=True, text=True, timeout=timeout)
+        if r.returncode != 0:
+            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
+                                 f"{r.stderr[-6000:]}")
+        d = np.load(fout)
+        return {k: d[k] for k in d.files}, r.stderr
+
+
+STEP_KEYS = ("sigma", "C", "z", "a", "iters", "status")
+
+
 def run_gp(groups, fiber, matrix, opts=(1e-10, 25, 10, 1e-4, 0, 0), prec=0, tuning=(),
            noalloc=False, defines=(B.VARIANTS,), timeout=900, sanitizer="address"):
     """groups: dicts with depth, w, E [T, P, 6] and either n or ori/p/q/lam.
@@ -30,46 +54,20 @@ def run_gp(groups, fiber, matrix, opts=(1e-10, 25, 10, 1e-4, 0, 0), prec=0, tuni
     for g, grp in enumerate(groups):
         for k, v in grp.items():
             case[f"g{g}_{k}"] = np.asarray(v)
-    with tempfile.TemporaryDirectory() as td:
-        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
-        np.savez(fin, **case)
-        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(sanitizer),
-                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
-                   TSAN_OPTIONS="halt_on_error=1:report_signal_unsafe=0",
-                   OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
-        r = subprocess.run([sys.executable, os.path.join(HERE, "run_gp.py"), lib, fin, fout],
-                           env=env, capture_output=True, text=True, timeout=timeout)
-        if r.returncode != 0:
-            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
-                                 f"{r.stderr[-6000:]}")
-        d = np.load(fout)
-        T = np.asarray(groups[0]["E"]).shape[0]
-        out = [[{k: d[f"g{g}_s{s}_{k}"] for k in ("sigma", "C", "z", "a", "iters", "status")}
-                for s in range(T)] for g in range(len(groups))]
-    return out, r.stderr
+    d, err = _child("run_gp.py", lib, case, sanitizer, timeout)
+    T = np.asarray(groups[0]["E"]).shape[0]
+    return [[{k: d[f"g{g}_s{s}_{k}"] for k in STEP_KEYS} for s in range(T)]
+            for g in range(len(groups))], err
 
 
 def run_f32_kernel(depth, lanes, w, n, E, fiber, matrix, timeout=900):
     """Load path through the FP32-storage kernel's CPU build (run_f32.py)."""
     lib = B.build_f32_kernel()
     fib, mat = material_arrays(fiber, matrix)
-    with tempfile.TemporaryDirectory() as td:
-        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
-        np.savez(fin, depth=depth, lanes=lanes, w=w, n=n, E=np.asarray(E, np.float32),
-                 fiber=fib, matrix=mat)
-        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(),
-                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-        r = subprocess.run([sys.executable, os.path.join(HERE, "run_f32.py"), lib, fin, fout],
-                           env=env, capture_output=True, text=True, timeout=timeout)
-        if r.returncode != 0:
-            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
-                                 f"{r.stderr[-6000:]}")
-        d = np.load(fout)
-        T = np.asarray(E).shape[0]
-        return [{k: d[f"s{s}_{k}"] for k in ("sigma", "C", "z", "a", "iters", "status")}
-                for s in range(T)]
+    case = dict(depth=depth, lanes=lanes, w=w, n=n, E=np.asarray(E, np.float32), fiber=fib,
+                matrix=mat)
+    d, _ = _child("run_f32.py", lib, case, "address", timeout)
+    return [{k: d[f"s{s}_{k}"] for k in STEP_KEYS} for s in range(np.asarray(E).shape[0])]
 
 
 def run_linear(depth, w, n, C1, C2, gCbar, input_grads=False, sanitizer="address", timeout=900,
@@ -77,23 +75,10 @@ def run_linear(depth, w, n, C1, C2, gCbar, input_grads=False, sanitizer="address
     """Linear map and backward through the CPU build (run_linear.py); ori =
     (code, p, q, lam) for per-sample orientations (n is then not used)."""
     lib = B.build(sanitizer=sanitizer)
-    with tempfile.TemporaryDirectory() as td:
-        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
-        extra = {} if ori is None else dict(ori=ori[0], p=ori[1], q=ori[2], lam=ori[3])
-        np.savez(fin, depth=depth, w=w, n=n if n is not None else np.zeros(1), C1=C1, C2=C2,
-                 gCbar=gCbar, input_grads=int(input_grads), **extra)
-        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(sanitizer),
-                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
-                   TSAN_OPTIONS="halt_on_error=1:report_signal_unsafe=0",
-                   OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
-        r = subprocess.run([sys.executable, os.path.join(HERE, "run_linear.py"), lib, fin, fout],
-                           env=env, capture_output=True, text=True, timeout=timeout)
-        if r.returncode != 0:
-            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
-                                 f"{r.stderr[-6000:]}")
-        d = np.load(fout)
-        return {k: d[k] for k in d.files}
+    extra = {} if ori is None else dict(ori=ori[0], p=ori[1], q=ori[2], lam=ori[3])
+    case = dict(depth=depth, w=w, n=n if n is not None else np.zeros(1), C1=C1, C2=C2,
+                gCbar=gCbar, input_grads=int(input_grads), **extra)
+    return _child("run_linear.py", lib, case, sanitizer, timeout)[0]
 
 
 def run_adjoint(depth, w, n, E, g, fiber, matrix, opts=(1e-13, 50, 10, 1e-4, 0, 1),
@@ -102,19 +87,14 @@ def run_adjoint(depth, w, n, E, g, fiber, matrix, opts=(1e-13, 50, 10, 1e-4, 0, 
     (run_adjoint.py)."""
     lib = B.build(sanitizer=sanitizer)
     fib, mat = material_arrays(fiber, matrix)
-    with tempfile.TemporaryDirectory() as td:
-        fin, fout = os.path.join(td, "in.npz"), os.path.join(td, "out.npz")
-        np.savez(fin, depth=depth, w=w, n=n, E=E, g=g, opts=np.array(opts, dtype=np.float64),
-                 fiber=fib, matrix=mat)
-        env = dict(os.environ, LD_PRELOAD=B.asan_runtime(sanitizer),
-                   ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
-                   TSAN_OPTIONS="halt_on_error=1:report_signal_unsafe=0",
-                   OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
-        r = subprocess.run([sys.executable, os.path.join(HERE, "run_adjoint.py"), lib, fin, fout],
-                           env=env, capture_output=True, text=True, timeout=timeout)
-        if r.returncode != 0:
-            raise AssertionError(f"CPU-build run failed (exit {r.returncode}):\n"
-                                 f"{r.stderr[-6000:]}")
-        d = np.load(fout)
-        return {k: d[k] for k in d.files}
+    case = dict(depth=depth, w=w, n=n, E=E, g=g, opts=np.array(opts, dtype=np.float64),
+                fiber=fib, matrix=mat)
+    return _child("run_adjoint.py", lib, case, sanitizer, timeout)[0]
+
+
+def run_train(case, sanitizer="address", timeout=900):
+    """Training calls through the CPU build (run_train.py): the loss for
+    Cbar/target/p/q, the stiffness sampler for u/sprec, the optimiser step for
+    v/alpha/beta/gw/gn/state/step/stats0/amsgrad, whichever the case holds."""
+    lib = B.build(sanitizer=sanitizer)
+    return _child("run_train.py", lib, case, sanitizer, timeout)[0]

@@ -18,6 +18,8 @@ import synthetic as S
 from oracle import training as T
 from oracle.grad import normals_from_angles
 from oracle.linear import dmn_linear
+from training_cases import (chain_gradient, loss_case, special_points, update_case,
+                            update_reference)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,15 +42,6 @@ def rel(got, ref):
 
 def tt(x, dtype=torch.float64):
     return torch.tensor(np.asarray(x), dtype=dtype, device=dev())
-
-
-def loss_case(B, seed):
-    rs = S.streams(seed)
-    Tt = S.random_spd(rs["stiffness"], B)
-    Cb = Tt * (1.0 + 0.2 * rs["noise"].standard_normal(Tt.shape))
-    Cb[0] = Tt[0]                      # a sample without error
-    Cb[1, :3, :3] = Tt[1, :3, :3]      # zero differences on some components
-    return Cb, Tt
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
@@ -91,15 +84,6 @@ def test_training_loss_edge_cases():
     assert np.isnan(stats.cpu().numpy()[0]) and torch.isnan(g).all()
 
 
-def special_points(n, seed):
-    from scipy.stats import qmc
-    u = qmc.Sobol(d=8, scramble=True, seed=seed).random(n)
-    extra = np.array([[0.0] * 8, [1.0] * 8, [0.5, 0.5, 0.5, 0.5, 0.375, 0.0, 0.25, 0.1],
-                      [0.9, 0.1, 0.9, 0.2, 0.875, 1.0, 1.0, 0.9],
-                      [0.3, 0.7, 0.2, 0.6, 0.125, 1e-9, 0.5, 0.5]])
-    return np.concatenate([u, extra])
-
-
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 def test_sample_stiffness_matches_oracle(dtype, tol):
     from paper_2103_08253_amd import dmn_sample_stiffness
@@ -114,66 +98,41 @@ def test_sample_stiffness_matches_oracle(dtype, tol):
         assert rel(C2[b], r2) < tol, b
 
 
-def chain_gradient(v, alpha, beta, gw, gn, lam):
-    """dJ/d(v, alpha, beta) from gw, gn: Macaulay cut-off and penalty by complex
-    steps of the oracle's penalty, angle chain by complex steps of its normals."""
-    h = 1e-30
-    gv = np.zeros_like(v)
-    for i in range(len(v)):
-        vc = v.astype(complex)
-        vc[i] += 1j * h
-        gv[i] = np.imag(np.dot(gw, T.macaulay(vc)) + T.penalty(vc, lam)) / h
-    ga = np.imag(np.sum(gn * normals_from_angles(alpha + 1j * h, beta), axis=1)) / h
-    gb = np.imag(np.sum(gn * normals_from_angles(alpha, beta + 1j * h), axis=1)) / h
-    return gv, ga, gb
-
-
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 def test_training_update_matches_oracle(dtype, tol):
     from paper_2103_08253_amd import AmsgradOpts, TrainParams, dmn_training_update
     from paper_2103_08253_amd.training import new_stats
     K = 4
     NL, L = 2 ** K, 2 ** K - 1
-    NP = NL + 2 * L
-    rng = np.random.default_rng(17)
-    v = rng.uniform(-0.05, 0.15, NL)
-    alpha, beta = rng.uniform(0, 2 * np.pi, L), rng.uniform(0, 2 * np.pi, L)
-    gw, gn = rng.normal(0, 1e-2, NL), rng.normal(0, 1e-2, (L, 3))
-    m1 = rng.normal(0, 1e-3, (NP,))
-    m2 = rng.uniform(0, 1e-5, NP)
-    mx = m2 + rng.uniform(0, 1e-5, NP)
-    t0 = 7
-    opts = AmsgradOpts(lr_min=1e-3, lr_max=2e-2, lr_decay=0.99, half_period=5,
-                       steps_per_epoch=3, penalty=10.0)
+    c = update_case(17, K)
+    opts = AmsgradOpts(**c["opts"])
     say(f"training update K={K} {dtype}")
     # round the inputs once so both sides see the same values
     rd = lambda x: tt(x, dtype).double().cpu().numpy()
-    v, alpha, beta, gw, gn, m1, m2, mx = map(rd, (v, alpha, beta, gw, gn, m1, m2, mx))
+    for k in ("v", "alpha", "beta", "gw", "gn", "m1", "m2", "mx"):
+        c[k] = rd(c[k])
+    v, alpha, beta, t0 = c["v"], c["alpha"], c["beta"], c["t0"]
     P = TrainParams.create(tt(v, dtype), tt(alpha, dtype), tt(beta, dtype))
-    P.state.copy_(tt(np.stack([m1, m2, mx]), dtype))
+    P.state.copy_(tt(np.stack([c["m1"], c["m2"], c["mx"]]), dtype))
     P.step.fill_(t0)
     stats = new_stats(dev())
-    stats[0] = 0.125
-    dmn_training_update(P, tt(gw, dtype), tt(gn, dtype), opts, stats)
+    stats[0] = c["data"]
+    dmn_training_update(P, tt(c["gw"], dtype), tt(c["gn"], dtype), opts, stats)
     torch.cuda.synchronize()
-    gv, ga, gb = chain_gradient(v, alpha, beta, gw, gn, opts.penalty)
-    lr = T.learning_rate(t0 // opts.steps_per_epoch, opts.lr_min, opts.lr_max, opts.half_period,
-                         opts.lr_decay)
-    th, n1, n2, nx = T.amsgrad(np.concatenate([v, alpha, beta]), np.concatenate([gv, ga, gb]),
-                               m1, m2, mx, t0 + 1, lr, opts.beta1, opts.beta2, opts.eps)
+    ref = update_reference(c)
+    th, th0 = ref["theta"], np.concatenate([v, alpha, beta])
     got = np.concatenate([P.v.double().cpu().numpy(), P.alpha.double().cpu().numpy(),
                           P.beta.double().cpu().numpy()])
-    assert rel(got - np.concatenate([v, alpha, beta]),
-               th - np.concatenate([v, alpha, beta])) < 50 * tol
+    assert rel(got - th0, th - th0) < 50 * tol
     assert rel(got, th) < tol
-    assert rel(P.state.double().cpu().numpy(), np.stack([n1, n2, nx])) < tol
+    assert rel(P.state.double().cpu().numpy(), ref["state"]) < tol
     assert int(P.step.item()) == t0 + 1
     assert rel(P.w.double().cpu().numpy(), T.macaulay(th[:NL])) < tol
     assert rel(P.n.double().cpu().numpy(), normals_from_angles(th[NL:NL + L], th[NL + L:])) < tol
     st = stats.cpu().numpy()
-    pen = T.penalty(v, opts.penalty)
+    pen, lr = ref["penalty"], ref["lr"]
     assert abs(st[4] - pen) <= 1e-12 * max(pen, 1.0)
-    assert abs(st[3] - (0.125 + pen)) <= 1e-12 * (0.125 + pen)
+    assert abs(st[3] - (c["data"] + pen)) <= 1e-12 * (c["data"] + pen)
     assert abs(st[5] - lr) <= 1e-14 * lr
     assert abs(st[6] - np.sum(T.macaulay(v))) <= 1e-12
 

@@ -11,8 +11,11 @@ the (8, 3) split that the device build leaves out, orientation-interpolated
 normals, one call over groups of depths 1-9 (the mixed-depth launch, with
 depth-9 points split over two waves), FP32 state, the entry point without a
 workspace, the failure statuses, and the FP32-storage kernel instantiation
-that the device build also leaves out (tests/simt/fp32_kernel.cpp).  Results must match the oracle to the
-GPU parity bar (FP64 relative 1e-10, equal iterations and status)."""
+that the device build also leaves out (tests/simt/fp32_kernel.cpp); then the
+linear map and its backward, the path adjoint, and the training kernels
+(objective, stiffness sampler, optimiser step).  Results must match the
+oracle to the GPU parity bar (FP64 relative 1e-10, equal iterations and
+status; FP32 as its GPU test states)."""
 import os
 import shutil
 import sys
@@ -310,3 +313,77 @@ def test_simt_oriented_linear_map_and_backward(K, B, kind, dtype, tol):
         r = oriented_directional_derivative(K, net.w, net.p, net.q, kind, lam, C1, C2, G,
                                             vw, vp, vq)
         assert abs(got - r) <= tol * abs(r), (got, r)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 1e-4)])
+def test_simt_training_loss(dtype, tol):
+    """The objective's data term, per-sample errors and cotangent (the loss's
+    three kernels: per-sample norms, the one-workgroup reduction, the
+    cotangent) in the sanitised build against the oracle, for B = 37 over two
+    64-sample workgroups and p, q pairs away from 1."""
+    from oracle import training as T
+    from training_cases import loss_case
+    Cb, Tt = loss_case(37, 41)
+    Cb, Tt = Cb.astype(dtype), Tt.astype(dtype)
+    C64, T64 = Cb.astype(np.float64), Tt.astype(np.float64)
+    for p, q in [(1.0, 10.0), (1.5, 1.0)]:
+        out = harness().run_train(dict(Cbar=Cb, target=Tt, p=p, q=q))
+        e_ref = T.sample_errors(C64, T64, p)
+        assert rel(out["e"].astype(np.float64), e_ref) < tol
+        st = out["loss_stats"]
+        assert abs(st[0] - T.data_term(e_ref, q)) <= tol * T.data_term(e_ref, q)
+        assert abs(st[1] - e_ref.max()) <= tol * e_ref.max()
+        assert rel(out["gCbar"].astype(np.float64), T.data_cotangent(C64, T64, p, q)) < tol
+        assert np.all(out["gCbar"][0] == 0.0)
+
+
+def test_simt_sample_stiffness():
+    """The stiffness sampler in the sanitised build, both output precisions,
+    against the oracle at scrambled Sobol points and the corner cases."""
+    from oracle import training as T
+    from training_cases import special_points
+    u = special_points(64, 13)
+    for sprec, tol in [(0, 1e-12), (1, 1e-5)]:
+        out = harness().run_train(dict(u=u, sprec=sprec))
+        for b, x in enumerate(u):
+            r1, r2 = T.sample_stiffness(x)
+            assert rel(out["C1"][b].astype(np.float64), r1) < tol, b
+            assert rel(out["C2"][b].astype(np.float64), r2) < tol, b
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 1e-5)])
+def test_simt_training_update(dtype, tol):
+    """One optimiser step (gradient chain through the Macaulay weights, the
+    normal angles and the mixing penalty; AMSGrad; the learning-rate
+    schedule; refreshed weights and normals) in the sanitised build against
+    the oracle."""
+    from oracle import training as T
+    from oracle.grad import normals_from_angles
+    from training_cases import update_case, update_reference
+    K = 4
+    NL, L = 2 ** K, 2 ** K - 1
+    c = update_case(17, K)
+    for k in ("v", "alpha", "beta", "gw", "gn", "m1", "m2", "mx"):
+        c[k] = np.asarray(c[k], dtype).astype(np.float64)
+    o = c["opts"]
+    f = (lambda x: np.ascontiguousarray(x, dtype))
+    case = dict(v=f(c["v"]), alpha=f(c["alpha"]), beta=f(c["beta"]), gw=f(c["gw"]),
+                gn=f(c["gn"]), state=f(np.stack([c["m1"], c["m2"], c["mx"]])), step=c["t0"],
+                stats0=c["data"],
+                amsgrad=np.array([o["lr_min"], o["lr_max"], o["lr_decay"], o["half_period"],
+                                  o["steps_per_epoch"], o["beta1"], o["beta2"], o["eps"],
+                                  o["penalty"]]))
+    out = harness().run_train(case)
+    ref = update_reference(c)
+    th = ref["theta"]
+    got = np.concatenate([out[k].astype(np.float64) for k in ("v", "alpha", "beta")])
+    assert rel(got, th) < tol
+    assert rel(out["state"].astype(np.float64), ref["state"]) < tol
+    assert int(out["step"][0]) == c["t0"] + 1
+    assert rel(out["w"].astype(np.float64), T.macaulay(th[:NL])) < tol
+    assert rel(out["n"].astype(np.float64),
+               normals_from_angles(th[NL:NL + L], th[NL + L:])) < tol
+    st = out["update_stats"]
+    assert abs(st[4] - ref["penalty"]) <= 1e-12 * max(ref["penalty"], 1.0)
+    assert abs(st[3] - (c["data"] + ref["penalty"])) <= 1e-12 * (c["data"] + ref["penalty"])
+    assert abs(st[5] - ref["lr"]) <= 1e-14 * ref["lr"]
