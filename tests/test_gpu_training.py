@@ -19,7 +19,7 @@ from oracle import training as T
 from oracle.grad import normals_from_angles
 from oracle.linear import dmn_linear
 from training_cases import (chain_gradient, loss_case, special_points, update_case,
-                            update_reference)
+                            update_reference, weight_chain)
 
 pytestmark = pytest.mark.gpu
 
@@ -177,7 +177,13 @@ def test_training_step_gradient_matches_complex_step():
     g_gpu = d * eps / (lr - np.abs(d))
     ref = T.objective_gradient(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
     g_ref = np.concatenate([ref["gv"], ref["galpha"], ref["gbeta"]])
-    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    # the batch gradient itself, chained on the host through the oracle's
+    # Macaulay bracket, penalty and normals
+    g_dir = np.concatenate(chain_gradient(v, alpha, beta, gw.cpu().numpy(), gn.cpu().numpy(),
+                                          lam))
+    say(f"   gradient rel err {rel(g_dir, g_ref):.2e} (chained), "
+        f"{rel(g_gpu, g_ref):.2e} (from the update)")
+    assert rel(g_dir, g_ref) < 1e-10
     assert rel(g_gpu, g_ref) < 1e-8
     J = T.objective(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
     assert abs(stats.cpu().numpy()[3] - J) <= 1e-10 * J
@@ -392,7 +398,13 @@ def test_training_step_with_dead_subtree_matches_complex_step():
     g_gpu = d * eps / (lr - np.abs(d))
     ref = T.objective_gradient(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
     g_ref = np.concatenate([ref["gv"], ref["galpha"], ref["gbeta"]])
-    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    # the batch gradient itself, chained on the host through the oracle's
+    # Macaulay bracket, penalty and normals
+    g_dir = np.concatenate(chain_gradient(v, alpha, beta, gw.cpu().numpy(), gn.cpu().numpy(),
+                                          lam))
+    say(f"   gradient rel err {rel(g_dir, g_ref):.2e} (chained), "
+        f"{rel(g_gpu, g_ref):.2e} (from the update)")
+    assert rel(g_dir, g_ref) < 1e-10
     assert rel(g_gpu, g_ref) < 1e-8
     J = T.objective(K, v, alpha, beta, C1, C2, Tt, 1.0, 10.0, lam)
     assert abs(stats.cpu().numpy()[3] - J) <= 1e-10 * J
@@ -574,7 +586,12 @@ def test_oriented_training_step_gradient_matches_complex_step(dead):
     g_gpu = d * eps / (lr - np.abs(d))
     ref = T.objective_oriented_gradient(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
     g_ref = np.concatenate([ref["gv"], ref["gP"].ravel(), ref["gQ"].ravel()])
-    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    g_dir = np.concatenate([weight_chain(v, g.gw.cpu().numpy(), lam_pen),
+                            g.gpq.cpu().numpy()[:, 0, :].ravel(),
+                            g.gpq.cpu().numpy()[:, 1, :].ravel()])
+    say(f"   gradient rel err {rel(g_dir, g_ref):.2e} (chained), "
+        f"{rel(g_gpu, g_ref):.2e} (from the update)")
+    assert rel(g_dir, g_ref) < 1e-10
     assert rel(g_gpu, g_ref) < 1e-8
     J = T.objective_oriented(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
     assert abs(g.stats.cpu().numpy()[3] - J) <= 1e-10 * J
@@ -640,7 +657,12 @@ def test_oriented_training_step_with_empty_groups():
     g_gpu = d * eps / (lr - np.abs(d))
     ref = T.objective_oriented_gradient(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
     g_ref = np.concatenate([ref["gv"], ref["gP"].ravel(), ref["gQ"].ravel()])
-    say(f"   gradient rel err {rel(g_gpu, g_ref):.2e}")
+    g_dir = np.concatenate([weight_chain(v, g.gw.cpu().numpy(), lam_pen),
+                            g.gpq.cpu().numpy()[:, 0, :].ravel(),
+                            g.gpq.cpu().numpy()[:, 1, :].ravel()])
+    say(f"   gradient rel err {rel(g_dir, g_ref):.2e} (chained), "
+        f"{rel(g_gpu, g_ref):.2e} (from the update)")
+    assert rel(g_dir, g_ref) < 1e-10
     assert rel(g_gpu, g_ref) < 1e-8
 
 

@@ -30,15 +30,23 @@ def special_points(n, seed):
     return np.concatenate([u, extra])
 
 
-def chain_gradient(v, alpha, beta, gw, gn, lam):
-    """dJ/d(v, alpha, beta) from gw, gn: Macaulay cut-off and penalty by complex
-    steps of the oracle's penalty, angle chain by complex steps of its normals."""
+def weight_chain(v, gw, lam):
+    """dJ/dv from the weight cotangent gw: Macaulay cut-off and mixing penalty
+    by complex steps of the oracle's functions."""
     h = 1e-30
     gv = np.zeros_like(v)
     for i in range(len(v)):
         vc = v.astype(complex)
         vc[i] += 1j * h
         gv[i] = np.imag(np.dot(gw, T.macaulay(vc)) + T.penalty(vc, lam)) / h
+    return gv
+
+
+def chain_gradient(v, alpha, beta, gw, gn, lam):
+    """dJ/d(v, alpha, beta) from gw, gn: the weight chain (weight_chain) and
+    the angle chain by complex steps of the oracle's normals."""
+    h = 1e-30
+    gv = weight_chain(v, gw, lam)
     ga = np.imag(np.sum(gn * normals_from_angles(alpha + 1j * h, beta), axis=1)) / h
     gb = np.imag(np.sum(gn * normals_from_angles(alpha, beta + 1j * h), axis=1)) / h
     return gv, ga, gb
