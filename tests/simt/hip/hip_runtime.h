@@ -115,8 +115,12 @@ struct Tls {
   int lane = 0;
   unsigned exchanges = 0;  // cross-lane operations this thread has taken part in
 };
+// Initial-exec TLS (a few dozen bytes of the static TLS reserve): no
+// __tls_get_addr calls, whose ThreadSanitizer interceptor fails on the
+// dynamic TLS of a dlopen'ed library once a launch creates a few hundred
+// threads.
 inline Tls& tls() {
-  static thread_local Tls t;
+  static thread_local Tls t __attribute__((tls_model("initial-exec")));
   return t;
 }
 

@@ -246,19 +246,23 @@ def test_simt_linear_no_race_between_lanes():
     check_linear(5, tw, G, out, 1e-10)
 
 
-@pytest.mark.parametrize("K,P,T,every", [(3, 3, 4, True), (5, 4, 3, False)])
-def test_simt_path_adjoint(K, P, T, every):
+@pytest.mark.parametrize("K,P,T,every,sanitizer", [(3, 3, 4, True, "address"),
+                                                   (5, 4, 3, False, "address"),
+                                                   (3, 2, 3, False, "thread")])
+def test_simt_path_adjoint(K, P, T, every, sanitizer):
     """The path gradient of J = sum_p g_p . sigma_p(final): forward path with
     the tight tolerance and one polishing step, then dmn_update_adjoint swept
     backwards over the steps, in the sanitised build, against the oracle's
     complex-step path derivative along unit directions (every parameter at
-    depth 3; weights and both angles of a few laminates at depth 5)."""
+    depth 3; weights and both angles of a few laminates at depth 5); under
+    ThreadSanitizer too (the per-wave partial sums and their reduction)."""
     from oracle.adjoint import path_directional_derivative
     rs = S.streams(400 + K)
     net = S.random_dmn(rs["dmn"], K, 0.25)
     E = S.ramp_with_noise(rs, P, T, 0.02, 1e-3)
     g = S.unit_directions(rs["cotangent"], P)
-    out = harness().run_adjoint(K, net.w, net.normals, E, g, S.FIBER, S.MATRIX)
+    out = harness().run_adjoint(K, net.w, net.normals, E, g, S.FIBER, S.MATRIX,
+                                sanitizer=sanitizer)
     assert not np.any(out["err"])
     alpha, beta = S.normals_to_angles(net.normals)
     gn = out["gn"]
@@ -387,3 +391,33 @@ def test_simt_training_update(dtype, tol):
     assert abs(st[4] - ref["penalty"]) <= 1e-12 * max(ref["penalty"], 1.0)
     assert abs(st[3] - (c["data"] + ref["penalty"])) <= 1e-12 * (c["data"] + ref["penalty"])
     assert abs(st[5] - ref["lr"]) <= 1e-14 * ref["lr"]
+
+
+def test_simt_training_no_race_between_lanes():
+    """The objective (per-sample norms, the one-workgroup reduction, the
+    cotangent), the stiffness sampler and the optimiser step (its workgroup
+    reductions of the penalty and the weight sum) in one run under
+    ThreadSanitizer; results as in the sanitised build."""
+    from oracle import training as T
+    from training_cases import loss_case, special_points, update_case, update_reference
+    Cb, Tt = loss_case(37, 41)
+    u = special_points(16, 13)
+    c = update_case(17, 4)
+    o = c["opts"]
+    case = dict(Cbar=Cb, target=Tt, p=1.5, q=3.0, u=u, sprec=0, v=c["v"], alpha=c["alpha"],
+                beta=c["beta"], gw=c["gw"], gn=c["gn"],
+                state=np.stack([c["m1"], c["m2"], c["mx"]]), step=c["t0"], stats0=c["data"],
+                amsgrad=np.array([o["lr_min"], o["lr_max"], o["lr_decay"], o["half_period"],
+                                  o["steps_per_epoch"], o["beta1"], o["beta2"], o["eps"],
+                                  o["penalty"]]))
+    out = harness().run_train(case, sanitizer="thread")
+    assert rel(out["gCbar"], T.data_cotangent(Cb, Tt, 1.5, 3.0)) < 1e-10
+    assert abs(out["loss_stats"][0] - T.data_term(T.sample_errors(Cb, Tt, 1.5), 3.0)) <= \
+        1e-10 * out["loss_stats"][0]
+    for b, x in enumerate(u):
+        r1, r2 = T.sample_stiffness(x)
+        assert rel(out["C1"][b], r1) < 1e-12 and rel(out["C2"][b], r2) < 1e-12, b
+    ref = update_reference(c)
+    got = np.concatenate([out[k] for k in ("v", "alpha", "beta")])
+    assert rel(got, ref["theta"]) < 1e-12
+    assert rel(out["state"], ref["state"]) < 1e-12
