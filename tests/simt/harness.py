@@ -98,3 +98,10 @@ def run_train(case, sanitizer="address", timeout=900):
     v/alpha/beta/gw/gn/state/step/stats0/amsgrad, whichever the case holds."""
     lib = B.build(sanitizer=sanitizer)
     return _child("run_train.py", lib, case, sanitizer, timeout)[0]
+
+
+def run_oriented_train(case, sanitizer="address", timeout=900):
+    """One orientation-grouped training step through the CPU build
+    (run_oriented_train.py)."""
+    lib = B.build(sanitizer=sanitizer)
+    return _child("run_oriented_train.py", lib, case, sanitizer, timeout)[0]

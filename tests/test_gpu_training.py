@@ -18,8 +18,8 @@ import synthetic as S
 from oracle import training as T
 from oracle.grad import normals_from_angles
 from oracle.linear import dmn_linear
-from training_cases import (chain_gradient, loss_case, special_points, update_case,
-                            update_reference, weight_chain)
+from training_cases import (chain_gradient, loss_case, oriented_case, special_points,
+                            update_case, update_reference, weight_chain)
 
 pytestmark = pytest.mark.gpu
 
@@ -540,27 +540,6 @@ def test_orientation_group_normals_and_chain(kind):
     got = gpq.cpu().numpy()
     assert rel(got[:, 0, :], gp_ref) < 1e-12
     assert rel(got[:, 1, :], gq_ref) < 1e-12
-
-
-def oriented_case(K, B, kind, seed, level=0):
-    from oracle.orientation import oriented_linear
-    rs = S.streams(seed)
-    lam_g = S.orientation_discretization(level)
-    G = len(lam_g)
-    group = np.arange(B) % G
-    order = np.argsort(group, kind="stable")
-    offsets = np.concatenate([[0], np.cumsum(np.bincount(group, minlength=G))])
-    C1 = S.random_spd(rs["stiffness"], B)[order]
-    C2 = S.random_spd(rs["stiffness"], B)[order]
-    lam_s = lam_g[group[order]]
-    truth = S.interpolated_dmn(rs["ground_truth"], K, 0.25, kind)
-    Tt = oriented_linear(K, truth.w, truth.p, truth.q, kind, lam_s, C1, C2)
-    M = S.SHAPE_COUNTS[kind]
-    v = rs["init"].uniform(0.0, 1.0, 2 ** K)
-    v = v / v.sum()
-    p = rs["init"].uniform(0.0, 2 * np.pi, (2 ** K - 1, M))
-    q = rs["init"].uniform(0.0, 2 * np.pi, (2 ** K - 1, M))
-    return C1, C2, Tt, lam_g, lam_s, offsets, v, p, q
 
 
 @pytest.mark.parametrize("dead", [False, True])

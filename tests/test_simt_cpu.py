@@ -12,8 +12,9 @@ normals, one call over groups of depths 1-9 (the mixed-depth launch, with
 depth-9 points split over two waves), FP32 state, the entry point without a
 workspace, the failure statuses, and the FP32-storage kernel instantiation
 that the device build also leaves out (tests/simt/fp32_kernel.cpp); then the
-linear map and its backward, the path adjoint, and the training kernels
-(objective, stiffness sampler, optimiser step).  Results must match the
+linear map and its backward, the path adjoint, the training kernels
+(objective, stiffness sampler, optimiser step) and a training step over a
+batch grouped by orientation.  Results must match the
 oracle to the GPU parity bar (FP64 relative 1e-10, equal iterations and
 status; FP32 as its GPU test states)."""
 import os
@@ -421,3 +422,47 @@ def test_simt_training_no_race_between_lanes():
     got = np.concatenate([out[k] for k in ("v", "alpha", "beta")])
     assert rel(got, ref["theta"]) < 1e-12
     assert rel(out["state"], ref["state"]) < 1e-12
+
+
+@pytest.mark.parametrize("kind,dead,dtype", [("trilinear", False, np.float64),
+                                             ("quadratic", True, np.float64),
+                                             ("linear", False, np.float32)])
+def test_simt_oriented_training_step(kind, dead, dtype):
+    """One training step of an orientation-interpolated DMN over a batch
+    grouped by orientation (the groups' normals, the grouped linear map and
+    VJP, the chain to the angle coefficients, the optimiser step) in the
+    sanitised build: the batch gradient, chained through the oracle's Macaulay
+    bracket and penalty, against the oracle's complex-step objective gradient,
+    and the objective; FP32 at its bar."""
+    from oracle import training as T
+    from training_cases import oriented_case, weight_chain
+    K, B, lam_pen = 3, 16, 10.0
+    C1, C2, Tt, lam_g, lam_s, offsets, v, p, q = oriented_case(K, B, kind, 92)
+    if dead:
+        v[2], v[3] = -0.01, -0.02
+    f = (lambda x: np.ascontiguousarray(x, dtype))
+    r = (lambda x: np.asarray(x, dtype).astype(np.float64))
+    v, p, q, C1, C2, Tt, lam_g = map(r, (v, p, q, C1, C2, Tt, lam_g))
+    lam_s = lam_g[np.repeat(np.arange(len(lam_g)), np.diff(offsets))]
+    code = {"linear": 1, "trilinear": 2, "quadratic": 3}[kind]
+    case = dict(ori=code, v=f(v), p=f(p), q=f(q), lam=f(lam_g), offsets=offsets, C1=f(C1),
+                C2=f(C2), target=f(Tt), p_norm=1.0, q_norm=10.0,
+                amsgrad=np.array([1e-3, 1e-2, 0.999, 50, 1, 0.9, 0.999, 1e-8, lam_pen]))
+    out = harness().run_oriented_train(case)
+    assert list(out["err"]) == [0, 0]
+    ref = T.objective_oriented_gradient(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
+    g_ref = np.concatenate([ref["gv"], ref["gP"].ravel(), ref["gQ"].ravel()])
+    gpq = out["gpq"].astype(np.float64)
+    g = np.concatenate([weight_chain(v, out["gw"].astype(np.float64), lam_pen),
+                        gpq[:, 0, :].ravel(), gpq[:, 1, :].ravel()])
+    tol = 1e-10 if dtype == np.float64 else 1e-4
+    assert rel(g, g_ref) < tol
+    J = T.objective_oriented(K, v, p, q, kind, lam_s, C1, C2, Tt, 1.0, 10.0, lam_pen)
+    assert abs(out["stats"][3] - J) <= tol * J
+    assert int(out["step"][0]) == 1
+    # the update: the oracle's AMSGrad step (first step, zero state) on its gradient
+    lr = T.learning_rate(0, 1e-3, 1e-2, 50, 0.999)
+    th, *_ = T.amsgrad(np.concatenate([v, p.ravel(), q.ravel()]), g_ref, *([np.zeros(len(g_ref))]
+                                                                           * 3), 1, lr)
+    got = np.concatenate([out[k].astype(np.float64).ravel() for k in ("v", "p", "q")])
+    assert rel(got, th) < tol

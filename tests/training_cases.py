@@ -82,3 +82,27 @@ def update_reference(c):
                                c["t0"] + 1, lr, o["beta1"], o["beta2"], o["eps"])
     return dict(theta=th, state=np.stack([n1, n2, nx]), lr=lr,
                 penalty=T.penalty(c["v"], o["penalty"]))
+
+
+def oriented_case(K, B, kind, seed, level=0):
+    """A batch of B samples grouped by orientation (level of the orientation
+    discretization), targets from a ground-truth interpolated DMN, and an
+    initial (v, p, q)."""
+    from oracle.orientation import oriented_linear
+    rs = S.streams(seed)
+    lam_g = S.orientation_discretization(level)
+    G = len(lam_g)
+    group = np.arange(B) % G
+    order = np.argsort(group, kind="stable")
+    offsets = np.concatenate([[0], np.cumsum(np.bincount(group, minlength=G))])
+    C1 = S.random_spd(rs["stiffness"], B)[order]
+    C2 = S.random_spd(rs["stiffness"], B)[order]
+    lam_s = lam_g[group[order]]
+    truth = S.interpolated_dmn(rs["ground_truth"], K, 0.25, kind)
+    Tt = oriented_linear(K, truth.w, truth.p, truth.q, kind, lam_s, C1, C2)
+    M = S.SHAPE_COUNTS[kind]
+    v = rs["init"].uniform(0.0, 1.0, 2 ** K)
+    v = v / v.sum()
+    p = rs["init"].uniform(0.0, 2 * np.pi, (2 ** K - 1, M))
+    q = rs["init"].uniform(0.0, 2 * np.pi, (2 ** K - 1, M))
+    return C1, C2, Tt, lam_g, lam_s, offsets, v, p, q
