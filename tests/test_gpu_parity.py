@@ -125,6 +125,55 @@ def test_gp_depth8_production_size_sampled():
     say(f"  plastic matrix-leaf fraction at the last step: {plastic:.3f}")
 
 
+def test_gp_depth8_state_offsets_beyond_32_bits():
+    """Maximum size: depth 8 with 2,818,048 points (43 copies of the
+    production workload's 65,536), so the element offsets of the last
+    points' internal variables and jumps pass 2^31 (about 75 GB of state in
+    HBM).  A large first increment (the path's tenth strain from the initial
+    state), then its eleventh: every copy's outputs equal the first copy's
+    bit for bit, and points of the last copy match the oracle."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    d = dev()
+    wl = S.config1()
+    net = wl.nets[0]
+    P0, reps = wl.n_points, 43
+    P = P0 * reps
+    M, L = 2 ** (net.depth - 1), 2 ** net.depth - 1
+    assert (P - 1) * M * 7 >= 2 ** 31 and (P - 1) * L * 3 >= 2 ** 31
+    torch.cuda.empty_cache()
+    need = P * (2 * M * 7 + 2 * L * 3 + 6 + 6 + 36) * 8
+    if torch.cuda.mem_get_info()[0] < need + (4 << 30):
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of free device memory")
+    say(f"case: gp depth 8, {P} points ({reps} copies of {P0}) x 2 steps, "
+        f"{need / 2 ** 30:.0f} GiB")
+    E2 = wl.E[[9, 10]]
+    picks = S.streams(1)["picks"].choice(P0, 3, replace=False)
+    last = (reps - 1) * P0 + picks
+    g = PointGroup.allocate(torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d),
+                            torch.tensor(E2[0], device=d).repeat(reps, 1))
+    gpu, ws = [], None
+    for step in range(2):
+        g.E.copy_(torch.tensor(E2[step], device=d).repeat(reps, 1))
+        ws = dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws)
+        torch.cuda.synchronize()
+        for name in ("sigma", "tangent", "z_out", "a_out", "iters", "status"):
+            t = getattr(g, name)
+            if t.dtype == torch.float64:
+                t = t.view(torch.int64)  # bit patterns: a failed point's NaN tangent too
+            t = t.view(reps, P0, -1)
+            assert torch.equal(t, t[:1].expand_as(t)), (step, name)
+        st = g.status.cpu().numpy()
+        say(f"  step {step}: copies equal; status counts {np.unique(st, return_counts=True)}, "
+            f"mean iterations {g.iters.double().mean().item():.2f}")
+        gpu.append(dict(sigma=g.sigma[last].cpu().numpy(), C=g.tangent[last].cpu().numpy(),
+                        z=g.z_out[last].cpu().numpy(), a=g.a_out[last].cpu().numpy(),
+                        iters=g.iters[last].cpu().numpy(), status=st[last]))
+        g.advance()
+    del g, ws
+    torch.cuda.empty_cache()
+    compare_paths(net, E2[:, picks, :], range(len(picks)), gpu)
+
+
 def test_gp_mixed_batch_full_size_sampled(tmp_path):
     """The mixed-depth batch at its full size (131,072 points over 16 DMNs of
     depths 5-9, 20 steps) in the launch configuration the bench times: tuned
