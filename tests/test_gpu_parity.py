@@ -557,6 +557,57 @@ def test_linear_backward_tree_reduction_vs_complex_step():
     assert ew <= RTOL and ea <= RTOL
 
 
+def test_linear_offsets_beyond_32_bits():
+    """Maximum size: the depth-8 linear map and its backward over 59,801,600
+    samples (14,600 copies of a 4,096-sample batch, 69 GB), so the element
+    offsets of the last samples' stiffnesses pass 2^31.  Every copy's Cbar
+    equals the first copy's bit for bit, sampled outputs of the last copy
+    match the oracle, and the batch gradient equals 14,600 times the single
+    batch's within rounding of the sum."""
+    from paper_2103_08253_amd import dmn_homogenize_backward, dmn_homogenize_linear
+    d = dev()
+    K, B0, reps = 8, 4096, 14600
+    B = B0 * reps
+    assert (B - 1) * 36 >= 2 ** 31
+    torch.cuda.empty_cache()
+    need = 4 * B * 36 * 8
+    if torch.cuda.mem_get_info()[0] < need + (4 << 30):
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of free device memory")
+    say(f"case: linear map and backward depth {K}, {B} samples ({reps} copies of {B0}), "
+        f"{need / 2 ** 30:.0f} GiB")
+    rs = S.streams(61)
+    net = S.random_dmn(rs["dmn"], K, 0.25)
+    C1s, C2s = S.random_spd(rs["stiffness"], B0), S.random_spd(rs["stiffness"], B0)
+    Gs = rs["cotangent"].standard_normal((B0, 6, 6))
+    w, n = torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d)
+    small = [torch.tensor(x, device=d) for x in (C1s, C2s, Gs)]
+    gw0, gn0, _, _, _ = dmn_homogenize_backward(w, n, *small)
+    C1, C2, G = (x.repeat(reps, 1, 1) for x in small)
+    del small
+    Cbar, ws = dmn_homogenize_linear(w, n, C1, C2)
+    torch.cuda.synchronize()
+    from paper_2103_08253_amd import error_word
+    assert error_word(ws) == 0
+    bits = Cbar.view(torch.int64).view(reps, B0, -1)
+    assert torch.equal(bits, bits[:1].expand_as(bits))
+    picks = np.array([0, 1777, B0 - 1])
+    got = Cbar[(reps - 1) * B0 + picks].cpu().numpy()
+    del Cbar, ws, bits
+    ref = dmn_linear(K, net.w, net.normals, C1s[picks], C2s[picks])
+    e_map = rel(got, ref)
+    gw, gn, _, _, wsb = dmn_homogenize_backward(w, n, C1, C2, G)
+    torch.cuda.synchronize()
+    assert error_word(wsb) == 0
+    del C1, C2, G, wsb
+    torch.cuda.empty_cache()
+    e_w = rel(gw.cpu().numpy(), reps * gw0.cpu().numpy())
+    e_n = rel(gn.cpu().numpy(), reps * gn0.cpu().numpy())
+    say(f"  map rel err {e_map:.2e}; batch gradient vs {reps} x one batch: gw {e_w:.2e}, "
+        f"gn {e_n:.2e}")
+    assert e_map <= RTOL
+    assert e_w <= 1e-12 and e_n <= 1e-12
+
+
 def test_linear_backward_finite_differences_and_f32():
     from paper_2103_08253_amd import dmn_homogenize_backward, dmn_homogenize_linear
     say("case: linear backward depth 8 batch 4096: FD h=1e-6 and FP32")
