@@ -291,3 +291,59 @@ def test_adjoint_with_dead_subtrees_matches_compressed_path():
                                           vb, compressed=True)
         say(f"   direction {trial}: gpu {got:.12e} oracle {ref:.12e}")
         assert abs(got - ref) <= 1e-9 * max(abs(ref), 1e-3)
+
+
+def test_adjoint_state_offsets_beyond_32_bits():
+    """Maximum size: the step adjoint over 2,818,048 depth-8 points (43 copies
+    of the production points after one converged load step from the initial
+    state; about 115 GB of state and cotangents), so the element offsets of
+    the last points' internal variables pass 2^31.  Every copy's state
+    cotangent equals that of a call on the first copy alone bit for bit, and
+    the accumulated parameter gradient equals 43 times that call's within
+    rounding of the sum."""
+    from paper_2103_08253_amd import (AdjointGroup, PointGroup, dmn_update_adjoint,
+                                      dmn_update_gauss_points)
+    d = dev()
+    wl = S.config1()
+    net = wl.nets[0]
+    P0, reps = wl.n_points, 43
+    P = P0 * reps
+    M, L = 2 ** (net.depth - 1), 2 ** net.depth - 1
+    assert (P - 1) * M * 7 >= 2 ** 31
+    torch.cuda.empty_cache()
+    need = P * (4 * M * 7 + 2 * L * 3 + 6 + 6 + 6 + 36) * 8
+    if torch.cuda.mem_get_info()[0] < need + (8 << 30):
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of free device memory")
+    say(f"case: step adjoint depth 8, {P} points ({reps} copies of {P0}), "
+        f"{need / 2 ** 30:.0f} GiB")
+    w, n = torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d)
+    E0 = torch.tensor(wl.E[9], device=d)
+    rs = S.streams(62)
+    gs0 = torch.tensor(S.unit_directions(rs["cotangent"], P0), device=d)
+    zn0 = torch.tensor(rs["cotangent"].standard_normal((P0, M, 7)) * 1e-3, device=d)
+
+    def step_and_adjoint(copies):
+        g = PointGroup.allocate(w, n, E0.repeat(copies, 1))
+        dmn_update_gauss_points([g], S.FIBER, S.MATRIX, tol=1e-13, max_iter=50, polish=1)
+        assert bool((g.status == 0).all())
+        a_conv, z_in = g.a_out, g.z_in
+        del g
+        ag = AdjointGroup(w, n, E0.repeat(copies, 1), z_in, a_conv, gs0.repeat(copies, 1),
+                          zn0.repeat(copies, 1, 1), torch.empty_like(z_in),
+                          torch.zeros_like(w), torch.zeros_like(n))
+        dmn_update_adjoint([ag], S.FIBER, S.MATRIX)
+        torch.cuda.synchronize()
+        return ag.g_z_prev, ag.gw, ag.gn
+
+    zp1, gw1, gn1 = step_and_adjoint(1)
+    zp, gw, gn = step_and_adjoint(reps)
+    bits = zp.view(torch.int64).view(reps, P0, -1)
+    assert torch.equal(bits, zp1.view(torch.int64).view(1, P0, -1).expand_as(bits))
+    del zp, bits
+    torch.cuda.empty_cache()
+    scale = lambda x: np.abs(x).max()
+    e_w = np.abs(gw.cpu().numpy() - reps * gw1.cpu().numpy()).max() / scale(reps * gw1.cpu().numpy())
+    e_n = np.abs(gn.cpu().numpy() - reps * gn1.cpu().numpy()).max() / scale(reps * gn1.cpu().numpy())
+    say(f"  state cotangents of every copy bit-identical; gradient vs {reps} x one copy: "
+        f"gw {e_w:.2e}, gn {e_n:.2e}")
+    assert e_w <= 1e-12 and e_n <= 1e-12
