@@ -174,6 +174,68 @@ def test_gp_depth8_state_offsets_beyond_32_bits():
     compare_paths(net, E2[:, picks, :], range(len(picks)), gpu)
 
 
+def test_gp_mixed_launch_offsets_beyond_32_bits():
+    """Maximum size for the mixed-depth launch: a depth-9 group of 1,441,792
+    points (44 copies of 32,768; each point split over the two waves of a
+    workgroup) with a depth-5 group in the same call, so the element offsets
+    of the last depth-9 points' internal variables and jumps pass 2^31
+    (about 77 GB).  Two steps; every copy's outputs equal those of the same
+    call with one copy, bit for bit (that call's points are held to the
+    oracle by the mixed-launch parity tests)."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    d = dev()
+    P0, reps = 32768, 44
+    P = P0 * reps
+    M, L = 2 ** 8, 2 ** 9 - 1
+    assert (P - 1) * M * 7 >= 2 ** 31 and (P - 1) * L * 3 >= 2 ** 31
+    torch.cuda.empty_cache()
+    need = P * (2 * M * 7 + 2 * L * 3 + 6 + 6 + 36) * 8
+    if torch.cuda.mem_get_info()[0] < need + (4 << 30):
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of free device memory")
+    say(f"case: mixed launch, depth 9 with {P} points ({reps} copies of {P0}) + depth 5, "
+        f"x 2 steps, {need / 2 ** 30:.0f} GiB")
+    rs = S.streams(63)
+    net9, net5 = S.random_dmn(rs["dmn"], 9, 0.25), S.random_dmn(rs["dmn"], 5, 0.3)
+    E9 = torch.tensor(S.ramp_with_noise(rs, P0, 11, 0.015, 1e-3)[[9, 10]], device=d)
+    E5 = torch.tensor(S.ramp_with_noise(rs, 333, 2, 0.02, 1e-3), device=d)
+
+    def run(copies):
+        g9 = PointGroup.allocate(torch.tensor(net9.w, device=d),
+                                 torch.tensor(net9.normals, device=d), E9[0].repeat(copies, 1))
+        g5 = PointGroup.allocate(torch.tensor(net5.w, device=d),
+                                 torch.tensor(net5.normals, device=d), E5[0].clone())
+        for step in range(2):
+            g9.E.copy_(E9[step].repeat(copies, 1))
+            g5.E.copy_(E5[step])
+            dmn_update_gauss_points([g9, g5], S.FIBER, S.MATRIX)
+            torch.cuda.synchronize()
+            yield g9, g5
+            g9.advance()
+            g5.advance()
+
+    one = []
+    for g9, g5 in run(1):
+        one.append({k: getattr(g9, k).clone() for k in
+                    ("sigma", "tangent", "z_out", "a_out", "iters", "status")})
+        one[-1]["g5"] = {k: getattr(g5, k).clone() for k in ("sigma", "tangent", "z_out")}
+    for step, (g9, g5) in enumerate(run(reps)):
+        for name in ("sigma", "tangent", "z_out", "a_out", "iters", "status"):
+            t, r = getattr(g9, name), one[step][name]
+            if t.dtype == torch.float64:
+                t, r = t.view(torch.int64), r.view(torch.int64)
+            t = t.view(reps, P0, -1)
+            assert torch.equal(t, r.view(1, P0, -1).expand_as(t)), (step, name)
+        for name in ("sigma", "tangent", "z_out"):
+            assert torch.equal(getattr(g5, name).view(torch.int64),
+                               one[step]["g5"][name].view(torch.int64)), (step, name)
+        st = g9.status.cpu().numpy()
+        say(f"  step {step}: every copy equals the one-copy call; status counts "
+            f"{np.unique(st, return_counts=True)}, mean iterations "
+            f"{g9.iters.double().mean().item():.2f}")
+    del one
+    torch.cuda.empty_cache()
+
+
 def test_gp_mixed_batch_full_size_sampled(tmp_path):
     """The mixed-depth batch at its full size (131,072 points over 16 DMNs of
     depths 5-9, 20 steps) in the launch configuration the bench times: tuned
