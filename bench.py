@@ -405,6 +405,56 @@ def extras(args, dev, g, E_path, gp_step, reset_state, B, C1, C2, Gc, wt, nt, tu
         all_converged=bool((go.status == 0).all().item()),
         fixed_normals_ms_same_step=batched_ms)
 
+    # tree compression (Sec. 3.1): the same load step with about a third of the
+    # laminates removed by zero leaf weights (the paper's compressed network keeps
+    # 513 of 765 jump unknowns: 171 of 255 laminates), the dead leaves either
+    # scattered (one leaf of a live pair) or whole 4-leaf subtrees (one lane's
+    # subtree each); the kernel evaluates dead rows in place, so only live work
+    # is credited in the rate below
+    from paper_2103_08253_amd.roofline import gp_update_flops_live, live_tree_counts
+
+    def live_tflops(counts, iters, ms):
+        it = iters.double()
+        tot = it.sum().item()
+        per_eval = gp_update_flops_live(*counts, 0)
+        desc = gp_update_flops_live(*counts, 1) - 2 * per_eval  # top-down flops per step
+        return ((tot + iters.numel()) * per_eval + tot * desc) / (ms * 1e-3) / 1e12
+
+    w_full = g.w.cpu().numpy()
+    comp = dict(load_step=10, points=P, target_live_laminates=171,
+                full=dict(live_laminates=255, ms=batched_ms,
+                          mean_iters=g.iters.double().mean().item(),
+                          live_credited_tflops=live_tflops(live_tree_counts(w_full), g.iters,
+                                                           batched_ms)))
+    rng_c = np.random.default_rng(11)
+    for pattern in ("scattered_leaves", "dead_lane_subtrees"):
+        wc = w_full.copy()
+        while live_tree_counts(wc)[0] > 171:
+            if pattern == "scattered_leaves":
+                j = int(rng_c.integers(0, len(wc)))
+                if wc[j ^ 1] > 0:
+                    wc[j] = 0.0
+            else:
+                b = 4 * int(rng_c.integers(0, len(wc) // 4))
+                wc[b:b + 4] = 0.0
+        counts = live_tree_counts(wc)
+        gc = PointGroup.allocate(torch.tensor(wc, device=dev), g.n, E_path[0].clone())
+        ws_c = None
+        for k in range(10):
+            gc.E = E_path[k]
+            ws_c = dmn_update_gauss_points([gc], S.FIBER, S.MATRIX, ws=ws_c)
+            gc.advance()
+        gc.E = E_path[10]
+        ms_c = _event_ms(lambda: dmn_update_gauss_points([gc], S.FIBER, S.MATRIX, ws=ws_c), 3) / 3
+        lanes_dead = int(sum(1 for b in range(0, len(wc), 4) if not (wc[b:b + 4] > 0).any()))
+        comp[pattern] = dict(live_laminates=counts[0], live_matrix_leaves=counts[1],
+                             live_fibre_leaves=counts[2], dead_lane_subtrees=lanes_dead,
+                             ms=ms_c, mean_iters=gc.iters.double().mean().item(),
+                             all_converged=bool((gc.status == 0).all().item()),
+                             live_credited_tflops=live_tflops(counts, gc.iters, ms_c))
+        del gc, ws_c
+    out["gp_update_compressed_tree"] = comp
+
     # the paper's inelastic load cases: six uniaxial strain hystereses (2.5 %,
     # 80 steps, the paper's material constants) over 65,536 points, each with
     # its own fibre orientation; the 80-step path captured as one graph

@@ -71,6 +71,33 @@ def gp_update_flops(depth: int, iters: int) -> int:
     return (iters + 1) * per_eval + iters * s.L * LAMINATE_DESCEND
 
 
+def live_tree_counts(w) -> tuple:
+    """(laminates, matrix leaves, fibre leaves) that tree compression (Sec. 3.1)
+    keeps for leaf weights w [2^K]: a leaf stays when its weight is positive,
+    a laminate when both of its subtrees carry weight (one with a dead child
+    passes the other through).  Leaves alternate fibre (even index) and
+    matrix (odd)."""
+    n = len(w)
+    W = [0.0] * (2 * n)  # heap order: node h has children 2h, 2h + 1; leaf j is n + j
+    for j in range(n):
+        W[n + j] = float(w[j]) if w[j] > 0 else 0.0
+    for h in range(n - 1, 0, -1):
+        W[h] = W[2 * h] + W[2 * h + 1]
+    lams = sum(1 for h in range(1, n) if W[2 * h] > 0 and W[2 * h + 1] > 0)
+    mat = sum(1 for j in range(1, n, 2) if W[n + j] > 0)
+    fib = sum(1 for j in range(0, n, 2) if W[n + j] > 0)
+    return lams, mat, fib
+
+
+def gp_update_flops_live(laminates: int, matrix_leaves: int, fibre_leaves: int,
+                         iters: int) -> int:
+    """gp_update_flops credited for the live part of a compressed tree only
+    (the kernel evaluates dead rows in place; that work is not credited)."""
+    per_eval = (laminates * (LAMINATE_NEWTON + LAMINATE_LOCALIZE)
+                + matrix_leaves * J2_LEAF + fibre_leaves * FIBER_LEAF)
+    return (iters + 1) * per_eval + iters * laminates * LAMINATE_DESCEND
+
+
 def gp_update_bytes(depth: int, elt: int = 8) -> int:
     """Compulsory HBM bytes of one update: E, z_in, a_in read; z_out, a_out, sigma,
     tangent written (elt bytes each), plus the 4-byte iteration count and status."""

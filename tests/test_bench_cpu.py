@@ -48,3 +48,28 @@ def test_source_digest_follows_every_kernel_source(tmp_path, monkeypatch):
     with open(files[1], "a") as f:
         f.write("int x;\n")
     assert bench.source_digest(files) != d0
+
+
+def test_live_tree_counts_match_the_oracles_compressed_tree():
+    """The compressed-tree counts that credit only live work in the bench equal
+    the live laminates and leaves of the oracle's compressed model, and with
+    no dead leaf the live flop count is the full tree's."""
+    import numpy as np
+    import synthetic as S
+    from oracle.compression import CompressedDmnModel
+    from paper_2103_08253_amd import roofline as R
+    for K in (1, 3, 5, 8):
+        net = S.random_dmn(S.streams(5)["dmn"], K, 0.25)
+        w = net.w.copy()
+        rng = np.random.default_rng(K)
+        if K > 1:
+            w[rng.choice(len(w), len(w) // 3, replace=False)] = 0.0
+        if K >= 3:
+            w[0:4] = 0.0
+        m = CompressedDmnModel(K, w, net.normals, S.FIBER, S.MATRIX)
+        live_mat = sum(1 for j in m.live_leaves if j % 2 == 1)
+        live_fib = sum(1 for j in m.live_leaves if j % 2 == 0)
+        assert R.live_tree_counts(w) == (len(m.live_lams), live_mat, live_fib), K
+        L, M = 2 ** K - 1, 2 ** (K - 1)
+        assert R.live_tree_counts(net.w) == (L, M, M)
+        assert R.gp_update_flops_live(L, M, M, 3) == R.gp_update_flops(K, 3)
