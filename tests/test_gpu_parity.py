@@ -464,6 +464,63 @@ def test_gp_f32_state_depth8_production_size_sampled():
     say(f"  worst rel vs oracle {worst:.2e}")
 
 
+def test_gp_f32_state_offsets_beyond_32_bits():
+    """Maximum size with FP32 state: depth 8, 2,818,048 points (43 copies of
+    the production points), so the widening and rounding of the per-point
+    arrays run over more than 2^31 elements (2.5e9 internal variables) and
+    the FP64 working copies sit past 2^31-element offsets (about 110 GB with
+    the workspace).  Two steps; every copy's outputs equal the first copy's
+    bit for bit, and points of the last copy match the FP64 oracle on the
+    FP32-rounded strains."""
+    from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
+    d = dev()
+    wl = S.config1()
+    net = wl.nets[0]
+    P0, reps = wl.n_points, 43
+    P = P0 * reps
+    M, L = 2 ** (net.depth - 1), 2 ** net.depth - 1
+    assert P * M * 7 >= 2 ** 31 and (P - 1) * L * 3 >= 2 ** 31
+    torch.cuda.empty_cache()
+    per_point = 2 * M * 7 + 2 * L * 3 + 6 + 6 + 36
+    need = P * per_point * (4 + 8)   # FP32 arrays and their FP64 working copies
+    if torch.cuda.mem_get_info()[0] < need + (8 << 30):
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of free device memory")
+    say(f"case: gp FP32 state, depth 8, {P} points ({reps} copies of {P0}) x 2 steps, "
+        f"{need / 2 ** 30:.0f} GiB")
+    E2 = torch.tensor(wl.E[[9, 10]], device=d, dtype=torch.float32)
+    picks = S.streams(1)["picks"].choice(P0, 3, replace=False)
+    last = (reps - 1) * P0 + picks
+    g = PointGroup.allocate(torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d),
+                            E2[0].repeat(reps, 1))
+    sig, tan, ws = [], [], None
+    for step in range(2):
+        g.E.copy_(E2[step].repeat(reps, 1))
+        ws = dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws)
+        torch.cuda.synchronize()
+        for name in ("sigma", "tangent", "z_out", "a_out", "iters", "status"):
+            t = getattr(g, name)
+            t = t.view(torch.int32).view(reps, P0, -1)   # float32 bit patterns too
+            assert torch.equal(t, t[:1].expand_as(t)), (step, name)
+        assert bool((g.status == 0).all())
+        sig.append(g.sigma[last].double().cpu().numpy())
+        tan.append(g.tangent[last].double().cpu().numpy())
+        g.advance()
+    del g, ws
+    torch.cuda.empty_cache()
+    model = DmnModel(net.depth, net.w, net.normals, S.FIBER, S.MATRIX)
+    E_ref = E2.double().cpu().numpy()
+    worst = 0.0
+    for i, p in enumerate(picks):
+        ref = run_path(model, E_ref[:, p, :], NewtonOptions())
+        if min(r["margin"] for r in ref) < 1e-5:
+            continue
+        for step, r in enumerate(ref):
+            e = max(rel(sig[step][i], r["sigma"]), rel(tan[step][i], r["C"]))
+            worst = max(worst, e)
+            assert e <= F32_STATE_RTOL, (p, step, e)
+    say(f"  every copy equal; worst rel vs oracle {worst:.2e}")
+
+
 def test_gp_status_codes_and_failure_state():
     from paper_2103_08253_amd import PointGroup, dmn_update_gauss_points
     say("case: gp status codes")
