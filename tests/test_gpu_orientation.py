@@ -207,3 +207,51 @@ def test_oriented_linear_backward_directional(K, B, kind, dtype, tol):
                                               vw, vp, vq)
         say(f"  gpu {got:.12e} oracle {ref:.12e}")
         assert abs(got - ref) <= tol * abs(ref)
+
+
+def test_orientation_offsets_beyond_32_bits():
+    """Maximum size with orientation-interpolated normals: depth 8, quadratic
+    shape functions, 2,818,048 points (43 copies of the orientation
+    workload's 65,536, each point its own (l1, l2)), so the element offsets of
+    the last points' internal variables and jumps pass 2^31 (about 71 GiB).
+    Two steps from the initial state (the path's tenth and eleventh
+    strains): every copy's outputs equal the first copy's bit for bit, and
+    points of the last copy match the oracle."""
+    from paper_2103_08253_amd import Orientation, PointGroup, dmn_update_gauss_points
+    d = dev()
+    net, lam, E = S.orientation_workload()
+    P0, reps = E.shape[1], 43
+    P = P0 * reps
+    M, L = 2 ** (net.depth - 1), 2 ** net.depth - 1
+    assert (P - 1) * M * 7 >= 2 ** 31 and (P - 1) * L * 3 >= 2 ** 31
+    torch.cuda.empty_cache()
+    need = P * (2 * M * 7 + 2 * L * 3 + 6 + 6 + 36 + 2) * 8
+    if torch.cuda.mem_get_info()[0] < need + (4 << 30):
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of free device memory")
+    say(f"case: orientation-interpolated normals, depth 8, {P} points ({reps} copies of {P0}) "
+        f"x 2 steps, {need / 2 ** 30:.0f} GiB")
+    E2 = torch.tensor(E[[9, 10]], device=d)
+    ori = Orientation(net.kind, torch.tensor(net.p, device=d), torch.tensor(net.q, device=d),
+                      torch.tensor(lam, device=d).repeat(reps, 1))
+    g = PointGroup.allocate(torch.tensor(net.w, device=d), None, E2[0].repeat(reps, 1), ori=ori)
+    picks = S.streams(5)["picks"].choice(P0, 3, replace=False)
+    last = torch.tensor((reps - 1) * P0 + picks, device=d)
+    gpu, ws = [], None
+    for step in range(2):
+        g.E.copy_(E2[step].repeat(reps, 1))
+        ws = dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws)
+        torch.cuda.synchronize()
+        for name in ("sigma", "tangent", "z_out", "a_out", "iters", "status"):
+            t = getattr(g, name)
+            if t.dtype == torch.float64:
+                t = t.view(torch.int64)
+            t = t.view(reps, P0, -1)
+            assert torch.equal(t, t[:1].expand_as(t)), (step, name)
+        gpu.append(dict(sigma=g.sigma[last].cpu().numpy(), C=g.tangent[last].cpu().numpy(),
+                        z=g.z_out[last].cpu().numpy(), a=g.a_out[last].cpu().numpy(),
+                        iters=g.iters[last].cpu().numpy(), status=g.status[last].cpu().numpy()))
+        g.advance()
+    say("  every copy equal")
+    del g, ws, ori
+    torch.cuda.empty_cache()
+    compare(net, lam, E[[9, 10]], picks, gpu, rows=range(len(picks)))
