@@ -563,6 +563,48 @@ def test_gp_status_codes_and_failure_state():
     assert int(g2.status[0]) == 0
 
 
+def test_empty_inputs_every_call():
+    """No points or samples: the linear map (FP64 and FP32) returns with its
+    error word clear; its backward overwrites gw, gn with zeros; the adjoint
+    of an empty group leaves the accumulated gradients as they were; the
+    Gauss-point update and its no-workspace form with only an empty group,
+    and the stiffness sampler, launch nothing and report success."""
+    from paper_2103_08253_amd import (AdjointGroup, PointGroup, dmn_homogenize_backward,
+                                      dmn_homogenize_linear, dmn_sample_stiffness,
+                                      dmn_update_adjoint, dmn_update_gauss_points,
+                                      dmn_update_gauss_points_noalloc, error_word)
+    say("case: empty inputs through every call")
+    d = dev()
+    K = 5
+    net = S.random_dmn(S.streams(64)["dmn"], K, 0.3)
+    M, L = 2 ** (K - 1), 2 ** K - 1
+    for dt in (torch.float64, torch.float32):
+        w, n = torch.tensor(net.w, device=d, dtype=dt), torch.tensor(net.normals, device=d,
+                                                                      dtype=dt)
+        empty = torch.empty((0, 6, 6), device=d, dtype=dt)
+        Cbar, ws = dmn_homogenize_linear(w, n, empty, empty)
+        assert Cbar.shape == (0, 6, 6) and error_word(ws) == 0
+        gw = torch.full((2 ** K,), float("nan"), device=d, dtype=dt)
+        gn = torch.full((L, 3), float("nan"), device=d, dtype=dt)
+        dmn_homogenize_backward(w, n, empty, empty, empty, gw=gw, gn=gn)
+        torch.cuda.synchronize()
+        assert bool((gw == 0).all()) and bool((gn == 0).all()), dt
+    w, n = torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d)
+    f64 = dict(device=d, dtype=torch.float64)
+    gw, gn = torch.full((2 ** K,), 3.0, **f64), torch.full((L, 3), 3.0, **f64)
+    ag = AdjointGroup(w, n, torch.empty((0, 6), **f64), torch.empty((0, M, 7), **f64),
+                      torch.empty((0, L, 3), **f64), torch.empty((0, 6), **f64), None,
+                      torch.empty((0, M, 7), **f64), gw, gn)
+    dmn_update_adjoint([ag], S.FIBER, S.MATRIX)
+    ge = PointGroup.allocate(w, n, torch.empty((0, 6), **f64))
+    dmn_update_gauss_points([ge], S.FIBER, S.MATRIX)
+    dmn_update_gauss_points_noalloc([ge], S.FIBER, S.MATRIX)
+    C1, C2 = dmn_sample_stiffness(torch.empty((0, 8), **f64))
+    torch.cuda.synchronize()
+    assert bool((gw == 3.0).all()) and bool((gn == 3.0).all())
+    assert C1.shape == (0, 6, 6) and C2.shape == (0, 6, 6)
+
+
 # ---------------------------------------------------------------- linear map
 
 @pytest.mark.parametrize("K,B", [(1, 5), (3, 37), (5, 70), (8, 33), (9, 3)])
