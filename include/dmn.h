@@ -31,6 +31,13 @@
  *     outcomes are written to the status arrays.
  *   - Workspace: each call needs a device workspace of at least the size its
  *     *_workspace_size() query returns (256-byte aligned base).
+ *   - Sizes: point and sample counts are int64 and every element offset into
+ *     a per-point or per-sample array is computed in 64 bits, so arrays may
+ *     exceed 2^31 elements; a count of 0 is valid (no data array is read and
+ *     its pointer may be NULL).  dmn_update_gauss_points returns DMN_EINVAL
+ *     when one launch would take more than 2^31 - 1 work items (batches of
+ *     points); the linear calls' limit, 2^31 - 1 workgroups of 1 to 64
+ *     samples, lies beyond any batch that fits in device memory.
  *   - No C++ exception crosses this interface.  Calls on different streams
  *     may run concurrently as long as they use different workspaces.
  */
