@@ -605,6 +605,56 @@ def test_empty_inputs_every_call():
     assert C1.shape == (0, 6, 6) and C2.shape == (0, 6, 6)
 
 
+def test_calls_on_two_streams_run_concurrently():
+    """Calls on different streams with their own workspaces may overlap: a
+    depth-7 Gauss-point update of 20,000 points on one stream and a depth-8
+    linear map with its backward on 4,096 samples on another (both default
+    priority), enqueued back to back, give bit for bit the results of the
+    same calls made one after the other."""
+    from paper_2103_08253_amd import (PointGroup, dmn_homogenize_backward,
+                                      dmn_homogenize_linear, dmn_update_gauss_points)
+    say("case: Gauss-point update and linear map + backward on two streams")
+    d = dev()
+    rs = S.streams(65)
+    net = S.random_dmn(rs["dmn"], 7, 0.25)
+    E = torch.tensor(S.ramp_with_noise(rs, 20000, 3, 0.02, 1e-3)[2], device=d)
+    tw = S.config3(batch=4096, depth=8)
+    w8, n8 = torch.tensor(tw.truth.w, device=d), torch.tensor(tw.truth.normals, device=d)
+    C1, C2 = torch.tensor(tw.C1, device=d), torch.tensor(tw.C2, device=d)
+    G = torch.tensor(rs["cotangent"].standard_normal((4096, 6, 6)), device=d)
+    w7, n7 = torch.tensor(net.w, device=d), torch.tensor(net.normals, device=d)
+
+    def run(streams):
+        g = PointGroup.allocate(w7, n7, E.clone())
+        ws_g = dmn_update_gauss_points([g], S.FIBER, S.MATRIX)     # sizes the workspace
+        Cb, ws_f = dmn_homogenize_linear(w8, n8, C1, C2)
+        gw, gn, _, _, ws_b = dmn_homogenize_backward(w8, n8, C1, C2, G)
+        torch.cuda.synchronize()
+        g.sigma.fill_(0.0)
+        Cb.fill_(0.0)
+        gw.fill_(0.0)
+        main = torch.cuda.current_stream()
+        for st in streams:
+            st.wait_stream(main)
+        with torch.cuda.stream(streams[0]):
+            dmn_update_gauss_points([g], S.FIBER, S.MATRIX, ws=ws_g)
+        with torch.cuda.stream(streams[-1]):
+            dmn_homogenize_linear(w8, n8, C1, C2, Cbar=Cb, ws=ws_f)
+            dmn_homogenize_backward(w8, n8, C1, C2, G, ws=ws_b, gw=gw, gn=gn)
+        for st in streams:
+            main.wait_stream(st)
+        torch.cuda.synchronize()
+        return [t.clone() for t in (g.sigma, g.tangent, g.z_out, g.a_out, g.iters, g.status,
+                                    Cb, gw, gn)]
+
+    one = run([torch.cuda.Stream(device=d)])
+    two = run([torch.cuda.Stream(device=d), torch.cuda.Stream(device=d)])
+    for a, b in zip(one, two):
+        if a.dtype == torch.float64:
+            a, b = a.view(torch.int64), b.view(torch.int64)
+        assert torch.equal(a, b)
+
+
 # ---------------------------------------------------------------- linear map
 
 @pytest.mark.parametrize("K,B", [(1, 5), (3, 37), (5, 70), (8, 33), (9, 3)])
