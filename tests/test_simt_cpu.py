@@ -42,6 +42,20 @@ def harness():
     return H
 
 
+@pytest.fixture(scope="module", autouse=True)
+def sanitised_builds():
+    """Build the three sanitised libraries side by side before the first case
+    (each build's time is mostly the single compile of the Gauss-point
+    source); later calls find them built."""
+    import concurrent.futures as cf
+    import build as B
+    with cf.ThreadPoolExecutor(3) as ex:
+        jobs = [ex.submit(B.build, sanitizer="address"), ex.submit(B.build, sanitizer="thread"),
+                ex.submit(B.build_f32_kernel)]
+        for j in jobs:
+            j.result()
+
+
 def rel(got, ref):
     scale = np.abs(ref).max()
     return np.abs(got - ref).max() / (scale if scale > 0 else 1.0)
