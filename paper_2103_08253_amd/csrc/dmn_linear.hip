@@ -216,6 +216,109 @@ __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ ta
   }
 }
 
+// Two samples per wave where the forward gives one sample all 64 lanes
+// (depths 7 and up with fixed normals).  Every lane runs its lane subtree for
+// sample B, parks the result in LDS, then runs it for sample A; the upper
+// levels then serve both samples in the same steps.  At level m (o = 2^(m-1))
+// sample A's laminate sits on the first lane of each group of 2o lanes and
+// takes its right child from lane t + o, sample B's on the group's last lane,
+// taking its left child from lane t - o; after level m A's partial results sit
+// on multiples of 2o and B's on lanes 2o - 1 mod 2o, so the two sets never
+// meet.  Each sample sees the same laminate operations in the same order as
+// in linear_fwd_kernel, so the results are the same bit for bit.  Two waves
+// per SIMD: the FP64 depth-8 instance fits the 256 registers that allows.
+template <typename T, int K, int D>
+__global__ __launch_bounds__(64, 2) void linear_fwd_pair_kernel(const T* __restrict__ tab0,
+                                                             const int32_t* __restrict__ flag0,
+                                                             const T* __restrict__ C1,
+                                                             const T* __restrict__ C2,
+                                                             T* __restrict__ Cbar,
+                                                             int32_t* __restrict__ err,
+                                                             const LinGroups grp) {
+  using C = LCfg<K, D>;
+  static_assert(C::LP == 64, "the pair mapping needs one sample per wave");
+  __shared__ T leafC[2][2][21];
+  __shared__ T rootB[21][64];
+  const int t = threadIdx.x;
+  const int g = lin_group(grp);
+  const T* tab = (const T*)((const char*)tab0 + g * grp.tab_stride);
+  const int32_t* flag = (const int32_t*)((const char*)flag0 + g * grp.tab_stride);
+  const long long s0 = grp.off[g], Bg = grp.off[g + 1] - s0;
+  const long long first = (long long)(blockIdx.x - grp.block0[g]) * 2;
+  // samples A = first (always in range) and B = first + 1 of the group; a
+  // missing B (odd group size) shadows A and is not stored
+  if (t < 2) {
+    const long long b = s0 + first + (t == 1 && first + 1 < Bg ? 1 : 0);
+    load_sym(C1 + (size_t)b * 36, leafC[t][0]);
+    load_sym(C2 + (size_t)b * 36, leafC[t][1]);
+  }
+  __syncthreads();
+  const Rows<T, C::L, false> rows{tab, nullptr};
+  int failA = 0, failB = 0;
+  T dummy[C::NLAM][21];
+  {
+    T cB[21];
+    lin_up<T, K, D, 1, false>(rows, t, leafC[1][0], leafC[1][1], cB, failB, dummy);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) rootB[k][t] = cB[k];  // read back by this lane only
+  }
+  T cur[21];
+  lin_up<T, K, D, 1, false>(rows, t, leafC[0][0], leafC[0][1], cur, failA, dummy);
+#pragma unroll 1
+  for (int m = 1; m <= C::UPLEV; ++m) {
+    const int o = 1 << (m - 1);
+    const int r = t & (2 * o - 1);
+    const bool actA = r == 0, actB = r == 2 * o - 1;
+    const int src = actA ? t + o : (actB ? t - o : t);
+    T rC[21];
+    if (m == 1) {
+      // every lane holds both lane roots: even lanes pass B's, odd lanes A's,
+      // and an odd lane's right child is its own B root
+#pragma unroll
+      for (int k = 0; k < 21; ++k) rC[k] = __shfl((t & 1) ? cur[k] : rootB[k][t], src, 64);
+      if (t & 1) {
+#pragma unroll
+        for (int k = 0; k < 21; ++k) cur[k] = rootB[k][t];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 21; ++k) rC[k] = __shfl(cur[k], src, 64);
+    }
+    if (actB) {  // B's left child arrived from the lane before: left = cur
+#pragma unroll
+      for (int k = 0; k < 21; ++k) {
+        const T x = cur[k];
+        cur[k] = rC[k];
+        rC[k] = x;
+      }
+    }
+    if (actA || actB) {
+      const LRow<T> row = rows(upos<K, D>(m, t));
+      // the result overwrites the left operand: laminate_linear reads each
+      // packed entry of its operands before it writes that entry of the result
+      const int bad = laminate_linear(cur, rC, row.nv, row.c1, row.c2, cur) ? 0 : 1;
+      if (actA) failA |= bad;
+      else failB |= bad;
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    failA |= __shfl_xor(failA, o, 64);
+    failB |= __shfl_xor(failB, o, 64);
+  }
+  const int invalid = *flag;
+  // A's root is on lane 0, B's on lane 63
+  if ((t == 0) || (t == 63 && first + 1 < Bg)) {
+    const int fail = t == 0 ? failA : failB;
+    if (fail || invalid) {
+#pragma unroll
+      for (int k = 0; k < 21; ++k) cur[k] = T(__builtin_nan(""));
+      atomicOr(err, (invalid ? 1 : 0) | (fail ? 2 : 0));
+    }
+    store_full(Cbar + (size_t)(s0 + first + (t == 0 ? 0 : 1)) * 36, cur);
+  }
+}
+
 // Angle cotangents of laminate pos of sample b from its normal cotangent gn:
 // d/dalpha = gn . dn/dalpha, d/dbeta = gn . (-n1, n0, 0).
 template <typename T, int L>
@@ -647,15 +750,27 @@ static int fwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
   const LinOri<T> ori{(const T*)o.p, (const T*)o.q, (const T*)o.lam, (T*)o.gang, o.m};
   // per-sample orientation: plain (one-group) calls only
   if (o.m > 0 && G != 1) return (int)hipErrorInvalidValue;
+  // fixed normals with one sample per wave at depths 7 and 8: two samples
+  // share a wave's upper levels (linear_fwd_pair_kernel; at depth 9 it would
+  // spill)
+  constexpr bool kPair = C::PPW == 1 && K <= 8;
+  const int per_block = (kPair && o.m == 0) ? 2 : C::PPW;
   for (int g0 = 0; g0 < G; g0 += kMaxLinGroups) {
     const int ng = G - g0 < kMaxLinGroups ? G - g0 : kMaxLinGroups;
     LinGroups gr;
     const long long nb = chunk_groups(gr, off, g0, ng, tab_stride,
-                                      [](long long B) { return (B + C::PPW - 1) / C::PPW; });
+                                      [&](long long B) { return (B + per_block - 1) / per_block; });
     if (nb < 0) return (int)hipErrorInvalidValue;
     if (nb == 0) continue;
     const T* tabc = (const T*)((const char*)tab + g0 * tab_stride);
     const int32_t* flagc = (const int32_t*)((const char*)flag + g0 * tab_stride);
+    if constexpr (kPair) {
+      if (o.m == 0) {
+        hipLaunchKernelGGL((linear_fwd_pair_kernel<T, K, D>), dim3((unsigned)nb), dim3(64), 0, s,
+                           tabc, flagc, (const T*)C1, (const T*)C2, (T*)Cbar, err, gr);
+        continue;
+      }
+    }
     if (o.m > 0) {
       // per-sample orientation is compiled up to the depth of the VJP kernels
       if constexpr (K <= kMaxOriLinearDepth)
