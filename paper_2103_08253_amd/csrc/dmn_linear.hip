@@ -752,11 +752,15 @@ static int fwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
   if (o.m > 0 && G != 1) return (int)hipErrorInvalidValue;
   // fixed normals with one sample per wave at depths 7 and 8: two samples
   // share a wave's upper levels (linear_fwd_pair_kernel; at depth 9 it would
-  // spill)
+  // spill) when the launch has more than 8 samples per CU, i.e. when one
+  // sample per wave would take more than one round of resident waves (two
+  // per SIMD); smaller batches are latency bound and keep one per wave
   constexpr bool kPair = C::PPW == 1 && K <= 8;
-  const int per_block = (kPair && o.m == 0) ? 2 : C::PPW;
+  const long long pair_min = 8LL * device_cu_count();
   for (int g0 = 0; g0 < G; g0 += kMaxLinGroups) {
     const int ng = G - g0 < kMaxLinGroups ? G - g0 : kMaxLinGroups;
+    const bool pair = kPair && o.m == 0 && off[g0 + ng] - off[g0] > pair_min;
+    const int per_block = pair ? 2 : C::PPW;
     LinGroups gr;
     const long long nb = chunk_groups(gr, off, g0, ng, tab_stride,
                                       [&](long long B) { return (B + per_block - 1) / per_block; });
@@ -765,7 +769,7 @@ static int fwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
     const T* tabc = (const T*)((const char*)tab + g0 * tab_stride);
     const int32_t* flagc = (const int32_t*)((const char*)flag + g0 * tab_stride);
     if constexpr (kPair) {
-      if (o.m == 0) {
+      if (pair) {
         hipLaunchKernelGGL((linear_fwd_pair_kernel<T, K, D>), dim3((unsigned)nb), dim3(64), 0, s,
                            tabc, flagc, (const T*)C1, (const T*)C2, (T*)Cbar, err, gr);
         continue;

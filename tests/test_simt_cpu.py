@@ -238,14 +238,15 @@ def check_linear(K, tw, G, out, tol):
 
 
 @pytest.mark.parametrize("K,B,dtype", [(3, 37, np.float64), (5, 70, np.float64),
-                                       (8, 4, np.float64), (8, 5, np.float64),
-                                       (7, 3, np.float64), (3, 37, np.float32),
-                                       (8, 3, np.float32)])
+                                       (8, 4, np.float64), (8, 19, np.float64),
+                                       (7, 17, np.float64), (3, 37, np.float32),
+                                       (8, 17, np.float32)])
 def test_simt_linear_map_and_backward(K, B, dtype):
     """The linear map and its backward (dmn_homogenize_linear / _backward) in
     the sanitised build against the oracle's map and complex-step gradients:
     ragged batches, depths 7 and 8 with two samples sharing a wave's upper
-    levels in the forward (odd batches leave the last wave one sample), and
+    levels in the forward once a batch has more than 8 samples per CU (two
+    emulated CUs here; odd batches leave the last wave one sample), and
     at depth 5 with 70 samples 72 partial-sum slots, so the batch sum runs
     through the workgroup tree reduction; FP32 storage and arithmetic within
     1e-4."""
@@ -260,7 +261,7 @@ def test_simt_linear_no_race_between_lanes():
     """The linear map, its backward and the reductions of the batch sum (the
     workgroup tree at depth 5 with 72 slots), and the depth-8 forward with two
     samples per wave (an odd batch), under ThreadSanitizer."""
-    for K, B in ((5, 70), (8, 3)):
+    for K, B in ((5, 70), (8, 17)):
         tw, G = linear_case(K, B, 4)
         out = harness().run_linear(K, tw.truth.w, tw.truth.normals, tw.C1, tw.C2, G,
                                    sanitizer="thread")
