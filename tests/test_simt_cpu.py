@@ -487,3 +487,17 @@ def test_simt_oriented_training_step(kind, dead, dtype):
                                                                            * 3), 1, lr)
     got = np.concatenate([out[k].astype(np.float64).ravel() for k in ("v", "p", "q")])
     assert rel(got, th) < tol
+
+
+def test_simt_linear_pair_forward_is_bit_identical(monkeypatch):
+    """The forward with two samples per wave (used once a launch has more than
+    8 samples per CU) gives every sample the same bits as one sample per wave:
+    17 depth-8 samples with two emulated CUs take the pair kernel, with three
+    the one-sample kernel."""
+    tw, G = linear_case(8, 17, 5)
+    outs = []
+    for cus in ("2", "3"):
+        monkeypatch.setenv("SIMT_CUS", cus)
+        outs.append(harness().run_linear(8, tw.truth.w, tw.truth.normals, tw.C1, tw.C2, G))
+    assert np.array_equal(outs[0]["Cbar"].view(np.int64), outs[1]["Cbar"].view(np.int64))
+    assert list(outs[0]["err"]) == [0, 0] and list(outs[1]["err"]) == [0, 0]
