@@ -555,6 +555,236 @@ __global__ __launch_bounds__(64) void linear_bwd_kernel(
   if (lane == 0 && (fail || *flag)) atomicOr(err, (*flag ? 1 : 0) | (fail ? 2 : 0));
 }
 
+// The backward with two samples per wave where it gives one sample all 64
+// lanes and the registers allow it (FP32 at depths 7 and 8, FP64 at depth 7;
+// fixed normals, no phase-stiffness cotangents).  Per pair of samples A, B:
+// every lane computes both samples' lane-subtree roots, and the upper levels
+// run forward for both in the same steps as in linear_fwd_pair_kernel,
+// storing the upper nodes' stiffnesses in LDS; their VJPs then run top-down
+// for both in the same steps down to level 2: A's laminate on the first lane
+// of a group of 2o lanes keeps its left child's cotangent and sends the right
+// one to lane t + o, B's on the group's last lane keeps the right one and
+// sends the left one to lane t - o (the lanes acting for A, for B, receiving
+// for A and receiving for B are four different residues mod 2o).  Last, for A
+// and then B, the sample's lane subtree is recomputed, its level-1 laminate's
+// VJP runs on one lane of each pair (the cotangent waited in the LDS the
+// upper nodes used) and the lane subtree's VJPs follow.  Each sample's
+// laminate operations are those of linear_bwd_kernel; the upper laminates'
+// cotangent sums are kept per sample slot and added A then B at the end, a
+// fixed order.
+template <typename T, int K, int D>
+__global__ __launch_bounds__(64) void linear_bwd_pair_kernel(
+    const T* __restrict__ tab0, const int32_t* __restrict__ flag0, const T* __restrict__ C1,
+    const T* __restrict__ C2, const T* __restrict__ gCbar, double* __restrict__ partials,
+    int32_t* __restrict__ err, const LinGroups grp) {
+  using C = LCfg<K, D>;
+  static_assert(C::LP == 64, "the pair mapping needs one sample per wave");
+  // upper nodes' stiffnesses per sample, [pos - UP0]; then each lane's
+  // level-1 cotangent, [lane]
+  __shared__ T nodeU[2][21][64];
+  __shared__ T leafC[2][2][21];
+  __shared__ double accU[2][4][C::NUP];
+  __shared__ double acc[C::NLAM][4][64];
+  const int t = threadIdx.x;
+  for (int u = t; u < C::NUP; u += 64)
+    for (int s = 0; s < 2; ++s)
+      for (int c = 0; c < 4; ++c) accU[s][c][u] = 0.0;
+#pragma unroll
+  for (int h = 0; h < C::NLAM; ++h)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[h][c][t] = 0.0;
+  int fail = 0;
+  const int g = lin_group(grp);
+  const T* tab = (const T*)((const char*)tab0 + g * grp.tab_stride);
+  const int32_t* flag = (const int32_t*)((const char*)flag0 + g * grp.tab_stride);
+  const long long s0 = grp.off[g], Bg = grp.off[g + 1] - s0;
+  const int gb = (int)blockIdx.x - grp.block0[g];
+  const int gblocks = grp.block0[g + 1] - grp.block0[g];
+  const Rows<T, C::L, false> rows{tab, nullptr};
+  const LinOri<T> none{};
+  __syncthreads();
+  for (long long sg = gb; sg * 2 < Bg; sg += gblocks) {
+    const long long first = sg * 2;
+    const bool liveB = first + 1 < Bg;  // a missing B shadows A and adds nothing
+    if (t < 2) {
+      const long long b = s0 + first + (t == 1 && liveB ? 1 : 0);
+      load_sym(C1 + (size_t)b * 36, leafC[t][0]);
+      load_sym(C2 + (size_t)b * 36, leafC[t][1]);
+    }
+    __syncthreads();
+    // lane-subtree roots of both samples, then the upper levels forward for both
+    {
+      T rootA[21], rootB[21];
+      {
+        T dummy[C::NLAM][21];
+        lin_up<T, K, D, 1, false>(rows, t, leafC[1][0], leafC[1][1], rootB, fail, dummy);
+        lin_up<T, K, D, 1, false>(rows, t, leafC[0][0], leafC[0][1], rootA, fail, dummy);
+      }
+      T cur[21];
+#pragma unroll 1
+      for (int m = 1; m <= C::UPLEV; ++m) {
+        const int o = 1 << (m - 1);
+        const int r = t & (2 * o - 1);
+        const bool actA = r == 0, actB = r == 2 * o - 1;
+        T rC[21];
+        if (m == 1) {
+          // even lanes combine A_t, A_t+1; odd lanes B_t-1, B_t
+#pragma unroll
+          for (int k = 0; k < 21; ++k) rC[k] = __shfl((t & 1) ? rootA[k] : rootB[k], t ^ 1, 64);
+#pragma unroll
+          for (int k = 0; k < 21; ++k) {
+            cur[k] = (t & 1) ? rC[k] : rootA[k];
+            rC[k] = (t & 1) ? rootB[k] : rC[k];
+          }
+        } else {
+          const int src = actA ? t + o : (actB ? t - o : t);
+#pragma unroll
+          for (int k = 0; k < 21; ++k) rC[k] = __shfl(cur[k], src, 64);
+          if (actB) {
+#pragma unroll
+            for (int k = 0; k < 21; ++k) {
+              const T x = cur[k];
+              cur[k] = rC[k];
+              rC[k] = x;
+            }
+          }
+        }
+        if (actA || actB) {
+          const int pos = upos<K, D>(m, t);
+          const LRow<T> row = rows(pos);
+          // in place: laminate_linear reads each packed entry before writing it
+          fail |= laminate_linear(cur, rC, row.nv, row.c1, row.c2, cur) ? 0 : 1;
+#pragma unroll
+          for (int k = 0; k < 21; ++k) nodeU[actA ? 0 : 1][k][pos - C::UP0] = cur[k];
+        }
+      }
+    }
+    __syncthreads();
+    // upper levels backward, both samples; root cotangents: A on lane 0, B on 63
+    T Gm[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Gm[k] = T(0);
+    if (t == 0 || t == 63)
+      load_sym(gCbar + (size_t)(s0 + first + (t == 63 && liveB ? 1 : 0)) * 36, Gm);
+#pragma unroll 1
+    for (int m = C::UPLEV; m >= 2; --m) {
+      const int o = 1 << (m - 1);
+      const int r = t & (2 * o - 1);
+      const bool actA = r == 0, actB = r == 2 * o - 1;
+      T send[21];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) send[k] = T(0);
+      if (actA || actB) {
+        const int s = actA ? 0 : 1;
+        const int pos = upos<K, D>(m, t);
+        const LRow<T> row = rows(pos);
+        const int base = t - r;
+        const int pL = upos<K, D>(m - 1, base) - C::UP0, pR = upos<K, D>(m - 1, base + o) - C::UP0;
+        T CL[21], CR[21], GL[21], GR[21], gc1, gn[3];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+          CL[k] = nodeU[s][k][pL];
+          CR[k] = nodeU[s][k][pR];
+        }
+        laminate_linear_vjp(CL, CR, row.nv, row.c1, row.c2, Gm, GL, GR, gc1, gn);
+        if (actA || liveB) {
+          const int u = pos - C::UP0;
+          accU[s][0][u] += (double)gc1;
+          accU[s][1][u] += (double)gn[0];
+          accU[s][2][u] += (double)gn[1];
+          accU[s][3][u] += (double)gn[2];
+        }
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+          Gm[k] = actA ? GL[k] : GR[k];
+          send[k] = actA ? GR[k] : GL[k];
+        }
+      }
+      const bool rcvA = r == o, rcvB = r == o - 1;
+      const int src = rcvA ? t - o : (rcvB ? t + o : t);
+      T rcv[21];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) rcv[k] = __shfl(send[k], src, 64);
+      if (rcvA || rcvB) {
+#pragma unroll
+        for (int k = 0; k < 21; ++k) Gm[k] = rcv[k];
+      }
+    }
+    // each lane's cotangent of its level-1 laminate (A's on even lanes, B's on
+    // odd ones) waits in LDS while the lane subtrees are recomputed
+    __syncthreads();  // the upper nodes are read no more
+#pragma unroll
+    for (int k = 0; k < 21; ++k) nodeU[0][k][t] = Gm[k];
+    T g1[1], g2[1];
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      const bool live = s == 0 || liveB;
+      T nodes[C::NLAM][21];
+      T cC[21], Gr[21];
+      lin_up<T, K, D, 1, true>(rows, t, leafC[s][0], leafC[s][1], cC, fail, nodes);
+      // level 1 of sample s: on the even lane of each pair for A, the odd one
+      // for B; the lane holding the laminate keeps the cotangent of its own
+      // lane root and sends the other to its neighbour
+      {
+        const bool act = (t & 1) == s;
+        T other[21], G1[21], GL[21], GR[21];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+          other[k] = __shfl(cC[k], t ^ 1, 64);
+          G1[k] = nodeU[0][k][t];
+          GL[k] = GR[k] = T(0);
+        }
+        if (act) {
+          const int pos = upos<K, D>(1, t);
+          const LRow<T> row = rows(pos);
+          T CL[21], CR[21], gc1, gn[3];
+#pragma unroll
+          for (int k = 0; k < 21; ++k) {
+            CL[k] = s ? other[k] : cC[k];
+            CR[k] = s ? cC[k] : other[k];
+          }
+          laminate_linear_vjp(CL, CR, row.nv, row.c1, row.c2, G1, GL, GR, gc1, gn);
+          if (live) {
+            const int u = pos - C::UP0;
+            accU[s][0][u] += (double)gc1;
+            accU[s][1][u] += (double)gn[0];
+            accU[s][2][u] += (double)gn[1];
+            accU[s][3][u] += (double)gn[2];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+          const T rcv = __shfl(s ? GL[k] : GR[k], t ^ 1, 64);
+          Gr[k] = act ? (s ? GR[k] : GL[k]) : rcv;
+        }
+      }
+      lin_back<T, K, D, 1, false, false>(rows, none, 0, 0, t, live, leafC[s][0], leafC[s][1],
+                                         nodes, Gr, acc, g1, g2);
+    }
+    __syncthreads();  // leafC and nodeU are rewritten by the next pair
+  }
+  // partial sums of this wave (one slot per wave), [pos * 4 + c][slot] in the
+  // group's region
+  const size_t pslot = (size_t)gb;
+  const size_t nslots = (size_t)gblocks;
+  double* gpart = partials + (size_t)grp.block0[g] * (4 * C::L);
+#pragma unroll
+  for (int h = 1; h <= C::NLAM; ++h) {
+    const int m = ilog2l(h);
+    const int k = K - D + 1 + m;
+    const int pos = (1 << K) - (1 << k) + t * (1 << m) + (h - (1 << m));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) gpart[((size_t)pos * 4 + c) * nslots + pslot] = acc[h - 1][c][t];
+  }
+  for (int u = t; u < C::NUP; u += 64)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      gpart[((size_t)(C::UP0 + u) * 4 + c) * nslots + pslot] = accU[0][c][u] + accU[1][c][u];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) fail |= __shfl_xor(fail, o, 64);
+  if (t == 0 && (fail || *flag)) atomicOr(err, (*flag ? 1 : 0) | (fail ? 2 : 0));
+}
+
 // Sum the partials over wave slots in a fixed order, gsum[g][pos * 4 + c].  A
 // group with at most kSeqSlots slots has one thread per row summing them in
 // slot order (reduce_partials_seq_kernel); a larger one has one workgroup per
@@ -869,7 +1099,25 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
     if (waves < 0 || (long long)ng * L4 > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     const void* tabc = (const char*)tab + g0 * tab_stride;
     const int32_t* flagc = (const int32_t*)((const char*)flag + g0 * tab_stride);
-    if (ig && oriented)
+    // fixed normals without phase-stiffness cotangents, one sample per wave:
+    // two samples per wave (linear_bwd_pair_kernel, same waves and partial
+    // slots) where that fits the registers without spilling, i.e. FP32 at
+    // depths 7 and 8 and FP64 at depth 7 (the FP64 depth-8 instance spills
+    // several hundred bytes per lane and keeps one sample per wave), and, as
+    // for the forward, only above 8 samples per CU: smaller batches are
+    // latency bound and pairs would idle half the waves
+    constexpr bool kPair = C::PPW == 1 && (K == 7 || (K == 8 && sizeof(T) == 4));
+    bool paired = false;
+    if constexpr (kPair) {
+      if (!ig && !oriented && off[g0 + ng] - off[g0] > 8LL * device_cu_count()) {
+        hipLaunchKernelGGL((linear_bwd_pair_kernel<T, K, D>), dim3((unsigned)waves), dim3(64), 0,
+                           s, (const T*)tabc, flagc, (const T*)C1, (const T*)C2,
+                           (const T*)gCbar, part, err, gr);
+        paired = true;
+      }
+    }
+    if (paired) {
+    } else if (ig && oriented)
       bwd_launch<T, K, true, true>(waves, tabc, flagc, off[G], C1, C2, gCbar, gC1, gC2, part, err,
                                    ori, gr, s);
     else if (ig)

@@ -696,7 +696,7 @@ def chain_angles(gn, alpha, beta):
     return np.sum(gn * da, -1), np.sum(gn * db, -1)
 
 
-@pytest.mark.parametrize("K,B,subset", [(3, 5, None), (5, 9, None), (8, 2, 24)])
+@pytest.mark.parametrize("K,B,subset", [(3, 5, None), (5, 9, None), (7, 9, 24), (8, 2, 24)])
 def test_linear_backward_f64_vs_complex_step(K, B, subset):
     from paper_2103_08253_amd import dmn_homogenize_backward
     say(f"case: linear backward f64 depth {K} batch {B}")

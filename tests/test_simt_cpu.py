@@ -246,7 +246,8 @@ def test_simt_linear_map_and_backward(K, B, dtype):
     the sanitised build against the oracle's map and complex-step gradients:
     ragged batches, depths 7 and 8 with two samples sharing a wave's upper
     levels in the forward once a batch has more than 8 samples per CU (two
-    emulated CUs here; odd batches leave the last wave one sample), and
+    emulated CUs here; odd batches leave the last wave one sample) and in the
+    backward at depth 7 and in FP32 at depth 8, and
     at depth 5 with 70 samples 72 partial-sum slots, so the batch sum runs
     through the workgroup tree reduction; FP32 storage and arithmetic within
     1e-4."""
@@ -259,9 +260,10 @@ def test_simt_linear_map_and_backward(K, B, dtype):
 
 def test_simt_linear_no_race_between_lanes():
     """The linear map, its backward and the reductions of the batch sum (the
-    workgroup tree at depth 5 with 72 slots), and the depth-8 forward with two
-    samples per wave (an odd batch), under ThreadSanitizer."""
-    for K, B in ((5, 70), (8, 17)):
+    workgroup tree at depth 5 with 72 slots), the depth-8 forward with two
+    samples per wave (an odd batch) and the depth-7 backward with two samples
+    per wave, under ThreadSanitizer."""
+    for K, B in ((5, 70), (8, 17), (7, 17)):
         tw, G = linear_case(K, B, 4)
         out = harness().run_linear(K, tw.truth.w, tw.truth.normals, tw.C1, tw.C2, G,
                                    sanitizer="thread")
