@@ -225,8 +225,10 @@ __global__ __launch_bounds__(64) void linear_fwd_kernel(const T* __restrict__ ta
 // taking its left child from lane t - o; after level m A's partial results sit
 // on multiples of 2o and B's on lanes 2o - 1 mod 2o, so the two sets never
 // meet.  Each sample sees the same laminate operations in the same order as
-// in linear_fwd_kernel, so the results are the same bit for bit.  Two waves
-// per SIMD: the FP64 depth-8 instance fits the 256 registers that allows.
+// in linear_fwd_kernel; the compiler may still contract them into FMAs
+// differently in the two kernels, so the results agree within rounding (a
+// few ulps), not always bit for bit.  Two waves per SIMD: the FP64 depth-8
+// instance fits the 256 registers that allows.
 template <typename T, int K, int D>
 __global__ __launch_bounds__(64, 2) void linear_fwd_pair_kernel(const T* __restrict__ tab0,
                                                              const int32_t* __restrict__ flag0,

@@ -850,3 +850,72 @@ def test_linear_backward_finite_differences_and_f32():
     en = (gn32.double() - gn).abs().max().item() / gn.abs().max().item()
     say(f"  FP32 vs FP64 gradient rel err: w {ew:.2e}, n {en:.2e}")
     assert ew <= 1e-4 and en <= 1e-4
+
+
+@pytest.mark.parametrize("K,dtype", [(7, "f64"), (7, "f32"), (8, "f64"), (8, "f32")])
+def test_linear_two_samples_per_wave_match_one_sample_calls(K, dtype):
+    """Above 8 samples per CU in a launch, the linear map at depths 7 and 8 and
+    its backward (FP32 at depths 7 and 8, FP64 at depth 7) run two samples per
+    wave that share the upper tree levels.  On a batch 37 samples above that
+    size, compare with calls on two chunks at or below it, which run one
+    sample per wave:
+    * Cbar agrees per sample within rounding (each sample sees the same
+      laminate operations, Sec. 3.1, in the same order, but the compiler may
+      contract them into FMAs differently in the two kernels);
+    * the batch gradient equals the sum of the chunks' gradients within
+      rounding.
+    The gradient is also checked against an independent reference:
+    * FP64 at depth 7: two weights and the root laminate's angles against the
+      oracle's complex-step derivative;
+    * FP32: the whole gradient against the FP64 call (1e-4 of its largest
+      entry)."""
+    from paper_2103_08253_amd import dmn_homogenize_backward, dmn_homogenize_linear
+    d = dev()
+    cus = torch.cuda.get_device_properties(d).multi_processor_count
+    cut = 8 * cus
+    B = cut + 37
+    say(f"case: linear map and backward, depth {K}, {dtype}, batch {B} ({cus} CUs)")
+    tw = S.config3(batch=B, depth=K)
+    net = tw.truth
+    G = S.streams(3)["cotangent"].standard_normal((B, 6, 6))
+    f = torch.float64 if dtype == "f64" else torch.float32
+    t = lambda x, dt=f: torch.tensor(x, device=d, dtype=dt)
+    w, n, C1, C2, Gt = t(net.w), t(net.normals), t(tw.C1), t(tw.C2), t(G)
+    Cb, _ = dmn_homogenize_linear(w, n, C1, C2)
+    gw, gn, _, _, _ = dmn_homogenize_backward(w, n, C1, C2, Gt)
+    parts = [(0, cut), (cut, B)]
+    Cc = torch.cat([dmn_homogenize_linear(w, n, C1[a:b], C2[a:b])[0] for a, b in parts])
+    gparts = [dmn_homogenize_backward(w, n, C1[a:b], C2[a:b], Gt[a:b])[:2] for a, b in parts]
+    torch.cuda.synchronize()
+    Cb_np, Cc_np = Cb.double().cpu().numpy(), Cc.double().cpu().numpy()
+    diff = np.abs(Cb_np - Cc_np).max(axis=(1, 2)) / np.abs(Cc_np).max(axis=(1, 2))
+    say(f"  Cbar batch vs chunks: {int((diff > 0).sum())} of {B} samples differ, "
+        f"worst {diff.max():.2e}")
+    assert diff.max() <= (1e-13 if dtype == "f64" else 1e-5)
+    gw_np, gn_np = gw.double().cpu().numpy(), gn.double().cpu().numpy()
+    gw_c = sum(g[0].double().cpu().numpy() for g in gparts)
+    gn_c = sum(g[1].double().cpu().numpy() for g in gparts)
+    ew, en = rel(gw_np, gw_c), rel(gn_np, gn_c)
+    say(f"  batch vs chunks: gw {ew:.2e}, gn {en:.2e}")
+    bar = 1e-12 if dtype == "f64" else 1e-5
+    assert ew <= bar and en <= bar
+    if dtype == "f32":
+        t64 = lambda x: t(x, torch.float64)
+        gw64, gn64, _, _, _ = dmn_homogenize_backward(t64(net.w), t64(net.normals), t64(tw.C1),
+                                                      t64(tw.C2), t64(G))
+        ew = rel(gw_np, gw64.cpu().numpy())
+        en = rel(gn_np, gn64.cpu().numpy())
+        say(f"  FP32 vs FP64: gw {ew:.2e}, gn {en:.2e}")
+        assert ew <= 1e-4 and en <= 1e-4
+    elif K == 7:
+        alpha, beta = S.normals_to_angles(net.normals)
+        iw = [int(np.argmax(net.w)), 5]
+        root = 2 ** K - 2
+        ref = linear_gradients(K, net.w, alpha, beta, tw.C1, tw.C2, G, iw, [root])
+        ga, gb = chain_angles(gn_np, alpha, beta)
+        e_w = rel(gw_np[iw], ref["gw"][iw])
+        got_a = np.array([ga[root], gb[root]])
+        ref_a = np.array([ref["galpha"][root], ref["gbeta"][root]])
+        e_a = rel(got_a, ref_a)
+        say(f"  vs oracle complex step: gw {e_w:.2e}, root angles {e_a:.2e}")
+        assert e_w <= RTOL and e_a <= RTOL
