@@ -1103,15 +1103,16 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
     const int32_t* flagc = (const int32_t*)((const char*)flag + g0 * tab_stride);
     // fixed normals without phase-stiffness cotangents, one sample per wave:
     // two samples per wave (linear_bwd_pair_kernel, same waves and partial
-    // slots) where that fits the registers without spilling, i.e. FP32 at
-    // depths 7 and 8 and FP64 at depth 7 (the FP64 depth-8 instance spills
-    // several hundred bytes per lane and keeps one sample per wave), and, as
-    // for the forward, only above 8 samples per CU: smaller batches are
-    // latency bound and pairs would idle half the waves
-    constexpr bool kPair = C::PPW == 1 && (K == 7 || (K == 8 && sizeof(T) == 4));
+    // slots) at depths 7 and 8 and, as for the forward, only above 8 samples
+    // per CU: smaller batches are latency bound and pairs would idle half the
+    // waves.  The FP64 depth-8 instance spills several hundred bytes per lane
+    // (the others fit the registers), which costs more than the pairing saves
+    // until a launch holds more than 64 samples per CU
+    constexpr bool kPair = C::PPW == 1 && (K == 7 || K == 8);
+    constexpr long long kPairPerCu = (K == 8 && sizeof(T) == 8) ? 64 : 8;
     bool paired = false;
     if constexpr (kPair) {
-      if (!ig && !oriented && off[g0 + ng] - off[g0] > 8LL * device_cu_count()) {
+      if (!ig && !oriented && off[g0 + ng] - off[g0] > kPairPerCu * device_cu_count()) {
         hipLaunchKernelGGL((linear_bwd_pair_kernel<T, K, D>), dim3((unsigned)waves), dim3(64), 0,
                            s, (const T*)tabc, flagc, (const T*)C1, (const T*)C2,
                            (const T*)gCbar, part, err, gr);

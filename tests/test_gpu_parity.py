@@ -855,10 +855,10 @@ def test_linear_backward_finite_differences_and_f32():
 @pytest.mark.parametrize("K,dtype", [(7, "f64"), (7, "f32"), (8, "f64"), (8, "f32")])
 def test_linear_two_samples_per_wave_match_one_sample_calls(K, dtype):
     """Above 8 samples per CU in a launch, the linear map at depths 7 and 8 and
-    its backward (FP32 at depths 7 and 8, FP64 at depth 7) run two samples per
-    wave that share the upper tree levels.  On a batch 37 samples above that
-    size, compare with calls on two chunks at or below it, which run one
-    sample per wave:
+    its backward run two samples per wave that share the upper tree levels
+    (the FP64 depth-8 backward only above 64 samples per CU).  On a batch 37
+    samples above the backward's size, compare with calls on chunks at or
+    below each kernel's size, which run one sample per wave:
     * Cbar agrees per sample within rounding (each sample sees the same
       laminate operations, Sec. 3.1, in the same order, but the compiler may
       contract them into FMAs differently in the two kernels);
@@ -872,8 +872,10 @@ def test_linear_two_samples_per_wave_match_one_sample_calls(K, dtype):
     from paper_2103_08253_amd import dmn_homogenize_backward, dmn_homogenize_linear
     d = dev()
     cus = torch.cuda.get_device_properties(d).multi_processor_count
-    cut = 8 * cus
-    B = cut + 37
+    fwd_cut = 8 * cus
+    bwd_cut = (64 if (K, dtype) == (8, "f64") else 8) * cus
+    B = bwd_cut + 37
+    chunks = lambda n: [(a, min(a + n, B)) for a in range(0, B, n)]
     say(f"case: linear map and backward, depth {K}, {dtype}, batch {B} ({cus} CUs)")
     tw = S.config3(batch=B, depth=K)
     net = tw.truth
@@ -883,9 +885,10 @@ def test_linear_two_samples_per_wave_match_one_sample_calls(K, dtype):
     w, n, C1, C2, Gt = t(net.w), t(net.normals), t(tw.C1), t(tw.C2), t(G)
     Cb, _ = dmn_homogenize_linear(w, n, C1, C2)
     gw, gn, _, _, _ = dmn_homogenize_backward(w, n, C1, C2, Gt)
-    parts = [(0, cut), (cut, B)]
-    Cc = torch.cat([dmn_homogenize_linear(w, n, C1[a:b], C2[a:b])[0] for a, b in parts])
-    gparts = [dmn_homogenize_backward(w, n, C1[a:b], C2[a:b], Gt[a:b])[:2] for a, b in parts]
+    Cc = torch.cat([dmn_homogenize_linear(w, n, C1[a:b], C2[a:b])[0]
+                    for a, b in chunks(fwd_cut)])
+    gparts = [dmn_homogenize_backward(w, n, C1[a:b], C2[a:b], Gt[a:b])[:2]
+              for a, b in chunks(bwd_cut)]
     torch.cuda.synchronize()
     Cb_np, Cc_np = Cb.double().cpu().numpy(), Cc.double().cpu().numpy()
     diff = np.abs(Cb_np - Cc_np).max(axis=(1, 2)) / np.abs(Cc_np).max(axis=(1, 2))
