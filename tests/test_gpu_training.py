@@ -698,6 +698,61 @@ def test_grouped_linear_matches_per_group_calls_and_oracle(K, G, per, dtype):
             assert rel(Cbar[a:b].cpu().numpy(), ref) < tol, k
 
 
+@pytest.mark.parametrize("K,dtype,per_cu", [(7, torch.float64, 8), (8, torch.float32, 8),
+                                             (8, torch.float64, 64)])
+def test_grouped_linear_above_the_pairing_size(K, dtype, per_cu):
+    """Grouped map and VJP over 31 groups whose total passes the size above
+    which a launch runs two samples per wave (8 samples per CU; 64 for the
+    FP64 depth-8 VJP) while every group stays below it: the grouped launch
+    pairs samples and the plain call per group does not, so the two agree
+    within rounding (the same laminate operations, contracted into FMAs
+    differently).  Cbar of sampled samples also against the oracle's
+    compressed-tree map."""
+    from oracle.compression import dmn_linear_compressed
+    from paper_2103_08253_amd import (dmn_homogenize_backward, dmn_homogenize_backward_groups,
+                                      dmn_homogenize_linear, dmn_homogenize_linear_groups,
+                                      error_word)
+    cus = torch.cuda.get_device_properties(dev()).multi_processor_count
+    thr = per_cu * cus
+    per = thr // 10
+    w, n_groups, offsets, C1, C2, gC = grouped_case(K, 31, per, 140 + K)
+    B = int(offsets[-1])
+    sizes = np.diff(offsets)
+    say(f"grouped linear above the pairing size K={K} {dtype} B={B} (pairs above {thr}), "
+        f"largest group {sizes.max()}")
+    assert B > thr and sizes.max() <= min(thr, 8 * cus)
+    wt, nt = tt(w, dtype), tt(n_groups, dtype)
+    C1t, C2t, gCt = tt(C1, dtype), tt(C2, dtype), tt(gC, dtype)
+    Cbar, wsf = dmn_homogenize_linear_groups(wt, nt, offsets, C1t, C2t)
+    gw, gn, wsb = dmn_homogenize_backward_groups(wt, nt, offsets, C1t, C2t, gCt)
+    torch.cuda.synchronize()
+    assert error_word(wsf) == 0 and error_word(wsb) == 0
+    f64 = dtype == torch.float64
+    worst_C = worst_g = 0.0
+    for k in range(31):
+        a, b = int(offsets[k]), int(offsets[k + 1])
+        if b == a:
+            assert not gw[k].any() and not gn[k].any(), k
+            continue
+        ref_C, _ = dmn_homogenize_linear(wt, nt[k].contiguous(), C1t[a:b], C2t[a:b])
+        ref_w, ref_n, _, _, _ = dmn_homogenize_backward(wt, nt[k].contiguous(), C1t[a:b],
+                                                        C2t[a:b], gCt[a:b])
+        got, ref = Cbar[a:b].double().cpu().numpy(), ref_C.double().cpu().numpy()
+        d = np.abs(got - ref).max(axis=(1, 2)) / np.abs(ref).max(axis=(1, 2))
+        worst_C = max(worst_C, d.max())
+        worst_g = max(worst_g, rel(gw[k].double().cpu().numpy(), ref_w.double().cpu().numpy()),
+                      rel(gn[k].double().cpu().numpy(), ref_n.double().cpu().numpy()))
+        if k % 10 == 0:
+            pick = range(a, min(b, a + 4))
+            ref_o = np.stack([dmn_linear_compressed(K, w, n_groups[k], C1[i], C2[i])
+                              for i in pick])
+            assert rel(Cbar[a:a + len(pick)].double().cpu().numpy(), ref_o) < \
+                (1e-10 if f64 else 1e-4), k
+    say(f"  grouped vs per-group calls: Cbar {worst_C:.2e}, gradients {worst_g:.2e}")
+    assert worst_C <= (1e-13 if f64 else 1e-4)
+    assert worst_g <= (1e-12 if f64 else 1e-4)
+
+
 def test_oriented_training_grouped_equals_per_group_calls():
     """The oriented step with grouped calls and with one call per group on
     four streams gives bit-identical parameters, state and statistics."""
