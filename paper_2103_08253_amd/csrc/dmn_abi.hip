@@ -155,7 +155,7 @@ size_t dmn_homogenize_backward_workspace_size(const dmn_net* net, int64_t B, int
   if (m < 0) return 0;
   const int depth = net->depth;
   const size_t L = ((size_t)1 << depth) - 1;
-  const size_t slots = (size_t)dmn::linear_backward_partials(depth, B);
+  const size_t slots = (size_t)dmn::linear_backward_partials(depth, B, prec == DMN_F32);
   const size_t gang = m > 0 ? align_up(L * 2 * (size_t)B * elt_size(prec)) : 0;
   return kAlign + table_bytes(depth, prec) + align_up(L * 4 * sizeof(double)) +
          align_up(slots * L * 4 * sizeof(double)) + gang;
@@ -176,7 +176,7 @@ int dmn_homogenize_backward(const dmn_net* net, int64_t B, int prec, const void*
   if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0) return DMN_EWORKSPACE;
   const int K = net->depth;
   const size_t L = ((size_t)1 << K) - 1;
-  const size_t slots = (size_t)dmn::linear_backward_partials(K, B);
+  const size_t slots = (size_t)dmn::linear_backward_partials(K, B, prec == DMN_F32);
   int32_t* err = (int32_t*)ws;
   Table tb = table_at(ws, kAlign);
   double* gsum = (double*)((char*)ws + kAlign + table_bytes(K, prec));
@@ -234,7 +234,8 @@ size_t dmn_homogenize_backward_groups_workspace_size(int32_t depth, int32_t G,
   if (!depth_ok(depth) || !group_offsets_ok(G, offsets) || (prec != DMN_F64 && prec != DMN_F32))
     return 0;
   const size_t L = ((size_t)1 << depth) - 1;
-  const size_t slots = (size_t)dmn::linear_backward_group_slots(depth, G, offsets);
+  const size_t slots =
+      (size_t)dmn::linear_backward_group_slots(depth, G, offsets, prec == DMN_F32);
   return kAlign + (size_t)G * table_bytes(depth, prec) +
          align_up((size_t)G * L * 4 * sizeof(double)) + align_up(slots * L * 4 * sizeof(double));
 }

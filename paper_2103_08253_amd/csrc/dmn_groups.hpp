@@ -32,7 +32,7 @@ int launch_linear_backward_groups(int depth, int prec, const void* tab, const in
                                   const void* C1, const void* C2, const void* gCbar, void* gw,
                                   void* gn, double* partials, double* gsum, int32_t* err,
                                   hipStream_t stream);
-long long linear_backward_group_slots(int depth, int G, const int64_t* off);
+long long linear_backward_group_slots(int depth, int G, const int64_t* off, bool f32);
 
 // Tables of G DMNs sharing the leaf weights w, with normals n + g L 3 and
 // tables and flags tab_stride bytes apart (one workgroup each); dead subtrees

@@ -115,7 +115,7 @@ int launch_linear_backward(int depth, int prec, const void* tab, const int32_t* 
                            double* gsum, int32_t* err, const LinOriArgs& ori,
                            hipStream_t stream);
 // number of partial-sum slots (waves x samples per wave) the backward uses
-long long linear_backward_partials(int depth, long long B);
+long long linear_backward_partials(int depth, long long B, bool f32);
 
 // One point group of the path adjoint (device pointers).
 struct AdjointLaunch {

@@ -919,7 +919,6 @@ __global__ __launch_bounds__(256) void reduce_orientation_kernel(const T* __rest
   }
 }
 
-constexpr int kMaxBwdWaves = 2048;
 // deepest DMN whose linear map and VJP are compiled with per-sample orientation
 constexpr int kMaxOriLinearDepth = 8;
 
@@ -932,23 +931,68 @@ static int lin_default_D(int depth) {
 
 static int lin_ppw(int depth) { return 64 >> (depth - lin_default_D(depth)); }
 
-// persistent waves of the backward for a group of B samples (at least one, so
-// that an empty group still writes zero gradients)
-static long long bwd_waves(int depth, long long B) {
+// One-wave workgroups of the plain backward of depth K in T that one CU
+// holds at once (its registers and LDS), from the runtime's occupancy query.
+template <typename T, int K>
+static int bwd_blocks_per_cu_t() {
+  constexpr int D = (K - 6) < 1 ? 1 : (K - 6);
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, linear_bwd_kernel<T, K, D, false, false>,
+                                                   64, 0) != hipSuccess ||
+      n < 1)
+    n = 1;
+  return n;
+}
+
+static int bwd_blocks_per_cu(int depth, bool f32) {
+  static int cached[64][2][11] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (depth < 1 || depth > 10) return 1;
+  int& c = cached[dev][f32 ? 1 : 0][depth];
+  if (c == 0) {
+    switch (depth) {
+#define DMN_OCC_CASE(KK)                                                               \
+  case KK:                                                                             \
+    c = f32 ? bwd_blocks_per_cu_t<float, KK>() : bwd_blocks_per_cu_t<double, KK>();    \
+    break;
+      DMN_OCC_CASE(1)
+      DMN_OCC_CASE(2)
+      DMN_OCC_CASE(3)
+      DMN_OCC_CASE(4)
+      DMN_OCC_CASE(5)
+      DMN_OCC_CASE(6)
+      DMN_OCC_CASE(7)
+      DMN_OCC_CASE(8)
+      DMN_OCC_CASE(9)
+      DMN_OCC_CASE(10)
+#undef DMN_OCC_CASE
+    }
+  }
+  return c;
+}
+
+// persistent waves of the backward for a group of B samples: at most as many
+// as the device holds at once (more would only add waves that stage the
+// table again and partial-sum slots that the reduction reads), and at least
+// one, so that an empty group still writes zero gradients
+static long long bwd_waves(int depth, long long B, bool f32) {
   const int ppw = lin_ppw(depth);
   long long waves = (B + ppw - 1) / ppw;
-  if (waves > kMaxBwdWaves) waves = kMaxBwdWaves;
+  const long long cap = (long long)bwd_blocks_per_cu(depth, f32) * device_cu_count();
+  if (waves > cap) waves = cap;
   if (waves < 1) waves = 1;
   return waves;
 }
 
-long long linear_backward_partials(int depth, long long B) {
-  return bwd_waves(depth, B) * lin_ppw(depth);
+long long linear_backward_partials(int depth, long long B, bool f32) {
+  return bwd_waves(depth, B, f32) * lin_ppw(depth);
 }
 
-long long linear_backward_group_slots(int depth, int G, const int64_t* off) {
+long long linear_backward_group_slots(int depth, int G, const int64_t* off, bool f32) {
   long long slots = 0;
-  for (int g = 0; g < G; ++g) slots += bwd_waves(depth, off[g + 1] - off[g]) * lin_ppw(depth);
+  for (int g = 0; g < G; ++g)
+    slots += bwd_waves(depth, off[g + 1] - off[g], f32) * lin_ppw(depth);
   return slots;
 }
 
@@ -1097,7 +1141,8 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
     const int ng = G - g0 < kMaxLinGroups ? G - g0 : kMaxLinGroups;
     LinGroups gr;
     const long long waves =
-        chunk_groups(gr, off, g0, ng, tab_stride, [](long long B) { return bwd_waves(K, B); });
+        chunk_groups(gr, off, g0, ng, tab_stride,
+                     [](long long B) { return bwd_waves(K, B, sizeof(T) == 4); });
     if (waves < 0 || (long long)ng * L4 > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     const void* tabc = (const char*)tab + g0 * tab_stride;
     const int32_t* flagc = (const int32_t*)((const char*)flag + g0 * tab_stride);

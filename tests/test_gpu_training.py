@@ -291,9 +291,9 @@ def test_training_full_size_step():
                        np.concatenate([gv, ga, gb]), z, z, z, 1, opts.lr_max)
     got = np.concatenate([P.v.cpu().numpy(), P.alpha.cpu().numpy(), P.beta.cpu().numpy()])
     assert rel(got, th) < 1e-12
-    # the batch gradient itself (2048 partial slots per row, tree reduction)
-    # against the oracle's complex-step derivative of sum_s <gCbar_s, Cbar_s>
-    # for one weight and the two angles of one laminate
+    # the batch gradient itself (more than 64 partial slots per row, so the
+    # tree reduction) against the oracle's complex-step derivative of
+    # sum_s <gCbar_s, Cbar_s> for one weight and the two angles of one laminate
     from oracle.grad import linear_gradients
     ref = linear_gradients(K, T.macaulay(wl.v0), wl.alpha0, wl.beta0, wl.C1, wl.C2,
                            gC.cpu().numpy(), [37], [101])
