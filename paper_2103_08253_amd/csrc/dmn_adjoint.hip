@@ -363,14 +363,47 @@ __global__ __launch_bounds__(256) void adjoint_finish_kernel(const double* __res
   }
 }
 
-constexpr int kMaxAdjWaves = 2048;
-
 // lanes per point of the adjoint kernels: one wave holds a point's tree
 // (lane subtrees of depth max(1, K - 6))
 int adjoint_lanes_per_point(int depth) {
   int d = depth - 6;
   if (d < 1) d = 1;
   return 1 << (depth - d);
+}
+
+// One-wave workgroups of adjoint_kernel<K, D> that one CU holds at once (its
+// registers and LDS), from the runtime's occupancy query.
+template <int K, int D>
+int adj_blocks_per_cu_t() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_kernel<K, D>, 64, 0) !=
+          hipSuccess ||
+      n < 1)
+    n = 1;
+  return n;
+}
+
+int adj_blocks_per_cu(int depth) {
+  static int cached[64][11] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (depth < 1 || depth > 10) return 1;
+  int& c = cached[dev][depth];
+  if (c == 0) {
+    switch (depth) {
+      case 1: c = adj_blocks_per_cu_t<1, 1>(); break;
+      case 2: c = adj_blocks_per_cu_t<2, 1>(); break;
+      case 3: c = adj_blocks_per_cu_t<3, 1>(); break;
+      case 4: c = adj_blocks_per_cu_t<4, 1>(); break;
+      case 5: c = adj_blocks_per_cu_t<5, 1>(); break;
+      case 6: c = adj_blocks_per_cu_t<6, 1>(); break;
+      case 7: c = adj_blocks_per_cu_t<7, 1>(); break;
+      case 8: c = adj_blocks_per_cu_t<8, 2>(); break;
+      case 9: c = adj_blocks_per_cu_t<9, 3>(); break;
+      default: c = adj_blocks_per_cu_t<10, 4>(); break;
+    }
+  }
+  return c;
 }
 
 template <int K, int D>
@@ -385,7 +418,10 @@ long long adjoint_partial_slots(int depth, long long P) {
   const int lp = adjoint_lanes_per_point(depth);
   const int ppw = 64 / lp;
   long long waves = (P + ppw - 1) / ppw;
-  if (waves > kMaxAdjWaves) waves = kMaxAdjWaves;
+  // persistent waves: at most as many as the device holds at once (more would
+  // only add partial-sum slots for the reduction to read)
+  const long long cap = (long long)adj_blocks_per_cu(depth) * device_cu_count();
+  if (waves > cap) waves = cap;
   if (waves < 1) waves = 1;
   return waves * ppw;
 }
