@@ -275,10 +275,12 @@ inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) {
   *v = e ? atoi(e) : 2;
   return hipSuccess;
 }
-// the emulated device holds every wave of a launch at once
+// workgroups the emulated CU holds at once: SIMT_BLOCKS_PER_CU, else 64 (every
+// wave of the small test launches at once)
 template <class F>
 inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, F, int, size_t) {
-  *n = 64;
+  const char* e = getenv("SIMT_BLOCKS_PER_CU");
+  *n = e ? atoi(e) : 64;
   return hipSuccess;
 }
 inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {

@@ -269,6 +269,20 @@ def test_simt_linear_fp64_depth8_pair_backward(monkeypatch):
     check_linear(8, tw, G, out, 1e-10)
 
 
+@pytest.mark.parametrize("K,B", [(8, 19), (7, 37)])
+def test_simt_linear_backward_more_samples_than_waves(monkeypatch, K, B):
+    """The backward's persistent waves are capped at what the device holds at
+    once; with one emulated CU holding 4 waves, each wave accumulates several
+    samples (depth 8: one per wave-step; depth 7: two per wave-step, an odd
+    batch leaving a last half pair), against the oracle's map and
+    complex-step gradients."""
+    monkeypatch.setenv("SIMT_CUS", "1")
+    monkeypatch.setenv("SIMT_BLOCKS_PER_CU", "4")
+    tw, G = linear_case(K, B, 6)
+    out = harness().run_linear(K, tw.truth.w, tw.truth.normals, tw.C1, tw.C2, G)
+    check_linear(K, tw, G, out, 1e-10)
+
+
 def test_simt_linear_no_race_between_lanes():
     """The linear map, its backward and the reductions of the batch sum (the
     workgroup tree at depth 5 with 72 slots), the depth-8 forward with two
