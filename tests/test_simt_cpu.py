@@ -295,16 +295,22 @@ def test_simt_linear_no_race_between_lanes():
         check_linear(K, tw, G, out, 1e-10)
 
 
-@pytest.mark.parametrize("K,P,T,every,sanitizer", [(3, 3, 4, True, "address"),
-                                                   (5, 4, 3, False, "address"),
-                                                   (3, 2, 3, False, "thread")])
-def test_simt_path_adjoint(K, P, T, every, sanitizer):
+@pytest.mark.parametrize("K,P,T,every,sanitizer,blocks", [(3, 3, 4, True, "address", None),
+                                                          (5, 4, 3, False, "address", None),
+                                                          (5, 9, 3, False, "address", "1"),
+                                                          (3, 2, 3, False, "thread", None)])
+def test_simt_path_adjoint(monkeypatch, K, P, T, every, sanitizer, blocks):
     """The path gradient of J = sum_p g_p . sigma_p(final): forward path with
     the tight tolerance and one polishing step, then dmn_update_adjoint swept
     backwards over the steps, in the sanitised build, against the oracle's
     complex-step path derivative along unit directions (every parameter at
     depth 3; weights and both angles of a few laminates at depth 5); under
-    ThreadSanitizer too (the per-wave partial sums and their reduction)."""
+    ThreadSanitizer too (the per-wave partial sums and their reduction).  With
+    one emulated CU holding one wave, the adjoint's single persistent wave
+    takes the 9 points of depth 5 in three turns of 4."""
+    if blocks:
+        monkeypatch.setenv("SIMT_CUS", "1")
+        monkeypatch.setenv("SIMT_BLOCKS_PER_CU", blocks)
     from oracle.adjoint import path_directional_derivative
     rs = S.streams(400 + K)
     net = S.random_dmn(rs["dmn"], K, 0.25)
