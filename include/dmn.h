@@ -30,7 +30,10 @@
  *     host-side argument validation and launch errors; per-point device
  *     outcomes are written to the status arrays.
  *   - Workspace: each call needs a device workspace of at least the size its
- *     *_workspace_size() query returns (256-byte aligned base).
+ *     *_workspace_size() query returns (256-byte aligned base), queried with
+ *     the device current that the call will run on: the sizes of the linear
+ *     VJP and of the adjoint follow the number of waves that device holds at
+ *     once.  A call given less than its device needs returns DMN_EWORKSPACE.
  *   - Sizes: point and sample counts are int64 and every element offset into
  *     a per-point or per-sample array is computed in 64 bits, so arrays may
  *     exceed 2^31 elements; a count of 0 is valid (no data array is read and
