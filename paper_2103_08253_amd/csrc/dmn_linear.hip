@@ -1150,14 +1150,12 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
     // two samples per wave (linear_bwd_pair_kernel, same waves and partial
     // slots) at depths 7 and 8 and, as for the forward, only above 8 samples
     // per CU: smaller batches are latency bound and pairs would idle half the
-    // waves.  The FP64 depth-8 instance spills several hundred bytes per lane
-    // (the others fit the registers), which costs more than the pairing saves
-    // until a launch holds more than 64 samples per CU
+    // waves (the FP64 depth-8 instance spills a few hundred bytes per lane and
+    // still issues less per sample)
     constexpr bool kPair = C::PPW == 1 && (K == 7 || K == 8);
-    constexpr long long kPairPerCu = (K == 8 && sizeof(T) == 8) ? 64 : 8;
     bool paired = false;
     if constexpr (kPair) {
-      if (!ig && !oriented && off[g0 + ng] - off[g0] > kPairPerCu * device_cu_count()) {
+      if (!ig && !oriented && off[g0 + ng] - off[g0] > 8LL * device_cu_count()) {
         hipLaunchKernelGGL((linear_bwd_pair_kernel<T, K, D>), dim3((unsigned)waves), dim3(64), 0,
                            s, (const T*)tabc, flagc, (const T*)C1, (const T*)C2,
                            (const T*)gCbar, part, err, gr);

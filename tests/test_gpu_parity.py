@@ -855,10 +855,9 @@ def test_linear_backward_finite_differences_and_f32():
 @pytest.mark.parametrize("K,dtype", [(7, "f64"), (7, "f32"), (8, "f64"), (8, "f32")])
 def test_linear_two_samples_per_wave_match_one_sample_calls(K, dtype):
     """Above 8 samples per CU in a launch, the linear map at depths 7 and 8 and
-    its backward run two samples per wave that share the upper tree levels
-    (the FP64 depth-8 backward only above 64 samples per CU).  On a batch 37
-    samples above the backward's size, compare with calls on chunks at or
-    below each kernel's size, which run one sample per wave:
+    its backward run two samples per wave that share the upper tree levels.
+    On a batch 37 samples above that size, compare with calls on chunks at
+    or below it, which run one sample per wave:
     * Cbar agrees per sample within rounding (each sample sees the same
       laminate operations, Sec. 3.1, in the same order, but the compiler may
       contract them into FMAs differently in the two kernels);
@@ -873,7 +872,7 @@ def test_linear_two_samples_per_wave_match_one_sample_calls(K, dtype):
     d = dev()
     cus = torch.cuda.get_device_properties(d).multi_processor_count
     fwd_cut = 8 * cus
-    bwd_cut = (64 if (K, dtype) == (8, "f64") else 8) * cus
+    bwd_cut = 8 * cus
     B = bwd_cut + 37
     chunks = lambda n: [(a, min(a + n, B)) for a in range(0, B, n)]
     say(f"case: linear map and backward, depth {K}, {dtype}, batch {B} ({cus} CUs)")

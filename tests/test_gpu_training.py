@@ -699,11 +699,13 @@ def test_grouped_linear_matches_per_group_calls_and_oracle(K, G, per, dtype):
 
 
 @pytest.mark.parametrize("K,dtype,per_cu", [(7, torch.float64, 8), (8, torch.float32, 8),
-                                             (8, torch.float64, 64)])
+                                             (8, torch.float64, 8), (8, torch.float64, 64)])
 def test_grouped_linear_above_the_pairing_size(K, dtype, per_cu):
     """Grouped map and VJP over 31 groups whose total passes the size above
-    which a launch runs two samples per wave (8 samples per CU; 64 for the
-    FP64 depth-8 VJP) while every group stays below it: the grouped launch
+    which a launch runs two samples per wave (8 samples per CU) while every
+    group stays below it (groups of up to a tenth of per_cu samples per CU:
+    per_cu = 8 puts the total just above that size, 64 about ten times
+    above it): the grouped launch
     pairs samples and the plain call per group does not, so the two agree
     within rounding (the same laminate operations, contracted into FMAs
     differently).  Cbar of sampled samples also against the oracle's

@@ -247,8 +247,7 @@ def test_simt_linear_map_and_backward(K, B, dtype):
     ragged batches, depths 7 and 8 with two samples sharing a wave's upper
     levels in the forward once a batch has more than 8 samples per CU (two
     emulated CUs here; odd batches leave the last wave one sample) and in the
-    backward at depth 7 and in FP32 at depth 8 (FP64 at depth 8 pairs only
-    above 64 samples per CU: the next test), and
+    backward at depths 7 and 8, and
     at depth 5 with 70 samples 72 partial-sum slots, so the batch sum runs
     through the workgroup tree reduction; FP32 storage and arithmetic within
     1e-4."""
@@ -260,9 +259,9 @@ def test_simt_linear_map_and_backward(K, B, dtype):
 
 
 def test_simt_linear_fp64_depth8_pair_backward(monkeypatch):
-    """The FP64 depth-8 backward with two samples per wave, which a launch takes
-    above 64 samples per CU: 71 samples on one emulated CU, against the
-    oracle's map and complex-step gradients."""
+    """The FP64 depth-8 backward with two samples per wave over many pair
+    steps per wave: 71 samples on one emulated CU, against the oracle's map
+    and complex-step gradients."""
     monkeypatch.setenv("SIMT_CUS", "1")
     tw, G = linear_case(8, 71, 3)
     out = harness().run_linear(8, tw.truth.w, tw.truth.normals, tw.C1, tw.C2, G)
