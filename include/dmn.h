@@ -526,10 +526,10 @@ size_t dmn_homogenize_backward_groups_workspace_size(int32_t depth, int32_t G,
  * being what dmn_homogenize_backward returns for the samples of group k at
  * normals n_groups[k] (zero for an empty group), bit-identical to it (the
  * same waves per group and the same fixed reduction order) when both launches
- * run the same kernel.  At depths 7 and 8 the linear map and its VJP take two
- * samples per wave once a launch holds more than 8 samples per CU; where the
- * grouped launch and the plain call fall on different sides of that size,
- * the two agree within rounding.  No phase
+ * run the same kernel.  At depths 7 and 8 the linear map takes two samples
+ * per wave once a launch holds more than 8 samples per CU (the VJP does so in
+ * plain calls only); where the grouped launch and the plain call fall on
+ * different sides of that size, the two agree within rounding.  No phase
  * stiffness cotangents.  The forward is recomputed inside the call.  Same
  * error word as the forward. */
 int dmn_homogenize_backward_groups(int32_t depth, int32_t G, const int64_t* offsets, int prec,

@@ -1151,11 +1151,14 @@ static int bwd_k(const void* tab, const int32_t* flag, long long tab_stride, int
     // slots) at depths 7 and 8 and, as for the forward, only above 8 samples
     // per CU: smaller batches are latency bound and pairs would idle half the
     // waves (the FP64 depth-8 instance spills a few hundred bytes per lane and
-    // still issues less per sample)
+    // still issues less per sample).  Only launches of one group: a group
+    // below the wave cap gets one wave per sample, so in a launch of many
+    // small groups (training over orientations) pairs would leave half the
+    // waves without work
     constexpr bool kPair = C::PPW == 1 && (K == 7 || K == 8);
     bool paired = false;
     if constexpr (kPair) {
-      if (!ig && !oriented && off[g0 + ng] - off[g0] > 8LL * device_cu_count()) {
+      if (!ig && !oriented && ng == 1 && off[g0 + 1] - off[g0] > 8LL * device_cu_count()) {
         hipLaunchKernelGGL((linear_bwd_pair_kernel<T, K, D>), dim3((unsigned)waves), dim3(64), 0,
                            s, (const T*)tabc, flagc, (const T*)C1, (const T*)C2,
                            (const T*)gCbar, part, err, gr);

@@ -705,9 +705,9 @@ def test_grouped_linear_above_the_pairing_size(K, dtype, per_cu):
     which a launch runs two samples per wave (8 samples per CU) while every
     group stays below it (groups of up to a tenth of per_cu samples per CU:
     per_cu = 8 puts the total just above that size, 64 about ten times
-    above it): the grouped launch
-    pairs samples and the plain call per group does not, so the two agree
-    within rounding (the same laminate operations, contracted into FMAs
+    above it): the grouped forward pairs samples and the plain call per group
+    does not (grouped backward launches keep one sample per wave), so the two
+    agree within rounding (the same laminate operations, contracted into FMAs
     differently).  Cbar of sampled samples also against the oracle's
     compressed-tree map."""
     from oracle.compression import dmn_linear_compressed
